@@ -1,0 +1,660 @@
+/*
+ * dgref.c — FP64 CPU oracle for the RKDG scheme with the jump filter
+ * (arXiv:2407.19169).  TEST INFRASTRUCTURE ONLY: the plain, slow reference
+ * the GPU library is checked against.  Nothing in the product path may load
+ * it; it shares no code, header or table generator with the GPU library.
+ *
+ * Every formula is written out in the paper's own form (the damping
+ * coefficient is built from c_f^l, the jump sums and (2/h)^2 l(l+1) exactly
+ * as stated, not from a simplified closed form), with plain cell loops.
+ * Readings of points the paper leaves open are marked "Reading:".
+ */
+#include "dgref.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define MAXK 4
+#define MAXQ 8
+#define MAXV 4
+
+/* ------------------------------------------------------------------------ */
+/* Legendre polynomials and Gauss–Legendre quadrature                       */
+/* ------------------------------------------------------------------------ */
+
+/* Monomial coefficients of P_0..P_kmax from the three-term recurrence
+ * (l+1) P_{l+1} = (2l+1) x P_l - l P_{l-1}. c[l][i] multiplies x^i. */
+static void legendre_coeffs(int kmax, double c[][MAXQ + 2])
+{
+    memset(c, 0, sizeof(double) * (size_t)(kmax + 1) * (MAXQ + 2));
+    c[0][0] = 1.0;
+    if (kmax >= 1) c[1][1] = 1.0;
+    for (int l = 1; l < kmax; ++l)
+        for (int i = 0; i <= l + 1; ++i) {
+            double a = (i >= 1) ? (2.0 * l + 1.0) * c[l][i - 1] : 0.0;
+            c[l + 1][i] = (a - l * c[l - 1][i]) / (l + 1.0);
+        }
+}
+
+double dgref_legendre_deriv(int l, int m, double xi)
+{
+    if (l < 0 || l > MAXQ || m < 0) return NAN;
+    double c[MAXQ + 2][MAXQ + 2];
+    legendre_coeffs(l < 1 ? 1 : l, c);
+    double d[MAXQ + 2];
+    for (int i = 0; i <= l; ++i) d[i] = c[l][i];
+    /* differentiate m times */
+    for (int r = 0; r < m; ++r)
+        for (int i = 0; i <= l; ++i) d[i] = (i + 1 <= l) ? (i + 1) * d[i + 1] : 0.0;
+    double s = 0.0;
+    for (int i = l; i >= 0; --i) s = s * xi + d[i];
+    return s;
+}
+
+/* Gauss–Legendre nodes and weights by Newton's method on P_q, with P_q and
+ * P_{q-1} from the three-term recurrence and
+ * P_q'(z) = q (z P_q - P_{q-1}) / (z^2 - 1),  w = 2 / ((1 - z^2) P_q'(z)^2). */
+static void legendre_pair(int q, double z, double* pq, double* pqm1)
+{
+    double p0 = 1.0, p1 = z;
+    for (int l = 1; l < q; ++l) {
+        double p2 = ((2.0 * l + 1.0) * z * p1 - l * p0) / (l + 1.0);
+        p0 = p1;
+        p1 = p2;
+    }
+    *pq = p1;
+    *pqm1 = p0;
+}
+
+int dgref_gauss(int q, double* x, double* w)
+{
+    if (q < 1 || q > MAXQ) return DGREF_ERR_ARG;
+    for (int i = 0; i < q; ++i) {
+        double z = cos(M_PI * (i + 0.75) / (q + 0.5));
+        double pq, pm1, dpq;
+        for (int it = 0; it < 100; ++it) {
+            legendre_pair(q, z, &pq, &pm1);
+            dpq = q * (z * pq - pm1) / (z * z - 1.0);
+            double dz = pq / dpq;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        legendre_pair(q, z, &pq, &pm1);
+        dpq = q * (z * pq - pm1) / (z * z - 1.0);
+        x[q - 1 - i] = z; /* ascending order */
+        w[q - 1 - i] = 2.0 / ((1.0 - z * z) * dpq * dpq);
+    }
+    return DGREF_OK;
+}
+
+typedef struct {
+    int k, nq;
+    double xq[MAXQ], wq[MAXQ];
+    double phi[MAXQ][MAXK + 1];       /* P_l(xi_q)                         */
+    double dphi[MAXQ][MAXK + 1];      /* P_l'(xi_q)                        */
+    double tr[2][MAXK + 1][MAXK + 1]; /* tr[side][l][m] = P_l^(m)(-1 / +1) */
+} basis;
+
+static int make_basis(int k, int nq, basis* B)
+{
+    if (k < 0 || k > MAXK) return DGREF_ERR_ARG;
+    if (nq == 0) nq = k + 1;
+    if (nq < 1 || nq > MAXQ) return DGREF_ERR_ARG;
+    B->k = k;
+    B->nq = nq;
+    dgref_gauss(nq, B->xq, B->wq);
+    for (int q = 0; q < nq; ++q)
+        for (int l = 0; l <= k; ++l) {
+            B->phi[q][l] = dgref_legendre_deriv(l, 0, B->xq[q]);
+            B->dphi[q][l] = dgref_legendre_deriv(l, 1, B->xq[q]);
+        }
+    for (int s = 0; s < 2; ++s)
+        for (int l = 0; l <= k; ++l)
+            for (int m = 0; m <= k; ++m)
+                B->tr[s][l][m] = dgref_legendre_deriv(l, m, s ? 1.0 : -1.0);
+    return DGREF_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Physical fluxes                                                          */
+/* ------------------------------------------------------------------------ */
+
+int dgref_nvars(int eq, int dim)
+{
+    if (eq == DGREF_EULER) return dim == 1 ? 3 : 4;
+    return 1;
+}
+
+/* 1D flux f(u) (Sec. 3.1: Burgers f = u^2/2; Euler F(U) for U=(rho,m,E)). */
+static void flux1d(int eq, double gamma, double a, const double* u, double* f)
+{
+    if (eq == DGREF_ADVECTION) {
+        f[0] = a * u[0];
+    } else if (eq == DGREF_BURGERS) {
+        f[0] = 0.5 * u[0] * u[0];
+    } else {
+        double rho = u[0], m = u[1], E = u[2];
+        double vel = m / rho;
+        double p = (gamma - 1.0) * (E - 0.5 * m * vel);
+        f[0] = m;
+        f[1] = m * vel + p;
+        f[2] = vel * (E + p);
+    }
+}
+
+/* Largest characteristic speed |f'(u)| (Euler: |u| + c). */
+static double lambda1d(int eq, double gamma, double a, const double* u)
+{
+    if (eq == DGREF_ADVECTION) return fabs(a);
+    if (eq == DGREF_BURGERS) return fabs(u[0]);
+    double rho = u[0], m = u[1], E = u[2];
+    double vel = m / rho;
+    double p = (gamma - 1.0) * (E - 0.5 * m * vel);
+    return fabs(vel) + sqrt(gamma * p / rho);
+}
+
+/* Average enthalpy H = (E + p)/rho of the cell-average state (Euler only;
+ * Reading: H-bar is evaluated at the cell-average conserved state). */
+static double enthalpy1d(int eq, double gamma, const double* u)
+{
+    if (eq != DGREF_EULER) return 1.0;
+    double rho = u[0], m = u[1], E = u[2];
+    double p = (gamma - 1.0) * (E - 0.5 * m * m / rho);
+    return (E + p) / rho;
+}
+
+/* Local Lax–Friedrichs flux (Sec. 3, named for all tests; the standard
+ * two-point form with the larger of the two one-sided wave speeds). */
+static void llf1d(int eq, double gamma, double a, const double* ul, const double* ur,
+                  double* fh)
+{
+    int nv = dgref_nvars(eq, 1);
+    double fl[MAXV], fr[MAXV];
+    flux1d(eq, gamma, a, ul, fl);
+    flux1d(eq, gamma, a, ur, fr);
+    double al = lambda1d(eq, gamma, a, ul);
+    double ar = lambda1d(eq, gamma, a, ur);
+    double alpha = al > ar ? al : ar;
+    for (int v = 0; v < nv; ++v) fh[v] = 0.5 * (fl[v] + fr[v]) - 0.5 * alpha * (ur[v] - ul[v]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* 1D helpers                                                               */
+/* ------------------------------------------------------------------------ */
+
+#define U1(u, v, l, j) ((u)[((size_t)(v) * (size_t)(K1) + (size_t)(l)) * (size_t)n + (size_t)(j)])
+
+static int check1d(const dgref_problem1d* P)
+{
+    if (!P || P->n < 1 || P->k < 0 || P->k > MAXK) return DGREF_ERR_ARG;
+    if (P->eq < 0 || P->eq > 2) return DGREF_ERR_ARG;
+    if (!(P->hi > P->lo)) return DGREF_ERR_ARG;
+    for (int s = 0; s < 2; ++s) {
+        if (P->bc[s] < 0 || P->bc[s] > 3) return DGREF_ERR_ARG;
+        if (P->bc[s] == DGREF_REFLECT && P->eq != DGREF_EULER) return DGREF_ERR_ARG;
+    }
+    if ((P->bc[0] == DGREF_PERIODIC) != (P->bc[1] == DGREF_PERIODIC)) return DGREF_ERR_ARG;
+    return DGREF_OK;
+}
+
+/* m-th x-derivative of cell j's polynomial at its left (side 0) or right
+ * (side 1) end: (2/h)^m sum_l u^l P_l^(m)(-1 / +1). */
+static void trace1d(const dgref_problem1d* P, const basis* B, const double* u, int64_t j,
+                    int side, int m, double h, double* out)
+{
+    const int K1 = P->k + 1;
+    const int64_t n = P->n;
+    int nv = dgref_nvars(P->eq, 1);
+    double scale = pow(2.0 / h, m);
+    for (int v = 0; v < nv; ++v) {
+        double s = 0.0;
+        for (int l = 0; l <= P->k; ++l) s += U1(u, v, l, j) * B->tr[side][l][m];
+        out[v] = scale * s;
+    }
+}
+
+/* Ghost value of the m-th derivative outside boundary `side` (0 = left end
+ * of the domain, 1 = right end) given the interior one-sided value.
+ * Reading of the boundary treatment: outflow copies the interior trace,
+ * reflection mirrors it (momentum odd, the m-th derivative picks up
+ * (-1)^m), Dirichlet is the prescribed constant state. */
+static void ghost1d(const dgref_problem1d* P, int side, int m, const double* inner, double* g)
+{
+    int nv = dgref_nvars(P->eq, 1);
+    int bc = P->bc[side];
+    for (int v = 0; v < nv; ++v) {
+        if (bc == DGREF_OUTFLOW) {
+            g[v] = inner[v];
+        } else if (bc == DGREF_REFLECT) {
+            double sgn = (m % 2) ? -1.0 : 1.0;
+            if (v == 1) sgn = -sgn;
+            g[v] = sgn * inner[v];
+        } else { /* Dirichlet */
+            g[v] = (m == 0) ? P->dirichlet[side][v] : 0.0;
+        }
+    }
+}
+
+/* Left/right values of the m-th derivative at interface i (0..n), i.e. at
+ * x_{i-1/2} between cells i-1 and i (0-based cells). */
+static void iface1d(const dgref_problem1d* P, const basis* B, const double* u, int64_t i,
+                    int m, double h, double* left, double* right)
+{
+    const int64_t n = P->n;
+    if (i == 0) {
+        trace1d(P, B, u, 0, 0, m, h, right);
+        if (P->bc[0] == DGREF_PERIODIC)
+            trace1d(P, B, u, n - 1, 1, m, h, left);
+        else
+            ghost1d(P, 0, m, right, left);
+    } else if (i == n) {
+        trace1d(P, B, u, n - 1, 1, m, h, left);
+        if (P->bc[1] == DGREF_PERIODIC)
+            trace1d(P, B, u, 0, 0, m, h, right);
+        else
+            ghost1d(P, 1, m, left, right);
+    } else {
+        trace1d(P, B, u, i - 1, 1, m, h, left);
+        trace1d(P, B, u, i, 0, m, h, right);
+    }
+}
+
+static void average1d(const dgref_problem1d* P, const double* u, int64_t j, double* ubar)
+{
+    const int K1 = P->k + 1;
+    const int64_t n = P->n;
+    int nv = dgref_nvars(P->eq, 1);
+    for (int v = 0; v < nv; ++v) ubar[v] = U1(u, v, 0, j);
+}
+
+/* ------------------------------------------------------------------------ */
+/* 1D semi-discrete DG operator (Sec. 2.1, scheme (scheme:DG))              */
+/* ------------------------------------------------------------------------ */
+
+/* L = du/dt of the semi-discrete scheme with v = P_l(xi):
+ *   (h/(2l+1)) du^l/dt = int_{-1}^{1} f(u_h) P_l'(xi) dxi
+ *                        - fhat_{j+1/2} P_l(1) + fhat_{j-1/2} P_l(-1).
+ * The volume integral uses the Gauss rule of B.  fhat (nullable) receives
+ * the interface fluxes, fhat[v*(n+1) + i]. */
+int dgref_residual1d(const dgref_problem1d* P, const double* u, double* L, double* fhat)
+{
+    int rc = check1d(P);
+    if (rc) return rc;
+    basis B;
+    if ((rc = make_basis(P->k, P->nq, &B))) return rc;
+    const int K1 = P->k + 1;
+    const int64_t n = P->n;
+    const int nv = dgref_nvars(P->eq, 1);
+    const double h = (P->hi - P->lo) / (double)n;
+
+    double* fh = (double*)malloc(sizeof(double) * (size_t)nv * (size_t)(n + 1));
+    if (!fh) return DGREF_ERR_ARG;
+
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i <= n; ++i) {
+        double ul[MAXV], ur[MAXV], f[MAXV];
+        iface1d(P, &B, u, i, 0, h, ul, ur);
+        llf1d(P->eq, P->gamma, P->adv_speed, ul, ur, f);
+        for (int v = 0; v < nv; ++v) fh[(size_t)v * (size_t)(n + 1) + (size_t)i] = f[v];
+    }
+
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j) {
+        double fq[MAXQ][MAXV];
+        for (int q = 0; q < B.nq; ++q) {
+            double uq[MAXV];
+            for (int v = 0; v < nv; ++v) {
+                double s = 0.0;
+                for (int l = 0; l <= P->k; ++l) s += U1(u, v, l, j) * B.phi[q][l];
+                uq[v] = s;
+            }
+            flux1d(P->eq, P->gamma, P->adv_speed, uq, fq[q]);
+        }
+        for (int v = 0; v < nv; ++v)
+            for (int l = 0; l <= P->k; ++l) {
+                double vol = 0.0;
+                for (int q = 0; q < B.nq; ++q) vol += B.wq[q] * fq[q][v] * B.dphi[q][l];
+                double fr = fh[(size_t)v * (size_t)(n + 1) + (size_t)(j + 1)];
+                double fl = fh[(size_t)v * (size_t)(n + 1) + (size_t)j];
+                double mass = h / (2.0 * l + 1.0);
+                U1(L, v, l, j) = (vol - fr * B.tr[1][l][0] + fl * B.tr[0][l][0]) / mass;
+            }
+    }
+    if (fhat) memcpy(fhat, fh, sizeof(double) * (size_t)nv * (size_t)(n + 1));
+    free(fh);
+    return DGREF_OK;
+}
+
+/* CFL wave speed: the largest |f'(u)| over the cell averages.
+ * Reading: the paper only requires tau <= gamma h (Theorem 2.1); the
+ * estimate from cell averages is the same quantity as beta_j. */
+double dgref_max_wavespeed1d(const dgref_problem1d* P, const double* u)
+{
+    if (check1d(P)) return NAN;
+    double amax = 0.0;
+    for (int64_t j = 0; j < P->n; ++j) {
+        double ub[MAXV];
+        average1d(P, u, j, ub);
+        double a = lambda1d(P->eq, P->gamma, P->adv_speed, ub);
+        if (!(a <= amax)) amax = a; /* propagates NaN */
+    }
+    return amax;
+}
+
+/* SSP-RK3 in Shu–Osher form (Sec. 3, third-order SSP-RK; general form
+ * (rkdg1)), without the post-stage filter:
+ *   stage 0: u1  = un + dt L(un)
+ *   stage 1: u2  = 3/4 un + 1/4 (u1 + dt L(u1))
+ *   stage 2: un+1 = 1/3 un + 2/3 (u2 + dt L(u2))                          */
+int dgref_stage1d(const dgref_problem1d* P, int stage, double dt, const double* un,
+                  const double* us, double* out, double* fhat)
+{
+    int rc = check1d(P);
+    if (rc) return rc;
+    if (stage < 0 || stage > 2) return DGREF_ERR_ARG;
+    const int nv = dgref_nvars(P->eq, 1);
+    const size_t ndof = (size_t)nv * (size_t)(P->k + 1) * (size_t)P->n;
+    const double* src = (stage == 0) ? un : us;
+    double* L = (double*)malloc(sizeof(double) * ndof);
+    if (!L) return DGREF_ERR_ARG;
+    rc = dgref_residual1d(P, src, L, fhat);
+    if (!rc) {
+        for (size_t i = 0; i < ndof; ++i) {
+            double adv = src[i] + dt * L[i];
+            if (stage == 0)
+                out[i] = adv;
+            else if (stage == 1)
+                out[i] = 0.75 * un[i] + 0.25 * adv;
+            else
+                out[i] = un[i] / 3.0 + 2.0 * adv / 3.0;
+        }
+    }
+    free(L);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 1D jump filter (Sec. 2.1 (para:damp2)-(para:damp21); systems Sec. 2.4    */
+/* (para:dampsystems1d); Euler parameter c_f^l = beta/(4l(l+1)) / H-bar)    */
+/* ------------------------------------------------------------------------ */
+
+/* Damping exponents E[j*(k+1)+l] = sigma_j^l * dt for l = 0..k (E[.,0] = 0),
+ * and the hybrid jump indicator eta_j = ||[u]||_{dK_j} / (2 h_j) (max over
+ * components; Algorithm 1).  Jumps are taken from v, the unfiltered stage
+ * output of all cells. */
+int dgref_exponents1d(const dgref_problem1d* P, double dt, const double* v, double* E,
+                      double* eta)
+{
+    int rc = check1d(P);
+    if (rc) return rc;
+    basis B;
+    if ((rc = make_basis(P->k, P->nq, &B))) return rc;
+    const int k = P->k;
+    const int64_t n = P->n;
+    const int nv = dgref_nvars(P->eq, 1);
+    const double h = (P->hi - P->lo) / (double)n;
+
+    /* |[d^m u]| at every interface: jmp[(i*(k+1) + m)*nv + var] */
+    double* jmp = (double*)malloc(sizeof(double) * (size_t)(n + 1) * (size_t)(k + 1) * nv);
+    if (!jmp) return DGREF_ERR_ARG;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i <= n; ++i)
+        for (int m = 0; m <= k; ++m) {
+            double a[MAXV], b[MAXV];
+            iface1d(P, &B, v, i, m, h, a, b);
+            for (int s = 0; s < nv; ++s)
+                jmp[((size_t)i * (size_t)(k + 1) + (size_t)m) * nv + s] = fabs(b[s] - a[s]);
+        }
+
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j) {
+        /* ||[d^m u^(s)]||_{dK_j}: sum of the two interface jumps */
+        double J[MAXK + 1][MAXV];
+        for (int m = 0; m <= k; ++m)
+            for (int s = 0; s < nv; ++s)
+                J[m][s] = jmp[((size_t)j * (size_t)(k + 1) + (size_t)m) * nv + s] +
+                          jmp[((size_t)(j + 1) * (size_t)(k + 1) + (size_t)m) * nv + s];
+        double ub[MAXV];
+        average1d(P, v, j, ub);
+        double beta = lambda1d(P->eq, P->gamma, P->adv_speed, ub); /* |f'(u-bar_j)| */
+        double Hbar = enthalpy1d(P->eq, P->gamma, ub);
+        E[(size_t)j * (size_t)(k + 1)] = 0.0; /* sigma^0 = 0: mode 0 is kept */
+        for (int l = 1; l <= k; ++l) {
+            double cf = beta / (4.0 * l * (l + 1.0)) / Hbar;
+            double sig = 0.0; /* max over components of sigma_{j,l}(u^(s)) */
+            for (int s = 0; s < nv; ++s) {
+                double acc = h * J[0][s];
+                for (int m = 1; m <= l; ++m) acc += m * (m + 1.0) * pow(h, m + 1) * J[m][s];
+                double sjl = cf * acc;
+                if (s == 0 || sjl > sig) sig = sjl;
+            }
+            double sigma_l = sig * (2.0 / h) * (2.0 / h) * l * (l + 1.0);
+            E[(size_t)j * (size_t)(k + 1) + (size_t)l] = sigma_l * dt;
+        }
+        if (eta) {
+            double e = 0.0;
+            for (int s = 0; s < nv; ++s) {
+                double es = J[0][s] / (2.0 * h);
+                if (s == 0 || es > e) e = es;
+            }
+            eta[j] = e;
+        }
+    }
+    free(jmp);
+    return DGREF_OK;
+}
+
+/* u_j^l <- exp(-sigma_j^l dt) u_j^l (time-split solution (timespli:sys)). */
+int dgref_filter1d(const dgref_problem1d* P, double dt, const double* v, double* out)
+{
+    int rc = check1d(P);
+    if (rc) return rc;
+    const int K1 = P->k + 1;
+    const int64_t n = P->n;
+    const int nv = dgref_nvars(P->eq, 1);
+    double* E = (double*)malloc(sizeof(double) * (size_t)n * (size_t)K1);
+    if (!E) return DGREF_ERR_ARG;
+    rc = dgref_exponents1d(P, dt, v, E, NULL);
+    if (!rc)
+        for (int s = 0; s < nv; ++s)
+            for (int l = 0; l < K1; ++l)
+                for (int64_t j = 0; j < n; ++j)
+                    U1(out, s, l, j) = exp(-E[(size_t)j * K1 + l]) * U1(v, s, l, j);
+    free(E);
+    return rc;
+}
+
+/* Hybrid procedure (Algorithm 1) with the jump filter as the low-order
+ * limiter: troubled cells (eta_j > 1) get
+ *   u_hyd = omega_j u_DG + (1 - omega_j) u_lim,
+ *   omega_j = (max eta - eta_j) / (max eta - 1),
+ * all other cells keep u_DG. */
+int dgref_hybrid1d(const dgref_problem1d* P, double dt, const double* v, double* out,
+                   int64_t* troubled)
+{
+    int rc = check1d(P);
+    if (rc) return rc;
+    const int K1 = P->k + 1;
+    const int64_t n = P->n;
+    const int nv = dgref_nvars(P->eq, 1);
+    double* E = (double*)malloc(sizeof(double) * (size_t)n * (size_t)K1);
+    double* eta = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!E || !eta) { free(E); free(eta); return DGREF_ERR_ARG; }
+    rc = dgref_exponents1d(P, dt, v, E, eta);
+    if (!rc) {
+        double M = 0.0;
+        for (int64_t j = 0; j < n; ++j)
+            if (!(eta[j] <= M)) M = eta[j];
+        int64_t cnt = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            int hit = eta[j] > 1.0;
+            double w = hit ? (M - eta[j]) / (M - 1.0) : 1.0;
+            cnt += hit;
+            for (int s = 0; s < nv; ++s)
+                for (int l = 0; l < K1; ++l) {
+                    double dg = U1(v, s, l, j);
+                    if (hit && l > 0) {
+                        /* mode 0: u_lim^0 = u_DG^0 (sigma^0 = 0), so the blend
+                         * of two equal values is that value */
+                        double lim = exp(-E[(size_t)j * K1 + l]) * dg;
+                        U1(out, s, l, j) = w * dg + (1.0 - w) * lim;
+                    } else {
+                        U1(out, s, l, j) = dg;
+                    }
+                }
+        }
+        if (troubled) *troubled += cnt;
+    }
+    free(E);
+    free(eta);
+    return rc;
+}
+
+/* Post-stage operator applied after every RK stage (Sec. 3).
+ * Reading of the damping duration: the split viscous problem is advanced
+ * over the full step dt after every stage (filter_dt = 0); filter_dt = 1
+ * uses the stage's own weight (1, 1/4, 2/3) of dt instead. */
+int dgref_post1d(const dgref_problem1d* P, int stage, double dt, const double* v,
+                 double* out, int64_t* troubled)
+{
+    static const double stage_weight[3] = {1.0, 0.25, 2.0 / 3.0};
+    int rc = check1d(P);
+    if (rc) return rc;
+    double tau = (P->filter_dt == 1) ? dt * stage_weight[stage] : dt;
+    const size_t ndof = (size_t)dgref_nvars(P->eq, 1) * (size_t)(P->k + 1) * (size_t)P->n;
+    if (P->filter == DGREF_FILTER_JUMP) return dgref_filter1d(P, tau, v, out);
+    if (P->filter == DGREF_FILTER_HYBRID) return dgref_hybrid1d(P, tau, v, out, troubled);
+    if (out != v) memcpy(out, v, sizeof(double) * ndof);
+    return DGREF_OK;
+}
+
+/* One SSP-RK3 step with the post-stage operator after each stage (err_rk1,
+ * err_rk2).  bflux (nullable) accumulates dt * sum_s b_s (fhat_right -
+ * fhat_left) with the effective weights b = (1/6, 1/6, 2/3). */
+int dgref_step1d(const dgref_problem1d* P, double dt, double* u, double* bflux,
+                 int64_t* troubled)
+{
+    static const double b[3] = {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0};
+    int rc = check1d(P);
+    if (rc) return rc;
+    const int nv = dgref_nvars(P->eq, 1);
+    const int64_t n = P->n;
+    const size_t ndof = (size_t)nv * (size_t)(P->k + 1) * (size_t)n;
+    double* un = (double*)malloc(sizeof(double) * ndof);
+    double* us = (double*)malloc(sizeof(double) * ndof);
+    double* w = (double*)malloc(sizeof(double) * ndof);
+    double* fh = (double*)malloc(sizeof(double) * (size_t)nv * (size_t)(n + 1));
+    if (!un || !us || !w || !fh) { rc = DGREF_ERR_ARG; goto done; }
+    memcpy(un, u, sizeof(double) * ndof);
+    memcpy(us, u, sizeof(double) * ndof);
+    for (int s = 0; s < 3 && !rc; ++s) {
+        rc = dgref_stage1d(P, s, dt, un, us, w, fh);
+        if (rc) break;
+        if (bflux)
+            for (int v = 0; v < nv; ++v)
+                bflux[v] += dt * b[s] *
+                            (fh[(size_t)v * (size_t)(n + 1) + (size_t)n] - fh[(size_t)v * (size_t)(n + 1)]);
+        rc = dgref_post1d(P, s, dt, w, us, troubled);
+    }
+    if (!rc) memcpy(u, us, sizeof(double) * ndof);
+done:
+    free(un);
+    free(us);
+    free(w);
+    free(fh);
+    return rc;
+}
+
+/* Positivity of density and pressure at every quadrature and trace point
+ * (Euler), and finiteness of every coefficient. */
+int dgref_check1d(const dgref_problem1d* P, const double* u, double* min_rho, double* min_p,
+                  int64_t* first_bad)
+{
+    int rc = check1d(P);
+    if (rc) return rc;
+    basis B;
+    if ((rc = make_basis(P->k, P->nq, &B))) return rc;
+    const int K1 = P->k + 1;
+    const int64_t n = P->n;
+    const int nv = dgref_nvars(P->eq, 1);
+    double mr = INFINITY, mp = INFINITY;
+    int status = DGREF_OK;
+    int64_t bad = -1;
+    for (int64_t j = 0; j < n; ++j) {
+        int finite = 1;
+        for (int s = 0; s < nv; ++s)
+            for (int l = 0; l < K1; ++l)
+                if (!isfinite(U1(u, s, l, j))) finite = 0;
+        if (!finite) {
+            if (status == DGREF_OK) { status = DGREF_ERR_NONFINITE; bad = j; }
+            continue;
+        }
+        if (P->eq != DGREF_EULER) continue;
+        for (int q = 0; q < B.nq + 2; ++q) {
+            double uq[MAXV];
+            for (int s = 0; s < nv; ++s) {
+                double acc = 0.0;
+                for (int l = 0; l < K1; ++l) {
+                    double ph = (q < B.nq) ? B.phi[q][l] : B.tr[q - B.nq][l][0];
+                    acc += U1(u, s, l, j) * ph;
+                }
+                uq[s] = acc;
+            }
+            double p = (P->gamma - 1.0) * (uq[2] - 0.5 * uq[1] * uq[1] / uq[0]);
+            if (uq[0] < mr) mr = uq[0];
+            if (p < mp) mp = p;
+            if ((!(uq[0] > 0.0) || !(p > 0.0)) && status == DGREF_OK) {
+                status = DGREF_ERR_POSITIVITY;
+                bad = j;
+            }
+        }
+    }
+    if (min_rho) *min_rho = mr;
+    if (min_p) *min_p = mp;
+    if (first_bad) *first_bad = bad;
+    return status;
+}
+
+/* Time loop: alpha from the cell averages, dt = cfl*h/alpha, the last step
+ * clamped to end exactly at t_end. */
+int dgref_run1d(const dgref_problem1d* P, double t_end, int64_t max_steps, double* u,
+                dgref_report* rep)
+{
+    int rc = check1d(P);
+    if (rc) return rc;
+    const int K1 = P->k + 1;
+    const int64_t n = P->n;
+    const int nv = dgref_nvars(P->eq, 1);
+    const double h = (P->hi - P->lo) / (double)n;
+    dgref_report r;
+    memset(&r, 0, sizeof r);
+    r.dt_min = INFINITY;
+    r.first_bad_cell = -1;
+    double t = 0.0;
+    while (t < t_end && r.steps < max_steps) {
+        double alpha = dgref_max_wavespeed1d(P, u);
+        if (!isfinite(alpha)) { rc = DGREF_ERR_NONFINITE; break; }
+        double dt = P->cfl * h / alpha;
+        int last = 0;
+        if (t + dt >= t_end) { dt = t_end - t; last = 1; }
+        rc = dgref_step1d(P, dt, u, r.boundary_flux, &r.troubled_cells);
+        if (rc) break;
+        t = last ? t_end : t + dt;
+        r.steps++;
+        if (dt < r.dt_min) r.dt_min = dt;
+        if (dt > r.dt_max) r.dt_max = dt;
+    }
+    r.t = t;
+    for (int s = 0; s < nv; ++s) {
+        double q = 0.0;
+        for (int64_t j = 0; j < n; ++j) q += h * U1(u, s, 0, j);
+        r.ledger[s] = q;
+    }
+    int crc = dgref_check1d(P, u, &r.min_rho, &r.min_p, &r.first_bad_cell);
+    if (!rc) rc = crc;
+    r.status = rc;
+    if (rep) *rep = r;
+    (void)K1;
+    return rc;
+}

@@ -1,0 +1,113 @@
+/*
+ * dgref.h — FP64 CPU oracle for the RKDG scheme with the jump filter
+ * (Wei, Zhou, Xia, "The jump filter in the discontinuous Galerkin method
+ * for hyperbolic conservation laws", arXiv:2407.19169).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, plain reference the
+ * GPU library is checked against.  Only the test-suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it.  It shares no source,
+ * header, table or constant generator with the GPU library.
+ *
+ * State layout (the same layout the inputs are exchanged in):
+ *   1D: u[(var * (k+1) + l) * n + j]            modal coefficient u_j^{l,(var)}
+ *   2D: u[((var * nm + p*(k+1) + q) * ny + jy) * nx + ix]   Q^k tensor modes
+ * with the standard Legendre basis P_l(xi), P_0 = 1, so mode 0 is the cell
+ * average (Sec. 2.1, basis expansion (eq:GLbasisequation)).
+ */
+#ifndef DGREF_H
+#define DGREF_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { DGREF_ADVECTION = 0, DGREF_BURGERS = 1, DGREF_EULER = 2 };
+enum { DGREF_PERIODIC = 0, DGREF_OUTFLOW = 1, DGREF_REFLECT = 2, DGREF_DIRICHLET = 3 };
+enum { DGREF_FILTER_NONE = 0, DGREF_FILTER_JUMP = 1, DGREF_FILTER_HYBRID = 2 };
+
+/* Status bits of a run. */
+enum { DGREF_OK = 0, DGREF_ERR_ARG = -1, DGREF_ERR_NONFINITE = -4, DGREF_ERR_POSITIVITY = -5 };
+
+typedef struct {
+    int eq;              /* DGREF_ADVECTION / BURGERS / EULER                  */
+    int k;               /* polynomial degree, 0..4                            */
+    int nq;              /* Gauss points per direction (0 -> k+1)              */
+    int filter;          /* DGREF_FILTER_*                                     */
+    int filter_dt;       /* 0: damping time = full dt after every stage;
+                            1: damping time = dt times the stage's RK weight   */
+    int bc[2];           /* left, right boundary                               */
+    int64_t n;           /* cells                                              */
+    double lo, hi;       /* domain                                             */
+    double gamma;        /* ratio of specific heats (Euler)                    */
+    double adv_speed;    /* a in f(u) = a u (advection)                        */
+    double cfl;          /* dt = cfl * h / alpha                               */
+    double dirichlet[2][3]; /* prescribed boundary states (conserved vars)     */
+} dgref_problem1d;
+
+typedef struct {
+    int eq, k, nq, filter, filter_dt;
+    int bc[4];           /* x-lo, x-hi, y-lo, y-hi                             */
+    int64_t nx, ny;
+    double xlo, xhi, ylo, yhi;
+    double gamma;
+    double adv_speed[2];
+    double cfl;
+    double dirichlet[4][4];
+} dgref_problem2d;
+
+typedef struct {
+    int64_t steps;
+    double t, dt_min, dt_max;
+    double ledger[4];          /* sum_j |K_j| * cell average, per variable     */
+    double boundary_flux[4];   /* time integral of the net outward flux        */
+    int64_t troubled_cells;    /* hybrid: troubled cells summed over stages    */
+    double min_rho, min_p;     /* Euler: over trace and quadrature points      */
+    double max_exponent;       /* largest damping exponent applied             */
+    int status;
+    int64_t first_bad_cell;
+} dgref_report;
+
+int dgref_nvars(int eq, int dim);
+
+/* ---- basis tables (exposed so tests can pin them) ---- */
+int dgref_gauss(int q, double* x, double* w);
+/* value of d^m/dxi^m P_l at xi */
+double dgref_legendre_deriv(int l, int m, double xi);
+
+/* ---- 1D ---- */
+int dgref_residual1d(const dgref_problem1d* P, const double* u, double* L, double* fhat);
+double dgref_max_wavespeed1d(const dgref_problem1d* P, const double* u);
+int dgref_stage1d(const dgref_problem1d* P, int stage, double dt, const double* un,
+                  const double* us, double* out, double* fhat);
+int dgref_exponents1d(const dgref_problem1d* P, double dt, const double* v, double* E,
+                      double* eta);
+int dgref_filter1d(const dgref_problem1d* P, double dt, const double* v, double* out);
+int dgref_hybrid1d(const dgref_problem1d* P, double dt, const double* v, double* out,
+                   int64_t* troubled);
+int dgref_post1d(const dgref_problem1d* P, int stage, double dt, const double* v,
+                 double* out, int64_t* troubled);
+int dgref_step1d(const dgref_problem1d* P, double dt, double* u, double* bflux,
+                 int64_t* troubled);
+int dgref_run1d(const dgref_problem1d* P, double t_end, int64_t max_steps, double* u,
+                dgref_report* rep);
+int dgref_check1d(const dgref_problem1d* P, const double* u, double* min_rho,
+                  double* min_p, int64_t* first_bad);
+
+/* ---- 2D, Q^k tensor-product Legendre ---- */
+int dgref_residual2d(const dgref_problem2d* P, double t, const double* u, double* L);
+double dgref_max_wavespeed2d(const dgref_problem2d* P, const double* u);
+int dgref_stage2d(const dgref_problem2d* P, int stage, double t, double dt, const double* un,
+                  const double* us, double* out);
+int dgref_exponents2d(const dgref_problem2d* P, double dt, const double* v, double* E,
+                      double* eta);
+int dgref_post2d(const dgref_problem2d* P, int stage, double dt, const double* v,
+                 double* out, int64_t* troubled);
+int dgref_step2d(const dgref_problem2d* P, double t, double dt, double* u, int64_t* troubled);
+int dgref_run2d(const dgref_problem2d* P, double t_end, int64_t max_steps, double* u,
+                dgref_report* rep);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,464 @@
+"""Pins of the 1D FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: numpy's
+Legendre routines, closed forms, the textbook first-order Rusanov scheme,
+exact solutions, the paper's printed Table 1, and invariants the paper
+states (conservation, L2 stability, mode 0 untouched)."""
+import math
+import os
+
+import numpy as np
+import pytest
+from numpy.polynomial import legendre as npleg
+
+import dg_inputs as I
+from oracle import exact
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------- tables --
+@pytest.mark.parametrize("q", [1, 2, 3, 4, 5, 6, 8])
+def test_gauss_matches_numpy_and_is_exact(ref, q):
+    x, w = ref.gauss(q)
+    xn, wn = npleg.leggauss(q)
+    np.testing.assert_allclose(x, xn, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(w, wn, rtol=0, atol=1e-15)
+    for i in range(2 * q):
+        exact_int = 2.0 / (i + 1) if i % 2 == 0 else 0.0
+        assert abs(np.sum(w * x ** i) - exact_int) < 1e-14
+
+
+@pytest.mark.parametrize("l", range(0, 6))
+def test_legendre_closed_forms(ref, l):
+    # P_l(+-1) = (+-1)^l and P_l^(m)(1) = (l+m)! / (2^m m! (l-m)!)
+    assert ref.legendre_deriv(l, 0, 1.0) == pytest.approx(1.0, abs=1e-15)
+    assert ref.legendre_deriv(l, 0, -1.0) == pytest.approx((-1.0) ** l, abs=1e-15)
+    for m in range(0, l + 1):
+        closed = math.factorial(l + m) / (2 ** m * math.factorial(m) * math.factorial(l - m))
+        assert ref.legendre_deriv(l, m, 1.0) == pytest.approx(closed, rel=1e-14)
+        assert ref.legendre_deriv(l, m, -1.0) == pytest.approx((-1) ** (l + m) * closed, rel=1e-14)
+    for xi in (-0.7, 0.1, 0.93):
+        c = np.zeros(l + 1)
+        c[l] = 1.0
+        for m in range(0, 3):
+            want = npleg.legval(xi, npleg.legder(c, m)) if m <= l else 0.0
+            assert ref.legendre_deriv(l, m, xi) == pytest.approx(want, abs=1e-13)
+
+
+# --------------------------------------------------------------- residual --
+@pytest.mark.parametrize("eq", [0, 1, 2])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_free_stream_residual_is_zero(ref, eq, bc):
+    n, k = 17, 3
+    nv = ref.nvars(eq)
+    u = np.zeros((nv, k + 1, n))
+    state = [1.3, 0.4, 2.7][:nv] if eq == 2 else [0.7]
+    for v in range(nv):
+        u[v, 0, :] = state[v]
+    P = ref.problem1d(eq, k, n, -1.0, 2.0, bc=(bc, bc), adv_speed=-0.8)
+    L, _ = ref.residual1d(P, u)
+    assert np.max(np.abs(L)) < 1e-13
+
+
+def _rusanov_fv(eq, ubar, h, gamma=1.4, a=1.0):
+    """Textbook first-order finite volume with the Rusanov flux, periodic."""
+    def f(u):
+        if eq == 0:
+            return a * u
+        if eq == 1:
+            return 0.5 * u * u
+        rho, m, E = u
+        vel = m / rho
+        p = (gamma - 1) * (E - 0.5 * m * vel)
+        return np.stack([m, m * vel + p, vel * (E + p)])
+
+    def lam(u):
+        if eq == 0:
+            return np.abs(a) * np.ones(u.shape[-1])
+        if eq == 1:
+            return np.abs(u[0])
+        rho, m, E = u
+        vel = m / rho
+        p = (gamma - 1) * (E - 0.5 * m * vel)
+        return np.abs(vel) + np.sqrt(gamma * p / rho)
+
+    uL = np.roll(ubar, 1, axis=-1)          # left neighbour of each cell
+    F = 0.5 * (f(uL) + f(ubar)) - 0.5 * np.maximum(lam(uL), lam(ubar)) * (ubar - uL)
+    return -(np.roll(F, -1, axis=-1) - F) / h
+
+
+@pytest.mark.parametrize("eq", [0, 1, 2])
+def test_p0_is_rusanov_finite_volume(ref, eq):
+    rng = np.random.default_rng(7)
+    n = 23
+    nv = ref.nvars(eq)
+    if eq == 2:
+        ubar = I.conserved(1 + rng.random(n), rng.uniform(-1, 1, n), 1 + rng.random(n))
+    else:
+        ubar = rng.uniform(-1, 2, (1, n))
+    u = ubar[:, None, :].copy()
+    P = ref.problem1d(eq, 0, n, 0.0, 3.0, adv_speed=1.0)
+    L, _ = ref.residual1d(P, u)
+    want = _rusanov_fv(eq, ubar, 3.0 / n)
+    np.testing.assert_allclose(L[:, 0, :], want, rtol=1e-13, atol=1e-13)
+
+
+def test_llf_is_upwind_for_advection(ref):
+    # With f = a u the LLF flux is the upwind flux; for a > 0 the residual
+    # of mode 0 is -(a/h) (u^-_{j+1/2} - u^-_{j-1/2}).
+    rng = np.random.default_rng(3)
+    n, k, a = 11, 2, 0.9
+    u = rng.standard_normal((1, k + 1, n))
+    P = ref.problem1d(0, k, n, 0.0, 1.0, adv_speed=a)
+    L, fh = ref.residual1d(P, u)
+    right_trace = u[0].sum(axis=0)          # P_l(1) = 1
+    np.testing.assert_allclose(fh[0, 1:], a * right_trace, rtol=1e-14, atol=1e-14)
+    np.testing.assert_allclose(fh[0, 0], a * right_trace[-1], rtol=1e-14)
+
+
+def test_rk3_amplification_factor(ref):
+    # P0 upwind advection is u_j' = -(a/h)(u_j - u_{j-1}); a Fourier mode
+    # e^{i theta j} is multiplied per step by 1 + z + z^2/2 + z^3/6 with
+    # z = -(a dt/h)(1 - e^{-i theta}) for the third-order SSP-RK scheme.
+    n = 32
+    a, h = 1.0, 1.0 / n
+    dt = 0.4 * h
+    P = ref.problem1d(0, 0, n, 0.0, 1.0, filter=0, adv_speed=a)
+    for mode in (1, 3, 7):
+        theta = 2 * math.pi * mode / n
+        u = np.cos(theta * np.arange(n))[None, None, :].copy()
+        z = -(a * dt / h) * (1 - np.exp(-1j * theta))
+        g = 1 + z + z * z / 2 + z ** 3 / 6
+        want = np.real(g * np.exp(1j * theta * np.arange(n)))
+        got = ref.step1d(P, dt, u)[0, 0]
+        np.testing.assert_allclose(got, want, rtol=0, atol=1e-14)
+
+
+def test_linear_advection_energy_is_non_increasing(ref):
+    # Sec. 2.2: with the upwind flux the fully discrete scheme with the
+    # filter is L2 stable; with SSP-RK3 (r = 3) under a small CFL the
+    # discrete norm does not grow.
+    w = I.advection_sine(64, 3)
+    for filt in (0, 1):
+        P = ref.problem1d(0, 3, 64, 0.0, 1.0, filter=filt, cfl=0.05, adv_speed=1.0)
+        u = w.u0.copy()
+        h = 1.0 / 64
+        l = np.arange(4)[:, None]
+
+        def norm2(u):
+            return float(np.sum(u[0] ** 2 * h / (2 * l + 1)))
+
+        prev = norm2(u)
+        dt = 0.05 * h
+        for _ in range(200):
+            u = ref.step1d(P, dt, u)
+            cur = norm2(u)
+            assert cur <= prev * (1 + 1e-14)
+            prev = cur
+
+
+# ----------------------------------------------------------------- filter --
+def _smooth_random(rng, nv, k, n):
+    u = np.zeros((nv, k + 1, n))
+    u[:, 0, :] = 1.0 + 0.2 * rng.random((nv, n))
+    for l in range(1, k + 1):
+        u[:, l, :] = 0.05 * rng.standard_normal((nv, n))
+    if nv == 3:  # a positive Euler state: E large enough
+        u[2, 0, :] += 3.0
+    return u
+
+
+@pytest.mark.parametrize("eq", [1, 2])
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_filter_keeps_mode_zero_bitwise(ref, eq, k):
+    rng = np.random.default_rng(11 + k)
+    n = 40
+    u = _smooth_random(rng, ref.nvars(eq), k, n)
+    P = ref.problem1d(eq, k, n, 0.0, 1.0, filter=1)
+    out, _ = ref.post1d(P, 0, 1e-3, u)
+    assert np.array_equal(out[:, 0, :], u[:, 0, :])
+    # contraction: every higher mode shrinks in magnitude (factor in (0,1])
+    assert np.all(np.abs(out[:, 1:, :]) <= np.abs(u[:, 1:, :]))
+
+
+def test_filter_identity_on_p0(ref):
+    rng = np.random.default_rng(5)
+    u = rng.random((3, 1, 30)) + 1.0
+    u[2] += 3.0
+    P = ref.problem1d(2, 0, 30, 0.0, 1.0, filter=1)
+    out, _ = ref.post1d(P, 0, 0.3, u)
+    assert np.array_equal(out, u)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_filter_identity_on_global_polynomial(ref, k):
+    # A single polynomial of degree <= k on the whole (outflow) domain has
+    # no jumps of any derivative, so every exponent vanishes up to roundoff.
+    n = 24
+    coeffs = [0.3, -0.7, 0.25, 0.1][: k + 1]
+    f = lambda x: np.polynomial.polynomial.polyval(x, coeffs) + 2.0
+    u = I.project1d(f, k, n, -1.0, 1.0)
+    P = ref.problem1d(1, k, n, -1.0, 1.0, bc=(1, 1), filter=1)
+    E, eta = ref.exponents1d(P, 0.01, u)
+    assert np.max(np.abs(E)) < 1e-10
+    out, _ = ref.post1d(P, 0, 0.01, u)
+    np.testing.assert_allclose(out, u, rtol=1e-10, atol=1e-13)
+
+
+def test_filter_exponent_monotone_in_jumps(ref):
+    # Raising the highest mode of a neighbour raises |[d^m u]| at the shared
+    # interface for every m, hence every exponent of the cell (the damping
+    # coefficient is a positive combination of jump magnitudes).
+    n, k = 9, 3
+    base = np.zeros((1, k + 1, n))
+    base[0, 0, :] = 1.0
+    P = ref.problem1d(1, k, n, 0.0, 1.0, bc=(1, 1), filter=1)
+    prev = None
+    for amp in (0.0, 0.01, 0.1, 0.5):
+        u = base.copy()
+        u[0, 3, 5] = amp
+        E, _ = ref.exponents1d(P, 1e-3, u)
+        if prev is not None:
+            assert np.all(E[4, 1:] >= prev[4, 1:])
+            assert E[4, 3] > prev[4, 3]
+        prev = E
+
+
+def test_filter_worked_example_two_cells(ref):
+    # Hand example on two periodic cells of width h = 1/2 (domain [0, 1]),
+    # Burgers, k = 2: cell 0 holds u = 1 + x' (x' = x - 1/4), cell 1 holds
+    # u = 2 + 3 x'^2 (x' = x - 3/4).  Derivative traces are evaluated
+    # directly from these polynomials in x (not from modes), and the
+    # exponent follows Sec. 2.1: sigma_j^l = c_f^l (2/h)^2 l(l+1) (h J0 +
+    # sum_{m<=l} m(m+1) h^{m+1} J^m), c_f^l = |u-bar| / (4 l(l+1)).
+    h = 0.5
+    from numpy.polynomial import Polynomial as Poly
+    p0 = Poly([1.0, 1.0])
+    p1 = Poly([2.0, 0.0, 3.0])
+    xl, xr = -h / 2, h / 2
+    d = lambda p, m, x: p.deriv(m)(x) if m else p(x)
+    # jumps at the interior interface (cell0 right | cell1 left) and at the
+    # periodic interface (cell1 right | cell0 left)
+    Jmid = [abs(d(p1, m, xl) - d(p0, m, xr)) for m in range(3)]
+    Jwrap = [abs(d(p0, m, xl) - d(p1, m, xr)) for m in range(3)]
+    J = [Jmid[m] + Jwrap[m] for m in range(3)]
+    ubar0 = p0.integ()(xr) - p0.integ()(xl)
+    ubar0 /= h
+    dt = 0.01
+    want = []
+    for l in (1, 2):
+        cf = abs(ubar0) / (4 * l * (l + 1))
+        s = h * J[0] + sum(m * (m + 1) * h ** (m + 1) * J[m] for m in range(1, l + 1))
+        want.append(cf * s * (2 / h) ** 2 * l * (l + 1) * dt)
+    u = I.project1d(lambda x: np.where(x < 0.5, 1 + (x - 0.25), 2 + 3 * (x - 0.75) ** 2), 2, 2,
+                    0.0, 1.0, nquad=8)
+    P = ref.problem1d(1, 2, 2, 0.0, 1.0, filter=1)
+    E, eta = ref.exponents1d(P, dt, u)
+    np.testing.assert_allclose(E[0, 1:], want, rtol=1e-12)
+    assert eta[0] == pytest.approx(J[0] / (2 * h), rel=1e-12)
+
+
+# ----------------------------------------------------------------- hybrid --
+def test_hybrid_weights(ref):
+    # Algorithm 1: cells with eta <= 1 are untouched; the argmax cell gets
+    # omega = 0 (fully filtered); omega -> 1 as eta -> 1+ (continuity).
+    n, k = 40, 2
+    rng = np.random.default_rng(1)
+    u = _smooth_random(rng, 1, k, n) * 0.01 + 1.0
+    u[0, 0, 20:] += 0.5             # a jump of 0.5 at x = 0.5
+    P = ref.problem1d(1, k, n, 0.0, 1.0, bc=(1, 1), filter=2)
+    dt = 1e-3
+    E, eta = ref.exponents1d(P, dt, u)
+    out, troubled = ref.post1d(P, 0, dt, u)
+    assert troubled == int(np.sum(eta > 1))
+    calm = eta <= 1
+    assert np.array_equal(out[:, :, calm], u[:, :, calm])
+    j = int(np.argmax(eta))
+    np.testing.assert_allclose(out[0, :, j], np.exp(-E[j]) * u[0, :, j], rtol=1e-14)
+    assert np.array_equal(out[:, 0, :], u[:, 0, :])
+    # continuity at the threshold: a cell with eta just above 1 is nearly
+    # unchanged
+    M = eta.max()
+    for jj in np.nonzero(eta > 1)[0]:
+        w = (M - eta[jj]) / (M - 1)
+        np.testing.assert_allclose(out[0, :, jj], w * u[0, :, jj] + (1 - w) * np.exp(-E[jj]) * u[0, :, jj],
+                                   rtol=1e-13, atol=1e-15)
+
+
+# -------------------------------------------------------------------- CFL --
+def test_max_wavespeed_is_brute_force_max(ref):
+    rng = np.random.default_rng(2)
+    n = 101
+    u = np.zeros((3, 3, n))
+    rho, vel, p = 0.5 + rng.random(n), rng.uniform(-2, 2, n), 0.1 + rng.random(n)
+    u[:, 0, :] = I.conserved(rho, vel, p)
+    u[:, 1:, :] = 0.1 * rng.standard_normal((3, 2, n))
+    P = ref.problem1d(2, 2, n, 0.0, 1.0)
+    want = np.max(np.abs(vel) + np.sqrt(1.4 * p / rho))
+    assert ref.max_wavespeed1d(P, u) == pytest.approx(want, rel=1e-15)
+    P1 = ref.problem1d(1, 2, n, 0.0, 1.0)
+    ub = rng.uniform(-3, 3, (1, 3, n))
+    assert ref.max_wavespeed1d(P1, ub) == np.max(np.abs(ub[0, 0]))
+
+
+# ----------------------------------------------------------- conservation --
+def test_burgers_conservation_to_roundoff(ref):
+    w = I.burgers_sine(200, 2)
+    P = ref.problem1d(1, 2, 200, 0.0, 2.0, filter=1, cfl=0.1)
+    u, rep, rc = ref.run1d(P, w.u0, 1.5)
+    assert rc == 0
+    # mean 1/2 over length 2: sum_j h u-bar_j = 1
+    assert abs(rep.ledger[0] - 1.0) < 1e-13
+    assert rep.t == 1.5
+
+
+def test_outflow_ledger_balances(ref):
+    w = I.shu_osher(400, 2)
+    P = ref.problem1d(2, 2, 400, -5.0, 5.0, bc=(1, 1), filter=2, cfl=0.1)
+    h = 10.0 / 400
+    q0 = h * w.u0[:, 0, :].sum(axis=1)
+    u, rep, rc = ref.run1d(P, w.u0, 0.3)
+    assert rc == 0
+    for v in range(3):
+        bal = rep.ledger[v] + rep.boundary_flux[v] - q0[v]
+        assert abs(bal) < 1e-12 * max(1.0, abs(q0[v]))
+
+
+# ------------------------------------------------------------------ order --
+def _burgers_errors(u, k, n, lo, hi, t):
+    h = (hi - lo) / n
+    xg, wg = npleg.leggauss(k + 3)
+    P = I._legendre_values(k, xg)
+    uh = np.einsum("ln,lq->nq", u[0], P)
+    X = lo + (np.arange(n) + 0.5)[:, None] * h + 0.5 * h * xg[None, :]
+    ex = exact.burgers_smooth(lambda x: 0.5 + np.sin(x), np.cos, X, t)
+    e = uh - ex
+    return math.sqrt(np.sum(e ** 2 * wg[None, :]) * h / 2), np.abs(e).max()
+
+
+def _table1():
+    rows = {}
+    for line in open(os.path.join(GOLD, "table1_burgers.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, n, l2f, lif, l2, li = line.split()
+        rows[(int(k), int(n))] = tuple(map(float, (l2f, lif, l2, li)))
+    return rows
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_table1_orders_and_magnitudes(ref, k):
+    """Table 1: with and without the filter the errors match the printed
+    magnitudes within a small factor, the filter's excess error shrinks with
+    refinement, and the order approaches k+1."""
+    T = _table1()
+    errs = {}
+    for n in (20, 40, 80, 160, 320):
+        w = I.burgers_table(n, k)
+        for filt in (0, 1):
+            P = ref.problem1d(1, k, n, w.lo, w.hi, filter=filt, cfl=0.1)
+            u, rep, rc = ref.run1d(P, w.u0, 0.5)
+            assert rc == 0
+            errs[(n, filt)] = _burgers_errors(u, k, n, w.lo, w.hi, 0.5)
+    for n in (160, 320):
+        paper = T[(k, n)]
+        for filt in (0, 1):
+            l2 = errs[(n, filt)][0]
+            pl2 = paper[0] if filt else paper[2]
+            assert pl2 / 4 < l2 < pl2 * 4, (k, n, filt, l2, pl2)
+    # order on the finest pair
+    for filt in (0, 1):
+        order = math.log2(errs[(160, filt)][0] / errs[(320, filt)][0])
+        assert order > k + 1 - 0.35, (k, filt, order)
+    # the filter's effect vanishes under refinement
+    r160 = errs[(160, 1)][0] / errs[(160, 0)][0]
+    r320 = errs[(320, 1)][0] / errs[(320, 0)][0]
+    assert abs(r320 - 1.0) <= max(abs(r160 - 1.0), 0.1)
+    assert 0.5 < r320 < 1.6
+
+
+def test_table1_selects_full_step_damping(ref):
+    """Reading of the damping duration after each RK stage.  Table 1's coarse
+    P2 rows (with filter / without filter: 164x at N=20, 150x at N=40)
+    require the split viscous problem to run over the full dt after every
+    stage; damping over the stage's own RK weight of dt is an order of
+    magnitude too weak at N=40."""
+    T = _table1()
+    ratio = {}
+    for fdt in (0, 1):
+        n, k = 40, 2
+        w = I.burgers_table(n, k)
+        P0 = ref.problem1d(1, k, n, w.lo, w.hi, filter=0, cfl=0.1)
+        P1 = ref.problem1d(1, k, n, w.lo, w.hi, filter=1, cfl=0.1, filter_dt=fdt)
+        e0 = _burgers_errors(ref.run1d(P0, w.u0, 0.5)[0], k, n, w.lo, w.hi, 0.5)[0]
+        e1 = _burgers_errors(ref.run1d(P1, w.u0, 0.5)[0], k, n, w.lo, w.hi, 0.5)[0]
+        ratio[fdt] = e1 / e0
+    paper = T[(2, 40)][0] / T[(2, 40)][2]
+    assert abs(math.log(ratio[0] / paper)) < abs(math.log(ratio[1] / paper))
+    assert ratio[0] > paper / 3
+    assert ratio[1] < paper / 10
+
+
+# ------------------------------------------------------------------ shocks --
+def test_burgers_shock_position(ref):
+    # u0 = 1/2 + sin(pi x) on [0,2]: the shock sits at x = 1 + t/2 = 1.75 at
+    # t = 1.5; away from it the solution matches the entropy solution.
+    w = I.burgers_sine(200, 2)
+    P = ref.problem1d(1, 2, 200, 0.0, 2.0, filter=1, cfl=0.1)
+    u, rep, rc = ref.run1d(P, w.u0, 1.5)
+    assert rc == 0
+    h = 0.01
+    xc = (np.arange(200) + 0.5) * h
+    ub = u[0, 0]
+    j = int(np.argmax(np.abs(np.diff(ub))))
+    xs = 0.5 * (xc[j] + xc[j + 1])
+    assert abs(xs - 1.75) < 2 * h
+    far = np.abs(xc - 1.75) > 0.1
+    ex = exact.burgers_sine_shock(xc, 1.5)
+    # the cell average of a smooth solution differs from the centre value by
+    # O(h^2); 2e-3 bounds both that and the scheme's error
+    assert np.max(np.abs(ub[far] - ex[far])) < 2e-3
+    # oscillation control: no overshoot beyond the exact range
+    assert ub.max() < 1.5 + 1e-2 and ub.min() > -0.5 - 1e-2
+
+
+def test_shu_osher_state_matches_paper():
+    vals = np.loadtxt(os.path.join(GOLD, "shu_osher_state.txt"))
+    r, u, p, _ = I.rankine_hugoniot(3.0, 1.0, 1.0)
+    np.testing.assert_allclose([r, u, p], vals, atol=6e-7)
+
+
+def test_exact_riemann_solver_sod():
+    # Sod problem: star pressure 0.30313, star velocity 0.92745 (standard
+    # reference values of the exact solution).
+    p, u = exact.star_state((1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+    assert p == pytest.approx(0.30313, abs=1e-5)
+    assert u == pytest.approx(0.92745, abs=1e-5)
+    # Rankine-Hugoniot consistency of the sampled right shock
+    rho, vel, pp = exact.riemann_exact((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), np.array([0.3]), 0.2)
+    assert rho[0] == pytest.approx(0.26557, abs=1e-5)
+
+
+@pytest.mark.parametrize("filt", [1, 2])
+def test_lax_problem_against_exact_solution(ref, filt):
+    states = np.loadtxt(os.path.join(GOLD, "lax_states.txt"))
+    left, right = tuple(states[0]), tuple(states[1])
+    w = I.lax(200, 2)
+    P = ref.problem1d(2, 2, 200, -1.0, 1.0, bc=(1, 1), filter=filt, cfl=0.1)
+    u, rep, rc = ref.run1d(P, w.u0, 0.13)
+    assert rc == 0 and rep.t == 0.13
+    h = 0.01
+    xc = -1.0 + (np.arange(200) + 0.5) * h
+    rho_ex, _, _ = exact.riemann_exact(left, right, xc, 0.13)
+    rho = u[0, 0]
+    # L1 error of the density small, shock position within 2h
+    assert np.sum(np.abs(rho - rho_ex)) * h < 0.02
+    _, _, sr = exact.riemann_waves(left, right)
+    xs_exact = sr * 0.13
+    jump = np.abs(np.diff(rho))
+    jj = int(np.argmax(np.where(xc[:-1] > 0.3, jump, 0.0)))
+    xs = 0.5 * (xc[jj] + xc[jj + 1])
+    assert abs(xs - xs_exact) < 2 * h
+    # no large over/undershoots
+    assert rho.max() < rho_ex.max() * 1.05 and rho.min() > rho_ex.min() * 0.95
