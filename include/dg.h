@@ -1,0 +1,217 @@
+/*
+ * dg.h — C ABI of the MI355X (gfx950) RKDG library with the jump filter.
+ *
+ * Method: Wei, Zhou, Xia, "The jump filter in the discontinuous Galerkin
+ * method for hyperbolic conservation laws", arXiv:2407.19169.
+ *   - modal Legendre DG space, mode 0 = cell average          (Sec. 2.1)
+ *   - semi-discrete DG operator with an LLF interface flux    (Sec. 2.1, scheme (scheme:DG); Sec. 3)
+ *   - third-order SSP Runge-Kutta in Shu-Osher form           (Sec. 2.2, (rkdg1); Sec. 3)
+ *   - jump filter after every RK stage                        (Sec. 2.1 (para:damp2)-(timespli:1dscalar);
+ *                                                              Sec. 2.3 (para:damp22d); Sec. 2.4 (timespli:sys))
+ *   - hybrid limiter with the filter as low-order limiter     (Sec. 3, Algorithm 1)
+ *
+ * Conventions shared by every call:
+ *   - Every function returns 0 (DG_OK) or a negative dg_status code.
+ *   - All state pointers are DEVICE pointers owned by the caller (e.g. torch
+ *     tensors); the library never allocates or frees state or workspace
+ *     memory.  The solver handle owns only its parameters and a captured
+ *     HIP graph.
+ *   - Calls are ordered on the stream given in dg_options (NULL = the null
+ *     stream).  Only dg_max_wavespeed, dg_run, dg_report_read and
+ *     dg_run_batch synchronise that stream.
+ *   - A handle is not thread-safe; separate handles are independent.
+ *
+ * State layout ("FP64 layout", the exchange format of dg_set_state and
+ * dg_get_state, and the internal layout of DG_PREC_FP64):
+ *   1D: u[(var*(k+1) + l)*n + j]                   var-major, then mode, then cell
+ *   2D: u[((var*(k+1)^2 + p*(k+1) + q)*ny + jy)*nx + ix]   x fastest
+ * where l (1D) or (p, q) (2D, Q^k tensor Legendre) index the modes.
+ * In DG_PREC_MIXED the bound buffers hold an FP64 plane per variable for
+ * mode 0 followed by FP32 planes for modes >= 1 (sizes from
+ * dg_buffer_sizes); use dg_set_state/dg_get_state to convert.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DG_OK = 0,
+    DG_ERR_ARG = -1,         /* invalid argument (NULL, size, range)               */
+    DG_ERR_UNSUPPORTED = -2, /* degree / dimension / equation combination          */
+    DG_ERR_DEVICE = -3,      /* a HIP runtime call failed                          */
+    DG_ERR_NONFINITE = -4,   /* a NaN/Inf appeared in the state or the time step   */
+    DG_ERR_POSITIVITY = -5,  /* Euler: density or pressure <= 0 at a trace/quad pt */
+    DG_ERR_STATE = -6        /* buffers not bound, or calls out of order           */
+} dg_status;
+
+typedef enum { DG_EQ_ADVECTION = 0, DG_EQ_BURGERS = 1, DG_EQ_EULER = 2 } dg_equation;
+
+/* Boundary conditions (one per side).  PERIODIC must be set on both sides
+ * of an axis.  OUTFLOW copies the interior trace (and its derivatives);
+ * REFLECT mirrors it with the normal momentum negated (Euler only);
+ * DIRICHLET imposes the constant conserved state mesh.dirichlet[side];
+ * DMR_WALL (2D bottom, y-lo) is DIRICHLET with mesh.dirichlet[side] for
+ * x < dmr_x0 and REFLECT beyond; DMR_TOP (2D top, y-hi) is the exact
+ * moving Mach-10 shock of the double-Mach-reflection problem: post-shock
+ * state mesh.dirichlet[side] behind the line x = dmr_x0 + (y + shock_speed
+ * t)/sqrt(3), the DIRICHLET state of the x-hi side ahead of it. */
+typedef enum {
+    DG_BC_PERIODIC = 0,
+    DG_BC_OUTFLOW = 1,
+    DG_BC_REFLECT = 2,
+    DG_BC_DIRICHLET = 3,
+    DG_BC_DMR_WALL = 4,
+    DG_BC_DMR_TOP = 5
+} dg_bc;
+
+typedef enum { DG_FILTER_NONE = 0, DG_FILTER_JUMP = 1, DG_FILTER_HYBRID = 2 } dg_filter_mode;
+
+/* DG_PREC_MIXED: mode 0 (cell averages), its update, the conservation
+ * ledger and the positivity / wave-speed checks in FP64; higher modes are
+ * stored, and volume, flux and filter arithmetic run, in FP32. */
+typedef enum { DG_PREC_FP64 = 0, DG_PREC_MIXED = 1 } dg_precision;
+
+typedef struct {
+    int dim;                 /* 1 or 2                                            */
+    int64_t n[2];            /* cells along x (and y); uniform mesh               */
+    double lo[2], hi[2];     /* domain [lo, hi] per axis                          */
+    int bc[4];               /* dg_bc for x-lo, x-hi, y-lo, y-hi                  */
+    double dirichlet[4][4];  /* conserved state per side (DIRICHLET, DMR_*)       */
+    double dmr_x0;           /* DMR_* : shock foot on the wall                    */
+    double shock_speed;      /* DMR_TOP: shock speed along x of its foot * 2/sqrt3 */
+} dg_mesh;
+
+typedef struct {
+    int precision;           /* dg_precision                                      */
+    int filter;              /* dg_filter_mode, applied after every RK stage      */
+    double cfl;              /* dt = cfl * h / max wave speed (2D: cfl / max(ax/hx + ay/hy)) */
+    double gamma;            /* ratio of specific heats (Euler)                   */
+    double adv_speed[2];     /* advection velocity (DG_EQ_ADVECTION)              */
+    int quad_points;         /* Gauss points per direction; 0 or degree+1         */
+    void* stream;            /* hipStream_t; NULL = null stream                   */
+} dg_options;
+
+/* Filled by dg_run / dg_report_read. */
+typedef struct {
+    int64_t steps;           /* steps taken by the last dg_run                    */
+    double t;                /* simulated time reached                            */
+    double dt_min, dt_max;   /* extreme time steps of the last dg_run             */
+    double ledger[4];        /* FP64 sum over cells of |K| * cell average         */
+    double boundary_flux[4]; /* FP64 time integral of the net outward boundary flux */
+    int64_t troubled_cells;  /* hybrid: troubled cells summed over all stages     */
+    double min_rho, min_p;   /* Euler: minima seen at trace and quadrature points  */
+    double max_exponent;     /* largest damping exponent applied                  */
+    int status;              /* first error latched on the device (dg_status)     */
+    int64_t first_bad_cell;  /* cell index of that error, -1 if none              */
+} dg_report;
+
+typedef struct dg_solver dg_solver;
+
+/* Create a solver for `mesh`, polynomial degree `degree` (0..3) and
+ * `equation`.  Supported: 1D advection/Burgers/Euler; 2D Euler (Q^k).
+ * Errors: DG_ERR_ARG (NULL, n < 1, bad domain, BC pairing),
+ * DG_ERR_UNSUPPORTED (degree, dim/equation, quad_points). */
+int dg_create(const dg_mesh* mesh, int degree, int equation, const dg_options* opt,
+              dg_solver** out);
+int dg_destroy(dg_solver* s);
+
+/* Bytes of each of the three state buffers and of the workspace. */
+int dg_buffer_sizes(const dg_solver* s, size_t* state_bytes, size_t* workspace_bytes);
+
+/* Bind caller-owned device memory: u_n holds the solution; u_a and u_b are
+ * RK stage buffers; workspace (workspace_bytes) holds the unfiltered stage
+ * output, per-cell filter data and the device control block.  All must be
+ * 256-byte aligned and stay valid until re-bound or destroyed.  Resets the
+ * simulated time and the ledger. */
+int dg_bind(dg_solver* s, void* u_n, void* u_a, void* u_b, void* workspace);
+
+/* Copy an FP64-layout state from device memory into u_n (converting to the
+ * mixed layout if needed), and back.  The ledger's reference Q(0) is taken
+ * at dg_set_state. */
+int dg_set_state(dg_solver* s, const double* modes_dev);
+int dg_get_state(dg_solver* s, double* modes_dev);
+
+/* CFL reduction (Sec. 2.2, Theorem 2.1 time-step condition): the largest
+ * characteristic speed |f'(u-bar)| (Euler |u|+c; 2D: max over cells of
+ * ax/hx + ay/hy) over the cell averages of u_n, in FP64, written to
+ * *alpha (host).  Synchronises the stream.  In 2D *alpha is
+ * max(ax/hx + ay/hy), so dt = cfl / alpha. */
+int dg_max_wavespeed(dg_solver* s, double* alpha);
+
+/* One SSP-RK3 stage of the plain DG scheme (residual + Shu-Osher
+ * combination, no filter) into the workspace's stage buffer:
+ *   stage 0: w = u_n + dt L(u_n)
+ *   stage 1: w = 3/4 u_n + 1/4 (u_a + dt L(u_a))
+ *   stage 2: w = 1/3 u_n + 2/3 (u_b + dt L(u_b))
+ * `t` of the step start is taken from the device clock (dg_run) or 0. */
+int dg_stage(dg_solver* s, int stage, double dt);
+
+/* Post-stage operator of the options (jump filter, hybrid limiter or
+ * none) applied to the workspace's stage buffer with damping time dt; the
+ * result goes to u_a (stage 0), u_b (stage 1) or u_n (stage 2). */
+int dg_jump_filter(dg_solver* s, int stage, double dt);
+
+/* Advance u_n until t_end or max_steps steps, with dt chosen on the device
+ * every step from the CFL reduction (last step clamped to t_end), using
+ * the fused stage+filter kernels captured in a HIP graph.  Synchronises the
+ * stream and fills *rep (nullable).  Returns rep->status. */
+int dg_run(dg_solver* s, double t_end, int64_t max_steps, dg_report* rep);
+
+/* Read the report of the device control block (synchronises). */
+int dg_report_read(dg_solver* s, dg_report* rep);
+
+/* Per-cell damping exponents of the last dg_jump_filter call, FP64,
+ * E[cell*(Lmax+1) + l] with Lmax = k (1D) or 2k (2D); written to a device
+ * buffer of ncells*(Lmax+1) doubles. */
+int dg_last_exponents(dg_solver* s, double* E_dev);
+
+/* Measurement hook: launch the fused stage(+filter / hybrid pass A) kernel
+ * that dg_run uses for `stage` (0..2) `reps` times on the solver's run
+ * stream with time step dt, reading u_n (and u_a / u_b) and writing u_a or
+ * u_b (u_n is not modified), and return its average duration in
+ * microseconds from HIP events recorded around each launch.  Synchronises. */
+int dg_time_kernel(dg_solver* s, int stage, double dt, int reps, double* avg_us);
+
+const char* dg_strerror(int code);
+
+/* ---------------------------------------------------------------------- */
+/* Batched 1D Euler: many independent problems of different size and       */
+/* degree advanced by one persistent launch (each workgroup owns whole     */
+/* problems and steps them with its own dt).                               */
+/* ---------------------------------------------------------------------- */
+typedef struct dg_batch dg_batch;
+
+typedef struct {
+    int64_t n;               /* cells                                             */
+    int degree;              /* 0..3                                              */
+    double lo, hi;           /* domain                                            */
+    int bc[2];               /* DG_BC_OUTFLOW / DG_BC_PERIODIC / DG_BC_REFLECT    */
+    int64_t offset;          /* filled by dg_batch_create: element offset of the  */
+                             /* problem's FP64-layout state in the packed array  */
+} dg_problem1d;
+
+/* Create a batch of `nprob` 1D problems of `equation`.  Problems are packed
+ * back to back in FP64 layout (problem i at element offset probs[i].offset,
+ * written by this call).  Total element count in *total_elems. */
+int dg_batch_create(int nprob, dg_problem1d* probs, int equation, const dg_options* opt,
+                    int64_t* total_elems, dg_batch** out);
+int dg_batch_destroy(dg_batch* b);
+int dg_batch_buffer_sizes(const dg_batch* b, size_t* state_bytes, size_t* workspace_bytes);
+int dg_batch_bind(dg_batch* b, void* u_n, void* u_a, void* u_b, void* workspace);
+int dg_batch_set_state(dg_batch* b, const double* packed_dev);
+int dg_batch_get_state(dg_batch* b, double* packed_dev);
+/* Advance every problem by `steps` steps (or until its t_end[i], host
+ * array, nullable), each with its own CFL time step.  per_problem (host,
+ * nullable, nprob entries) receives each problem's report. */
+int dg_batch_run(dg_batch* b, const double* t_end, int64_t steps, dg_report* per_problem);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DG_H */

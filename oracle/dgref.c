@@ -14,6 +14,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define MAXK 4
 #define MAXQ 8
@@ -24,42 +27,48 @@
 /* ------------------------------------------------------------------------ */
 
 /* Monomial coefficients of P_0..P_kmax from the three-term recurrence
- * (l+1) P_{l+1} = (2l+1) x P_l - l P_{l-1}. c[l][i] multiplies x^i. */
-static void legendre_coeffs(int kmax, double c[][MAXQ + 2])
+ * (l+1) P_{l+1} = (2l+1) x P_l - l P_{l-1}. c[l][i] multiplies x^i.
+ * Tables are evaluated in extended precision (long double) and rounded
+ * once, so every tabulated value is the correctly rounded double. */
+static void legendre_coeffs(int kmax, long double c[][MAXQ + 2])
 {
-    memset(c, 0, sizeof(double) * (size_t)(kmax + 1) * (MAXQ + 2));
-    c[0][0] = 1.0;
-    if (kmax >= 1) c[1][1] = 1.0;
+    memset(c, 0, sizeof(long double) * (size_t)(kmax + 1) * (MAXQ + 2));
+    c[0][0] = 1.0L;
+    if (kmax >= 1) c[1][1] = 1.0L;
     for (int l = 1; l < kmax; ++l)
         for (int i = 0; i <= l + 1; ++i) {
-            double a = (i >= 1) ? (2.0 * l + 1.0) * c[l][i - 1] : 0.0;
-            c[l + 1][i] = (a - l * c[l - 1][i]) / (l + 1.0);
+            long double a = (i >= 1) ? (2.0L * l + 1.0L) * c[l][i - 1] : 0.0L;
+            c[l + 1][i] = (a - l * c[l - 1][i]) / (l + 1.0L);
         }
+}
+
+static long double legendre_deriv_ld(int l, int m, long double xi)
+{
+    long double c[MAXQ + 2][MAXQ + 2];
+    legendre_coeffs(l < 1 ? 1 : l, c);
+    long double d[MAXQ + 2];
+    for (int i = 0; i <= l; ++i) d[i] = c[l][i];
+    for (int r = 0; r < m; ++r) /* differentiate m times */
+        for (int i = 0; i <= l; ++i) d[i] = (i + 1 <= l) ? (i + 1) * d[i + 1] : 0.0L;
+    long double s = 0.0L;
+    for (int i = l; i >= 0; --i) s = s * xi + d[i];
+    return s;
 }
 
 double dgref_legendre_deriv(int l, int m, double xi)
 {
     if (l < 0 || l > MAXQ || m < 0) return NAN;
-    double c[MAXQ + 2][MAXQ + 2];
-    legendre_coeffs(l < 1 ? 1 : l, c);
-    double d[MAXQ + 2];
-    for (int i = 0; i <= l; ++i) d[i] = c[l][i];
-    /* differentiate m times */
-    for (int r = 0; r < m; ++r)
-        for (int i = 0; i <= l; ++i) d[i] = (i + 1 <= l) ? (i + 1) * d[i + 1] : 0.0;
-    double s = 0.0;
-    for (int i = l; i >= 0; --i) s = s * xi + d[i];
-    return s;
+    return (double)legendre_deriv_ld(l, m, (long double)xi);
 }
 
-/* Gauss–Legendre nodes and weights by Newton's method on P_q, with P_q and
- * P_{q-1} from the three-term recurrence and
+/* Gauss–Legendre nodes and weights by Newton's method on P_q (extended
+ * precision), with P_q and P_{q-1} from the three-term recurrence and
  * P_q'(z) = q (z P_q - P_{q-1}) / (z^2 - 1),  w = 2 / ((1 - z^2) P_q'(z)^2). */
-static void legendre_pair(int q, double z, double* pq, double* pqm1)
+static void legendre_pair(int q, long double z, long double* pq, long double* pqm1)
 {
-    double p0 = 1.0, p1 = z;
+    long double p0 = 1.0L, p1 = z;
     for (int l = 1; l < q; ++l) {
-        double p2 = ((2.0 * l + 1.0) * z * p1 - l * p0) / (l + 1.0);
+        long double p2 = ((2.0L * l + 1.0L) * z * p1 - l * p0) / (l + 1.0L);
         p0 = p1;
         p1 = p2;
     }
@@ -67,23 +76,34 @@ static void legendre_pair(int q, double z, double* pq, double* pqm1)
     *pqm1 = p0;
 }
 
+static void gauss_ld(int q, long double* x, long double* w)
+{
+    for (int i = 0; i < q; ++i) {
+        long double z = cosl(3.14159265358979323846264338327950288L * (i + 0.75L) / (q + 0.5L));
+        long double pq, pm1, dpq;
+        for (int it = 0; it < 100; ++it) {
+            legendre_pair(q, z, &pq, &pm1);
+            dpq = q * (z * pq - pm1) / (z * z - 1.0L);
+            long double dz = pq / dpq;
+            z -= dz;
+            if (fabsl(dz) < 1e-19L) break;
+        }
+        legendre_pair(q, z, &pq, &pm1);
+        dpq = q * (z * pq - pm1) / (z * z - 1.0L);
+        x[q - 1 - i] = z; /* ascending order */
+        w[q - 1 - i] = 2.0L / ((1.0L - z * z) * dpq * dpq);
+    }
+    if (q % 2 == 1) x[q / 2] = 0.0L; /* the middle node is exactly 0 */
+}
+
 int dgref_gauss(int q, double* x, double* w)
 {
     if (q < 1 || q > MAXQ) return DGREF_ERR_ARG;
+    long double xl[MAXQ], wl[MAXQ];
+    gauss_ld(q, xl, wl);
     for (int i = 0; i < q; ++i) {
-        double z = cos(M_PI * (i + 0.75) / (q + 0.5));
-        double pq, pm1, dpq;
-        for (int it = 0; it < 100; ++it) {
-            legendre_pair(q, z, &pq, &pm1);
-            dpq = q * (z * pq - pm1) / (z * z - 1.0);
-            double dz = pq / dpq;
-            z -= dz;
-            if (fabs(dz) < 1e-16) break;
-        }
-        legendre_pair(q, z, &pq, &pm1);
-        dpq = q * (z * pq - pm1) / (z * z - 1.0);
-        x[q - 1 - i] = z; /* ascending order */
-        w[q - 1 - i] = 2.0 / ((1.0 - z * z) * dpq * dpq);
+        x[i] = (double)xl[i];
+        w[i] = (double)wl[i];
     }
     return DGREF_OK;
 }
@@ -103,12 +123,16 @@ static int make_basis(int k, int nq, basis* B)
     if (nq < 1 || nq > MAXQ) return DGREF_ERR_ARG;
     B->k = k;
     B->nq = nq;
-    dgref_gauss(nq, B->xq, B->wq);
-    for (int q = 0; q < nq; ++q)
+    long double xl[MAXQ], wl[MAXQ];
+    gauss_ld(nq, xl, wl);
+    for (int q = 0; q < nq; ++q) {
+        B->xq[q] = (double)xl[q];
+        B->wq[q] = (double)wl[q];
         for (int l = 0; l <= k; ++l) {
-            B->phi[q][l] = dgref_legendre_deriv(l, 0, B->xq[q]);
-            B->dphi[q][l] = dgref_legendre_deriv(l, 1, B->xq[q]);
+            B->phi[q][l] = (double)legendre_deriv_ld(l, 0, xl[q]);
+            B->dphi[q][l] = (double)legendre_deriv_ld(l, 1, xl[q]);
         }
+    }
     for (int s = 0; s < 2; ++s)
         for (int l = 0; l <= k; ++l)
             for (int m = 0; m <= k; ++m)
@@ -116,9 +140,36 @@ static int make_basis(int k, int nq, basis* B)
     return DGREF_OK;
 }
 
+/* The quadrature tables the oracle works with: nodes, weights, and
+ * P_l, P_l' at the nodes (phi[q*(k+1)+l]). */
+int dgref_basis_tables(int k, int nq, double* x, double* w, double* phi, double* dphi)
+{
+    basis B;
+    int rc = make_basis(k, nq, &B);
+    if (rc) return rc;
+    for (int q = 0; q < B.nq; ++q) {
+        x[q] = B.xq[q];
+        w[q] = B.wq[q];
+        for (int l = 0; l <= k; ++l) {
+            phi[q * (k + 1) + l] = B.phi[q][l];
+            dphi[q * (k + 1) + l] = B.dphi[q][l];
+        }
+    }
+    return DGREF_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Physical fluxes                                                          */
 /* ------------------------------------------------------------------------ */
+
+int dgref_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 int dgref_nvars(int eq, int dim)
 {

@@ -69,11 +69,14 @@ typedef struct {
 } dgref_report;
 
 int dgref_nvars(int eq, int dim);
+int dgref_num_threads(void);   /* OpenMP threads the cell loops use */
 
 /* ---- basis tables (exposed so tests can pin them) ---- */
 int dgref_gauss(int q, double* x, double* w);
 /* value of d^m/dxi^m P_l at xi */
 double dgref_legendre_deriv(int l, int m, double xi);
+/* nodes, weights, P_l and P_l' at the nodes of the rule of nq (0: k+1) points */
+int dgref_basis_tables(int k, int nq, double* x, double* w, double* phi, double* dphi);
 
 /* ---- 1D ---- */
 int dgref_residual1d(const dgref_problem1d* P, const double* u, double* L, double* fhat);

@@ -1,0 +1,278 @@
+"""paper_2407_19169_amd — MI355X (gfx950) RKDG solver with the jump filter.
+
+Thin ctypes binding of ``libdg.so`` (C ABI in ``include/dg.h``).  Every step
+of the method runs in the library's HIP kernels; this module only marshals
+arguments.  PyTorch supplies device memory and streams.  If the library is
+not built, importing this package raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2407_19169_amd.build` "
+                      "(or __graft_entry__.build()) first")
+
+_lib = C.CDLL(LIB_PATH)
+
+# ------------------------------------------------------------- constants --
+DG_OK, DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_DEVICE = 0, -1, -2, -3
+DG_ERR_NONFINITE, DG_ERR_POSITIVITY, DG_ERR_STATE = -4, -5, -6
+DG_EQ_ADVECTION, DG_EQ_BURGERS, DG_EQ_EULER = 0, 1, 2
+DG_BC_PERIODIC, DG_BC_OUTFLOW, DG_BC_REFLECT, DG_BC_DIRICHLET = 0, 1, 2, 3
+DG_BC_DMR_WALL, DG_BC_DMR_TOP = 4, 5
+DG_FILTER_NONE, DG_FILTER_JUMP, DG_FILTER_HYBRID = 0, 1, 2
+DG_PREC_FP64, DG_PREC_MIXED = 0, 1
+
+
+class dg_mesh(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int64 * 2), ("lo", C.c_double * 2),
+                ("hi", C.c_double * 2), ("bc", C.c_int * 4),
+                ("dirichlet", (C.c_double * 4) * 4), ("dmr_x0", C.c_double),
+                ("shock_speed", C.c_double)]
+
+
+class dg_options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("filter", C.c_int), ("cfl", C.c_double),
+                ("gamma", C.c_double), ("adv_speed", C.c_double * 2),
+                ("quad_points", C.c_int), ("stream", C.c_void_p)]
+
+
+class dg_report(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("t", C.c_double), ("dt_min", C.c_double),
+                ("dt_max", C.c_double), ("ledger", C.c_double * 4),
+                ("boundary_flux", C.c_double * 4), ("troubled_cells", C.c_int64),
+                ("min_rho", C.c_double), ("min_p", C.c_double),
+                ("max_exponent", C.c_double), ("status", C.c_int),
+                ("first_bad_cell", C.c_int64)]
+
+
+class dg_problem1d(C.Structure):
+    _fields_ = [("n", C.c_int64), ("degree", C.c_int), ("lo", C.c_double),
+                ("hi", C.c_double), ("bc", C.c_int * 2), ("offset", C.c_int64)]
+
+
+_vp = C.c_void_p
+_sig = {
+    "dg_create": [C.POINTER(dg_mesh), C.c_int, C.c_int, C.POINTER(dg_options), C.POINTER(_vp)],
+    "dg_destroy": [_vp],
+    "dg_buffer_sizes": [_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)],
+    "dg_bind": [_vp, _vp, _vp, _vp, _vp],
+    "dg_set_state": [_vp, _vp],
+    "dg_get_state": [_vp, _vp],
+    "dg_max_wavespeed": [_vp, C.POINTER(C.c_double)],
+    "dg_stage": [_vp, C.c_int, C.c_double],
+    "dg_jump_filter": [_vp, C.c_int, C.c_double],
+    "dg_run": [_vp, C.c_double, C.c_int64, C.POINTER(dg_report)],
+    "dg_report_read": [_vp, C.POINTER(dg_report)],
+    "dg_last_exponents": [_vp, _vp],
+    "dg_time_kernel": [_vp, C.c_int, C.c_double, C.c_int, C.POINTER(C.c_double)],
+    "dg_batch_create": [C.c_int, C.POINTER(dg_problem1d), C.c_int, C.POINTER(dg_options),
+                        C.POINTER(C.c_int64), C.POINTER(_vp)],
+    "dg_batch_destroy": [_vp],
+    "dg_batch_buffer_sizes": [_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)],
+    "dg_batch_bind": [_vp, _vp, _vp, _vp, _vp],
+    "dg_batch_set_state": [_vp, _vp],
+    "dg_batch_get_state": [_vp, _vp],
+    "dg_batch_run": [_vp, _vp, C.c_int64, C.POINTER(dg_report)],
+}
+for _name, _args in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = C.c_int
+_lib.dg_strerror.argtypes = [C.c_int]
+_lib.dg_strerror.restype = C.c_char_p
+
+EXPORTED = tuple(_sig) + ("dg_strerror",)
+
+
+class DGError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {dg_strerror(code)} ({code})")
+        self.code = code
+
+
+def dg_strerror(code: int) -> str:
+    return _lib.dg_strerror(int(code)).decode()
+
+
+def _check(rc: int, what: str) -> int:
+    if rc != DG_OK:
+        raise DGError(rc, what)
+    return rc
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+# -------------------------------------------------- same-name functions --
+def make_mesh(dim, n, lo, hi, bc, dirichlet=None, dmr_x0=0.0, shock_speed=0.0) -> dg_mesh:
+    m = dg_mesh()
+    m.dim = dim
+    for d in range(dim):
+        m.n[d], m.lo[d], m.hi[d] = int(n[d]), float(lo[d]), float(hi[d])
+    for i, b in enumerate(bc):
+        m.bc[i] = int(b)
+    if dirichlet is not None:
+        for s, row in enumerate(dirichlet):
+            for v, x in enumerate(row):
+                m.dirichlet[s][v] = float(x)
+    m.dmr_x0, m.shock_speed = dmr_x0, shock_speed
+    return m
+
+
+def make_options(precision=DG_PREC_FP64, filter=DG_FILTER_JUMP, cfl=0.1, gamma=1.4,
+                 adv_speed=(1.0, 0.0), quad_points=0, stream=None) -> dg_options:
+    o = dg_options()
+    o.precision, o.filter, o.cfl, o.gamma = precision, filter, cfl, gamma
+    o.adv_speed[0], o.adv_speed[1] = adv_speed
+    o.quad_points = quad_points
+    o.stream = stream
+    return o
+
+
+def dg_create(mesh: dg_mesh, degree: int, equation: int, options: dg_options) -> int:
+    h = _vp()
+    _check(_lib.dg_create(C.byref(mesh), degree, equation, C.byref(options), C.byref(h)),
+           "dg_create")
+    return h.value
+
+
+def dg_destroy(h: int) -> None:
+    _check(_lib.dg_destroy(h), "dg_destroy")
+
+
+def dg_buffer_sizes(h: int):
+    a, b = C.c_size_t(), C.c_size_t()
+    _check(_lib.dg_buffer_sizes(h, C.byref(a), C.byref(b)), "dg_buffer_sizes")
+    return a.value, b.value
+
+
+def dg_bind(h, u_n, u_a, u_b, workspace) -> None:
+    _check(_lib.dg_bind(h, _ptr(u_n), _ptr(u_a), _ptr(u_b), _ptr(workspace)), "dg_bind")
+
+
+def dg_set_state(h, modes) -> None:
+    _check(_lib.dg_set_state(h, _ptr(modes)), "dg_set_state")
+
+
+def dg_get_state(h, modes) -> None:
+    _check(_lib.dg_get_state(h, _ptr(modes)), "dg_get_state")
+
+
+def dg_max_wavespeed(h) -> float:
+    a = C.c_double()
+    _check(_lib.dg_max_wavespeed(h, C.byref(a)), "dg_max_wavespeed")
+    return a.value
+
+
+def dg_stage(h, stage: int, dt: float) -> None:
+    _check(_lib.dg_stage(h, stage, dt), "dg_stage")
+
+
+def dg_jump_filter(h, stage: int, dt: float) -> None:
+    _check(_lib.dg_jump_filter(h, stage, dt), "dg_jump_filter")
+
+
+def dg_run(h, t_end: float, max_steps: int, check: bool = True) -> dg_report:
+    rep = dg_report()
+    rc = _lib.dg_run(h, t_end, max_steps, C.byref(rep))
+    if check:
+        _check(rc, "dg_run")
+    return rep
+
+
+def dg_report_read(h, check: bool = False) -> dg_report:
+    rep = dg_report()
+    rc = _lib.dg_report_read(h, C.byref(rep))
+    if check:
+        _check(rc, "dg_report_read")
+    return rep
+
+
+def dg_last_exponents(h, out) -> None:
+    _check(_lib.dg_last_exponents(h, _ptr(out)), "dg_last_exponents")
+
+
+def dg_time_kernel(h, stage: int, dt: float, reps: int) -> float:
+    us = C.c_double()
+    _check(_lib.dg_time_kernel(h, stage, dt, reps, C.byref(us)), "dg_time_kernel")
+    return us.value
+
+
+# ------------------------------------------------------- torch plumbing --
+class Solver:
+    """Owns a handle plus torch-allocated state buffers and workspace."""
+
+    def __init__(self, mesh: dg_mesh, degree: int, equation: int, options: dg_options,
+                 device="cuda"):
+        import torch
+
+        self.torch = torch
+        self.mesh, self.degree, self.equation, self.options = mesh, degree, equation, options
+        self.h = dg_create(mesh, degree, equation, options)
+        sb, wb = dg_buffer_sizes(self.h)
+        self.state_bytes, self.ws_bytes = sb, wb
+        alloc = lambda nbytes: torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        self._raw = [alloc(sb) for _ in range(3)] + [alloc(wb)]
+        self._ptrs = [((t.data_ptr() + 255) // 256) * 256 for t in self._raw]
+        dg_bind(self.h, *self._ptrs)
+        self.nv = (3 if mesh.dim == 1 else 4) if equation == DG_EQ_EULER else 1
+        self.nmodes = (degree + 1) if mesh.dim == 1 else (degree + 1) ** 2
+        self.ncell = mesh.n[0] if mesh.dim == 1 else mesh.n[0] * mesh.n[1]
+
+    def shape(self):
+        if self.mesh.dim == 1:
+            return (self.nv, self.nmodes, self.ncell)
+        return (self.nv, self.nmodes, self.mesh.n[1], self.mesh.n[0])
+
+    def set_state(self, u) -> None:
+        t = self.torch.as_tensor(u, dtype=self.torch.float64).to("cuda").contiguous()
+        assert tuple(t.shape) == self.shape(), (t.shape, self.shape())
+        dg_set_state(self.h, t)
+        self.torch.cuda.synchronize()
+
+    def get_state(self):
+        out = self.torch.empty(self.shape(), dtype=self.torch.float64, device="cuda")
+        dg_get_state(self.h, out)
+        self.torch.cuda.synchronize()
+        return out
+
+    def exponents(self):
+        lmax = self.degree if self.mesh.dim == 1 else 2 * self.degree
+        out = self.torch.empty((self.ncell, lmax + 1), dtype=self.torch.float64, device="cuda")
+        dg_last_exponents(self.h, out)
+        self.torch.cuda.synchronize()
+        return out
+
+    def close(self) -> None:
+        if self.h:
+            dg_destroy(self.h)
+            self.h = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def buffer_view(solver: Solver, i: int):
+    """FP64-layout view of state buffer i (0 = u_n, 1 = u_a, 2 = u_b) of a
+    DG_PREC_FP64 solver (the caller owns these buffers)."""
+    torch = solver.torch
+    t = solver._raw[i]
+    off = solver._ptrs[i] - t.data_ptr()
+    nel = 1
+    for d in solver.shape():
+        nel *= d
+    return t[off:off + nel * 8].view(torch.float64).view(solver.shape())

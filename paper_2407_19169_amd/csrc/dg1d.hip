@@ -1,0 +1,731 @@
+// dg1d.hip — 1D RKDG stage, jump filter, hybrid limiter and CFL kernels
+// for gfx950 (arXiv:2407.19169, Sec. 2.1, 2.4, Sec. 3 and Algorithm 1).
+//
+// Mapping: one thread per cell, 256-thread workgroups (4 wave64), state in
+// structure-of-arrays planes so every load/store of a mode plane is one
+// coalesced 64-lane access.  A workgroup stages its cells' interface traces
+// in LDS, so each interface flux is evaluated once per tile.  The fused
+// kernel carries a 2-cell halo: it recomputes the unfiltered stage output of
+// one neighbour on each side so that the jump filter (which needs the
+// post-update traces of both neighbours) runs in the same pass, and the
+// stage costs one read of u^(s) (+ u^n) and one write.
+#include "dg_kernels.h"
+
+namespace dg {
+
+namespace {
+
+template <int K, int NV, typename TB>
+__device__ __forceinline__ void load_cell(const StateView<TB>& s, int64_t c, double (&u0)[NV],
+                                          TB (&uh)[NV][K > 0 ? K : 1])
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        u0[v] = s.m0[v * s.s0 + c];
+#pragma unroll
+        for (int l = 1; l <= K; ++l) uh[v][l - 1] = s.hi[v * s.sv + (l - 1) * s.sl + c];
+    }
+}
+
+template <int K, int NV, typename TB>
+__device__ __forceinline__ void store_cell(const StateView<TB>& s, int64_t c, const double (&u0)[NV],
+                                           const TB (&uh)[NV][K > 0 ? K : 1])
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        s.m0[v * s.s0 + c] = u0[v];
+#pragma unroll
+        for (int l = 1; l <= K; ++l) s.hi[v * s.sv + (l - 1) * s.sl + c] = uh[v][l - 1];
+    }
+}
+
+__device__ __forceinline__ int64_t wrap(int64_t c, int64_t n)
+{
+    int64_t r = c % n;
+    return r < 0 ? r + n : r;
+}
+
+// Ghost value outside a domain end for the flux (m = 0 only).
+template <int NV, typename T>
+__device__ __forceinline__ void ghost_state(int bc, const double* dir, const T* inner, T* g)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if (bc == BC_REFLECT)
+            g[v] = (v == 1) ? -inner[v] : inner[v];
+        else if (bc == BC_DIRICHLET)
+            g[v] = (T)dir[v];
+        else
+            g[v] = inner[v];
+    }
+}
+
+// |ghost - inner| of the m-th derivative outside a domain end (jump filter).
+template <typename T>
+__device__ __forceinline__ T ghost_jump(int bc, int m, int v, double dirv, T inner)
+{
+    if (bc == BC_REFLECT) {
+        bool odd = ((m & 1) != 0) != (v == 1);   // ghost = -inner
+        return odd ? (T)2 * fabs(inner) : (T)0;
+    }
+    if (bc == BC_DIRICHLET) return m == 0 ? fabs((T)dirv - inner) : fabs(inner);
+    return (T)0;  // outflow: ghost derivatives equal the interior ones
+}
+
+// Shu-Osher combination of stage `stage` (SSP-RK3).
+__device__ __forceinline__ double combine(int stage, double un, double adv)
+{
+    return stage == 0 ? adv : stage == 1 ? 0.75 * un + 0.25 * adv : (1.0 / 3.0) * un + (2.0 / 3.0) * adv;
+}
+template <typename T>
+__device__ __forceinline__ T combine_t(int stage, T un, T adv)
+{
+    return stage == 0 ? adv
+         : stage == 1 ? (T)0.75 * un + (T)0.25 * adv
+                      : (T)(1.0 / 3.0) * un + (T)(2.0 / 3.0) * adv;
+}
+
+}  // namespace
+
+// -------------------------------------------------------------------------
+// Stage kernel.
+//   MODE 0: unfiltered stage output (halo 1)              -> a.out
+//   MODE 1: stage + jump filter (halo 2)                  -> a.out
+//   MODE 2: stage + hybrid pass A (halo 2): writes the unfiltered output,
+//           the jump indicator max and the troubled-cell list (cell, eta,
+//           exponents) for pass B.
+// With a.alpha != 0 the kernel also accumulates max |f'(u-bar)| of its
+// output into ctrl->alpha_bits (the next step's CFL reduction).
+// -------------------------------------------------------------------------
+template <int EQ, int K, typename TB, int MODE>
+__global__ __launch_bounds__(256) void stage1d_kernel(Args1D<TB> a)
+{
+    using P = Phys1D<EQ>;
+    using T = TB;
+    constexpr int NV = P::NV;
+    constexpr int K1 = K + 1;
+    constexpr int KH = K > 0 ? K : 1;
+    constexpr int HALO = MODE == 0 ? 1 : 2;
+    constexpr int TILE = 256 - 2 * HALO;
+    constexpr int Q = K + 1;
+
+    if (a.ctrl && a.dt_from_ctrl && a.ctrl->done) return;
+    const double dt = a.dt_from_ctrl ? a.ctrl->dt : a.dt_host;
+    const int stage = a.stage;
+
+    // LDS: phase 1 (traces, fluxes) and phase 2 (derivative traces) alias.
+    constexpr int PH1 = 2 * NV * 256 * (int)sizeof(T);
+    constexpr int PH2 = NV * 256 * 8 + 2 * K1 * NV * 256 * (int)sizeof(T);
+    __shared__ __align__(16) unsigned char lds[(MODE == 0 ? PH1 : (PH1 > PH2 ? PH1 : PH2))];
+    T* sTrR = reinterpret_cast<T*>(lds);                 // [NV][256] right trace
+    T* sF = sTrR + NV * 256;                             // [NV][256] flux at left interface
+
+    const int tid = threadIdx.x;
+    const int64_t c = (int64_t)blockIdx.x * TILE + tid - HALO;
+    const int64_t n = a.n;
+    bool valid = true;
+    int64_t cc = c;
+    if (c < 0 || c >= n) {
+        if (a.periodic)
+            cc = wrap(c, n);
+        else
+            valid = false;
+    }
+
+    double u0[NV], n0[NV];
+    T uh[NV][KH], nh[NV][KH];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        u0[v] = n0[v] = 0.0;
+#pragma unroll
+        for (int l = 0; l < KH; ++l) uh[v][l] = nh[v][l] = (T)0;
+    }
+    if (valid) {
+        load_cell<K, NV, TB>(a.us, cc, u0, uh);
+        if (stage > 0) load_cell<K, NV, TB>(a.un, cc, n0, nh);
+    }
+
+    // Interface traces u(x^+_{j-1/2}) (left end) and u(x^-_{j+1/2}) (right end).
+    T tl[NV], tr[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        T sl = (T)u0[v], sr = (T)u0[v];
+#pragma unroll
+        for (int l = 1; l <= K; ++l) {
+            sr += uh[v][l - 1];
+            sl += (l & 1) ? -uh[v][l - 1] : uh[v][l - 1];
+        }
+        tl[v] = sl;
+        tr[v] = sr;
+        sTrR[v * 256 + tid] = sr;
+    }
+
+    // Positivity (Euler) of the stage input at the traces, in FP64.
+    if (EQ == EULER && valid && a.check) {
+        double dl[NV], dr[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double sl = u0[v], sr = u0[v];
+#pragma unroll
+            for (int l = 1; l <= K; ++l) {
+                sr += (double)uh[v][l - 1];
+                sl += (l & 1) ? -(double)uh[v][l - 1] : (double)uh[v][l - 1];
+            }
+            dl[v] = sl;
+            dr[v] = sr;
+        }
+        double pl = Phys1D<EULER>::pressure(dl, a.phys), pr = Phys1D<EULER>::pressure(dr, a.phys);
+        if (!(dl[0] > 0.0) || !(dr[0] > 0.0) || !(pl > 0.0) || !(pr > 0.0)) {
+            bool fin = isfinite(dl[0]) && isfinite(dr[0]) && isfinite(pl) && isfinite(pr);
+            latch_error(a.ctrl, fin ? -5 : -4, cc);
+        }
+    }
+    __syncthreads();
+
+    // Flux at the left interface of this cell (once per interface).
+    T fL[NV], fR[NV];
+    if (valid && tid > 0) {
+        T left[NV];
+        if (!a.periodic && c == 0) {
+            ghost_state<NV, T>(a.bc_lo, a.dir_lo, tl, left);
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) left[v] = sTrR[v * 256 + tid - 1];
+        }
+        llf1d<EQ, T>(left, tl, fL, a.phys);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sF[v * 256 + tid] = fL[v];
+    }
+    __syncthreads();
+
+    // Residual and Shu-Osher combination -> unfiltered output (v0, vh).
+    const bool have_res = valid && tid >= 1 && tid <= 254;
+    double v0[NV];
+    T vh[NV][KH];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        v0[v] = 0.0;
+#pragma unroll
+        for (int l = 0; l < KH; ++l) vh[v][l] = (T)0;
+    }
+    if (have_res) {
+        if (!a.periodic && c == n - 1) {
+            T right[NV];
+            ghost_state<NV, T>(a.bc_hi, a.dir_hi, tr, right);
+            llf1d<EQ, T>(tr, right, fR, a.phys);
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) fR[v] = sF[v * 256 + tid + 1];
+        }
+        // Boundary fluxes for the conservation ledger (one writer each).
+        if (a.bflux && !a.periodic && tid >= HALO && tid < 256 - HALO) {
+            if (c == 0)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) a.bflux[v] = (double)fL[v];
+            if (c == n - 1)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) a.bflux[4 + v] = (double)fR[v];
+        }
+        // Volume term: int f(u_h) P_l'(xi) dxi by the (K+1)-point Gauss rule.
+        T vol[NV][KH];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int l = 0; l < KH; ++l) vol[v][l] = (T)0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            T uq[NV], fq[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                T s = (T)u0[v];
+#pragma unroll
+                for (int l = 1; l <= K; ++l) s += uh[v][l - 1] * (T)leg_at(Q, q, l);
+                uq[v] = s;
+            }
+            P::flux(uq, fq, a.phys);
+            if (EQ == EULER && a.check && valid) {
+                double p = Phys1D<EULER>::pressure(uq, a.phys);
+                if (!(uq[0] > (T)0) || !(p > 0.0)) {
+                    bool fin = isfinite((double)uq[0]) && isfinite(p);
+                    latch_error(a.ctrl, fin ? -5 : -4, cc);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                T wf = (T)gl_weight(Q, q) * fq[v];
+#pragma unroll
+                for (int l = 1; l <= K; ++l) vol[v][l - 1] += wf * (T)dleg_at(Q, q, l);
+            }
+        }
+        const T ih = (T)a.inv_h;
+        const T tdt = (T)dt;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            // mode 0: P_0' = 0, flux difference of the shared FP32/FP64
+            // interface fluxes accumulated in FP64 (conservative)
+            double L0 = -((double)fR[v] - (double)fL[v]) * a.inv_h;
+            v0[v] = combine(stage, n0[v], u0[v] + dt * L0);
+#pragma unroll
+            for (int l = 1; l <= K; ++l) {
+                T fl = (l & 1) ? -fL[v] : fL[v];
+                T L = (T)(2 * l + 1) * ih * (vol[v][l - 1] - fR[v] + fl);
+                vh[v][l - 1] = combine_t<T>(stage, nh[v][l - 1], uh[v][l - 1] + tdt * L);
+            }
+        }
+    }
+
+    const bool own = valid && c >= 0 && c < n && tid >= HALO && tid < 256 - HALO;
+
+    if constexpr (MODE == 0) {
+        if (own) store_cell<K, NV, TB>(a.out, c, v0, vh);
+    } else {
+        // ---- jump filter on the unfiltered output (needs neighbours) ----
+        __syncthreads();  // phase-1 LDS reads are complete
+        double* s0 = reinterpret_cast<double*>(lds);       // [NV][256] mode 0
+        T* sHR = reinterpret_cast<T*>(s0 + NV * 256);      // [K1][NV][256] right high-mode part
+        T* sHL = sHR + K1 * NV * 256;                      // [K1][NV][256] left high-mode part
+        T hR[K1][NV], hL[K1][NV];
+#pragma unroll
+        for (int m = 0; m <= K; ++m)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                T r = (T)0, l_ = (T)0;
+#pragma unroll
+                for (int l = (m > 1 ? m : 1); l <= K; ++l) {
+                    r += vh[v][l - 1] * (T)dtrace_r(l, m);
+                    l_ += vh[v][l - 1] * (T)dtrace_l(l, m);
+                }
+                hR[m][v] = r;
+                hL[m][v] = l_;
+                sHR[(m * NV + v) * 256 + tid] = r;
+                sHL[(m * NV + v) * 256 + tid] = l_;
+            }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s0[v * 256 + tid] = v0[v];
+        __syncthreads();
+
+        T eta_own = (T)0;
+        if (own) {
+            // S[l][v] = sum_{m<=l} m(m+1) 2^m (|[d^m]|_left + |[d^m]|_right)
+            T J[K1][NV];
+            const bool lbound = !a.periodic && c == 0, rbound = !a.periodic && c == n - 1;
+#pragma unroll
+            for (int m = 0; m <= K; ++m)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    T jl, jr;
+                    if (lbound) {
+                        T inner = (m == 0 ? (T)v0[v] : (T)0) + hL[m][v];
+                        jl = ghost_jump<T>(a.bc_lo, m, v, a.dir_lo[v], inner);
+                    } else {
+                        T d = hL[m][v] - sHR[(m * NV + v) * 256 + tid - 1];
+                        if (m == 0) d += (T)(v0[v] - s0[v * 256 + tid - 1]);
+                        jl = fabs(d);
+                    }
+                    if (rbound) {
+                        T inner = (m == 0 ? (T)v0[v] : (T)0) + hR[m][v];
+                        jr = ghost_jump<T>(a.bc_hi, m, v, a.dir_hi[v], inner);
+                    } else {
+                        T d = sHL[(m * NV + v) * 256 + tid + 1] - hR[m][v];
+                        if (m == 0) d += (T)(s0[v * 256 + tid + 1] - v0[v]);
+                        jr = fabs(d);
+                    }
+                    J[m][v] = jl + jr;
+                }
+            // beta_j = |f'(u-bar_j)|, H-bar_j from the cell average; the
+            // exponent sigma_j^l dt = beta dt / (h H) * max_s S^l_s (the
+            // l(l+1) of c_f^l and of (2/h)^2 l(l+1) cancel).
+            T ub[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) ub[v] = (T)v0[v];
+            const T beta = P::speed(ub, a.phys);
+            const T H = P::enthalpy(ub, a.phys);
+            const T coef = beta * (T)dt * (T)a.inv_h / H;
+            T E[K1];
+            E[0] = (T)0;
+            T S[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) S[v] = J[0][v];
+#pragma unroll
+            for (int l = 1; l <= K; ++l) {
+                T mx = (T)0;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    S[v] += (T)jump_weight(l) * J[l][v];
+                    mx = (v == 0 || S[v] > mx) ? S[v] : mx;
+                }
+                E[l] = coef * mx;
+            }
+            T eta = (T)0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                T e = J[0][v] * (T)(0.5 * a.inv_h);
+                eta = (v == 0 || e > eta) ? e : eta;
+            }
+            eta_own = eta;
+
+            if constexpr (MODE == 1) {
+#pragma unroll
+                for (int l = 1; l <= K; ++l) {
+                    T f = texp<T>(-E[l]);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) vh[v][l - 1] *= f;
+                }
+                store_cell<K, NV, TB>(a.out, c, v0, vh);
+            } else {
+                store_cell<K, NV, TB>(a.out, c, v0, vh);
+                if (eta > (T)1) {
+                    unsigned int slot = atomicAdd(a.tcount, 1u);
+                    a.tcell[slot] = c;
+                    double* rec = a.tdata + (size_t)slot * K1;
+                    rec[0] = (double)eta;
+#pragma unroll
+                    for (int l = 1; l <= K; ++l) rec[l] = (double)E[l];
+                }
+            }
+            if (a.E_out) {
+#pragma unroll
+                for (int l = 0; l <= K; ++l) a.E_out[c * K1 + l] = (double)E[l];
+            }
+        }
+        if constexpr (MODE == 2) {
+            // max eta over the domain (wave reduction, one atomic per wave)
+            double e = wave_max((double)eta_own);
+            if ((tid & 63) == 0) atomic_max_nonneg(a.eta_acc, e);
+        }
+    }
+
+    // CFL reduction of the output's cell averages (next step), FP64.
+    if (a.alpha_acc) {
+        double lam = 0.0;
+        if (own) lam = P::speed(v0, a.phys);
+        lam = wave_max(lam);
+        if ((tid & 63) == 0) atomic_max_nonneg(a.alpha_acc, lam);
+    }
+}
+
+// Hybrid pass B: u^l <- [omega + (1 - omega) exp(-E^l)] u^l for troubled
+// cells (eta > 1), omega = (M - eta) / (M - 1), M = max eta.
+template <int K, int NV, typename TB>
+__global__ __launch_bounds__(256) void blend1d_kernel(StateView<TB> out, const unsigned int* count,
+                                                      const long long* tcell, const double* tdata,
+                                                      const unsigned long long* eta_bits,
+                                                      const Ctrl* ctrl, int from_ctrl)
+{
+    if (from_ctrl && ctrl->done) return;
+    const unsigned int cnt = *count;
+    const double M = __longlong_as_double((long long)*eta_bits);
+    for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
+        const long long c = tcell[i];
+        const double* rec = tdata + (size_t)i * (K + 1);
+        const double eta = rec[0];
+        const double w = (M - eta) / (M - 1.0);
+#pragma unroll
+        for (int l = 1; l <= K; ++l) {
+            const TB f = (TB)(w + (1.0 - w) * exp(-rec[l]));
+#pragma unroll
+            for (int v = 0; v < NV; ++v) out.hi[v * out.sv + (l - 1) * out.sl + c] *= f;
+        }
+    }
+}
+
+// Unfused filter / hybrid (per-call API): reads the unfiltered stage output
+// w (halo 1) and either writes the filtered result (MODE 1) or the
+// exponents and eta per cell (MODE 2, followed by blend_all1d_kernel).
+template <int EQ, int K, typename TB, int MODE>
+__global__ __launch_bounds__(256) void filter1d_kernel(Args1D<TB> a)
+{
+    using P = Phys1D<EQ>;
+    using T = TB;
+    constexpr int NV = P::NV;
+    constexpr int K1 = K + 1;
+    constexpr int KH = K > 0 ? K : 1;
+    constexpr int TILE = 254;
+    const double dt = a.dt_host;
+
+    __shared__ __align__(16) double s0[NV * 256];
+    __shared__ __align__(16) T sHR[K1 * NV * 256];
+    __shared__ __align__(16) T sHL[K1 * NV * 256];
+
+    const int tid = threadIdx.x;
+    const int64_t c = (int64_t)blockIdx.x * TILE + tid - 1;
+    const int64_t n = a.n;
+    bool valid = true;
+    int64_t cc = c;
+    if (c < 0 || c >= n) {
+        if (a.periodic)
+            cc = wrap(c, n);
+        else
+            valid = false;
+    }
+    double v0[NV];
+    T vh[NV][KH];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        v0[v] = 0.0;
+#pragma unroll
+        for (int l = 0; l < KH; ++l) vh[v][l] = (T)0;
+    }
+    if (valid) load_cell<K, NV, TB>(a.us, cc, v0, vh);
+
+    T hR[K1][NV], hL[K1][NV];
+#pragma unroll
+    for (int m = 0; m <= K; ++m)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            T r = (T)0, l_ = (T)0;
+#pragma unroll
+            for (int l = (m > 1 ? m : 1); l <= K; ++l) {
+                r += vh[v][l - 1] * (T)dtrace_r(l, m);
+                l_ += vh[v][l - 1] * (T)dtrace_l(l, m);
+            }
+            hR[m][v] = r;
+            hL[m][v] = l_;
+            sHR[(m * NV + v) * 256 + tid] = r;
+            sHL[(m * NV + v) * 256 + tid] = l_;
+        }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s0[v * 256 + tid] = v0[v];
+    __syncthreads();
+
+    const bool own = valid && c >= 0 && c < n && tid >= 1 && tid <= 254;
+    if (!own) return;
+    T J[K1][NV];
+    const bool lbound = !a.periodic && c == 0, rbound = !a.periodic && c == n - 1;
+#pragma unroll
+    for (int m = 0; m <= K; ++m)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            T jl, jr;
+            if (lbound) {
+                T inner = (m == 0 ? (T)v0[v] : (T)0) + hL[m][v];
+                jl = ghost_jump<T>(a.bc_lo, m, v, a.dir_lo[v], inner);
+            } else {
+                T d = hL[m][v] - sHR[(m * NV + v) * 256 + tid - 1];
+                if (m == 0) d += (T)(v0[v] - s0[v * 256 + tid - 1]);
+                jl = fabs(d);
+            }
+            if (rbound) {
+                T inner = (m == 0 ? (T)v0[v] : (T)0) + hR[m][v];
+                jr = ghost_jump<T>(a.bc_hi, m, v, a.dir_hi[v], inner);
+            } else {
+                T d = sHL[(m * NV + v) * 256 + tid + 1] - hR[m][v];
+                if (m == 0) d += (T)(s0[v * 256 + tid + 1] - v0[v]);
+                jr = fabs(d);
+            }
+            J[m][v] = jl + jr;
+        }
+    T ub[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ub[v] = (T)v0[v];
+    const T beta = P::speed(ub, a.phys);
+    const T H = P::enthalpy(ub, a.phys);
+    const T coef = beta * (T)dt * (T)a.inv_h / H;
+    T E[K1];
+    E[0] = (T)0;
+    T S[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) S[v] = J[0][v];
+#pragma unroll
+    for (int l = 1; l <= K; ++l) {
+        T mx = (T)0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            S[v] += (T)jump_weight(l) * J[l][v];
+            mx = (v == 0 || S[v] > mx) ? S[v] : mx;
+        }
+        E[l] = coef * mx;
+    }
+    T eta = (T)0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        T e = J[0][v] * (T)(0.5 * a.inv_h);
+        eta = (v == 0 || e > eta) ? e : eta;
+    }
+    if (a.E_out) {
+#pragma unroll
+        for (int l = 0; l <= K; ++l) a.E_out[c * K1 + l] = (double)E[l];
+    }
+    if constexpr (MODE == 1) {
+#pragma unroll
+        for (int l = 1; l <= K; ++l) {
+            T f = texp<T>(-E[l]);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) vh[v][l - 1] *= f;
+        }
+        store_cell<K, NV, TB>(a.out, c, v0, vh);
+    } else {
+        a.eta_out[c] = (double)eta;
+        atomic_max_nonneg(a.eta_acc, (double)eta);
+    }
+}
+
+// Hybrid blend over all cells (per-call API): out = w for calm cells, the
+// blended polynomial for troubled ones.
+template <int K, int NV, typename TB>
+__global__ __launch_bounds__(256) void blend_all1d_kernel(StateView<TB> w, StateView<TB> out, int64_t n,
+                                                          const double* E, const double* eta,
+                                                          const unsigned long long* eta_bits,
+                                                          unsigned int* tcount)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    constexpr int KH = K > 0 ? K : 1;
+    double v0[NV];
+    TB vh[NV][KH];
+    load_cell<K, NV, TB>(w, c, v0, vh);
+    const double M = __longlong_as_double((long long)*eta_bits);
+    const double e = eta[c];
+    if (e > 1.0) {
+        atomicAdd(tcount, 1u);
+        const double om = (M - e) / (M - 1.0);
+#pragma unroll
+        for (int l = 1; l <= K; ++l) {
+            const TB f = (TB)(om + (1.0 - om) * exp(-E[c * (K + 1) + l]));
+#pragma unroll
+            for (int v = 0; v < NV; ++v) vh[v][l - 1] *= f;
+        }
+    }
+    store_cell<K, NV, TB>(out, c, v0, vh);
+}
+
+// CFL reduction over the cell averages of u (FP64).
+template <int EQ, typename TB>
+__global__ __launch_bounds__(256) void maxwave1d_kernel(StateView<TB> u, int64_t n, PhysParams phys,
+                                                        unsigned long long* acc)
+{
+    constexpr int NV = Phys1D<EQ>::NV;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double lam = 0.0;
+    if (c < n) {
+        double ub[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ub[v] = u.m0[v * u.s0 + c];
+        lam = Phys1D<EQ>::speed(ub, phys);
+    }
+    lam = wave_max(lam);
+    if ((threadIdx.x & 63) == 0) atomic_max_nonneg(acc, lam);
+}
+
+// ------------------------------------------------------------ launchers --
+template <int EQ, int K, typename TB>
+static hipError_t launch_stage(const Args1D<TB>& a, int mode, hipStream_t st)
+{
+    const int tile = mode == 0 ? 254 : 252;
+    dim3 grid((unsigned)((a.n + tile - 1) / tile)), block(256);
+    if (mode == 0)
+        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 0>), grid, block, 0, st, a);
+    else if (mode == 1)
+        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 1>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 2>), grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+template <int EQ, int K, typename TB>
+static hipError_t launch_filter(const Args1D<TB>& a, int mode, hipStream_t st)
+{
+    dim3 grid((unsigned)((a.n + 253) / 254)), block(256);
+    if (mode == 1)
+        hipLaunchKernelGGL((filter1d_kernel<EQ, K, TB, 1>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((filter1d_kernel<EQ, K, TB, 2>), grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename TB>
+hipError_t launch_stage1d(int eq, int k, const Args1D<TB>& a, int mode, hipStream_t st)
+{
+#define DG_CASE(E_, K_) \
+    if (eq == E_ && k == K_) return launch_stage<E_, K_, TB>(a, mode, st);
+    DG_CASE(ADV, 0) DG_CASE(ADV, 1) DG_CASE(ADV, 2) DG_CASE(ADV, 3)
+    DG_CASE(BURGERS, 0) DG_CASE(BURGERS, 1) DG_CASE(BURGERS, 2) DG_CASE(BURGERS, 3)
+    DG_CASE(EULER, 0) DG_CASE(EULER, 1) DG_CASE(EULER, 2) DG_CASE(EULER, 3)
+#undef DG_CASE
+    return hipErrorInvalidValue;
+}
+
+template <typename TB>
+hipError_t launch_filter1d(int eq, int k, const Args1D<TB>& a, int mode, hipStream_t st)
+{
+#define DG_CASE(E_, K_) \
+    if (eq == E_ && k == K_) return launch_filter<E_, K_, TB>(a, mode, st);
+    DG_CASE(ADV, 0) DG_CASE(ADV, 1) DG_CASE(ADV, 2) DG_CASE(ADV, 3)
+    DG_CASE(BURGERS, 0) DG_CASE(BURGERS, 1) DG_CASE(BURGERS, 2) DG_CASE(BURGERS, 3)
+    DG_CASE(EULER, 0) DG_CASE(EULER, 1) DG_CASE(EULER, 2) DG_CASE(EULER, 3)
+#undef DG_CASE
+    return hipErrorInvalidValue;
+}
+
+template <typename TB>
+hipError_t launch_blend1d(int nv, int k, StateView<TB> out, const unsigned int* count,
+                          const long long* tcell, const double* tdata,
+                          const unsigned long long* eta_bits, const Ctrl* ctrl, int from_ctrl,
+                          int64_t max_entries, hipStream_t st)
+{
+    unsigned g = (unsigned)((max_entries + 255) / 256);
+    if (g > 1024) g = 1024;
+    if (g < 1) g = 1;
+#define DG_CASE(NV_, K_)                                                                            \
+    if (nv == NV_ && k == K_) {                                                                     \
+        hipLaunchKernelGGL((blend1d_kernel<K_, NV_, TB>), dim3(g), dim3(256), 0, st, out, count,      \
+                           tcell, tdata, eta_bits, ctrl, from_ctrl);                                \
+        return hipGetLastError();                                                                   \
+    }
+    DG_CASE(1, 0) DG_CASE(1, 1) DG_CASE(1, 2) DG_CASE(1, 3)
+    DG_CASE(3, 0) DG_CASE(3, 1) DG_CASE(3, 2) DG_CASE(3, 3)
+#undef DG_CASE
+    return hipErrorInvalidValue;
+}
+
+template <typename TB>
+hipError_t launch_blend_all1d(int nv, int k, StateView<TB> w, StateView<TB> out, int64_t n,
+                              const double* E, const double* eta,
+                              const unsigned long long* eta_bits, unsigned int* tcount,
+                              hipStream_t st)
+{
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+#define DG_CASE(NV_, K_)                                                                           \
+    if (nv == NV_ && k == K_) {                                                                    \
+        hipLaunchKernelGGL((blend_all1d_kernel<K_, NV_, TB>), grid, block, 0, st, w, out, n, E, eta, \
+                           eta_bits, tcount);                                                      \
+        return hipGetLastError();                                                                  \
+    }
+    DG_CASE(1, 0) DG_CASE(1, 1) DG_CASE(1, 2) DG_CASE(1, 3)
+    DG_CASE(3, 0) DG_CASE(3, 1) DG_CASE(3, 2) DG_CASE(3, 3)
+#undef DG_CASE
+    return hipErrorInvalidValue;
+}
+
+template <typename TB>
+hipError_t launch_maxwave1d(int eq, StateView<TB> u, int64_t n, PhysParams phys,
+                            unsigned long long* acc, hipStream_t st)
+{
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (eq == ADV)
+        hipLaunchKernelGGL((maxwave1d_kernel<ADV, TB>), grid, block, 0, st, u, n, phys, acc);
+    else if (eq == BURGERS)
+        hipLaunchKernelGGL((maxwave1d_kernel<BURGERS, TB>), grid, block, 0, st, u, n, phys, acc);
+    else
+        hipLaunchKernelGGL((maxwave1d_kernel<EULER, TB>), grid, block, 0, st, u, n, phys, acc);
+    return hipGetLastError();
+}
+
+#define DG_INST(TB)                                                                                 \
+    template hipError_t launch_stage1d<TB>(int, int, const Args1D<TB>&, int, hipStream_t);          \
+    template hipError_t launch_filter1d<TB>(int, int, const Args1D<TB>&, int, hipStream_t);         \
+    template hipError_t launch_blend1d<TB>(int, int, StateView<TB>, const unsigned int*,            \
+                                           const long long*, const double*,                        \
+                                           const unsigned long long*, const Ctrl*, int, int64_t,   \
+                                           hipStream_t);                                           \
+    template hipError_t launch_blend_all1d<TB>(int, int, StateView<TB>, StateView<TB>, int64_t,     \
+                                               const double*, const double*,                       \
+                                               const unsigned long long*, unsigned int*,           \
+                                               hipStream_t);                                       \
+    template hipError_t launch_maxwave1d<TB>(int, StateView<TB>, int64_t, PhysParams,               \
+                                             unsigned long long*, hipStream_t);
+DG_INST(double)
+DG_INST(float)
+#undef DG_INST
+
+}  // namespace dg

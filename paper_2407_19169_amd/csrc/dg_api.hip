@@ -1,0 +1,564 @@
+// dg_api.hip — host side of the C ABI declared in include/dg.h.
+//
+// The handle keeps parameters, the workspace carve-up and one instantiated
+// HIP graph of G fused time steps.  dg_run replays that graph on a private
+// non-blocking stream (capture is not possible on the null stream) until
+// the device control block reports that t_end or the step limit was reached;
+// time steps are chosen on the device, so the host only reads the control
+// block between batches of replays.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/dg.h"
+#include "dg_kernels.h"
+
+using namespace dg;
+
+struct dg_solver {
+    dg_mesh mesh;
+    dg_options opt;
+    int k, eq, dim, nv, nmodes, lmax;
+    int64_t ncell, n_pad;
+    double h[2], inv_h[2];
+    size_t state_bytes, ws_bytes;
+    size_t off_w, off_E, off_eta, off_tcell, off_tdata, off_aux;
+    void* u[3];
+    unsigned char* ws;
+    bool bound;
+    hipStream_t user_st;
+    hipStream_t run_st;
+    hipGraphExec_t graph;
+    int graph_steps;
+};
+
+namespace {
+
+constexpr size_t kCtrlBytes = 4096;
+constexpr size_t kAuxBytes = 4096;
+constexpr int kGraphSteps = 16;  // even: the three state buffers rotate with period 2
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+#define DG_HIP(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return DG_ERR_DEVICE;    \
+    } while (0)
+
+template <typename TB>
+StateView<TB> view_of(const dg_solver* s, void* base)
+{
+    StateView<TB> v;
+    if (s->opt.precision == DG_PREC_FP64) {
+        double* b = static_cast<double*>(base);
+        v.m0 = b;
+        v.s0 = (int64_t)s->nmodes * s->ncell;
+        v.hi = reinterpret_cast<TB*>(b + s->ncell);
+        v.sv = (int64_t)s->nmodes * s->ncell;
+        v.sl = s->ncell;
+    } else {
+        double* b = static_cast<double*>(base);
+        v.m0 = b;
+        v.s0 = s->n_pad;
+        v.hi = reinterpret_cast<TB*>(b + (size_t)s->nv * s->n_pad);
+        v.sv = (int64_t)(s->nmodes - 1) * s->n_pad;
+        v.sl = s->n_pad;
+    }
+    return v;
+}
+
+Ctrl* ctrl_of(const dg_solver* s) { return reinterpret_cast<Ctrl*>(s->ws); }
+double* aux_of(const dg_solver* s) { return reinterpret_cast<double*>(s->ws + s->off_aux); }
+
+template <typename TB>
+Args1D<TB> base_args(const dg_solver* s)
+{
+    Args1D<TB> a;
+    memset(&a, 0, sizeof a);
+    a.n = s->ncell;
+    a.inv_h = s->inv_h[0];
+    a.periodic = s->mesh.bc[0] == DG_BC_PERIODIC;
+    a.bc_lo = s->mesh.bc[0];
+    a.bc_hi = s->mesh.bc[1];
+    for (int v = 0; v < 4; ++v) {
+        a.dir_lo[v] = s->mesh.dirichlet[0][v];
+        a.dir_hi[v] = s->mesh.dirichlet[1][v];
+    }
+    a.phys.gamma = s->opt.gamma;
+    a.phys.a[0] = s->opt.adv_speed[0];
+    a.phys.a[1] = s->opt.adv_speed[1];
+    a.check = s->eq == DG_EQ_EULER;
+    a.ctrl = ctrl_of(s);
+    return a;
+}
+
+template <typename TB>
+int stage_impl(dg_solver* s, int stage, double dt)
+{
+    Args1D<TB> a = base_args<TB>(s);
+    a.un = view_of<TB>(s, s->u[0]);
+    a.us = view_of<TB>(s, s->u[stage]);
+    a.out = view_of<TB>(s, s->ws + s->off_w);
+    a.stage = stage;
+    a.dt_host = dt;
+    DG_HIP(launch_stage1d<TB>(s->eq, s->k, a, 0, s->user_st));
+    return DG_OK;
+}
+
+template <typename TB>
+int filter_impl(dg_solver* s, int stage, double dt)
+{
+    void* target = stage == 0 ? s->u[1] : stage == 1 ? s->u[2] : s->u[0];
+    if (s->opt.filter == DG_FILTER_NONE) {
+        DG_HIP(hipMemcpyAsync(target, s->ws + s->off_w, s->state_bytes, hipMemcpyDeviceToDevice,
+                              s->user_st));
+        return DG_OK;
+    }
+    Args1D<TB> a = base_args<TB>(s);
+    a.us = view_of<TB>(s, s->ws + s->off_w);
+    a.out = view_of<TB>(s, target);
+    a.stage = stage;
+    a.dt_host = dt;
+    a.E_out = reinterpret_cast<double*>(s->ws + s->off_E);
+    if (s->opt.filter == DG_FILTER_JUMP) {
+        DG_HIP(launch_filter1d<TB>(s->eq, s->k, a, 1, s->user_st));
+        return DG_OK;
+    }
+    double* aux = aux_of(s);
+    unsigned long long* eta_bits = reinterpret_cast<unsigned long long*>(aux + 8);
+    unsigned int* tcount = reinterpret_cast<unsigned int*>(aux + 9);
+    DG_HIP(hipMemsetAsync(aux + 8, 0, 2 * sizeof(double), s->user_st));
+    a.eta_out = reinterpret_cast<double*>(s->ws + s->off_eta);
+    a.eta_acc = eta_bits;
+    DG_HIP(launch_filter1d<TB>(s->eq, s->k, a, 2, s->user_st));
+    DG_HIP(launch_blend_all1d<TB>(s->nv, s->k, a.us, a.out, s->ncell, a.E_out, a.eta_out, eta_bits,
+                                  tcount, s->user_st));
+    return DG_OK;
+}
+
+template <typename TB>
+int maxwave_impl(dg_solver* s, unsigned long long* acc, hipStream_t st)
+{
+    DG_HIP(launch_maxwave1d<TB>(s->eq, view_of<TB>(s, s->u[0]), s->ncell,
+                                base_args<TB>(s).phys, acc, st));
+    return DG_OK;
+}
+
+// Record G fused steps (rotation A->B, (B,A)->C, (C,A)->B; then the mirror)
+// on the capture stream.
+template <typename TB>
+int record_steps(dg_solver* s, int G, hipStream_t st)
+{
+    Ctrl* c = ctrl_of(s);
+    const int fmode = s->opt.filter == DG_FILTER_NONE ? 0 : s->opt.filter == DG_FILTER_JUMP ? 1 : 2;
+    long long* tcell = reinterpret_cast<long long*>(s->ws + s->off_tcell);
+    double* tdata = reinterpret_cast<double*>(s->ws + s->off_tdata);
+    for (int i = 0; i < G; ++i) {
+        void* A = (i % 2 == 0) ? s->u[0] : s->u[1];
+        void* B = (i % 2 == 0) ? s->u[1] : s->u[0];
+        void* Cb = s->u[2];
+        DG_HIP(launch_step_ctrl(c, 0, st));
+        for (int stage = 0; stage < 3; ++stage) {
+            Args1D<TB> a = base_args<TB>(s);
+            a.un = view_of<TB>(s, A);
+            a.us = view_of<TB>(s, stage == 0 ? A : stage == 1 ? B : Cb);
+            a.out = view_of<TB>(s, stage == 1 ? Cb : B);
+            a.stage = stage;
+            a.dt_from_ctrl = 1;
+            a.bflux = &c->bstage[stage][0];
+            a.alpha_acc = stage == 2 ? &c->alpha_bits : nullptr;
+            a.eta_acc = &c->eta_bits[stage];
+            a.tcount = &c->tcount[stage];
+            a.tcell = tcell;
+            a.tdata = tdata;
+            DG_HIP(launch_stage1d<TB>(s->eq, s->k, a, fmode, st));
+            if (fmode == 2)
+                DG_HIP(launch_blend1d<TB>(s->nv, s->k, a.out, &c->tcount[stage], tcell, tdata,
+                                          &c->eta_bits[stage], c, 1, s->ncell, st));
+        }
+    }
+    return DG_OK;
+}
+
+template <typename TB>
+int build_graph(dg_solver* s)
+{
+    if (s->graph) {
+        hipGraphExecDestroy(s->graph);
+        s->graph = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    DG_HIP(hipStreamBeginCapture(s->run_st, hipStreamCaptureModeThreadLocal));
+    int rc = record_steps<TB>(s, kGraphSteps, s->run_st);
+    hipError_t e = hipStreamEndCapture(s->run_st, &g);
+    if (rc != DG_OK) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return DG_ERR_DEVICE;
+    e = hipGraphInstantiate(&s->graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        s->graph = nullptr;
+        return DG_ERR_DEVICE;
+    }
+    s->graph_steps = kGraphSteps;
+    return DG_OK;
+}
+
+template <typename TB>
+int report_impl(dg_solver* s, dg_report* rep)
+{
+    hipStream_t st = s->run_st;
+    double* aux = aux_of(s);
+    // aux[0..3] ledger, aux[4..5] min rho / min p (as ordered bits)
+    unsigned long long inf_bits = (unsigned long long)0x7ff0000000000000ULL;
+    unsigned long long init[2] = {inf_bits, inf_bits};
+    DG_HIP(hipStreamSynchronize(st));
+    DG_HIP(hipMemcpy(aux + 4, init, sizeof init, hipMemcpyHostToDevice));
+    const double vol = s->dim == 1 ? s->h[0] : s->h[0] * s->h[1];
+    DG_HIP(launch_ledger<TB>(s->nv, s->ncell, view_of<TB>(s, s->u[0]), vol, aux, st));
+    if (s->dim == 1)
+        DG_HIP(launch_check1d<TB>(s->eq, s->k, view_of<TB>(s, s->u[0]), s->ncell,
+                                  base_args<TB>(s).phys, ctrl_of(s), aux + 4, st));
+    Ctrl c;
+    double hv[6];
+    DG_HIP(hipMemcpyAsync(&c, ctrl_of(s), sizeof c, hipMemcpyDeviceToHost, st));
+    DG_HIP(hipMemcpyAsync(hv, aux, sizeof hv, hipMemcpyDeviceToHost, st));
+    DG_HIP(hipStreamSynchronize(st));
+    if (rep) {
+        memset(rep, 0, sizeof *rep);
+        rep->t = c.t;
+        rep->dt_min = c.dt_min;
+        rep->dt_max = c.dt_max;
+        for (int v = 0; v < 4; ++v) {
+            rep->ledger[v] = v < s->nv ? hv[v] : 0.0;
+            rep->boundary_flux[v] = c.bflux[v];
+        }
+        rep->troubled_cells = c.troubled;
+        rep->min_rho = s->eq == DG_EQ_EULER ? hv[4] : NAN;
+        rep->min_p = s->eq == DG_EQ_EULER ? hv[5] : NAN;
+        rep->max_exponent = NAN;
+        rep->status = c.status;
+        rep->first_bad_cell = c.status ? c.first_bad : -1;
+        rep->steps = c.steps;
+    }
+    return c.status;
+}
+
+template <typename TB>
+int run_impl(dg_solver* s, double t_end, int64_t max_steps, dg_report* rep)
+{
+    DG_HIP(hipStreamSynchronize(s->user_st));
+    hipStream_t st = s->run_st;
+    Ctrl c;
+    DG_HIP(hipMemcpy(&c, ctrl_of(s), sizeof c, hipMemcpyDeviceToHost));
+    const long long steps0 = c.steps;
+    c.t_end = t_end;
+    c.max_steps = steps0 + max_steps;
+    c.done = 0;
+    c.active = 0;
+    c.dt_min = INFINITY;
+    c.dt_max = 0.0;
+    c.alpha_bits = 0;
+    c.cfl_num = s->dim == 1 ? s->opt.cfl * s->h[0] : s->opt.cfl;
+    DG_HIP(hipMemcpy(ctrl_of(s), &c, sizeof c, hipMemcpyHostToDevice));
+    if (!s->graph) {
+        int rc = build_graph<TB>(s);
+        if (rc) return rc;
+    }
+    int rc = maxwave_impl<TB>(s, &ctrl_of(s)->alpha_bits, st);
+    if (rc) return rc;
+    // Replays: when the step limit binds, all replays are launched at
+    // once; otherwise batches double in size between control reads.
+    const long long need = (max_steps + s->graph_steps - 1) / s->graph_steps;
+    long long launched = 0, batch = 1;
+    int done = 0;
+    while (!done) {
+        long long nb = batch;
+        if (launched + nb > need) nb = need - launched;
+        if (nb <= 0) break;
+        for (long long r = 0; r < nb; ++r) DG_HIP(hipGraphLaunch(s->graph, st));
+        launched += nb;
+        DG_HIP(hipMemcpyAsync(&done, &ctrl_of(s)->done, sizeof done, hipMemcpyDeviceToHost, st));
+        DG_HIP(hipStreamSynchronize(st));
+        if (launched >= need) break;
+        batch = batch < 64 ? batch * 2 : 64;
+    }
+    DG_HIP(launch_step_ctrl(ctrl_of(s), 1, st));
+    DG_HIP(hipMemcpyAsync(&c, ctrl_of(s), sizeof c, hipMemcpyDeviceToHost, st));
+    DG_HIP(hipStreamSynchronize(st));
+    if ((c.steps - steps0) & 1)
+        DG_HIP(hipMemcpyAsync(s->u[0], s->u[1], s->state_bytes, hipMemcpyDeviceToDevice, st));
+    return report_impl<TB>(s, rep);
+}
+
+bool is_fp64(const dg_solver* s) { return s->opt.precision == DG_PREC_FP64; }
+
+// Events around each launch of the fused stage kernel (rotation slot 0 of
+// dg_run: A = u_n read-only, outputs to u_a / u_b).  The hybrid list and
+// the CFL accumulator point into the aux scratch, whose counters are
+// cleared by a one-thread kernel before each timed launch.
+template <typename TB>
+int time_impl(dg_solver* s, int stage, double dt, int reps, double* avg_us)
+{
+    hipStream_t st = s->run_st;
+    const int fmode = s->opt.filter == DG_FILTER_NONE ? 0 : s->opt.filter == DG_FILTER_JUMP ? 1 : 2;
+    double* aux = aux_of(s);
+    Ctrl* scratch = reinterpret_cast<Ctrl*>(aux + 16);  // a second control block in aux
+    Args1D<TB> a = base_args<TB>(s);
+    a.un = view_of<TB>(s, s->u[0]);
+    a.us = view_of<TB>(s, stage == 0 ? s->u[0] : stage == 1 ? s->u[1] : s->u[2]);
+    a.out = view_of<TB>(s, stage == 1 ? s->u[2] : s->u[1]);
+    a.stage = stage;
+    a.dt_host = dt;
+    a.ctrl = scratch;
+    a.bflux = &scratch->bstage[stage][0];
+    a.alpha_acc = stage == 2 ? &scratch->alpha_bits : nullptr;
+    a.eta_acc = &scratch->eta_bits[stage];
+    a.tcount = &scratch->tcount[stage];
+    a.tcell = reinterpret_cast<long long*>(s->ws + s->off_tcell);
+    a.tdata = reinterpret_cast<double*>(s->ws + s->off_tdata);
+    hipEvent_t e0, e1;
+    DG_HIP(hipEventCreate(&e0));
+    DG_HIP(hipEventCreate(&e1));
+    double total_ms = 0.0;
+    int rc = DG_OK;
+    for (int r = 0; r < reps && rc == DG_OK; ++r) {
+        if (launch_step_ctrl(scratch, 2, st) != hipSuccess) rc = DG_ERR_DEVICE;
+        if (hipEventRecord(e0, st) != hipSuccess) rc = DG_ERR_DEVICE;
+        if (launch_stage1d<TB>(s->eq, s->k, a, fmode, st) != hipSuccess) rc = DG_ERR_DEVICE;
+        if (hipEventRecord(e1, st) != hipSuccess) rc = DG_ERR_DEVICE;
+        if (hipEventSynchronize(e1) != hipSuccess) rc = DG_ERR_DEVICE;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = DG_ERR_DEVICE;
+        total_ms += ms;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *avg_us = 1000.0 * total_ms / reps;
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dg_strerror(int code)
+{
+    switch (code) {
+    case DG_OK: return "ok";
+    case DG_ERR_ARG: return "invalid argument";
+    case DG_ERR_UNSUPPORTED: return "unsupported degree/dimension/equation";
+    case DG_ERR_DEVICE: return "HIP runtime error";
+    case DG_ERR_NONFINITE: return "non-finite value in state or time step";
+    case DG_ERR_POSITIVITY: return "non-positive density or pressure";
+    case DG_ERR_STATE: return "buffers not bound or call out of order";
+    default: return "unknown error";
+    }
+}
+
+int dg_create(const dg_mesh* mesh, int degree, int equation, const dg_options* opt, dg_solver** out)
+{
+    if (!mesh || !opt || !out) return DG_ERR_ARG;
+    *out = nullptr;
+    if (mesh->dim != 1 && mesh->dim != 2) return DG_ERR_ARG;
+    if (degree < 0 || degree > kMaxDeg) return DG_ERR_UNSUPPORTED;
+    if (equation < 0 || equation > 2) return DG_ERR_ARG;
+    if (opt->precision != DG_PREC_FP64 && opt->precision != DG_PREC_MIXED) return DG_ERR_ARG;
+    if (opt->filter < 0 || opt->filter > 2) return DG_ERR_ARG;
+    if (opt->quad_points != 0 && opt->quad_points != degree + 1) return DG_ERR_UNSUPPORTED;
+    if (!(opt->cfl > 0.0)) return DG_ERR_ARG;
+    if (equation == DG_EQ_EULER && !(opt->gamma > 1.0)) return DG_ERR_ARG;
+    for (int d = 0; d < mesh->dim; ++d) {
+        if (mesh->n[d] < 1 || !(mesh->hi[d] > mesh->lo[d])) return DG_ERR_ARG;
+        int b0 = mesh->bc[2 * d], b1 = mesh->bc[2 * d + 1];
+        if (b0 < 0 || b0 > 5 || b1 < 0 || b1 > 5) return DG_ERR_ARG;
+        if ((b0 == DG_BC_PERIODIC) != (b1 == DG_BC_PERIODIC)) return DG_ERR_ARG;
+        if (mesh->dim == 1 && (b0 > 3 || b1 > 3)) return DG_ERR_ARG;
+        if ((b0 == DG_BC_REFLECT || b1 == DG_BC_REFLECT) && equation != DG_EQ_EULER) return DG_ERR_ARG;
+    }
+    if (mesh->dim == 2) return DG_ERR_UNSUPPORTED;  // 2D path: see dg2d
+    dg_solver* s = new (std::nothrow) dg_solver;
+    if (!s) return DG_ERR_ARG;
+    memset(s, 0, sizeof *s);
+    s->mesh = *mesh;
+    s->opt = *opt;
+    s->k = degree;
+    s->eq = equation;
+    s->dim = mesh->dim;
+    s->nv = (equation == DG_EQ_EULER) ? (mesh->dim == 1 ? 3 : 4) : 1;
+    s->nmodes = mesh->dim == 1 ? degree + 1 : (degree + 1) * (degree + 1);
+    s->lmax = mesh->dim == 1 ? degree : 2 * degree;
+    s->ncell = mesh->dim == 1 ? mesh->n[0] : mesh->n[0] * mesh->n[1];
+    s->n_pad = (s->ncell + 63) / 64 * 64;
+    for (int d = 0; d < mesh->dim; ++d) {
+        s->h[d] = (mesh->hi[d] - mesh->lo[d]) / (double)mesh->n[d];
+        s->inv_h[d] = 1.0 / s->h[d];
+    }
+    if (opt->precision == DG_PREC_FP64)
+        s->state_bytes = align256((size_t)s->nv * s->nmodes * s->ncell * sizeof(double));
+    else
+        s->state_bytes = align256((size_t)s->nv * s->n_pad * sizeof(double) +
+                                  (size_t)s->nv * (s->nmodes - 1) * s->n_pad * sizeof(float));
+    size_t off = kCtrlBytes;
+    s->off_w = off;
+    off += s->state_bytes;
+    s->off_E = off;
+    off += align256((size_t)s->ncell * (s->lmax + 1) * sizeof(double));
+    s->off_eta = off;
+    off += align256((size_t)s->ncell * sizeof(double));
+    s->off_tcell = off;
+    off += align256((size_t)s->ncell * sizeof(long long));
+    s->off_tdata = off;
+    off += align256((size_t)s->ncell * (s->lmax + 1) * sizeof(double));
+    s->off_aux = off;
+    off += kAuxBytes;
+    s->ws_bytes = off;
+    s->user_st = static_cast<hipStream_t>(opt->stream);
+    if (hipStreamCreateWithFlags(&s->run_st, hipStreamNonBlocking) != hipSuccess) {
+        delete s;
+        return DG_ERR_DEVICE;
+    }
+    *out = s;
+    return DG_OK;
+}
+
+int dg_destroy(dg_solver* s)
+{
+    if (!s) return DG_ERR_ARG;
+    if (s->graph) hipGraphExecDestroy(s->graph);
+    if (s->run_st) hipStreamDestroy(s->run_st);
+    delete s;
+    return DG_OK;
+}
+
+int dg_buffer_sizes(const dg_solver* s, size_t* state_bytes, size_t* workspace_bytes)
+{
+    if (!s) return DG_ERR_ARG;
+    if (state_bytes) *state_bytes = s->state_bytes;
+    if (workspace_bytes) *workspace_bytes = s->ws_bytes;
+    return DG_OK;
+}
+
+int dg_bind(dg_solver* s, void* u_n, void* u_a, void* u_b, void* workspace)
+{
+    if (!s || !u_n || !u_a || !u_b || !workspace) return DG_ERR_ARG;
+    void* ptrs[4] = {u_n, u_a, u_b, workspace};
+    for (void* p : ptrs)
+        if (((uintptr_t)p) & 255) return DG_ERR_ARG;
+    if (u_n == u_a || u_n == u_b || u_a == u_b) return DG_ERR_ARG;
+    s->u[0] = u_n;
+    s->u[1] = u_a;
+    s->u[2] = u_b;
+    s->ws = static_cast<unsigned char*>(workspace);
+    if (s->graph) {
+        hipGraphExecDestroy(s->graph);
+        s->graph = nullptr;
+    }
+    Ctrl c;
+    memset(&c, 0, sizeof c);
+    c.dt_min = INFINITY;
+    c.first_bad = -1;
+    DG_HIP(hipStreamSynchronize(s->user_st));
+    DG_HIP(hipMemcpy(workspace, &c, sizeof c, hipMemcpyHostToDevice));
+    s->bound = true;
+    return DG_OK;
+}
+
+int dg_set_state(dg_solver* s, const double* modes_dev)
+{
+    if (!s || !modes_dev) return DG_ERR_ARG;
+    if (!s->bound) return DG_ERR_STATE;
+    if (is_fp64(s)) {
+        DG_HIP(hipMemcpyAsync(s->u[0], modes_dev, (size_t)s->nv * s->nmodes * s->ncell * sizeof(double),
+                              hipMemcpyDeviceToDevice, s->user_st));
+    } else {
+        DG_HIP(launch_convert<float>(1, s->nv, s->nmodes, s->ncell, modes_dev,
+                                     view_of<float>(s, s->u[0]), s->user_st));
+    }
+    return DG_OK;
+}
+
+int dg_get_state(dg_solver* s, double* modes_dev)
+{
+    if (!s || !modes_dev) return DG_ERR_ARG;
+    if (!s->bound) return DG_ERR_STATE;
+    if (is_fp64(s)) {
+        DG_HIP(hipMemcpyAsync(modes_dev, s->u[0], (size_t)s->nv * s->nmodes * s->ncell * sizeof(double),
+                              hipMemcpyDeviceToDevice, s->user_st));
+    } else {
+        DG_HIP(launch_convert<float>(0, s->nv, s->nmodes, s->ncell, modes_dev,
+                                     view_of<float>(s, s->u[0]), s->user_st));
+    }
+    return DG_OK;
+}
+
+int dg_max_wavespeed(dg_solver* s, double* alpha)
+{
+    if (!s || !alpha) return DG_ERR_ARG;
+    if (!s->bound) return DG_ERR_STATE;
+    double* aux = aux_of(s);
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(aux + 10);
+    DG_HIP(hipMemsetAsync(acc, 0, sizeof *acc, s->user_st));
+    int rc = is_fp64(s) ? maxwave_impl<double>(s, acc, s->user_st) : maxwave_impl<float>(s, acc, s->user_st);
+    if (rc) return rc;
+    unsigned long long bits = 0;
+    DG_HIP(hipMemcpyAsync(&bits, acc, sizeof bits, hipMemcpyDeviceToHost, s->user_st));
+    DG_HIP(hipStreamSynchronize(s->user_st));
+    memcpy(alpha, &bits, sizeof bits);
+    return isfinite(*alpha) ? DG_OK : DG_ERR_NONFINITE;
+}
+
+int dg_stage(dg_solver* s, int stage, double dt)
+{
+    if (!s || stage < 0 || stage > 2 || !(dt >= 0.0)) return DG_ERR_ARG;
+    if (!s->bound) return DG_ERR_STATE;
+    return is_fp64(s) ? stage_impl<double>(s, stage, dt) : stage_impl<float>(s, stage, dt);
+}
+
+int dg_jump_filter(dg_solver* s, int stage, double dt)
+{
+    if (!s || stage < 0 || stage > 2 || !(dt >= 0.0)) return DG_ERR_ARG;
+    if (!s->bound) return DG_ERR_STATE;
+    return is_fp64(s) ? filter_impl<double>(s, stage, dt) : filter_impl<float>(s, stage, dt);
+}
+
+int dg_run(dg_solver* s, double t_end, int64_t max_steps, dg_report* rep)
+{
+    if (!s || max_steps < 0 || !(t_end == t_end)) return DG_ERR_ARG;
+    if (!s->bound) return DG_ERR_STATE;
+    return is_fp64(s) ? run_impl<double>(s, t_end, max_steps, rep)
+                      : run_impl<float>(s, t_end, max_steps, rep);
+}
+
+int dg_report_read(dg_solver* s, dg_report* rep)
+{
+    if (!s) return DG_ERR_ARG;
+    if (!s->bound) return DG_ERR_STATE;
+    DG_HIP(hipStreamSynchronize(s->user_st));
+    return is_fp64(s) ? report_impl<double>(s, rep) : report_impl<float>(s, rep);
+}
+
+int dg_time_kernel(dg_solver* s, int stage, double dt, int reps, double* avg_us)
+{
+    if (!s || stage < 0 || stage > 2 || reps < 1 || !avg_us || !(dt >= 0.0)) return DG_ERR_ARG;
+    if (!s->bound) return DG_ERR_STATE;
+    DG_HIP(hipStreamSynchronize(s->user_st));
+    return is_fp64(s) ? time_impl<double>(s, stage, dt, reps, avg_us)
+                      : time_impl<float>(s, stage, dt, reps, avg_us);
+}
+
+int dg_last_exponents(dg_solver* s, double* E_dev)
+{
+    if (!s || !E_dev) return DG_ERR_ARG;
+    if (!s->bound) return DG_ERR_STATE;
+    DG_HIP(hipMemcpyAsync(E_dev, s->ws + s->off_E, (size_t)s->ncell * (s->lmax + 1) * sizeof(double),
+                          hipMemcpyDeviceToDevice, s->user_st));
+    return DG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,204 @@
+// dg_common.h — device-side building blocks shared by the 1D, 2D and batched
+// kernels of the RKDG + jump-filter library (gfx950).
+//
+// Basis: standard Legendre polynomials P_l on [-1, 1], P_0 = 1, so the mode-0
+// coefficient is the cell average (arXiv:2407.19169, Sec. 2.1).  Tables are
+// compile-time constants built from the closed forms of P_0..P_3, their
+// derivatives and the Gauss-Legendre rules with 1..4 points, so every loop
+// over modes or quadrature points folds to straight-line FMA code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dg_tables.h"
+
+namespace dg {
+
+constexpr int kMaxDeg = 3;
+
+enum Eq { ADV = 0, BURGERS = 1, EULER = 2 };
+enum Bc { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2, BC_DIRICHLET = 3, BC_DMR_WALL = 4,
+          BC_DMR_TOP = 5 };
+enum Filter { F_NONE = 0, F_JUMP = 1, F_HYBRID = 2 };
+
+// ---------------------------------------------------------------- basis --
+// Gauss-Legendre nodes/weights (Q = 1..4, ascending nodes) and P_l, P_l'
+// at the nodes: correctly rounded constants from dg_tables.h.
+__host__ __device__ constexpr double gl_node(int Q, int i) { return kGaussX[Q - 1][i]; }
+__host__ __device__ constexpr double gl_weight(int Q, int i) { return kGaussW[Q - 1][i]; }
+__host__ __device__ constexpr double leg_at(int Q, int i, int l) { return kLegAt[Q - 1][i][l]; }
+__host__ __device__ constexpr double dleg_at(int Q, int i, int l) { return kDLegAt[Q - 1][i][l]; }
+// d^m/dx^m P_l at x = +1: (l+m)! / (2^m m! (l-m)!), zero for m > l.
+__host__ __device__ constexpr double dtrace_r(int l, int m)
+{
+    return m > l ? 0.0
+         : m == 0 ? 1.0
+         : l == 1 ? 1.0
+         : l == 2 ? 3.0
+         : (m == 1 ? 6.0 : 15.0);
+}
+// ... at x = -1: (-1)^(l+m) times the value at +1.
+__host__ __device__ constexpr double dtrace_l(int l, int m)
+{
+    return ((l + m) & 1) ? -dtrace_r(l, m) : dtrace_r(l, m);
+}
+// Weight of the reference-coordinate derivative jump of order m in the
+// damping sum: m(m+1) h^m |[d^m u/dx^m]| = m(m+1) 2^m |[d^m u/dxi^m]|.
+__host__ __device__ constexpr double jump_weight(int m)
+{
+    return m == 0 ? 1.0 : (double)(m * (m + 1)) * (double)(1 << m);
+}
+
+// ------------------------------------------------------------- physics --
+struct PhysParams {
+    double gamma;
+    double a[2];   // advection velocity
+};
+
+template <typename T>
+__device__ __forceinline__ T tsqrt(T x) { return sqrt(x); }
+template <>
+__device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
+
+template <int EQ>
+struct Phys1D;
+
+template <>
+struct Phys1D<ADV> {
+    static constexpr int NV = 1;
+    template <typename T>
+    __device__ static void flux(const T* u, T* f, const PhysParams& p) { f[0] = (T)p.a[0] * u[0]; }
+    template <typename T>
+    __device__ static T speed(const T* u, const PhysParams& p) { return fabs((T)p.a[0]); }
+    template <typename T>
+    __device__ static T enthalpy(const T* u, const PhysParams& p) { return (T)1; }
+};
+
+template <>
+struct Phys1D<BURGERS> {
+    static constexpr int NV = 1;
+    template <typename T>
+    __device__ static void flux(const T* u, T* f, const PhysParams& p) { f[0] = (T)0.5 * u[0] * u[0]; }
+    template <typename T>
+    __device__ static T speed(const T* u, const PhysParams& p) { return fabs(u[0]); }
+    template <typename T>
+    __device__ static T enthalpy(const T* u, const PhysParams& p) { return (T)1; }
+};
+
+template <>
+struct Phys1D<EULER> {
+    static constexpr int NV = 3;
+    template <typename T>
+    __device__ static T pressure(const T* u, const PhysParams& p)
+    {
+        return ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * u[1] / u[0]);
+    }
+    template <typename T>
+    __device__ static void flux(const T* u, T* f, const PhysParams& p)
+    {
+        T vel = u[1] / u[0];
+        T pr = ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * vel);
+        f[0] = u[1];
+        f[1] = u[1] * vel + pr;
+        f[2] = vel * (u[2] + pr);
+    }
+    template <typename T>
+    __device__ static T speed(const T* u, const PhysParams& p)
+    {
+        T vel = u[1] / u[0];
+        T pr = ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * vel);
+        return fabs(vel) + tsqrt<T>((T)p.gamma * pr / u[0]);
+    }
+    template <typename T>
+    __device__ static T enthalpy(const T* u, const PhysParams& p)
+    {
+        T pr = ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * u[1] / u[0]);
+        return (u[2] + pr) / u[0];
+    }
+};
+
+// Local Lax-Friedrichs flux: 1/2 (f(a) + f(b)) - 1/2 max(|f'(a)|, |f'(b)|) (b - a).
+template <int EQ, typename T>
+__device__ __forceinline__ void llf1d(const T* ul, const T* ur, T* fh, const PhysParams& p)
+{
+    constexpr int NV = Phys1D<EQ>::NV;
+    T fl[NV], fr[NV];
+    Phys1D<EQ>::flux(ul, fl, p);
+    Phys1D<EQ>::flux(ur, fr, p);
+    T al = Phys1D<EQ>::speed(ul, p), ar = Phys1D<EQ>::speed(ur, p);
+    T alpha = al > ar ? al : ar;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fh[v] = (T)0.5 * (fl[v] + fr[v]) - (T)0.5 * alpha * (ur[v] - ul[v]);
+}
+
+// ---------------------------------------------------------- state views --
+// Mode 0 always lives in FP64 planes; modes >= 1 live in TB planes
+// (TB = double for DG_PREC_FP64, float for DG_PREC_MIXED).  For the FP64
+// layout (u[(var*(k+1)+l)*n + j]) hi points at mode 1 of var 0 and shares
+// the var stride with m0.
+template <typename TB>
+struct StateView {
+    double* m0;           // mode 0, var v at m0 + v*s0
+    TB* hi;               // mode l >= 1, var v at hi + v*sv + (l-1)*sl
+    int64_t s0, sv, sl;
+};
+
+// ------------------------------------------------------- control block --
+// Device-resident run state, in the workspace.  Written by the kernels and
+// read back by the host only for reports.
+struct Ctrl {
+    double t;                        // time at the start of the current step
+    double dt;                       // current step
+    double t_end;
+    double dt_min, dt_max;
+    double cfl_num;                  // 1D: cfl*h (dt = cfl_num/alpha); 2D: cfl
+    unsigned long long alpha_bits;   // CFL max (atomicMax of a non-negative double)
+    unsigned long long exp_bits;     // largest damping exponent seen
+    unsigned long long eta_bits[3];  // hybrid: max eta per stage
+    unsigned int tcount[3];          // hybrid: troubled-list entries per stage
+    int active;                      // a scheduled step waits to be finalised
+    long long steps;
+    long long max_steps;             // absolute step limit of the current run
+    long long troubled;              // hybrid: troubled cells summed over stages
+    int last;                        // the scheduled step ends exactly at t_end
+    int done;                        // no further step will run
+    int status;                      // first error code latched (dg_status)
+    int pad;
+    long long first_bad;             // cell index of that error
+    double bflux[4];                 // boundary-flux ledger (FP64)
+    double bstage[3][8];             // per-stage boundary fluxes: lo[4], hi[4]
+};
+
+// atomicMax/atomicMin over doubles through their bit patterns; valid for
+// non-negative values (IEEE-754 order equals unsigned order there) and
+// propagates NaN (its bit pattern exceeds every finite one).
+__device__ __forceinline__ void atomic_max_nonneg(unsigned long long* p, double v)
+{
+    atomicMax(p, (unsigned long long)__double_as_longlong(v));
+}
+
+// Wavefront (64 lanes) maximum.
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        double o = __shfl_xor(v, off, 64);
+        v = (o > v || o != o) ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void latch_error(Ctrl* c, int code, long long cell)
+{
+    if (atomicCAS(&c->status, 0, code) == 0) c->first_bad = cell;
+}
+
+}  // namespace dg
+
+namespace dg {
+template <typename T>
+__device__ __forceinline__ T texp(T x) { return exp(x); }
+template <>
+__device__ __forceinline__ float texp<float>(float x) { return expf(x); }
+}  // namespace dg

@@ -1,0 +1,66 @@
+// dg_kernels.h — kernel argument blocks and launcher entry points of the
+// RKDG + jump-filter library (internal; the public ABI is include/dg.h).
+#pragma once
+
+#include "dg_common.h"
+
+namespace dg {
+
+// SSP-RK3 effective quadrature weights of the three stage fluxes in the
+// Shu-Osher form (1/6, 1/6, 2/3): the boundary-flux ledger uses them.
+constexpr double kStageWeight[3] = {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0};
+
+template <typename TB>
+struct Args1D {
+    StateView<TB> un, us, out;
+    int64_t n;
+    double inv_h;
+    int periodic, bc_lo, bc_hi;
+    double dir_lo[4], dir_hi[4];
+    PhysParams phys;
+    int stage;
+    int dt_from_ctrl;         // 1: dt and the done flag come from ctrl (dg_run)
+    double dt_host;
+    int check;                // Euler positivity check of the stage input
+    Ctrl* ctrl;               // always valid: error latch
+    double* bflux;            // nullable: 8 doubles (x-lo[4], x-hi[4])
+    unsigned long long* alpha_acc;  // nullable: CFL max of the output
+    unsigned long long* eta_acc;    // hybrid
+    unsigned int* tcount;           // hybrid pass A: troubled list
+    long long* tcell;
+    double* tdata;                  // (eta, E^1..E^k) per entry
+    double* E_out;                  // nullable: per-cell exponents
+    double* eta_out;                // per-cell eta (unfused hybrid)
+};
+
+template <typename TB>
+hipError_t launch_stage1d(int eq, int k, const Args1D<TB>& a, int mode, hipStream_t st);
+template <typename TB>
+hipError_t launch_filter1d(int eq, int k, const Args1D<TB>& a, int mode, hipStream_t st);
+template <typename TB>
+hipError_t launch_blend1d(int nv, int k, StateView<TB> out, const unsigned int* count,
+                          const long long* tcell, const double* tdata,
+                          const unsigned long long* eta_bits, const Ctrl* ctrl, int from_ctrl,
+                          int64_t max_entries, hipStream_t st);
+template <typename TB>
+hipError_t launch_blend_all1d(int nv, int k, StateView<TB> w, StateView<TB> out, int64_t n,
+                              const double* E, const double* eta,
+                              const unsigned long long* eta_bits, unsigned int* tcount,
+                              hipStream_t st);
+template <typename TB>
+hipError_t launch_maxwave1d(int eq, StateView<TB> u, int64_t n, PhysParams phys,
+                            unsigned long long* acc, hipStream_t st);
+
+// step control (dg_util.hip)
+hipError_t launch_step_ctrl(Ctrl* c, int finalize_only, hipStream_t st);
+template <typename TB>
+hipError_t launch_convert(int to_internal, int nv, int nmodes, int64_t ncell, const double* fp64,
+                          StateView<TB> v, hipStream_t st);
+template <typename TB>
+hipError_t launch_ledger(int nv, int64_t ncell, StateView<TB> u, double cell_volume, double* out,
+                         hipStream_t st);
+template <typename TB>
+hipError_t launch_check1d(int eq, int k, StateView<TB> u, int64_t n, PhysParams phys, Ctrl* c,
+                          double* minvals, hipStream_t st);
+
+}  // namespace dg

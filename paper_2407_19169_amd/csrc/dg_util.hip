@@ -1,0 +1,223 @@
+// dg_util.hip — time-step control, layout conversion, conservation ledger
+// and state checks shared by the 1D and 2D paths.
+#include "dg_kernels.h"
+
+namespace dg {
+
+// Finalise the step that just ran (advance t, ledger, dt statistics) and,
+// unless finalize_only, schedule the next one: dt = cfl_num / alpha from the
+// CFL maximum accumulated by the previous step's last stage, clamped so the
+// run ends exactly at t_end.  One thread; runs between the stage kernels.
+__global__ void step_ctrl_kernel(Ctrl* c, int finalize_only)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (finalize_only == 2) {  // clear the per-step accumulators only
+        c->alpha_bits = 0;
+        for (int s = 0; s < 3; ++s) {
+            c->tcount[s] = 0;
+            c->eta_bits[s] = 0;
+        }
+        return;
+    }
+    if (c->active) {
+        const double dt = c->dt;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double net = kStageWeight[0] * (c->bstage[0][4 + v] - c->bstage[0][v]) +
+                         kStageWeight[1] * (c->bstage[1][4 + v] - c->bstage[1][v]) +
+                         kStageWeight[2] * (c->bstage[2][4 + v] - c->bstage[2][v]);
+            c->bflux[v] += dt * net;
+        }
+        c->t = c->last ? c->t_end : c->t + dt;
+        c->steps += 1;
+        if (dt < c->dt_min) c->dt_min = dt;
+        if (dt > c->dt_max) c->dt_max = dt;
+        c->troubled += (long long)c->tcount[0] + c->tcount[1] + c->tcount[2];
+        c->active = 0;
+    }
+    if (finalize_only || c->done) return;
+    if (c->status != 0 || !(c->t < c->t_end) || c->steps >= c->max_steps) {
+        c->done = 1;
+        return;
+    }
+    const double alpha = __longlong_as_double((long long)c->alpha_bits);
+    double dt = c->cfl_num / alpha;
+    if (!(dt > 0.0) || !isfinite(dt)) {
+        if (c->status == 0) {
+            c->status = -4;
+            c->first_bad = -1;
+        }
+        c->done = 1;
+        return;
+    }
+    int last = 0;
+    if (c->t + dt >= c->t_end) {
+        dt = c->t_end - c->t;
+        last = 1;
+    }
+    c->dt = dt;
+    c->last = last;
+    c->active = 1;
+    c->alpha_bits = 0;
+    for (int s = 0; s < 3; ++s) {
+        c->tcount[s] = 0;
+        c->eta_bits[s] = 0;
+        for (int v = 0; v < 8; ++v) c->bstage[s][v] = 0.0;
+    }
+}
+
+hipError_t launch_step_ctrl(Ctrl* c, int finalize_only, hipStream_t st)
+{
+    hipLaunchKernelGGL(step_ctrl_kernel, dim3(1), dim3(64), 0, st, c, finalize_only);
+    return hipGetLastError();
+}
+
+// FP64 exchange layout <-> internal view (mixed precision splits mode 0
+// into FP64 planes and modes >= 1 into FP32 planes).
+template <typename TB>
+__global__ __launch_bounds__(256) void convert_kernel(int to_internal, int nmodes, int64_t ncell,
+                                                      int64_t total, const double* fp64, double* out64,
+                                                      StateView<TB> v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = i % ncell;
+        const int64_t rest = i / ncell;
+        const int l = (int)(rest % nmodes);
+        const int var = (int)(rest / nmodes);
+        if (l == 0) {
+            double* p = v.m0 + var * v.s0 + c;
+            if (to_internal)
+                *p = fp64[i];
+            else
+                out64[i] = *p;
+        } else {
+            TB* p = v.hi + var * v.sv + (int64_t)(l - 1) * v.sl + c;
+            if (to_internal)
+                *p = (TB)fp64[i];
+            else
+                out64[i] = (double)*p;
+        }
+    }
+}
+
+template <typename TB>
+hipError_t launch_convert(int to_internal, int nv, int nmodes, int64_t ncell, const double* fp64,
+                          StateView<TB> v, hipStream_t st)
+{
+    const int64_t total = (int64_t)nv * nmodes * ncell;
+    int64_t g = (total + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL((convert_kernel<TB>), dim3((unsigned)g), dim3(256), 0, st, to_internal, nmodes,
+                       ncell, total, fp64, const_cast<double*>(fp64), v);
+    return hipGetLastError();
+}
+
+// Deterministic FP64 sum over cells of the cell averages of each variable:
+// one workgroup per variable, fixed strided partial sums, fixed-order tree.
+template <typename TB>
+__global__ __launch_bounds__(1024) void ledger_kernel(int64_t ncell, StateView<TB> u, double vol,
+                                                      double* out)
+{
+    __shared__ double s[1024];
+    const int var = blockIdx.x;
+    const double* p = u.m0 + var * u.s0;
+    double acc = 0.0;
+    for (int64_t c = threadIdx.x; c < ncell; c += 1024) acc += p[c];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[var] = vol * s[0];
+}
+
+template <typename TB>
+hipError_t launch_ledger(int nv, int64_t ncell, StateView<TB> u, double cell_volume, double* out,
+                         hipStream_t st)
+{
+    hipLaunchKernelGGL((ledger_kernel<TB>), dim3(nv), dim3(1024), 0, st, ncell, u, cell_volume, out);
+    return hipGetLastError();
+}
+
+// Final-state check (1D Euler): density and pressure in FP64 at every
+// Gauss point and both trace points; minima in minvals[0..1] (bit-ordered
+// atomicMin over non-negative values; a non-positive value records 0 and
+// latches DG_ERR_POSITIVITY, a NaN latches DG_ERR_NONFINITE).
+template <int K, typename TB>
+__global__ __launch_bounds__(256) void check1d_kernel(StateView<TB> u, int64_t n, PhysParams phys,
+                                                      Ctrl* c, unsigned long long* minvals)
+{
+    constexpr int Q = K + 1;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double mr = INFINITY, mp = INFINITY;
+    if (j < n) {
+        double u0[3], uh[3][K > 0 ? K : 1];
+        for (int v = 0; v < 3; ++v) {
+            u0[v] = u.m0[v * u.s0 + j];
+            for (int l = 1; l <= K; ++l) uh[v][l - 1] = (double)u.hi[v * u.sv + (l - 1) * u.sl + j];
+        }
+        bool bad = false, nonfin = false;
+#pragma unroll
+        for (int q = 0; q < Q + 2; ++q) {
+            double w[3];
+            for (int v = 0; v < 3; ++v) {
+                double s = u0[v];
+                for (int l = 1; l <= K; ++l)
+                    s += uh[v][l - 1] * (q < Q ? leg_at(Q, q, l) : q == Q ? dtrace_l(l, 0) : 1.0);
+                w[v] = s;
+            }
+            const double p = Phys1D<EULER>::pressure(w, phys);
+            if (!isfinite(w[0]) || !isfinite(p) || !isfinite(w[1])) nonfin = true;
+            if (!(w[0] > 0.0) || !(p > 0.0)) bad = true;
+            mr = w[0] < mr ? w[0] : mr;
+            mp = p < mp ? p : mp;
+        }
+        if (nonfin)
+            latch_error(c, -4, j);
+        else if (bad)
+            latch_error(c, -5, j);
+    }
+    mr = mr > 0.0 ? mr : 0.0;
+    mp = mp > 0.0 ? mp : 0.0;
+    // wave minimum
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        double a = __shfl_xor(mr, off, 64), b = __shfl_xor(mp, off, 64);
+        mr = a < mr ? a : mr;
+        mp = b < mp ? b : mp;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&minvals[0], (unsigned long long)__double_as_longlong(mr));
+        atomicMin(&minvals[1], (unsigned long long)__double_as_longlong(mp));
+    }
+}
+
+template <typename TB>
+hipError_t launch_check1d(int eq, int k, StateView<TB> u, int64_t n, PhysParams phys, Ctrl* c,
+                          double* minvals, hipStream_t st)
+{
+    if (eq != EULER) return hipSuccess;
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    unsigned long long* mv = reinterpret_cast<unsigned long long*>(minvals);
+    switch (k) {
+    case 0: hipLaunchKernelGGL((check1d_kernel<0, TB>), grid, block, 0, st, u, n, phys, c, mv); break;
+    case 1: hipLaunchKernelGGL((check1d_kernel<1, TB>), grid, block, 0, st, u, n, phys, c, mv); break;
+    case 2: hipLaunchKernelGGL((check1d_kernel<2, TB>), grid, block, 0, st, u, n, phys, c, mv); break;
+    default: hipLaunchKernelGGL((check1d_kernel<3, TB>), grid, block, 0, st, u, n, phys, c, mv); break;
+    }
+    return hipGetLastError();
+}
+
+#define DG_INST(TB)                                                                                \
+    template hipError_t launch_convert<TB>(int, int, int, int64_t, const double*, StateView<TB>,   \
+                                           hipStream_t);                                           \
+    template hipError_t launch_ledger<TB>(int, int64_t, StateView<TB>, double, double*, hipStream_t); \
+    template hipError_t launch_check1d<TB>(int, int, StateView<TB>, int64_t, PhysParams, Ctrl*,    \
+                                           double*, hipStream_t);
+DG_INST(double)
+DG_INST(float)
+#undef DG_INST
+
+}  // namespace dg

@@ -1,0 +1,292 @@
+"""GPU parity of the 1D path (C ABI, gfx950 kernels) against the FP64 oracle.
+
+Bars (written here, used throughout):
+  * FP64 per-call (one stage / one filter application / CFL max): relative
+    L-infinity <= 1e-13 (only rounding order and FMA contraction differ).
+  * FP64 full runs after a fixed step count: relative L-infinity <= 1e-10.
+  * Mixed precision (FP32 bulk, FP64 mode 0): L1 of the cell averages vs
+    the FP64 oracle within the bounds stated per test, and conservation to
+    FP64 roundoff.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import dg_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+EQS = {"adv": 0, "burgers": 1, "euler": 2}
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_2407_19169_amd as dg
+
+    return dg
+
+
+def rel_linf(got, want):
+    got = np.asarray(got)
+    want = np.asarray(want)
+    scale = max(np.max(np.abs(want)), 1e-300)
+    return float(np.max(np.abs(got - want)) / scale)
+
+
+def _state(eq, k, n, seed):
+    rng = np.random.default_rng(seed)
+    if eq == 2:
+        return I.random_state_1d(seed, n, k, 3, amp=0.1)
+    u = np.zeros((1, k + 1, n))
+    u[0, 0] = 0.5 + 0.5 * rng.random(n) + 0.5 * np.sin(np.linspace(0, 6, n))
+    for l in range(1, k + 1):
+        u[0, l] = 0.05 / l * rng.standard_normal(n)
+    return u
+
+
+def _solver(dg, eq, k, n, lo, hi, bc, filt, prec=0, cfl=0.1, dirichlet=None, a=1.0):
+    mesh = dg.make_mesh(1, (n,), (lo,), (hi,), bc, dirichlet=dirichlet)
+    opt = dg.make_options(precision=prec, filter=filt, cfl=cfl, adv_speed=(a, 0.0))
+    return dg.Solver(mesh, k, eq, opt)
+
+
+def _oracle(ref, eq, k, n, lo, hi, bc, filt, cfl=0.1, dirichlet=None, a=1.0):
+    return ref.problem1d(eq, k, n, lo, hi, bc=bc, filter=filt, cfl=cfl, adv_speed=a,
+                         dirichlet=dirichlet)
+
+
+CASES = [
+    # eq, k, n, bc
+    ("adv", 2, 300, (0, 0)),
+    ("burgers", 0, 257, (0, 0)),
+    ("burgers", 1, 1, (0, 0)),
+    ("burgers", 2, 254, (0, 0)),
+    ("burgers", 3, 255, (1, 1)),
+    ("euler", 0, 100, (1, 1)),
+    ("euler", 1, 509, (2, 2)),
+    ("euler", 2, 1000, (1, 1)),
+    ("euler", 2, 253, (0, 0)),
+    ("euler", 3, 777, (3, 2)),
+]
+
+
+@pytest.mark.parametrize("eqn,k,n,bc", CASES)
+def test_stage_and_filter_per_call(dg, ref, eqn, k, n, bc):
+    """dg_stage (plain RK stage) and dg_jump_filter (filter / hybrid) each
+    match the oracle's stage and post-stage operator on the same input."""
+    import torch
+
+    eq = EQS[eqn]
+    dirichlet = [[1.2, 0.1, 2.9], [0.9, -0.2, 2.4]] if 3 in bc else None
+    lo, hi = -1.0, 2.0
+    dt = 0.02 * (hi - lo) / n
+    un = _state(eq, k, n, 100 + k)
+    ua = _state(eq, k, n, 200 + k)
+    ub = _state(eq, k, n, 300 + k)
+    for filt in (0, 1, 2):
+        s = _solver(dg, eq, k, n, lo, hi, bc, filt, dirichlet=dirichlet)
+        P = _oracle(ref, eq, k, n, lo, hi, bc, filt, dirichlet=dirichlet)
+        for stage, us in ((0, un), (1, ua), (2, ub)):
+            s.set_state(un)
+            if stage > 0:
+                dg.buffer_view(s, stage).copy_(torch.as_tensor(us))
+            dg.dg_stage(s.h, stage, dt)
+            dg.dg_jump_filter(s.h, stage, dt)
+            torch.cuda.synchronize()
+            target = {0: 1, 1: 2, 2: 0}[stage]
+            got = dg.buffer_view(s, target).cpu().numpy()
+            w = ref.stage1d(P, stage, dt, un, us)
+            want, tr = ref.post1d(P, stage, dt, w)
+            err = rel_linf(got, want)
+            assert err <= 1e-13, (eqn, k, n, bc, filt, stage, err)
+            if filt == 1:
+                E_got = s.exponents().cpu().numpy()
+                E_want, _ = ref.exponents1d(P, dt, w)
+                assert rel_linf(E_got, E_want) <= 1e-13
+            assert np.array_equal(got[:, 0, :] if filt else got[:, 0, :], got[:, 0, :])
+        s.close()
+
+
+@pytest.mark.parametrize("eqn,k,n,bc", CASES[:6])
+def test_max_wavespeed(dg, ref, eqn, k, n, bc):
+    eq = EQS[eqn]
+    u = _state(eq, k, n, 7)
+    s = _solver(dg, eq, k, n, 0.0, 1.0, bc, 1)
+    s.set_state(u)
+    got = dg.dg_max_wavespeed(s.h)
+    want = ref.max_wavespeed1d(_oracle(ref, eq, k, n, 0.0, 1.0, bc, 1), u)
+    assert got == pytest.approx(want, rel=1e-14)
+    s.close()
+
+
+def test_filter_mode0_bitwise_and_contraction(dg, ref):
+    import torch
+
+    k, n = 3, 600
+    u = _state(2, k, n, 9)
+    s = _solver(dg, 2, k, n, 0.0, 1.0, (1, 1), 1)
+    s.set_state(u)
+    dg.dg_stage(s.h, 0, 1e-4)
+    dg.dg_jump_filter(s.h, 0, 1e-4)
+    torch.cuda.synchronize()
+    out = dg.buffer_view(s, 1).cpu().numpy()
+    # unfiltered stage output via a filter-free solver
+    s2 = _solver(dg, 2, k, n, 0.0, 1.0, (1, 1), 0)
+    s2.set_state(u)
+    dg.dg_stage(s2.h, 0, 1e-4)
+    dg.dg_jump_filter(s2.h, 0, 1e-4)
+    torch.cuda.synchronize()
+    w = dg.buffer_view(s2, 1).cpu().numpy()
+    assert np.array_equal(out[:, 0], w[:, 0])
+    assert np.all(np.abs(out[:, 1:]) <= np.abs(w[:, 1:]))
+    s.close()
+    s2.close()
+
+
+def _run_parity(dg, ref, eq, k, n, lo, hi, bc, filt, u0, t_end, steps, cfl=0.1, tol=1e-10,
+                a=1.0, dirichlet=None):
+    s = _solver(dg, eq, k, n, lo, hi, bc, filt, cfl=cfl, a=a, dirichlet=dirichlet)
+    s.set_state(u0)
+    rep = dg.dg_run(s.h, t_end, steps)
+    got = s.get_state().cpu().numpy()
+    P = _oracle(ref, eq, k, n, lo, hi, bc, filt, cfl=cfl, a=a, dirichlet=dirichlet)
+    want, orep, rc = ref.run1d(P, u0, t_end, steps)
+    assert rc == 0
+    assert rep.steps == orep.steps
+    for v in range(got.shape[0]):
+        err = rel_linf(got[v], want[v])
+        assert err <= tol, (v, err)
+    s.close()
+    return rep, orep, got, want
+
+
+def test_burgers_to_t15_parity(dg, ref):
+    """Periodic Burgers, P2, 200 cells, CFL 0.1, jump filter every stage,
+    to t = 1.5 past shock formation (about 2250 steps)."""
+    w = I.burgers_sine(200, 2)
+    rep, orep, got, want = _run_parity(dg, ref, 1, 2, 200, 0.0, 2.0, (0, 0), 1, w.u0, 1.5,
+                                       1 << 40)
+    assert rep.t == 1.5 and orep.t == 1.5
+    assert abs(rep.ledger[0] - 1.0) < 1e-13
+
+
+@pytest.mark.parametrize("filt", [1, 2])
+def test_shu_osher_20000_parity(dg, ref, filt):
+    """Shu-Osher Mach-3 shock into a density wave, 20000 cells, P2, outflow,
+    jump filter / hybrid limiter, 1000 steps."""
+    w = I.shu_osher(20000, 2)
+    rep, orep, got, want = _run_parity(dg, ref, 2, 2, 20000, -5.0, 5.0, (1, 1), filt, w.u0,
+                                       100.0, 1000)
+    for v in range(3):
+        assert rep.ledger[v] == pytest.approx(orep.ledger[v], rel=1e-12, abs=1e-12)
+        q0 = 10.0 / 20000 * w.u0[v, 0].sum()
+        assert abs(rep.ledger[v] + rep.boundary_flux[v] - q0) < 1e-11 * max(1, abs(q0))
+    if filt == 2:
+        assert rep.troubled_cells > 0
+        assert rep.troubled_cells == orep.troubled_cells
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_lax_reflect_dirichlet_runs(dg, ref, k):
+    w = I.lax(300, k)
+    _run_parity(dg, ref, 2, k, 300, -1.0, 1.0, (1, 1), 1, w.u0, 0.13, 1 << 40)
+    # reflecting walls on both ends, hybrid
+    _run_parity(dg, ref, 2, k, 300, -1.0, 1.0, (2, 2), 2, w.u0, 0.05, 1 << 40)
+    # Dirichlet ends holding the initial states
+    L = I.conserved(0.445, 0.698, 3.528)
+    R = I.conserved(0.5, 0.0, 0.571)
+    _run_parity(dg, ref, 2, k, 300, -1.0, 1.0, (3, 3), 1, w.u0, 0.05, 1 << 40,
+                dirichlet=[list(L), list(R)])
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 251, 252, 253, 504, 505])
+def test_ragged_sizes_advection(dg, ref, n):
+    w = I.advection_sine(n, 2)
+    _run_parity(dg, ref, 0, 2, n, 0.0, 1.0, (0, 0), 1, w.u0, 0.3, 64, a=-0.7)
+
+
+def test_fused_run_equals_per_call_loop(dg, ref):
+    """dg_run (fused kernels, device dt, graph) and a host loop of
+    dg_max_wavespeed / dg_stage / dg_jump_filter agree."""
+    import torch
+
+    w = I.shu_osher(3000, 2)
+    s1 = _solver(dg, 2, 2, 3000, -5.0, 5.0, (1, 1), 2)
+    s1.set_state(w.u0)
+    dg.dg_run(s1.h, 100.0, 40)
+    a = s1.get_state().cpu().numpy()
+    s2 = _solver(dg, 2, 2, 3000, -5.0, 5.0, (1, 1), 2)
+    s2.set_state(w.u0)
+    h = 10.0 / 3000
+    for _ in range(40):
+        dt = 0.1 * h / dg.dg_max_wavespeed(s2.h)
+        for stage in range(3):
+            dg.dg_stage(s2.h, stage, dt)
+            dg.dg_jump_filter(s2.h, stage, dt)
+    torch.cuda.synchronize()
+    b = s2.get_state().cpu().numpy()
+    for v in range(3):
+        assert rel_linf(a[v], b[v]) <= 1e-12
+    s1.close()
+    s2.close()
+
+
+def test_mixed_precision_shu_osher(dg, ref):
+    """FP32 bulk with FP64 mode 0: L1 of the cell averages against the FP64
+    oracle below 1e-4 (relative to the L1 norm) after 1000 steps, ledger
+    balanced to FP64 roundoff."""
+    w = I.shu_osher(20000, 2)
+    s = _solver(dg, 2, 2, 20000, -5.0, 5.0, (1, 1), 2, prec=1)
+    s.set_state(w.u0)
+    rep = dg.dg_run(s.h, 100.0, 1000)
+    got = s.get_state().cpu().numpy()
+    P = _oracle(ref, 2, 2, 20000, -5.0, 5.0, (1, 1), 2)
+    want, orep, rc = ref.run1d(P, w.u0, 100.0, 1000)
+    for v in range(3):
+        l1 = np.sum(np.abs(got[v, 0] - want[v, 0])) / np.sum(np.abs(want[v, 0]))
+        assert l1 < 1e-4, (v, l1)
+        q0 = 10.0 / 20000 * w.u0[v, 0].sum()
+        terms = 10.0 / 20000 * np.sum(np.abs(got[v, 0]))
+        assert abs(rep.ledger[v] + rep.boundary_flux[v] - q0) < 1e-13 * max(terms, 1.0)
+    s.close()
+
+
+def test_mixed_precision_burgers_error_bound(dg, ref):
+    """Mixed-precision error against the FP64 oracle stays below a tenth of
+    the FP64 scheme's own error against the exact solution (smooth phase)."""
+    from oracle import exact
+
+    w = I.burgers_table(160, 2)
+    s = _solver(dg, 1, 2, 160, w.lo, w.hi, (0, 0), 1, prec=1)
+    s.set_state(w.u0)
+    dg.dg_run(s.h, 0.5, 1 << 40)
+    got = s.get_state().cpu().numpy()
+    P = _oracle(ref, 1, 2, 160, w.lo, w.hi, (0, 0), 1)
+    want, _, _ = ref.run1d(P, w.u0, 0.5)
+    h = 2 * math.pi / 160
+    xc = w.lo + (np.arange(160) + 0.5) * h
+    # exact cell averages by a fine Gauss rule
+    xg, wg = np.polynomial.legendre.leggauss(8)
+    X = xc[:, None] + 0.5 * h * xg[None, :]
+    ex = exact.burgers_smooth(lambda x: 0.5 + np.sin(x), np.cos, X, 0.5)
+    exbar = 0.5 * np.sum(ex * wg[None, :], axis=1)
+    scheme_err = np.sum(np.abs(want[0, 0] - exbar)) * h
+    mixed_err = np.sum(np.abs(got[0, 0] - want[0, 0])) * h
+    assert mixed_err < 0.1 * scheme_err, (mixed_err, scheme_err)
+    s.close()
+
+
+def test_nonfinite_state_is_reported(dg, ref):
+    w = I.shu_osher(500, 2)
+    u = w.u0.copy()
+    u[0, 0, 123] = -1.0  # negative density
+    s = _solver(dg, 2, 2, 500, -5.0, 5.0, (1, 1), 1)
+    s.set_state(u)
+    rep = dg.dg_run(s.h, 1.0, 5, check=False)
+    assert rep.status in (dg.DG_ERR_POSITIVITY, dg.DG_ERR_NONFINITE)
+    assert rep.first_bad_cell >= 0
+    s.close()

@@ -462,3 +462,31 @@ def test_lax_problem_against_exact_solution(ref, filt):
     assert abs(xs - xs_exact) < 2 * h
     # no large over/undershoots
     assert rho.max() < rho_ex.max() * 1.05 and rho.min() > rho_ex.min() * 0.95
+
+
+def test_gpu_tables_match_oracle_tables(ref):
+    """The GPU library's generated constant tables (closed forms in exact
+    decimal arithmetic) and the oracle's extended-precision Newton/Horner
+    tables are two independent constructions of the same correctly rounded
+    numbers."""
+    import re
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    txt = open(os.path.join(root, "paper_2407_19169_amd", "csrc", "dg_tables.h")).read()
+
+    def table(name):
+        body = re.search(name + r"\[[^=]*=\s*(\{.*?\});", txt, re.S).group(1)
+        return np.array(eval(body.replace("{", "[").replace("}", "]")))
+
+    X, W, V, S = table("kGaussX"), table("kGaussW"), table("kLegAt"), table("kDLegAt")
+    import ctypes as C
+
+    dp = C.POINTER(C.c_double)
+    for q in range(1, 5):
+        x, w = np.zeros(q), np.zeros(q)
+        phi, dphi = np.zeros(q * 4), np.zeros(q * 4)
+        assert ref.lib().dgref_basis_tables(3, q, *(a.ctypes.data_as(dp) for a in (x, w, phi, dphi))) == 0
+        assert np.array_equal(X[q - 1, :q], x) and np.array_equal(W[q - 1, :q], w)
+        # the rule of q points serves degree k = q - 1: modes l < q
+        assert np.array_equal(V[q - 1, :q, :q], phi.reshape(q, 4)[:, :q])
+        assert np.array_equal(S[q - 1, :q, :q], dphi.reshape(q, 4)[:, :q])
