@@ -592,7 +592,7 @@ __global__ __launch_bounds__(256) void blend_all1d_kernel(StateView<TB> w, State
 // CFL reduction over the cell averages of u (FP64).
 template <int EQ, typename TB>
 __global__ __launch_bounds__(256) void maxwave1d_kernel(StateView<TB> u, int64_t n, PhysParams phys,
-                                                        unsigned long long* acc)
+                                                        unsigned long long* acc, Ctrl* err)
 {
     constexpr int NV = Phys1D<EQ>::NV;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -602,6 +602,12 @@ __global__ __launch_bounds__(256) void maxwave1d_kernel(StateView<TB> u, int64_t
 #pragma unroll
         for (int v = 0; v < NV; ++v) ub[v] = u.m0[v * u.s0 + c];
         lam = Phys1D<EQ>::speed(ub, phys);
+        if (EQ == EULER) {
+            const double p = Phys1D<EULER>::pressure(ub, phys);
+            if (!(ub[0] > 0.0) || !(p > 0.0))
+                latch_error(err, (isfinite(ub[0]) && isfinite(p)) ? -5 : -4, c);
+        }
+        if (!isfinite(lam)) latch_error(err, -4, c);
     }
     lam = wave_max(lam);
     if ((threadIdx.x & 63) == 0) atomic_max_nonneg(acc, lam);
@@ -699,15 +705,15 @@ hipError_t launch_blend_all1d(int nv, int k, StateView<TB> w, StateView<TB> out,
 
 template <typename TB>
 hipError_t launch_maxwave1d(int eq, StateView<TB> u, int64_t n, PhysParams phys,
-                            unsigned long long* acc, hipStream_t st)
+                            unsigned long long* acc, Ctrl* err, hipStream_t st)
 {
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
     if (eq == ADV)
-        hipLaunchKernelGGL((maxwave1d_kernel<ADV, TB>), grid, block, 0, st, u, n, phys, acc);
+        hipLaunchKernelGGL((maxwave1d_kernel<ADV, TB>), grid, block, 0, st, u, n, phys, acc, err);
     else if (eq == BURGERS)
-        hipLaunchKernelGGL((maxwave1d_kernel<BURGERS, TB>), grid, block, 0, st, u, n, phys, acc);
+        hipLaunchKernelGGL((maxwave1d_kernel<BURGERS, TB>), grid, block, 0, st, u, n, phys, acc, err);
     else
-        hipLaunchKernelGGL((maxwave1d_kernel<EULER, TB>), grid, block, 0, st, u, n, phys, acc);
+        hipLaunchKernelGGL((maxwave1d_kernel<EULER, TB>), grid, block, 0, st, u, n, phys, acc, err);
     return hipGetLastError();
 }
 
@@ -723,7 +729,7 @@ hipError_t launch_maxwave1d(int eq, StateView<TB> u, int64_t n, PhysParams phys,
                                                const unsigned long long*, unsigned int*,           \
                                                hipStream_t);                                       \
     template hipError_t launch_maxwave1d<TB>(int, StateView<TB>, int64_t, PhysParams,               \
-                                             unsigned long long*, hipStream_t);
+                                             unsigned long long*, Ctrl*, hipStream_t);
 DG_INST(double)
 DG_INST(float)
 #undef DG_INST

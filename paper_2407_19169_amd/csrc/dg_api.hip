@@ -143,7 +143,7 @@ template <typename TB>
 int maxwave_impl(dg_solver* s, unsigned long long* acc, hipStream_t st)
 {
     DG_HIP(launch_maxwave1d<TB>(s->eq, view_of<TB>(s, s->u[0]), s->ncell,
-                                base_args<TB>(s).phys, acc, st));
+                                base_args<TB>(s).phys, acc, ctrl_of(s), st));
     return DG_OK;
 }
 

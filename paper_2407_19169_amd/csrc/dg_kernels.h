@@ -49,7 +49,7 @@ hipError_t launch_blend_all1d(int nv, int k, StateView<TB> w, StateView<TB> out,
                               hipStream_t st);
 template <typename TB>
 hipError_t launch_maxwave1d(int eq, StateView<TB> u, int64_t n, PhysParams phys,
-                            unsigned long long* acc, hipStream_t st);
+                            unsigned long long* acc, Ctrl* err, hipStream_t st);
 
 // step control (dg_util.hip)
 hipError_t launch_step_ctrl(Ctrl* c, int finalize_only, hipStream_t st);
