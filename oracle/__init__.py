@@ -29,7 +29,8 @@ def build(force: bool = True) -> str:
     """Compile ``dgref.c`` with gcc into ``libdgref.so`` (FP64, OpenMP)."""
     if force or not os.path.exists(_LIB_PATH):
         cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC", "-shared",
-               "-o", _LIB_PATH + ".tmp", os.path.join(_HERE, "dgref.c"), "-lm"]
+               "-o", _LIB_PATH + ".tmp", os.path.join(_HERE, "dgref.c"),
+               os.path.join(_HERE, "dgref2d.c"), "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
     return _LIB_PATH
@@ -49,7 +50,8 @@ class Problem2D(C.Structure):
                 ("ny", C.c_int64), ("xlo", C.c_double), ("xhi", C.c_double),
                 ("ylo", C.c_double), ("yhi", C.c_double), ("gamma", C.c_double),
                 ("adv_speed", C.c_double * 2), ("cfl", C.c_double),
-                ("dirichlet", (C.c_double * 4) * 4)]
+                ("dirichlet", (C.c_double * 4) * 4), ("shock_x0", C.c_double),
+                ("shock_speed", C.c_double), ("post", C.c_double * 4), ("pre", C.c_double * 4)]
 
 
 class Report(C.Structure):
@@ -109,8 +111,12 @@ def problem1d(eq, k, n, lo, hi, bc=(PERIODIC, PERIODIC), filter=FILTER_JUMP, cfl
 
 def problem2d(eq, k, nx, ny, xlo, xhi, ylo, yhi, bc=(PERIODIC,) * 4, filter=FILTER_JUMP,
               cfl=0.1, gamma=1.4, adv_speed=(1.0, 1.0), nq=0, filter_dt=0,
-              dirichlet=None) -> Problem2D:
+              dirichlet=None, shock_x0=0.0, shock_speed=0.0, post=None, pre=None) -> Problem2D:
     P = Problem2D()
+    P.shock_x0, P.shock_speed = shock_x0, shock_speed
+    for v in range(4):
+        P.post[v] = float(post[v]) if post is not None else 0.0
+        P.pre[v] = float(pre[v]) if pre is not None else 0.0
     P.eq, P.k, P.nq, P.filter, P.filter_dt = eq, k, nq, filter, filter_dt
     for i in range(4):
         P.bc[i] = bc[i]
@@ -232,23 +238,31 @@ def stage2d(P: Problem2D, stage: int, dt: float, un: np.ndarray, us: np.ndarray 
     return out
 
 
-def exponents2d(P: Problem2D, dt: float, v: np.ndarray):
+def exponents2d(P: Problem2D, dt: float, v: np.ndarray, t: float = 0.0):
     v = np.ascontiguousarray(v, dtype=np.float64)
     nc = P.nx * P.ny
     E = np.empty(nc * (2 * P.k + 1))
     eta = np.empty(nc)
-    _chk(lib().dgref_exponents2d(C.byref(P), C.c_double(dt), _ptr(v), _ptr(E), _ptr(eta)),
-         "exponents2d")
+    _chk(lib().dgref_exponents2d(C.byref(P), C.c_double(t), C.c_double(dt), _ptr(v), _ptr(E),
+                                 _ptr(eta)), "exponents2d")
     return E.reshape(P.ny, P.nx, 2 * P.k + 1), eta.reshape(P.ny, P.nx)
 
 
-def post2d(P: Problem2D, stage: int, dt: float, v: np.ndarray):
+def post2d(P: Problem2D, stage: int, dt: float, v: np.ndarray, t: float = 0.0):
     v = np.ascontiguousarray(v, dtype=np.float64)
     out = np.empty_like(v)
     tr = C.c_int64(0)
-    _chk(lib().dgref_post2d(C.byref(P), stage, C.c_double(dt), _ptr(v), _ptr(out), C.byref(tr)),
-         "post2d")
+    _chk(lib().dgref_post2d(C.byref(P), stage, C.c_double(t), C.c_double(dt), _ptr(v), _ptr(out),
+                            C.byref(tr)), "post2d")
     return out, tr.value
+
+
+def check2d(P: Problem2D, u: np.ndarray):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    mr, mp = C.c_double(), C.c_double()
+    bad = C.c_int64()
+    rc = lib().dgref_check2d(C.byref(P), _ptr(u), C.byref(mr), C.byref(mp), C.byref(bad))
+    return rc, mr.value, mp.value, bad.value
 
 
 def step2d(P: Problem2D, dt: float, u: np.ndarray, t: float = 0.0):

@@ -10,6 +10,7 @@
  * Readings of points the paper leaves open are marked "Reading:".
  */
 #include "dgref.h"
+#include "dgref_internal.h"
 
 #include <math.h>
 #include <stdlib.h>
@@ -18,9 +19,6 @@
 #include <omp.h>
 #endif
 
-#define MAXK 4
-#define MAXQ 8
-#define MAXV 4
 
 /* ------------------------------------------------------------------------ */
 /* Legendre polynomials and Gauss–Legendre quadrature                       */
@@ -108,15 +106,7 @@ int dgref_gauss(int q, double* x, double* w)
     return DGREF_OK;
 }
 
-typedef struct {
-    int k, nq;
-    double xq[MAXQ], wq[MAXQ];
-    double phi[MAXQ][MAXK + 1];       /* P_l(xi_q)                         */
-    double dphi[MAXQ][MAXK + 1];      /* P_l'(xi_q)                        */
-    double tr[2][MAXK + 1][MAXK + 1]; /* tr[side][l][m] = P_l^(m)(-1 / +1) */
-} basis;
-
-static int make_basis(int k, int nq, basis* B)
+int dgref_make_basis(int k, int nq, dgref_basis* B)
 {
     if (k < 0 || k > MAXK) return DGREF_ERR_ARG;
     if (nq == 0) nq = k + 1;
@@ -144,8 +134,8 @@ static int make_basis(int k, int nq, basis* B)
  * P_l, P_l' at the nodes (phi[q*(k+1)+l]). */
 int dgref_basis_tables(int k, int nq, double* x, double* w, double* phi, double* dphi)
 {
-    basis B;
-    int rc = make_basis(k, nq, &B);
+    dgref_basis B;
+    int rc = dgref_make_basis(k, nq, &B);
     if (rc) return rc;
     for (int q = 0; q < B.nq; ++q) {
         x[q] = B.xq[q];
@@ -251,7 +241,7 @@ static int check1d(const dgref_problem1d* P)
 
 /* m-th x-derivative of cell j's polynomial at its left (side 0) or right
  * (side 1) end: (2/h)^m sum_l u^l P_l^(m)(-1 / +1). */
-static void trace1d(const dgref_problem1d* P, const basis* B, const double* u, int64_t j,
+static void trace1d(const dgref_problem1d* P, const dgref_basis* B, const double* u, int64_t j,
                     int side, int m, double h, double* out)
 {
     const int K1 = P->k + 1;
@@ -289,7 +279,7 @@ static void ghost1d(const dgref_problem1d* P, int side, int m, const double* inn
 
 /* Left/right values of the m-th derivative at interface i (0..n), i.e. at
  * x_{i-1/2} between cells i-1 and i (0-based cells). */
-static void iface1d(const dgref_problem1d* P, const basis* B, const double* u, int64_t i,
+static void iface1d(const dgref_problem1d* P, const dgref_basis* B, const double* u, int64_t i,
                     int m, double h, double* left, double* right)
 {
     const int64_t n = P->n;
@@ -332,8 +322,8 @@ int dgref_residual1d(const dgref_problem1d* P, const double* u, double* L, doubl
 {
     int rc = check1d(P);
     if (rc) return rc;
-    basis B;
-    if ((rc = make_basis(P->k, P->nq, &B))) return rc;
+    dgref_basis B;
+    if ((rc = dgref_make_basis(P->k, P->nq, &B))) return rc;
     const int K1 = P->k + 1;
     const int64_t n = P->n;
     const int nv = dgref_nvars(P->eq, 1);
@@ -439,8 +429,8 @@ int dgref_exponents1d(const dgref_problem1d* P, double dt, const double* v, doub
 {
     int rc = check1d(P);
     if (rc) return rc;
-    basis B;
-    if ((rc = make_basis(P->k, P->nq, &B))) return rc;
+    dgref_basis B;
+    if ((rc = dgref_make_basis(P->k, P->nq, &B))) return rc;
     const int k = P->k;
     const int64_t n = P->n;
     const int nv = dgref_nvars(P->eq, 1);
@@ -624,8 +614,8 @@ int dgref_check1d(const dgref_problem1d* P, const double* u, double* min_rho, do
 {
     int rc = check1d(P);
     if (rc) return rc;
-    basis B;
-    if ((rc = make_basis(P->k, P->nq, &B))) return rc;
+    dgref_basis B;
+    if ((rc = dgref_make_basis(P->k, P->nq, &B))) return rc;
     const int K1 = P->k + 1;
     const int64_t n = P->n;
     const int nv = dgref_nvars(P->eq, 1);

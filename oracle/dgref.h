@@ -54,6 +54,11 @@ typedef struct {
     double adv_speed[2];
     double cfl;
     double dirichlet[4][4];
+    /* double-Mach-reflection boundaries: the shock line is
+     * x = shock_x0 + y / sqrt(3) + shock_speed * t; post/pre are the
+     * conserved states behind (left of) and ahead of it */
+    double shock_x0, shock_speed;
+    double post[4], pre[4];
 } dgref_problem2d;
 
 typedef struct {
@@ -102,10 +107,12 @@ int dgref_residual2d(const dgref_problem2d* P, double t, const double* u, double
 double dgref_max_wavespeed2d(const dgref_problem2d* P, const double* u);
 int dgref_stage2d(const dgref_problem2d* P, int stage, double t, double dt, const double* un,
                   const double* us, double* out);
-int dgref_exponents2d(const dgref_problem2d* P, double dt, const double* v, double* E,
+int dgref_exponents2d(const dgref_problem2d* P, double t, double dt, const double* v, double* E,
                       double* eta);
-int dgref_post2d(const dgref_problem2d* P, int stage, double dt, const double* v,
+int dgref_post2d(const dgref_problem2d* P, int stage, double t, double dt, const double* v,
                  double* out, int64_t* troubled);
+int dgref_check2d(const dgref_problem2d* P, const double* u, double* min_rho, double* min_p,
+                  int64_t* first_bad);
 int dgref_step2d(const dgref_problem2d* P, double t, double dt, double* u, int64_t* troubled);
 int dgref_run2d(const dgref_problem2d* P, double t_end, int64_t max_steps, double* u,
                 dgref_report* rep);

@@ -1,0 +1,264 @@
+"""Pins of the 2D (Q^k) oracle.
+
+The strongest pins reduce the 2D scheme to the separately pinned 1D oracle:
+for data that vary along one axis only, the 2D residual equals the 1D
+residual, the 2D hybrid indicator equals the 1D one, and the 2D damping
+exponent equals the 1D exponent times h_x^2/h_y (the 2D Euler coefficient
+of Sec. 2.4 carries h_x beta_x where the 1D one carries beta, and the 2D
+factor (2/h_x)(2/h_y) replaces (2/h)^2).  Further pins: free-stream
+preservation with every boundary type, conservation, mode 0 untouched,
+exponents depending on p+q only, zero jumps for global polynomials, the
+CFL maximum, and order k+1 on smooth solutions (advection and the
+isentropic vortex)."""
+import math
+
+import numpy as np
+import pytest
+
+import dg_inputs as I
+
+
+def _lift_x(u1, k, ny):
+    """1D Euler state along x -> 2D y-invariant state (rho, m, 0, E)."""
+    n = u1.shape[-1]
+    u2 = np.zeros((4, (k + 1) ** 2, ny, n))
+    for p in range(k + 1):
+        for v2, v1 in ((0, 0), (1, 1), (3, 2)):
+            u2[v2, p * (k + 1), :, :] = u1[v1, p]
+    return u2
+
+
+def _lift_y(u1, k, nx):
+    """1D Euler state along y -> 2D x-invariant state (rho, 0, m, E)."""
+    n = u1.shape[-1]
+    u2 = np.zeros((4, (k + 1) ** 2, n, nx))
+    for q in range(k + 1):
+        for v2, v1 in ((0, 0), (2, 1), (3, 2)):
+            u2[v2, q, :, :] = u1[v1, q][:, None]
+    return u2
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+@pytest.mark.parametrize("bc", [0, 1, 2])
+def test_reduces_to_1d_along_x(ref, k, bc):
+    n, ny = 13, 3
+    hx, hy = 1.0 / n, 0.3 / ny
+    u1 = I.random_state_1d(10 + k, n, k, 3, amp=0.2)
+    u2 = _lift_x(u1, k, ny)
+    P1 = ref.problem1d(2, k, n, 0.0, 1.0, bc=(bc, bc))
+    P2 = ref.problem2d(2, k, n, ny, 0.0, 1.0, 0.0, 0.3, bc=(bc, bc, 0, 0))
+    L1, _ = ref.residual1d(P1, u1)
+    L2 = ref.residual2d(P2, u2)
+    scale = np.max(np.abs(L1))
+    for v2, v1 in ((0, 0), (1, 1), (3, 2)):
+        got = L2[v2][[p * (k + 1) for p in range(k + 1)]]
+        assert np.max(np.abs(got - L1[v1][:, None, :])) <= 1e-13 * scale
+    assert np.max(np.abs(L2[2])) <= 1e-13 * scale
+    # every mode with q > 0 stays zero
+    for p in range(k + 1):
+        for q in range(1, k + 1):
+            assert np.max(np.abs(L2[:, p * (k + 1) + q])) <= 1e-13 * scale
+    if k == 0:
+        return
+    dt = 1e-3
+    E1, eta1 = ref.exponents1d(P1, dt, u1)
+    E2, eta2 = ref.exponents2d(P2, dt, u2)
+    np.testing.assert_allclose(eta2, np.broadcast_to(eta1, eta2.shape), rtol=1e-13, atol=1e-300)
+    want = E1 * hx * hx / hy
+    for jy in range(ny):
+        np.testing.assert_allclose(E2[jy, :, : k + 1], want, rtol=1e-12, atol=1e-300)
+        # modes p + q > k have only jumps of order <= k: same exponent as l = k
+        for l in range(k + 1, 2 * k + 1):
+            np.testing.assert_allclose(E2[jy, :, l], want[:, k], rtol=1e-12)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("bc", [1, 2])
+def test_reduces_to_1d_along_y(ref, k, bc):
+    n, nx = 11, 2
+    hx, hy = 0.5 / nx, 2.0 / n
+    u1 = I.random_state_1d(20 + k, n, k, 3, amp=0.2)
+    u2 = _lift_y(u1, k, nx)
+    P1 = ref.problem1d(2, k, n, -1.0, 1.0, bc=(bc, bc))
+    P2 = ref.problem2d(2, k, nx, n, 0.0, 0.5, -1.0, 1.0, bc=(0, 0, bc, bc))
+    L1, _ = ref.residual1d(P1, u1)
+    L2 = ref.residual2d(P2, u2)
+    scale = np.max(np.abs(L1))
+    for v2, v1 in ((0, 0), (2, 1), (3, 2)):
+        got = L2[v2][: k + 1]                       # modes (0, q)
+        assert np.max(np.abs(got - L1[v1][:, :, None])) <= 1e-13 * scale
+    dt = 1e-3
+    E1, eta1 = ref.exponents1d(P1, dt, u1)
+    E2, eta2 = ref.exponents2d(P2, dt, u2)
+    np.testing.assert_allclose(eta2, np.broadcast_to(eta1[:, None], eta2.shape), rtol=1e-13)
+    np.testing.assert_allclose(E2[:, 0, : k + 1], E1 * hy * hy / hx, rtol=1e-12, atol=1e-300)
+
+
+def test_advection_reduces_to_1d(ref):
+    n, k = 16, 2
+    u1 = np.random.default_rng(4).standard_normal((1, k + 1, n))
+    u2 = np.zeros((1, (k + 1) ** 2, 2, n))
+    for p in range(k + 1):
+        u2[0, p * (k + 1)] = u1[0, p]
+    P1 = ref.problem1d(0, k, n, 0.0, 1.0, adv_speed=0.7)
+    P2 = ref.problem2d(0, k, n, 2, 0.0, 1.0, 0.0, 1.0, adv_speed=(0.7, -0.3))
+    L1, _ = ref.residual1d(P1, u1)
+    L2 = ref.residual2d(P2, u2)
+    np.testing.assert_allclose(L2[0][[0, 3, 6]], np.broadcast_to(L1[0][:, None, :], (3, 2, n)),
+                               rtol=1e-13, atol=1e-12)
+
+
+@pytest.mark.parametrize("bcs", [(0, 0, 0, 0), (1, 1, 2, 2), (3, 1, 4, 5), (2, 2, 3, 3)])
+def test_free_stream_preserved(ref, bcs):
+    k = 2
+    state = I.conserved2d(1.3, 0.0, 0.0, 0.9) if 2 in bcs or 4 in bcs else I.conserved2d(1.3, 0.4, -0.2, 0.9)
+    u = np.zeros((4, 9, 5, 6))
+    u[:, 0] = state[:, None, None]
+    dir_ = [list(state)] * 4
+    P = ref.problem2d(2, k, 6, 5, 0.0, 1.0, 0.0, 1.0, bc=bcs, dirichlet=dir_, shock_x0=-10.0,
+                      shock_speed=0.0, post=state, pre=state)
+    L = ref.residual2d(P, u, t=0.1)
+    assert np.max(np.abs(L)) < 1e-13
+    E, eta = ref.exponents2d(P, 1e-2, u, t=0.1)
+    assert np.max(np.abs(E)) < 1e-13 and np.max(eta) < 1e-13
+
+
+def test_double_mach_boundaries_see_the_moving_shock(ref):
+    """With the exact oblique shock as data (post-shock behind the line
+    x = x0 + y/sqrt(3), pre-shock ahead) the top boundary states follow the
+    line at its position at time t: at t = 0 the residual of the top-row
+    cells away from the shock vanishes; at a later time the cells the shock
+    has passed at the top see the post-shock state through the boundary."""
+    w = I.double_mach(32, 8, 1)
+    post = I.conserved2d(*w.extra["post"])
+    pre = I.conserved2d(1.4, 0.0, 0.0, 1.0)
+    speed = w.extra["shock_speed"] / math.sin(math.pi / 3)
+    P = ref.problem2d(2, 1, 32, 8, 0.0, 4.0, 0.0, 1.0, bc=(3, 1, 4, 5), dirichlet=[list(post)] * 4,
+                      shock_x0=1.0 / 6.0, shock_speed=speed, post=post, pre=pre)
+    L = ref.residual2d(P, w.u0, t=0.0)
+    top = L[:, :, -1, :]
+    far = np.abs((np.arange(32) + 0.5) * 0.125 - (1 / 6 + 1 / math.sqrt(3))) > 0.4
+    assert np.max(np.abs(top[:, :, far])) < 1e-10 * np.max(np.abs(post))
+    # the same data at t = 0.05: the shock has moved right by speed*0.05 at
+    # the top; cells between the old and new position now see post-shock
+    # states through the top boundary: a nonzero residual appears there
+    L5 = ref.residual2d(P, w.u0, t=0.05)
+    x_old = 1 / 6 + 1 / math.sqrt(3)
+    x_new = x_old + speed * 0.05
+    xc = (np.arange(32) + 0.5) * 0.125
+    mid = (xc > x_old + 0.2) & (xc < x_new - 0.2)
+    assert np.min(np.max(np.abs(L5[0, 0, -1, mid]), axis=0)) > 1.0
+
+
+def test_filter_mode0_and_exponents_depend_on_l_only(ref):
+    k = 3
+    rng = np.random.default_rng(8)
+    u = np.zeros((4, 16, 6, 7))
+    u[:, 0] = I.conserved2d(1 + 0.3 * rng.random((6, 7)), rng.uniform(-0.5, 0.5, (6, 7)),
+                            rng.uniform(-0.5, 0.5, (6, 7)), 1 + rng.random((6, 7)))
+    u[:, 1:] = 0.05 * rng.standard_normal((4, 15, 6, 7))
+    P = ref.problem2d(2, k, 7, 6, 0.0, 1.0, 0.0, 1.0, bc=(0, 0, 0, 0), filter=1)
+    out, _ = ref.post2d(P, 0, 1e-4, u)
+    assert np.array_equal(out[:, 0], u[:, 0])
+    assert np.all(np.abs(out[:, 1:]) <= np.abs(u[:, 1:]))
+    # the factor applied to mode (p, q) depends on l = p + q only
+    ratio = out[0] / u[0]
+    for l in range(1, 2 * k + 1):
+        ms = [p * (k + 1) + (l - p) for p in range(k + 1) if 0 <= l - p <= k]
+        for m in ms[1:]:
+            np.testing.assert_allclose(ratio[m], ratio[ms[0]], rtol=1e-12)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_filter_identity_on_global_polynomial(ref, k):
+    coeff = np.random.default_rng(k).standard_normal((k + 1, k + 1)) * 0.1
+    f = lambda X, Y: 2.0 + np.polynomial.polynomial.polyval2d(X, Y, coeff)
+    u = I.project2d(f, k, 6, 5, -1.0, 1.0, 0.0, 2.0)
+    P = ref.problem2d(0, k, 6, 5, -1.0, 1.0, 0.0, 2.0, bc=(1, 1, 1, 1), adv_speed=(1.0, 0.5))
+    E, eta = ref.exponents2d(P, 1e-2, u)
+    assert np.max(np.abs(E)) < 1e-10 and np.max(eta) < 1e-10
+
+
+def test_hybrid_2d_weights(ref):
+    k = 2
+    rng = np.random.default_rng(2)
+    u = np.zeros((4, 9, 10, 10))
+    rho = np.where(np.arange(10)[None, :] < 5, 1.0, 2.0) * np.ones((10, 1))
+    u[:, 0] = I.conserved2d(rho, 0.1, 0.0, 1.0)
+    u[:, 1:] = 0.01 * rng.standard_normal((4, 8, 10, 10))
+    P = ref.problem2d(2, k, 10, 10, 0.0, 1.0, 0.0, 1.0, bc=(1, 1, 0, 0), filter=2)
+    dt = 1e-3
+    E, eta = ref.exponents2d(P, dt, u)
+    out, troubled = ref.post2d(P, 0, dt, u)
+    assert troubled == int(np.sum(eta > 1)) > 0
+    calm = eta <= 1
+    assert np.array_equal(out[:, :, calm], u[:, :, calm])
+    M = eta.max()
+    jy, ix = np.unravel_index(np.argmax(eta), eta.shape)
+    lvec = np.array([p + q for p in range(3) for q in range(3)])
+    np.testing.assert_allclose(out[0, :, jy, ix], np.exp(-E[jy, ix, lvec]) * u[0, :, jy, ix],
+                               rtol=1e-12)
+
+
+def test_max_wavespeed_2d_brute_force(ref):
+    rng = np.random.default_rng(1)
+    u = np.zeros((4, 4, 7, 9))
+    r, vx, vy, p = 0.5 + rng.random((7, 9)), rng.uniform(-1, 1, (7, 9)), rng.uniform(-1, 1, (7, 9)), 0.2 + rng.random((7, 9))
+    u[:, 0] = I.conserved2d(r, vx, vy, p)
+    P = ref.problem2d(2, 1, 9, 7, 0.0, 0.9, 0.0, 1.4)
+    c = np.sqrt(1.4 * p / r)
+    want = np.max((np.abs(vx) + c) / 0.1 + (np.abs(vy) + c) / 0.2)
+    assert ref.max_wavespeed2d(P, u) == pytest.approx(want, rel=1e-14)
+
+
+def test_conservation_2d_periodic(ref):
+    w = I.quadrant2d(12, 1, seed=3002)
+    P = ref.problem2d(2, 1, 12, 12, 0.0, 10.0, -5.0, 5.0, bc=(0, 0, 0, 0), filter=2, cfl=0.1)
+    u, rep, rc = ref.run2d(P, w.u0, 0.5)
+    assert rc == 0
+    h2 = (10.0 / 12) ** 2
+    for v in range(4):
+        q0 = h2 * w.u0[v, 0].sum()
+        assert abs(rep.ledger[v] - q0) < 1e-12 * max(1.0, abs(q0))
+
+
+def _advection_error(ref, n, k, T):
+    f = lambda X, Y: np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y) + 0.5
+    u0 = I.project2d(lambda X, Y: f(X, Y), k, n, n, 0.0, 1.0, 0.0, 1.0)
+    P = ref.problem2d(0, k, n, n, 0.0, 1.0, 0.0, 1.0, bc=(0, 0, 0, 0), filter=1, cfl=0.1,
+                      adv_speed=(1.0, 0.5))
+    u, rep, rc = ref.run2d(P, u0, T)
+    assert rc == 0
+    ex = I.project2d(lambda X, Y: f(X - T, Y - 0.5 * T), k, n, n, 0.0, 1.0, 0.0, 1.0)
+    h = 1.0 / n
+    # L2 norm of the modal difference (orthogonal basis, mass h^2/((2p+1)(2q+1)))
+    mass = np.array([h * h / ((2 * p + 1) * (2 * q + 1)) for p in range(k + 1) for q in range(k + 1)])
+    return math.sqrt(np.sum((u - ex) ** 2 * mass[None, :, None, None]))
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_advection_order_k_plus_1(ref, k):
+    e1 = _advection_error(ref, 8, k, 0.25)
+    e2 = _advection_error(ref, 16, k, 0.25)
+    e3 = _advection_error(ref, 32, k, 0.25)
+    assert math.log2(e2 / e3) > k + 1 - 0.4, (e1, e2, e3)
+
+
+@pytest.mark.slow
+def test_vortex_order_q2(ref):
+    """Isentropic vortex (Sec. 3.2, vortex accuracy test, beta = 5),
+    Q^2 with the jump filter: order approaches k+1 = 3 against the exact
+    solution."""
+    errs = []
+    T = 0.5
+    for n in (16, 32):
+        w = I.vortex2d(n, 2, seed=None)
+        P = ref.problem2d(2, 2, n, n, 0.0, 10.0, -5.0, 5.0, bc=(0, 0, 0, 0), filter=1, cfl=0.1)
+        u, rep, rc = ref.run2d(P, w.u0, T)
+        assert rc == 0
+        ex = I.project2d(lambda X, Y: I.vortex_exact(X, Y, T), 2, n, n, 0.0, 10.0, -5.0, 5.0,
+                         nquad=6)
+        h = 10.0 / n
+        mass = np.array([h * h / ((2 * p + 1) * (2 * q + 1)) for p in range(3) for q in range(3)])
+        errs.append(math.sqrt(np.sum((u[0] - ex[0]) ** 2 * mass[:, None, None])))
+    assert math.log2(errs[0] / errs[1]) > 2.4, errs
