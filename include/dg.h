@@ -55,12 +55,14 @@ typedef enum { DG_EQ_ADVECTION = 0, DG_EQ_BURGERS = 1, DG_EQ_EULER = 2 } dg_equa
 /* Boundary conditions (one per side).  PERIODIC must be set on both sides
  * of an axis.  OUTFLOW copies the interior trace (and its derivatives);
  * REFLECT mirrors it with the normal momentum negated (Euler only);
- * DIRICHLET imposes the constant conserved state mesh.dirichlet[side];
- * DMR_WALL (2D bottom, y-lo) is DIRICHLET with mesh.dirichlet[side] for
- * x < dmr_x0 and REFLECT beyond; DMR_TOP (2D top, y-hi) is the exact
- * moving Mach-10 shock of the double-Mach-reflection problem: post-shock
- * state mesh.dirichlet[side] behind the line x = dmr_x0 + (y + shock_speed
- * t)/sqrt(3), the DIRICHLET state of the x-hi side ahead of it. */
+ * DIRICHLET imposes the constant conserved state mesh.dirichlet[side]
+ * (inflow).  The two double-Mach-reflection boundaries (2D Euler, y sides)
+ * use the oblique shock line x = shock_x0 + y/sqrt(3) + shock_speed*t:
+ * DMR_WALL imposes mesh.post for x < shock_x0 and reflects beyond;
+ * DMR_TOP imposes mesh.post behind the line and mesh.pre ahead of it.
+ * Boundary states of the flux are taken at the RK stage times t, t+dt,
+ * t+dt/2; those of the filter's jumps at the time the stage output stands
+ * for, t+dt, t+dt/2, t+dt. */
 typedef enum {
     DG_BC_PERIODIC = 0,
     DG_BC_OUTFLOW = 1,
@@ -82,9 +84,10 @@ typedef struct {
     int64_t n[2];            /* cells along x (and y); uniform mesh               */
     double lo[2], hi[2];     /* domain [lo, hi] per axis                          */
     int bc[4];               /* dg_bc for x-lo, x-hi, y-lo, y-hi                  */
-    double dirichlet[4][4];  /* conserved state per side (DIRICHLET, DMR_*)       */
-    double dmr_x0;           /* DMR_* : shock foot on the wall                    */
-    double shock_speed;      /* DMR_TOP: shock speed along x of its foot * 2/sqrt3 */
+    double dirichlet[4][4];  /* conserved state per side (DIRICHLET)              */
+    double shock_x0;         /* DMR_*: foot of the shock on the wall at t = 0     */
+    double shock_speed;      /* DMR_*: speed of the shock line along x            */
+    double post[4], pre[4];  /* DMR_*: conserved states behind / ahead of it      */
 } dg_mesh;
 
 typedef struct {
@@ -171,11 +174,14 @@ int dg_report_read(dg_solver* s, dg_report* rep);
  * buffer of ncells*(Lmax+1) doubles. */
 int dg_last_exponents(dg_solver* s, double* E_dev);
 
-/* Measurement hook: launch the fused stage(+filter / hybrid pass A) kernel
- * that dg_run uses for `stage` (0..2) `reps` times on the solver's run
- * stream with time step dt, reading u_n (and u_a / u_b) and writing u_a or
- * u_b (u_n is not modified), and return its average duration in
- * microseconds from HIP events recorded around each launch.  Synchronises. */
+/* Measurement hook: launch a kernel of dg_run `reps` times on the solver's
+ * run stream with time step dt and return its average duration in
+ * microseconds from HIP events recorded around each launch.  1D: `stage`
+ * 0..2 selects the fused stage(+filter / hybrid pass A) kernel of that RK
+ * stage (reads u_n, u_a, u_b; writes u_a or u_b).  2D: 0..2 the residual
+ * kernel of that stage (writes the workspace), 3..5 the filter kernel
+ * (jump: workspace -> u_a) or hybrid pass A (reads u_a).  u_n is never
+ * modified.  Synchronises. */
 int dg_time_kernel(dg_solver* s, int stage, double dt, int reps, double* avg_us);
 
 const char* dg_strerror(int code);

@@ -32,8 +32,8 @@ DG_PREC_FP64, DG_PREC_MIXED = 0, 1
 class dg_mesh(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int64 * 2), ("lo", C.c_double * 2),
                 ("hi", C.c_double * 2), ("bc", C.c_int * 4),
-                ("dirichlet", (C.c_double * 4) * 4), ("dmr_x0", C.c_double),
-                ("shock_speed", C.c_double)]
+                ("dirichlet", (C.c_double * 4) * 4), ("shock_x0", C.c_double),
+                ("shock_speed", C.c_double), ("post", C.c_double * 4), ("pre", C.c_double * 4)]
 
 
 class dg_options(C.Structure):
@@ -115,8 +115,13 @@ def _ptr(t) -> int | None:
 
 
 # -------------------------------------------------- same-name functions --
-def make_mesh(dim, n, lo, hi, bc, dirichlet=None, dmr_x0=0.0, shock_speed=0.0) -> dg_mesh:
+def make_mesh(dim, n, lo, hi, bc, dirichlet=None, shock_x0=0.0, shock_speed=0.0, post=None,
+              pre=None) -> dg_mesh:
     m = dg_mesh()
+    m.shock_x0, m.shock_speed = shock_x0, shock_speed
+    for v in range(4):
+        m.post[v] = float(post[v]) if post is not None else 0.0
+        m.pre[v] = float(pre[v]) if pre is not None else 0.0
     m.dim = dim
     for d in range(dim):
         m.n[d], m.lo[d], m.hi[d] = int(n[d]), float(lo[d]), float(hi[d])
@@ -126,7 +131,6 @@ def make_mesh(dim, n, lo, hi, bc, dirichlet=None, dmr_x0=0.0, shock_speed=0.0) -
         for s, row in enumerate(dirichlet):
             for v, x in enumerate(row):
                 m.dirichlet[s][v] = float(x)
-    m.dmr_x0, m.shock_speed = dmr_x0, shock_speed
     return m
 
 

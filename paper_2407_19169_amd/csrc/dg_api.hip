@@ -96,8 +96,58 @@ Args1D<TB> base_args(const dg_solver* s)
 }
 
 template <typename TB>
+Args2D<TB> base_args2d(const dg_solver* s)
+{
+    Args2D<TB> a;
+    memset(&a, 0, sizeof a);
+    a.nx = s->mesh.n[0];
+    a.ny = s->mesh.n[1];
+    a.hx = s->h[0];
+    a.hy = s->h[1];
+    a.inv_hx = s->inv_h[0];
+    a.inv_hy = s->inv_h[1];
+    a.xlo = s->mesh.lo[0];
+    a.ylo = s->mesh.lo[1];
+    for (int i = 0; i < 4; ++i) {
+        a.bc[i] = s->mesh.bc[i];
+        for (int v = 0; v < 4; ++v) a.dir[i][v] = s->mesh.dirichlet[i][v];
+        a.post[i] = s->mesh.post[i];
+        a.pre[i] = s->mesh.pre[i];
+    }
+    a.shock_x0 = s->mesh.shock_x0;
+    a.shock_speed = s->mesh.shock_speed;
+    a.phys.gamma = s->opt.gamma;
+    a.phys.a[0] = s->opt.adv_speed[0];
+    a.phys.a[1] = s->opt.adv_speed[1];
+    a.check = s->eq == DG_EQ_EULER;
+    a.ctrl = ctrl_of(s);
+    a.tcap = s->ncell;
+    // jump weights of the multi-index (a1, a2), m = a1 + a2: hx (m = 0),
+    // m(m+1) hx^(m+1) (2/hx)^a1 (2/hy)^a2 (x edges); likewise with hy
+    for (int a1 = 0; a1 < 4; ++a1)
+        for (int a2 = 0; a2 < 4; ++a2) {
+            const int m = a1 + a2;
+            const double d = pow(2.0 / a.hx, a1) * pow(2.0 / a.hy, a2);
+            a.jsx[a1 * 4 + a2] = m == 0 ? a.hx : m * (m + 1.0) * pow(a.hx, m + 1) * d;
+            a.jsy[a1 * 4 + a2] = m == 0 ? a.hy : m * (m + 1.0) * pow(a.hy, m + 1) * d;
+        }
+    return a;
+}
+
+template <typename TB>
 int stage_impl(dg_solver* s, int stage, double dt)
 {
+    if (s->dim == 2) {
+        Args2D<TB> a = base_args2d<TB>(s);
+        a.un = view_of<TB>(s, s->u[0]);
+        a.us = view_of<TB>(s, s->u[stage]);
+        a.out = view_of<TB>(s, s->ws + s->off_w);
+        a.stage = stage;
+        a.dt_host = dt;
+        a.t_host = 0.0;
+        DG_HIP(launch_stage2d<TB>(s->eq, s->k, a, s->user_st));
+        return DG_OK;
+    }
     Args1D<TB> a = base_args<TB>(s);
     a.un = view_of<TB>(s, s->u[0]);
     a.us = view_of<TB>(s, s->u[stage]);
@@ -115,6 +165,38 @@ int filter_impl(dg_solver* s, int stage, double dt)
     if (s->opt.filter == DG_FILTER_NONE) {
         DG_HIP(hipMemcpyAsync(target, s->ws + s->off_w, s->state_bytes, hipMemcpyDeviceToDevice,
                               s->user_st));
+        return DG_OK;
+    }
+    if (s->dim == 2) {
+        Args2D<TB> a = base_args2d<TB>(s);
+        a.stage = stage;
+        a.dt_host = dt;
+        a.t_host = 0.0;
+        a.E_out = reinterpret_cast<double*>(s->ws + s->off_E);
+        if (s->opt.filter == DG_FILTER_JUMP) {
+            a.us = view_of<TB>(s, s->ws + s->off_w);
+            a.out = view_of<TB>(s, target);
+            DG_HIP(launch_filter2d<TB>(s->eq, s->k, a, 1, s->user_st));
+            return DG_OK;
+        }
+        // hybrid: the unfiltered output goes to the target, pass A records
+        // the troubled cells, pass B blends them in place
+        DG_HIP(hipMemcpyAsync(target, s->ws + s->off_w, s->state_bytes, hipMemcpyDeviceToDevice,
+                              s->user_st));
+        double* aux = aux_of(s);
+        unsigned long long* eta_bits = reinterpret_cast<unsigned long long*>(aux + 8);
+        unsigned int* tcount = reinterpret_cast<unsigned int*>(aux + 9);
+        DG_HIP(hipMemsetAsync(aux + 8, 0, 2 * sizeof(double), s->user_st));
+        a.us = view_of<TB>(s, target);
+        a.out = a.us;
+        a.eta_acc = eta_bits;
+        a.tcount = tcount;
+        a.tcell = reinterpret_cast<long long*>(s->ws + s->off_tcell);
+        a.tdata = reinterpret_cast<double*>(s->ws + s->off_tdata);
+        a.eta_out = reinterpret_cast<double*>(s->ws + s->off_eta);
+        DG_HIP(launch_filter2d<TB>(s->eq, s->k, a, 2, s->user_st));
+        DG_HIP(launch_blend2d<TB>(s->nv, s->k, a.out, s->ncell, tcount, a.tcell, a.tdata, eta_bits,
+                                  ctrl_of(s), 0, s->ncell, s->user_st));
         return DG_OK;
     }
     Args1D<TB> a = base_args<TB>(s);
@@ -142,6 +224,12 @@ int filter_impl(dg_solver* s, int stage, double dt)
 template <typename TB>
 int maxwave_impl(dg_solver* s, unsigned long long* acc, hipStream_t st)
 {
+    if (s->dim == 2) {
+        DG_HIP(launch_maxwave2d<TB>(s->eq, view_of<TB>(s, s->u[0]), s->mesh.n[0], s->mesh.n[1],
+                                    s->inv_h[0], s->inv_h[1], base_args2d<TB>(s).phys, acc,
+                                    ctrl_of(s), st));
+        return DG_OK;
+    }
     DG_HIP(launch_maxwave1d<TB>(s->eq, view_of<TB>(s, s->u[0]), s->ncell,
                                 base_args<TB>(s).phys, acc, ctrl_of(s), st));
     return DG_OK;
@@ -161,6 +249,43 @@ int record_steps(dg_solver* s, int G, hipStream_t st)
         void* B = (i % 2 == 0) ? s->u[1] : s->u[0];
         void* Cb = s->u[2];
         DG_HIP(launch_step_ctrl(c, 0, st));
+        if (s->dim == 2) {
+            for (int stage = 0; stage < 3; ++stage) {
+                void* target = stage == 1 ? Cb : B;
+                void* src = stage == 0 ? A : stage == 1 ? B : Cb;
+                Args2D<TB> a = base_args2d<TB>(s);
+                a.un = view_of<TB>(s, A);
+                a.us = view_of<TB>(s, src);
+                a.stage = stage;
+                a.dt_from_ctrl = 1;
+                a.alpha_acc = stage == 2 ? &c->alpha_bits : nullptr;
+                Args2D<TB> f = base_args2d<TB>(s);
+                f.stage = stage;
+                f.dt_from_ctrl = 1;
+                if (fmode == 1) {
+                    // residual -> workspace, filter workspace -> target
+                    a.out = view_of<TB>(s, s->ws + s->off_w);
+                    DG_HIP(launch_stage2d<TB>(s->eq, s->k, a, st));
+                    f.us = a.out;
+                    f.out = view_of<TB>(s, target);
+                    DG_HIP(launch_filter2d<TB>(s->eq, s->k, f, 1, st));
+                } else {
+                    a.out = view_of<TB>(s, target);
+                    DG_HIP(launch_stage2d<TB>(s->eq, s->k, a, st));
+                    if (fmode == 2) {
+                        f.us = f.out = a.out;
+                        f.eta_acc = &c->eta_bits[stage];
+                        f.tcount = &c->tcount[stage];
+                        f.tcell = tcell;
+                        f.tdata = tdata;
+                        DG_HIP(launch_filter2d<TB>(s->eq, s->k, f, 2, st));
+                        DG_HIP(launch_blend2d<TB>(s->nv, s->k, f.out, s->ncell, &c->tcount[stage], tcell,
+                                                  tdata, &c->eta_bits[stage], c, 1, s->ncell, st));
+                    }
+                }
+            }
+            continue;
+        }
         for (int stage = 0; stage < 3; ++stage) {
             Args1D<TB> a = base_args<TB>(s);
             a.un = view_of<TB>(s, A);
@@ -309,6 +434,50 @@ int time_impl(dg_solver* s, int stage, double dt, int reps, double* avg_us)
     const int fmode = s->opt.filter == DG_FILTER_NONE ? 0 : s->opt.filter == DG_FILTER_JUMP ? 1 : 2;
     double* aux = aux_of(s);
     Ctrl* scratch = reinterpret_cast<Ctrl*>(aux + 16);  // a second control block in aux
+    if (s->dim == 2) {
+        // which 0..2: residual kernel of that stage (u_n, u_a, u_b -> workspace);
+        // which 3..5: the filter (jump: workspace -> u_a) or hybrid pass A (on u_a)
+        const int which = stage;
+        Args2D<TB> a = base_args2d<TB>(s);
+        a.ctrl = scratch;
+        a.stage = which % 3;
+        a.dt_host = dt;
+        a.un = view_of<TB>(s, s->u[0]);
+        a.us = view_of<TB>(s, s->u[which % 3]);
+        a.out = view_of<TB>(s, s->ws + s->off_w);
+        a.alpha_acc = a.stage == 2 ? &scratch->alpha_bits : nullptr;
+        Args2D<TB> f = base_args2d<TB>(s);
+        f.ctrl = scratch;
+        f.stage = which % 3;
+        f.dt_host = dt;
+        f.us = fmode == 1 ? view_of<TB>(s, s->ws + s->off_w) : view_of<TB>(s, s->u[1]);
+        f.out = view_of<TB>(s, s->u[1]);
+        f.eta_acc = &scratch->eta_bits[0];
+        f.tcount = &scratch->tcount[0];
+        f.tcell = reinterpret_cast<long long*>(s->ws + s->off_tcell);
+        f.tdata = reinterpret_cast<double*>(s->ws + s->off_tdata);
+        hipEvent_t e0, e1;
+        DG_HIP(hipEventCreate(&e0));
+        DG_HIP(hipEventCreate(&e1));
+        double total_ms = 0.0;
+        int rc = DG_OK;
+        for (int r = 0; r < reps && rc == DG_OK; ++r) {
+            if (launch_step_ctrl(scratch, 2, st) != hipSuccess) rc = DG_ERR_DEVICE;
+            if (hipEventRecord(e0, st) != hipSuccess) rc = DG_ERR_DEVICE;
+            hipError_t e = which < 3 ? launch_stage2d<TB>(s->eq, s->k, a, st)
+                                     : launch_filter2d<TB>(s->eq, s->k, f, fmode == 1 ? 1 : 2, st);
+            if (e != hipSuccess) rc = DG_ERR_DEVICE;
+            if (hipEventRecord(e1, st) != hipSuccess) rc = DG_ERR_DEVICE;
+            if (hipEventSynchronize(e1) != hipSuccess) rc = DG_ERR_DEVICE;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = DG_ERR_DEVICE;
+            total_ms += ms;
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        *avg_us = 1000.0 * total_ms / reps;
+        return rc;
+    }
     Args1D<TB> a = base_args<TB>(s);
     a.un = view_of<TB>(s, s->u[0]);
     a.us = view_of<TB>(s, stage == 0 ? s->u[0] : stage == 1 ? s->u[1] : s->u[2]);
@@ -381,7 +550,14 @@ int dg_create(const dg_mesh* mesh, int degree, int equation, const dg_options* o
         if (mesh->dim == 1 && (b0 > 3 || b1 > 3)) return DG_ERR_ARG;
         if ((b0 == DG_BC_REFLECT || b1 == DG_BC_REFLECT) && equation != DG_EQ_EULER) return DG_ERR_ARG;
     }
-    if (mesh->dim == 2) return DG_ERR_UNSUPPORTED;  // 2D path: see dg2d
+    if (mesh->dim == 2) {
+        if (equation == DG_EQ_BURGERS) return DG_ERR_UNSUPPORTED;
+        for (int side = 0; side < 4; ++side) {
+            const int b = mesh->bc[side];
+            if ((b == DG_BC_DMR_WALL || b == DG_BC_DMR_TOP) && (side < 2 || equation != DG_EQ_EULER))
+                return DG_ERR_ARG;
+        }
+    }
     dg_solver* s = new (std::nothrow) dg_solver;
     if (!s) return DG_ERR_ARG;
     memset(s, 0, sizeof *s);
@@ -545,7 +721,8 @@ int dg_report_read(dg_solver* s, dg_report* rep)
 
 int dg_time_kernel(dg_solver* s, int stage, double dt, int reps, double* avg_us)
 {
-    if (!s || stage < 0 || stage > 2 || reps < 1 || !avg_us || !(dt >= 0.0)) return DG_ERR_ARG;
+    const int top = (s && s->dim == 2) ? 5 : 2;
+    if (!s || stage < 0 || stage > top || reps < 1 || !avg_us || !(dt >= 0.0)) return DG_ERR_ARG;
     if (!s->bound) return DG_ERR_STATE;
     DG_HIP(hipStreamSynchronize(s->user_st));
     return is_fp64(s) ? time_impl<double>(s, stage, dt, reps, avg_us)

@@ -34,6 +34,47 @@ struct Args1D {
 };
 
 template <typename TB>
+struct Args2D {
+    StateView<TB> un, us, out;
+    int64_t nx, ny;
+    double hx, hy, inv_hx, inv_hy;
+    double xlo, ylo;
+    int bc[4];                // x-lo, x-hi, y-lo, y-hi
+    double dir[4][4];         // Dirichlet states per side
+    double shock_x0, shock_speed, post[4], pre[4];  // double-Mach boundaries
+    PhysParams phys;
+    int stage;
+    int dt_from_ctrl;         // 1: dt, t and the done flag come from ctrl
+    double dt_host, t_host;   // step size and step start time (per-call API)
+    int check;
+    Ctrl* ctrl;
+    double* bflux;            // unused in 2D (periodic / open ledger via fluxes)
+    unsigned long long* alpha_acc;
+    unsigned long long* eta_acc;
+    unsigned int* tcount;
+    long long* tcell;
+    double* tdata;            // (eta, E^1..E^{2k}) per entry
+    long long tcap;
+    double* E_out;            // nullable: per-cell exponents, (2k+1) per cell
+    double* eta_out;
+    double jsx[16], jsy[16];  // jump weights per multi-index a1*4+a2 (see filter2d)
+};
+
+template <typename TB>
+hipError_t launch_stage2d(int eq, int k, const Args2D<TB>& a, hipStream_t st);
+template <typename TB>
+hipError_t launch_filter2d(int eq, int k, const Args2D<TB>& a, int mode, hipStream_t st);
+template <typename TB>
+hipError_t launch_blend2d(int nv, int k, StateView<TB> out, int64_t ncell, const unsigned int* count,
+                          const long long* tcell, const double* tdata,
+                          const unsigned long long* eta_bits, const Ctrl* ctrl, int from_ctrl,
+                          int64_t max_entries, hipStream_t st);
+template <typename TB>
+hipError_t launch_maxwave2d(int eq, StateView<TB> u, int64_t nx, int64_t ny, double inv_hx,
+                            double inv_hy, PhysParams phys, unsigned long long* acc, Ctrl* err,
+                            hipStream_t st);
+
+template <typename TB>
 hipError_t launch_stage1d(int eq, int k, const Args1D<TB>& a, int mode, hipStream_t st);
 template <typename TB>
 hipError_t launch_filter1d(int eq, int k, const Args1D<TB>& a, int mode, hipStream_t st);

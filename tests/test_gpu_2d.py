@@ -1,0 +1,263 @@
+"""GPU parity of the 2D Q^k path (C ABI, gfx950 kernels) against the FP64
+oracle.
+
+Bars: FP64 per call (one residual stage, one filter / hybrid application,
+the CFL max) relative L-infinity <= 1e-13; FP64 full runs <= 1e-10 after the
+stated step counts; sampled cells of one step at the full workload sizes
+<= 1e-12 (FP64) and <= 2e-5 (mixed: FP32 bulk)."""
+import math
+
+import numpy as np
+import pytest
+
+import dg_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_2407_19169_amd as dg
+
+    return dg
+
+
+def rel_linf(got, want):
+    return float(np.max(np.abs(np.asarray(got) - np.asarray(want))) / max(np.max(np.abs(want)), 1e-300))
+
+
+def random_euler2d(seed, k, ny, nx, amp=0.05):
+    rng = np.random.default_rng(seed)
+    u = np.zeros((4, (k + 1) ** 2, ny, nx))
+    u[:, 0] = I.conserved2d(1 + 0.5 * rng.random((ny, nx)), rng.uniform(-0.5, 0.5, (ny, nx)),
+                            rng.uniform(-0.5, 0.5, (ny, nx)), 1 + 0.5 * rng.random((ny, nx)))
+    if k > 0:
+        u[:, 1:] = amp * rng.standard_normal((4, (k + 1) ** 2 - 1, ny, nx)) * np.abs(u[:, :1])
+    return u
+
+
+DMR_POST = I.conserved2d(8.0, 8.25 * math.cos(math.pi / 6), -8.25 * math.sin(math.pi / 6), 116.5)
+DMR_PRE = I.conserved2d(1.4, 0.0, 0.0, 1.0)
+
+
+def _mesh_kwargs(bcs):
+    st = I.conserved2d(1.1, 0.2, -0.1, 0.9)
+    return dict(dirichlet=[list(st)] * 4, shock_x0=0.3, shock_speed=5.0,
+                post=list(DMR_POST / 8.0 + np.array([0.5, 0, 0, 2.0])), pre=list(DMR_PRE))
+
+
+def _pair(dg, ref, eq, k, nx, ny, bcs, filt, prec=0, cfl=0.1, box=(0.0, 1.0, 0.0, 0.8)):
+    kw = _mesh_kwargs(bcs)
+    mesh = dg.make_mesh(2, (nx, ny), (box[0], box[2]), (box[1], box[3]), bcs, **kw)
+    opt = dg.make_options(precision=prec, filter=filt, cfl=cfl, adv_speed=(0.8, -0.5))
+    s = dg.Solver(mesh, k, eq, opt)
+    P = ref.problem2d(eq, k, nx, ny, box[0], box[1], box[2], box[3], bc=bcs, filter=filt, cfl=cfl,
+                      adv_speed=(0.8, -0.5), dirichlet=kw["dirichlet"], shock_x0=kw["shock_x0"],
+                      shock_speed=kw["shock_speed"], post=kw["post"], pre=kw["pre"])
+    return s, P
+
+
+CASES = [
+    # eq, k, nx, ny, bcs
+    (2, 0, 17, 9, (0, 0, 0, 0)),
+    (2, 1, 16, 16, (0, 0, 0, 0)),
+    (2, 1, 33, 20, (1, 1, 2, 2)),
+    (2, 2, 20, 13, (0, 0, 0, 0)),
+    (2, 2, 31, 17, (3, 1, 4, 5)),
+    (2, 2, 1, 1, (0, 0, 0, 0)),
+    (2, 3, 18, 35, (2, 2, 1, 1)),
+    (2, 3, 40, 24, (3, 1, 4, 5)),
+    (0, 2, 19, 21, (0, 0, 0, 0)),
+    (0, 3, 17, 16, (1, 1, 3, 3)),
+]
+
+
+@pytest.mark.parametrize("eq,k,nx,ny,bcs", CASES)
+def test_stage_and_filter_per_call_2d(dg, ref, eq, k, nx, ny, bcs):
+    import torch
+
+    nm = (k + 1) ** 2
+    if eq == 2:
+        un, ua, ub = (random_euler2d(s, k, ny, nx) for s in (1, 2, 3))
+    else:
+        rng = np.random.default_rng(4)
+        un, ua, ub = (rng.standard_normal((1, nm, ny, nx)) for _ in range(3))
+    dt = 0.05 / nx
+    for filt in (0, 1, 2):
+        s, P = _pair(dg, ref, eq, k, nx, ny, bcs, filt)
+        for stage, us in ((0, un), (1, ua), (2, ub)):
+            s.set_state(un)
+            if stage:
+                dg.buffer_view(s, stage).copy_(torch.as_tensor(us))
+            dg.dg_stage(s.h, stage, dt)
+            dg.dg_jump_filter(s.h, stage, dt)
+            torch.cuda.synchronize()
+            got = dg.buffer_view(s, {0: 1, 1: 2, 2: 0}[stage]).cpu().numpy()
+            w = ref.stage2d(P, stage, dt, un, us, t=0.0)
+            tf = (1.0, 0.5, 1.0)[stage] * dt
+            want, _ = ref.post2d(P, stage, dt, w, t=tf)
+            for v in range(got.shape[0]):
+                err = rel_linf(got[v], want[v])
+                assert err <= 1e-13, (eq, k, nx, ny, bcs, filt, stage, v, err)
+            if filt == 1:
+                Eg = s.exponents().cpu().numpy().reshape(ny, nx, 2 * k + 1)
+                Ew, _ = ref.exponents2d(P, dt, w, t=tf)
+                assert rel_linf(Eg, Ew) <= 1e-13
+        s.close()
+
+
+@pytest.mark.parametrize("eq,k,nx,ny,bcs", CASES[:5])
+def test_max_wavespeed_2d(dg, ref, eq, k, nx, ny, bcs):
+    u = random_euler2d(5, k, ny, nx) if eq == 2 else np.ones((1, (k + 1) ** 2, ny, nx))
+    s, P = _pair(dg, ref, eq, k, nx, ny, bcs, 1)
+    s.set_state(u)
+    assert dg.dg_max_wavespeed(s.h) == pytest.approx(ref.max_wavespeed2d(P, u), rel=1e-14)
+    s.close()
+
+
+def _run_pair(dg, ref, w, eq, filt, steps, t_end=1e30, prec=0):
+    mesh = dg.make_mesh(2, (w.nx, w.ny), (w.xlo, w.ylo), (w.xhi, w.yhi), w.bc)
+    s = dg.Solver(mesh, w.k, eq, dg.make_options(precision=prec, filter=filt, cfl=w.cfl))
+    s.set_state(w.u0)
+    rep = dg.dg_run(s.h, t_end, steps)
+    got = s.get_state().cpu().numpy()
+    P = ref.problem2d(eq, w.k, w.nx, w.ny, w.xlo, w.xhi, w.ylo, w.yhi, bc=w.bc, filter=filt,
+                      cfl=w.cfl)
+    want, orep, rc = ref.run2d(P, w.u0, t_end, steps)
+    s.close()
+    return got, want, rep, orep, rc
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_vortex_run_parity(dg, ref, k):
+    """Smooth isentropic vortex (seeded centre), 40x40, jump filter, 60 steps."""
+    w = I.vortex2d(40, k, seed=3001)
+    got, want, rep, orep, rc = _run_pair(dg, ref, w, 2, 1, 60)
+    assert rc == 0 and rep.steps == orep.steps == 60
+    for v in range(4):
+        assert rel_linf(got[v], want[v]) <= 1e-10
+    h2 = (10.0 / 40) ** 2
+    for v in range(4):
+        q0 = h2 * w.u0[v, 0].sum()
+        assert abs(rep.ledger[v] - q0) < 1e-12 * max(1.0, abs(q0))
+
+
+def test_quadrant_hybrid_run_parity(dg, ref):
+    """Seeded four-quadrant Riemann problem, 32x32, Q2, hybrid, 30 steps."""
+    w = I.quadrant2d(32, 2, seed=3002)
+    got, want, rep, orep, rc = _run_pair(dg, ref, w, 2, 2, 30)
+    assert rc == 0 and rep.steps == 30
+    for v in range(4):
+        assert rel_linf(got[v], want[v]) <= 1e-10
+    assert rep.troubled_cells > 0
+
+
+def test_double_mach_small_run_parity(dg, ref):
+    """Double Mach reflection on 64x16, Q3, hybrid, moving top boundary, 20 steps."""
+    w = I.double_mach(64, 16, 3)
+    post, pre = I.conserved2d(*w.extra["post"]), I.conserved2d(1.4, 0.0, 0.0, 1.0)
+    speed = w.extra["shock_speed"] / math.sin(math.pi / 3)
+    mesh = dg.make_mesh(2, (64, 16), (0.0, 0.0), (4.0, 1.0), (3, 1, 4, 5),
+                        dirichlet=[list(post)] * 4, shock_x0=1 / 6, shock_speed=speed,
+                        post=list(post), pre=list(pre))
+    s = dg.Solver(mesh, 3, 2, dg.make_options(filter=2, cfl=0.1))
+    s.set_state(w.u0)
+    rep = dg.dg_run(s.h, 1e30, 20)
+    got = s.get_state().cpu().numpy()
+    P = ref.problem2d(2, 3, 64, 16, 0.0, 4.0, 0.0, 1.0, bc=(3, 1, 4, 5), filter=2, cfl=0.1,
+                      dirichlet=[list(post)] * 4, shock_x0=1 / 6, shock_speed=speed, post=post,
+                      pre=pre)
+    want, orep, rc = ref.run2d(P, w.u0, 1e30, 20)
+    assert rc == 0 and rep.status == 0
+    for v in range(4):
+        assert rel_linf(got[v], want[v]) <= 1e-10, v
+    s.close()
+
+
+def test_mixed_precision_vortex_2d(dg, ref):
+    """FP32 bulk / FP64 mode 0: cell averages within 1e-6 (relative L1) of
+    the FP64 oracle after 60 steps; conservation to FP64 roundoff."""
+    w = I.vortex2d(40, 2, seed=3001)
+    got, want, rep, orep, rc = _run_pair(dg, ref, w, 2, 1, 60, prec=1)
+    h2 = (10.0 / 40) ** 2
+    for v in range(4):
+        l1 = np.sum(np.abs(got[v, 0] - want[v, 0])) / np.sum(np.abs(want[v, 0]))
+        assert l1 < 1e-6, (v, l1)
+        q0 = h2 * w.u0[v, 0].sum()
+        assert abs(rep.ledger[v] - q0) < 1e-13 * max(1.0, h2 * np.abs(got[v, 0]).sum())
+
+
+def _patch_step(ref, P_full, u0, jy, ix, dt, r=7):
+    """Oracle step of a (2r+1)^2 patch around (jy, ix); the centre cell's
+    value after one step depends on cells within radius 6 only."""
+    ny, nx = u0.shape[-2:]
+    rows = np.arange(jy - r, jy + r + 1) % ny
+    cols = np.arange(ix - r, ix + r + 1) % nx
+    patch = np.ascontiguousarray(u0[:, :, rows][:, :, :, cols])
+    hx = (P_full.xhi - P_full.xlo) / nx
+    hy = (P_full.yhi - P_full.ylo) / ny
+    P = ref.problem2d(P_full.eq, P_full.k, 2 * r + 1, 2 * r + 1, P_full.xlo + (ix - r) * hx,
+                      P_full.xlo + (ix + r + 1) * hx, P_full.ylo + (jy - r) * hy,
+                      P_full.ylo + (jy + r + 1) * hy, bc=(1, 1, 1, 1), filter=P_full.filter,
+                      cfl=P_full.cfl)
+    out = ref.step2d(P, dt, patch, t=0.0)
+    return out[:, :, r, r]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_full_size_vortex_sampled_step(dg, ref, prec):
+    """1024x1024, Q2, periodic, jump filter (vortex workload): one dg_run step
+    on the GPU vs oracle steps of patches around 24 sampled cells."""
+    n, k = 1024, 2
+    w = I.vortex2d(n, k, seed=3001)
+    mesh = dg.make_mesh(2, (n, n), (0.0, -5.0), (10.0, 5.0), (0, 0, 0, 0))
+    s = dg.Solver(mesh, k, 2, dg.make_options(precision=prec, filter=1, cfl=0.1))
+    s.set_state(w.u0)
+    rep = dg.dg_run(s.h, 1e30, 1)
+    got = s.get_state().cpu().numpy()
+    P = ref.problem2d(2, k, n, n, 0.0, 10.0, -5.0, 5.0, bc=(0, 0, 0, 0), filter=1, cfl=0.1)
+    dt = 0.1 / ref.max_wavespeed2d(P, w.u0)
+    assert rep.dt_max == pytest.approx(dt, rel=1e-14)
+    rng = np.random.default_rng(7)
+    samples = [(int(jy), int(ix)) for jy, ix in rng.integers(0, n, (20, 2))]
+    samples += [(512, 512), (0, 0), (n - 1, 3), (400, 600)]
+    tol = 1e-12 if prec == 0 else 2e-5
+    for jy, ix in samples:
+        want = _patch_step(ref, P, w.u0, jy, ix, dt)
+        err = np.max(np.abs(got[:, :, jy, ix] - want)) / np.max(np.abs(want[:, 0]))
+        assert err <= tol, (jy, ix, err)
+    s.close()
+
+
+def test_full_size_double_mach_sampled_step(dg, ref):
+    """4096x1024, Q3, mixed precision, jump filter (double-Mach workload):
+    one GPU step vs oracle patches at sampled interior cells along the
+    shock."""
+    w = I.double_mach(4096, 1024, 3)
+    post, pre = I.conserved2d(*w.extra["post"]), I.conserved2d(1.4, 0.0, 0.0, 1.0)
+    speed = w.extra["shock_speed"] / math.sin(math.pi / 3)
+    mesh = dg.make_mesh(2, (4096, 1024), (0.0, 0.0), (4.0, 1.0), (3, 1, 4, 5),
+                        dirichlet=[list(post)] * 4, shock_x0=1 / 6, shock_speed=speed,
+                        post=list(post), pre=list(pre))
+    for prec, tol in ((0, 1e-12), (1, 2e-5)):
+        s = dg.Solver(mesh, 3, 2, dg.make_options(precision=prec, filter=1, cfl=0.1))
+        s.set_state(w.u0)
+        rep = dg.dg_run(s.h, 1e30, 1)
+        assert rep.status == 0
+        got = s.get_state().cpu().numpy()
+        s.close()
+        P = ref.problem2d(2, 3, 4096, 1024, 0.0, 4.0, 0.0, 1.0, bc=(3, 1, 4, 5), filter=1,
+                          cfl=0.1, dirichlet=[list(post)] * 4, shock_x0=1 / 6, shock_speed=speed,
+                          post=post, pre=pre)
+        dt = 0.1 / ref.max_wavespeed2d(P, w.u0)
+        rng = np.random.default_rng(11)
+        for jy in list(rng.integers(20, 1000, 10)) + [500]:
+            y = (jy + 0.5) / 1024
+            ix = int((1 / 6 + y / math.sqrt(3)) * 1024)  # on the shock
+            for dx in (-8, 0, 3, 40):
+                want = _patch_step(ref, P, w.u0, int(jy), ix + dx, dt)
+                err = np.max(np.abs(got[:, :, jy, ix + dx] - want)) / np.max(np.abs(want[:, 0]))
+                assert err <= tol, (prec, jy, ix + dx, err)
