@@ -202,9 +202,12 @@ typedef struct {
                              /* problem's FP64-layout state in the packed array  */
 } dg_problem1d;
 
-/* Create a batch of `nprob` 1D problems of `equation`.  Problems are packed
- * back to back in FP64 layout (problem i at element offset probs[i].offset,
- * written by this call).  Total element count in *total_elems. */
+/* Create a batch of `nprob` 1D Euler problems (each one a separate domain
+ * with its own degree, cells and boundary conditions; jump filter or no
+ * post-stage operator).  Problems are packed back to back in FP64 layout
+ * (problem i at element offset probs[i].offset, written by this call);
+ * total element count in *total_elems.  Errors: DG_ERR_ARG (sizes, BCs),
+ * DG_ERR_UNSUPPORTED (degree > 3, other equations, hybrid limiter). */
 int dg_batch_create(int nprob, dg_problem1d* probs, int equation, const dg_options* opt,
                     int64_t* total_elems, dg_batch** out);
 int dg_batch_destroy(dg_batch* b);
@@ -216,6 +219,14 @@ int dg_batch_get_state(dg_batch* b, double* packed_dev);
  * array, nullable), each with its own CFL time step.  per_problem (host,
  * nullable, nprob entries) receives each problem's report. */
 int dg_batch_run(dg_batch* b, const double* t_end, int64_t steps, dg_report* per_problem);
+
+/* Autotuner of the batched launch: times `trial_steps` steps of the whole
+ * batch for each candidate schedule (persistent workgroups per compute
+ * unit: 1, 2, 4, 8; queue order: longest-first or as given), each from the
+ * same saved state (u_n is restored afterwards), keeps the fastest for
+ * later dg_batch_run calls, and writes a JSON summary of all candidates
+ * into json (nullable; truncated to cap bytes).  Synchronises. */
+int dg_batch_tune(dg_batch* b, int64_t trial_steps, char* json, size_t cap);
 
 #ifdef __cplusplus
 }

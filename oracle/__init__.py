@@ -51,7 +51,8 @@ class Problem2D(C.Structure):
                 ("ylo", C.c_double), ("yhi", C.c_double), ("gamma", C.c_double),
                 ("adv_speed", C.c_double * 2), ("cfl", C.c_double),
                 ("dirichlet", (C.c_double * 4) * 4), ("shock_x0", C.c_double),
-                ("shock_speed", C.c_double), ("post", C.c_double * 4), ("pre", C.c_double * 4)]
+                ("shock_speed", C.c_double), ("post", C.c_double * 4), ("pre", C.c_double * 4),
+                ("cf_mesh", C.c_int), ("basis", C.c_int), ("cf_scale", C.c_double)]
 
 
 class Report(C.Structure):
@@ -111,8 +112,10 @@ def problem1d(eq, k, n, lo, hi, bc=(PERIODIC, PERIODIC), filter=FILTER_JUMP, cfl
 
 def problem2d(eq, k, nx, ny, xlo, xhi, ylo, yhi, bc=(PERIODIC,) * 4, filter=FILTER_JUMP,
               cfl=0.1, gamma=1.4, adv_speed=(1.0, 1.0), nq=0, filter_dt=0,
-              dirichlet=None, shock_x0=0.0, shock_speed=0.0, post=None, pre=None) -> Problem2D:
+              dirichlet=None, shock_x0=0.0, shock_speed=0.0, post=None, pre=None, cf_mesh=1,
+              basis=0, cf_scale=1.0) -> Problem2D:
     P = Problem2D()
+    P.cf_mesh, P.basis, P.cf_scale = cf_mesh, basis, cf_scale
     P.shock_x0, P.shock_speed = shock_x0, shock_speed
     for v in range(4):
         P.post[v] = float(post[v]) if post is not None else 0.0

@@ -59,6 +59,10 @@ typedef struct {
      * conserved states behind (left of) and ahead of it */
     double shock_x0, shock_speed;
     double post[4], pre[4];
+    int cf_mesh;   /* 1: (c_fx, c_fy) carry the factors (h_x, h_y) as printed in
+                      Sec. 2.4; 0: they do not (see the readings in the 2D part) */
+    int basis;     /* 0: Q^k tensor product; 1: P^k total degree (p + q <= k) */
+    double cf_scale; /* multiplies (c_fx, c_fy); 0 means 1 */
 } dgref_problem2d;
 
 typedef struct {

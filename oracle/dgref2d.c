@@ -330,7 +330,9 @@ static void cell_residual(const ctx2d* C, double t, const double* u, int64_t ix,
         for (int p = 0; p < K1; ++p)
             for (int q = 0; q < K1; ++q) {
                 double mass = C->hx * C->hy / ((2.0 * p + 1.0) * (2.0 * q + 1.0));
-                L[v][p * K1 + q] = acc[v][p * K1 + q] / mass;
+                /* P^k (basis 1): the modes with p + q > k are not in the
+                 * space and stay zero */
+                L[v][p * K1 + q] = (P->basis == 1 && p + q > C->k) ? 0.0 : acc[v][p * K1 + q] / mass;
             }
 }
 
@@ -476,8 +478,10 @@ static void cell_exponents(const ctx2d* C, double t, double dt, const double* u,
                 continue;
             }
             double lam = p * (p + 1.0) + q * (q + 1.0);
-            double cfx = C->hx * bx / (4.0 * lam * H);
-            double cfy = C->hy * by / (4.0 * lam * H);
+            double sc = P->cf_scale > 0.0 ? P->cf_scale : 1.0;
+            double mx = (P->cf_mesh ? C->hx : 1.0) * sc, my = (P->cf_mesh ? C->hy : 1.0) * sc;
+            double cfx = mx * bx / (4.0 * lam * H);
+            double cfy = my * by / (4.0 * lam * H);
             double sig = 0.0;
             for (int v = 0; v < nv; ++v) {
                 double sx = C->hx * Jx[0][0][v], sy = C->hy * Jy[0][0][v];

@@ -79,6 +79,7 @@ _sig = {
     "dg_batch_set_state": [_vp, _vp],
     "dg_batch_get_state": [_vp, _vp],
     "dg_batch_run": [_vp, _vp, C.c_int64, C.POINTER(dg_report)],
+    "dg_batch_tune": [_vp, C.c_int64, C.c_char_p, C.c_size_t],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -280,3 +281,107 @@ def buffer_view(solver: Solver, i: int):
     for d in solver.shape():
         nel *= d
     return t[off:off + nel * 8].view(torch.float64).view(solver.shape())
+
+
+# ----------------------------------------------------------------- batch --
+def dg_batch_create(problems, equation: int, options: dg_options):
+    """problems: sequence of (n, degree, lo, hi, bc_lo, bc_hi).  Returns
+    (handle, offsets, total_elems)."""
+    arr = (dg_problem1d * len(problems))()
+    for i, (n, k, lo, hi, b0, b1) in enumerate(problems):
+        arr[i].n, arr[i].degree, arr[i].lo, arr[i].hi = int(n), int(k), float(lo), float(hi)
+        arr[i].bc[0], arr[i].bc[1] = int(b0), int(b1)
+    total = C.c_int64()
+    h = _vp()
+    _check(_lib.dg_batch_create(len(problems), arr, equation, C.byref(options), C.byref(total),
+                                C.byref(h)), "dg_batch_create")
+    return h.value, [arr[i].offset for i in range(len(problems))], total.value
+
+
+def dg_batch_destroy(h) -> None:
+    _check(_lib.dg_batch_destroy(h), "dg_batch_destroy")
+
+
+def dg_batch_buffer_sizes(h):
+    a, b = C.c_size_t(), C.c_size_t()
+    _check(_lib.dg_batch_buffer_sizes(h, C.byref(a), C.byref(b)), "dg_batch_buffer_sizes")
+    return a.value, b.value
+
+
+def dg_batch_bind(h, u_n, u_a, u_b, workspace) -> None:
+    _check(_lib.dg_batch_bind(h, _ptr(u_n), _ptr(u_a), _ptr(u_b), _ptr(workspace)), "dg_batch_bind")
+
+
+def dg_batch_set_state(h, packed) -> None:
+    _check(_lib.dg_batch_set_state(h, _ptr(packed)), "dg_batch_set_state")
+
+
+def dg_batch_get_state(h, packed) -> None:
+    _check(_lib.dg_batch_get_state(h, _ptr(packed)), "dg_batch_get_state")
+
+
+def dg_batch_run(h, nprob: int, steps: int, t_end=None, check: bool = True):
+    reps = (dg_report * nprob)()
+    te = None
+    if t_end is not None:
+        te = (C.c_double * nprob)(*[float(x) for x in t_end])
+    rc = _lib.dg_batch_run(h, te, steps, reps)
+    if check:
+        _check(rc, "dg_batch_run")
+    return list(reps)
+
+
+def dg_batch_tune(h, trial_steps: int) -> str:
+    buf = C.create_string_buffer(8192)
+    _check(_lib.dg_batch_tune(h, trial_steps, buf, 8192), "dg_batch_tune")
+    return buf.value.decode()
+
+
+class Batch:
+    """Owns a batch handle plus torch-allocated buffers."""
+
+    def __init__(self, problems, options: dg_options, equation: int = DG_EQ_EULER):
+        import torch
+
+        self.torch = torch
+        self.problems = list(problems)
+        self.h, self.offsets, self.total = dg_batch_create(self.problems, equation, options)
+        sb, wb = dg_batch_buffer_sizes(self.h)
+        alloc = lambda nbytes: torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        self._raw = [alloc(sb) for _ in range(3)] + [alloc(wb)]
+        self._ptrs = [((t.data_ptr() + 255) // 256) * 256 for t in self._raw]
+        dg_batch_bind(self.h, *self._ptrs)
+
+    def set_state(self, states) -> None:
+        flat = self.torch.cat([self.torch.as_tensor(s, dtype=self.torch.float64).reshape(-1)
+                               for s in states]).to("cuda")
+        assert flat.numel() == self.total
+        dg_batch_set_state(self.h, flat)
+        self.torch.cuda.synchronize()
+
+    def get_state(self):
+        flat = self.torch.empty(self.total, dtype=self.torch.float64, device="cuda")
+        dg_batch_get_state(self.h, flat)
+        self.torch.cuda.synchronize()
+        flat = flat.cpu().numpy()
+        out = []
+        for (n, k, *_), off in zip(self.problems, self.offsets):
+            out.append(flat[off:off + 3 * (k + 1) * n].reshape(3, k + 1, n))
+        return out
+
+    def run(self, steps: int, t_end=None, check: bool = True):
+        return dg_batch_run(self.h, len(self.problems), steps, t_end, check)
+
+    def tune(self, trial_steps: int = 5) -> str:
+        return dg_batch_tune(self.h, trial_steps)
+
+    def close(self) -> None:
+        if self.h:
+            dg_batch_destroy(self.h)
+            self.h = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

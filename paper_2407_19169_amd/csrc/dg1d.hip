@@ -98,7 +98,21 @@ __device__ __forceinline__ T combine_t(int stage, T un, T adv)
 // output into ctrl->alpha_bits (the next step's CFL reduction).
 // -------------------------------------------------------------------------
 template <int EQ, int K, typename TB, int MODE>
-__global__ __launch_bounds__(256) void stage1d_kernel(Args1D<TB> a)
+struct Stage1DLds {
+    static constexpr int NV = Phys1D<EQ>::NV;
+    // phase 1 (traces, fluxes) and phase 2 (derivative traces) alias
+    static constexpr int PH1 = 2 * NV * 256 * (int)sizeof(TB);
+    static constexpr int PH2 = NV * 256 * 8 + 2 * (K + 1) * NV * 256 * (int)sizeof(TB);
+    static constexpr int bytes = MODE == 0 ? PH1 : (PH1 > PH2 ? PH1 : PH2);
+};
+
+// One 256-cell tile (tile index blk) of the stage; `lds` provides
+// Stage1DLds::bytes of shared memory.  Returns, per thread, the CFL
+// quantity of its output cell (*lam_out, 0 for halo / outside lanes) and
+// its hybrid indicator (*eta_out); reductions are left to the caller.
+template <int EQ, int K, typename TB, int MODE>
+__device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, double dt,
+                                             unsigned char* lds, double* lam_out, double* eta_out)
 {
     using P = Phys1D<EQ>;
     using T = TB;
@@ -109,19 +123,12 @@ __global__ __launch_bounds__(256) void stage1d_kernel(Args1D<TB> a)
     constexpr int TILE = 256 - 2 * HALO;
     constexpr int Q = K + 1;
 
-    if (a.ctrl && a.dt_from_ctrl && a.ctrl->done) return;
-    const double dt = a.dt_from_ctrl ? a.ctrl->dt : a.dt_host;
     const int stage = a.stage;
-
-    // LDS: phase 1 (traces, fluxes) and phase 2 (derivative traces) alias.
-    constexpr int PH1 = 2 * NV * 256 * (int)sizeof(T);
-    constexpr int PH2 = NV * 256 * 8 + 2 * K1 * NV * 256 * (int)sizeof(T);
-    __shared__ __align__(16) unsigned char lds[(MODE == 0 ? PH1 : (PH1 > PH2 ? PH1 : PH2))];
     T* sTrR = reinterpret_cast<T*>(lds);                 // [NV][256] right trace
     T* sF = sTrR + NV * 256;                             // [NV][256] flux at left interface
 
     const int tid = threadIdx.x;
-    const int64_t c = (int64_t)blockIdx.x * TILE + tid - HALO;
+    const int64_t c = blk * TILE + tid - HALO;
     const int64_t n = a.n;
     bool valid = true;
     int64_t cc = c;
@@ -278,6 +285,7 @@ __global__ __launch_bounds__(256) void stage1d_kernel(Args1D<TB> a)
 
     if constexpr (MODE == 0) {
         if (own) store_cell<K, NV, TB>(a.out, c, v0, vh);
+        *eta_out = 0.0;
     } else {
         // ---- jump filter on the unfiltered output (needs neighbours) ----
         __syncthreads();  // phase-1 LDS reads are complete
@@ -388,19 +396,29 @@ __global__ __launch_bounds__(256) void stage1d_kernel(Args1D<TB> a)
                 for (int l = 0; l <= K; ++l) a.E_out[c * K1 + l] = (double)E[l];
             }
         }
-        if constexpr (MODE == 2) {
-            // max eta over the domain (wave reduction, one atomic per wave)
-            double e = wave_max((double)eta_own);
-            if ((tid & 63) == 0) atomic_max_nonneg(a.eta_acc, e);
-        }
+        *eta_out = (double)eta_own;
     }
+    // CFL quantity of the output's cell average (FP64)
+    *lam_out = own ? (double)P::speed(v0, a.phys) : 0.0;
+}
 
-    // CFL reduction of the output's cell averages (next step), FP64.
+template <int EQ, int K, typename TB, int MODE>
+__global__ __launch_bounds__(256) void stage1d_kernel(Args1D<TB> a)
+{
+    if (a.ctrl && a.dt_from_ctrl && a.ctrl->done) return;
+    const double dt = a.dt_from_ctrl ? a.ctrl->dt : a.dt_host;
+    __shared__ __align__(16) unsigned char lds[Stage1DLds<EQ, K, TB, MODE>::bytes];
+    double lam, eta;
+    stage1d_tile<EQ, K, TB, MODE>(a, (int64_t)blockIdx.x, dt, lds, &lam, &eta);
+    if (MODE == 2) {
+        // max eta over the domain (wave reduction, one atomic per wave)
+        const double e = wave_max(eta);
+        if ((threadIdx.x & 63) == 0) atomic_max_nonneg(a.eta_acc, e);
+    }
     if (a.alpha_acc) {
-        double lam = 0.0;
-        if (own) lam = P::speed(v0, a.phys);
-        lam = wave_max(lam);
-        if ((tid & 63) == 0) atomic_max_nonneg(a.alpha_acc, lam);
+        // CFL reduction of the output's cell averages (next step)
+        const double l = wave_max(lam);
+        if ((threadIdx.x & 63) == 0) atomic_max_nonneg(a.alpha_acc, l);
     }
 }
 
@@ -735,3 +753,4 @@ DG_INST(float)
 #undef DG_INST
 
 }  // namespace dg
+#include "dg_batch_kernel.h"

@@ -198,6 +198,44 @@ __device__ __forceinline__ constexpr double dtr(int l, int m, int side)
     return side ? dtrace_r(l, m) : dtrace_l(l, m);
 }
 
+// Values of a cell's polynomial at the Q Gauss points of one face (FACE 0
+// left xi=-1, 1 right xi=+1, 2 bottom eta=-1, 3 top eta=+1): first the sum
+// across the face, then the along-face Legendre series.  Own cells and the
+// tile's ring cells both use this routine, so the two workgroups that
+// evaluate a tile-boundary edge flux see bitwise identical traces (the
+// FP64 mode-0 update then telescopes exactly).
+template <int FACE, int NV, int K, typename TB, typename T>
+__device__ __forceinline__ void face_trace(const double (&u0)[NV],
+                                           const TB (&uh)[NV][(K + 1) * (K + 1) > 1 ? (K + 1) * (K + 1) - 1 : 1],
+                                           T (&tr)[K + 1][NV])
+{
+    constexpr int K1 = K + 1;
+    constexpr bool xface = FACE < 2;
+    constexpr bool plus = (FACE & 1) != 0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        T c[K1];
+#pragma unroll
+        for (int o = 0; o < K1; ++o) {
+            T s = (T)0;
+#pragma unroll
+            for (int n = 0; n < K1; ++n) {
+                const int p = xface ? n : o, q = xface ? o : n;
+                const T val = (p == 0 && q == 0) ? (T)u0[v] : (T)uh[v][p * K1 + q - 1];
+                s += (plus || !(n & 1)) ? val : -val;
+            }
+            c[o] = s;
+        }
+#pragma unroll
+        for (int b = 0; b < K1; ++b) {
+            T s = (T)0;
+#pragma unroll
+            for (int o = 0; o < K1; ++o) s += c[o] * (T)leg_at(K1, b, o);
+            tr[b][v] = s;
+        }
+    }
+}
+
 }  // namespace
 
 template <int EQ, int K, typename TB>
@@ -264,48 +302,11 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
 
     // Edge traces at the Gauss points: u(+-1, eta_b) and u(xi_a, +-1).
     T trL[Q][NV], trR[Q][NV], trB[Q][NV], trT[Q][NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        T cL[K1], cR[K1], rB[K1], rT[K1];
-#pragma unroll
-        for (int q = 0; q < K1; ++q) {
-            T sl = (T)0, sr = (T)0;
-#pragma unroll
-            for (int p = 0; p < K1; ++p) {
-                sr += mode(v, p, q);
-                sl += (p & 1) ? -mode(v, p, q) : mode(v, p, q);
-            }
-            cL[q] = sl;
-            cR[q] = sr;
-        }
-#pragma unroll
-        for (int p = 0; p < K1; ++p) {
-            T sb = (T)0, st = (T)0;
-#pragma unroll
-            for (int q = 0; q < K1; ++q) {
-                st += mode(v, p, q);
-                sb += (q & 1) ? -mode(v, p, q) : mode(v, p, q);
-            }
-            rB[p] = sb;
-            rT[p] = st;
-        }
-#pragma unroll
-        for (int b = 0; b < Q; ++b) {
-            T l_ = (T)0, r_ = (T)0, bo = (T)0, to = (T)0;
-#pragma unroll
-            for (int q = 0; q < K1; ++q) {
-                const T ph = (T)leg_at(Q, b, q);
-                l_ += cL[q] * ph;
-                r_ += cR[q] * ph;
-                bo += rB[q] * ph;
-                to += rT[q] * ph;
-            }
-            trL[b][v] = l_;
-            trR[b][v] = r_;
-            trB[b][v] = bo;
-            trT[b][v] = to;
-        }
-    }
+    face_trace<0, NV, K, TB, T>(u0, uh, trL);
+    face_trace<1, NV, K, TB, T>(u0, uh, trR);
+    face_trace<2, NV, K, TB, T>(u0, uh, trB);
+    face_trace<3, NV, K, TB, T>(u0, uh, trT);
+    (void)mode;
 #pragma unroll
     for (int b = 0; b < Q; ++b)
 #pragma unroll
@@ -325,35 +326,25 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
             double w0[NV];
             T wh[NV][NH];
             load_cell2d<NV, NM, TB>(a.us, hy_ * a.nx + hx_, w0, wh);
-            // side of the ring cell facing the tile: g=0 right, 1 left, 2 top, 3 bottom
-            const bool xface = g < 2;
-            const int sgn_side = (g == 0 || g == 2) ? 1 : 0;  // +1 end or -1 end
+            // the face of the ring cell that faces the tile: g=0 right, 1 left,
+            // 2 top, 3 bottom
             T* dst = g == 0 ? &sR[(i * 17 + 0) * TS]
                    : g == 1 ? &sLr[i * TS]
                    : g == 2 ? &sT[(i * 17 + 0) * TS]
                             : &sBr[i * TS];
+            T tr[Q][NV];
+            if (g == 0)
+                face_trace<1, NV, K, TB, T>(w0, wh, tr);
+            else if (g == 1)
+                face_trace<0, NV, K, TB, T>(w0, wh, tr);
+            else if (g == 2)
+                face_trace<3, NV, K, TB, T>(w0, wh, tr);
+            else
+                face_trace<2, NV, K, TB, T>(w0, wh, tr);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                T c[K1];
+            for (int b = 0; b < Q; ++b)
 #pragma unroll
-                for (int o = 0; o < K1; ++o) {  // o: the mode index along the edge
-                    T s = (T)0;
-#pragma unroll
-                    for (int n_ = 0; n_ < K1; ++n_) {  // n_: the mode index across the edge
-                        const int p = xface ? n_ : o, q = xface ? o : n_;
-                        const T val = (p == 0 && q == 0) ? (T)w0[v] : wh[v][p * K1 + q - 1];
-                        s += (sgn_side || !(n_ & 1)) ? val : -val;
-                    }
-                    c[o] = s;
-                }
-#pragma unroll
-                for (int b = 0; b < Q; ++b) {
-                    T s = (T)0;
-#pragma unroll
-                    for (int o = 0; o < K1; ++o) s += c[o] * (T)leg_at(Q, b, o);
-                    dst[b * NV + v] = s;
-                }
-            }
+                for (int v = 0; v < NV; ++v) dst[b * NV + v] = tr[b][v];
         }
     }
     __syncthreads();

@@ -1,0 +1,333 @@
+// dg_batch_api.hip — host side of the batched 1D ABI (include/dg.h) and
+// its autotuner.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "../../include/dg.h"
+#include "dg_batch.h"
+
+using namespace dg;
+
+struct dg_batch {
+    int nprob, eq;
+    dg_options opt;
+    std::vector<BatchProb> probs;
+    std::vector<unsigned int> order_lpt, order_natural;
+    size_t state_bytes, ws_bytes;
+    size_t off_probs, off_order, off_queue, off_ctrl, off_report, off_backup;
+    void* u[3];
+    unsigned char* ws;
+    bool bound;
+    hipStream_t st;
+    int grid;          // persistent workgroups
+    int use_lpt;       // queue order
+    int cus;           // compute units of the device
+};
+
+namespace {
+
+size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+#define DG_HIP(call)                                \
+    do {                                            \
+        hipError_t e_ = (call);                     \
+        if (e_ != hipSuccess) return DG_ERR_DEVICE; \
+    } while (0)
+
+BatchArgs batch_args(const dg_batch* b, long long steps)
+{
+    BatchArgs a;
+    memset(&a, 0, sizeof a);
+    for (int i = 0; i < 3; ++i) a.u[i] = b->u[i];
+    a.probs = reinterpret_cast<const BatchProb*>(b->ws + b->off_probs);
+    a.order = reinterpret_cast<const unsigned int*>(b->ws + b->off_order);
+    a.queue = reinterpret_cast<unsigned int*>(b->ws + b->off_queue);
+    a.ctrl = reinterpret_cast<Ctrl*>(b->ws + b->off_ctrl);
+    a.report = reinterpret_cast<BatchReport*>(b->ws + b->off_report);
+    a.nprob = b->nprob;
+    a.steps = steps;
+    a.cfl = b->opt.cfl;
+    a.phys.gamma = b->opt.gamma;
+    return a;
+}
+
+int upload_order(dg_batch* b, int lpt)
+{
+    const std::vector<unsigned int>& o = lpt ? b->order_lpt : b->order_natural;
+    DG_HIP(hipMemcpy(b->ws + b->off_order, o.data(), o.size() * sizeof(unsigned int),
+                     hipMemcpyHostToDevice));
+    b->use_lpt = lpt;
+    return DG_OK;
+}
+
+// Clear the queue head and the per-problem error latches (stream ordered).
+int reset_run(dg_batch* b)
+{
+    DG_HIP(hipMemsetAsync(b->ws + b->off_queue, 0, 256, b->st));
+    DG_HIP(hipMemsetAsync(b->ws + b->off_ctrl, 0, (size_t)b->nprob * sizeof(Ctrl), b->st));
+    return DG_OK;
+}
+
+int launch(dg_batch* b, long long steps)
+{
+    const int mode = b->opt.filter == DG_FILTER_NONE ? 0 : 1;
+    DG_HIP(launch_batch1d(b->opt.precision == DG_PREC_MIXED, mode, batch_args(b, steps), b->grid, b->st));
+    return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dg_batch_create(int nprob, dg_problem1d* probs, int equation, const dg_options* opt,
+                    int64_t* total_elems, dg_batch** out)
+{
+    if (!out) return DG_ERR_ARG;
+    *out = nullptr;
+    if (nprob < 1 || !probs || !opt || !total_elems) return DG_ERR_ARG;
+    if (equation != DG_EQ_EULER) return DG_ERR_UNSUPPORTED;
+    if (opt->filter == DG_FILTER_HYBRID) return DG_ERR_UNSUPPORTED;
+    if (opt->precision != DG_PREC_FP64 && opt->precision != DG_PREC_MIXED) return DG_ERR_ARG;
+    if (!(opt->cfl > 0.0) || !(opt->gamma > 1.0)) return DG_ERR_ARG;
+    dg_batch* b = new (std::nothrow) dg_batch();
+    if (!b) return DG_ERR_ARG;
+    b->nprob = nprob;
+    b->eq = equation;
+    b->opt = *opt;
+    b->probs.resize(nprob);
+    long long ext = 0;
+    size_t off = 0;
+    for (int i = 0; i < nprob; ++i) {
+        const dg_problem1d& p = probs[i];
+        const bool per = p.bc[0] == DG_BC_PERIODIC, per1 = p.bc[1] == DG_BC_PERIODIC;
+        if (p.n < 1 || p.degree < 0 || p.degree > 3 || !(p.hi > p.lo) || per != per1 || p.bc[0] < 0 ||
+            p.bc[0] > 2 || p.bc[1] < 0 || p.bc[1] > 2) {
+            delete b;
+            return p.degree > 3 ? DG_ERR_UNSUPPORTED : DG_ERR_ARG;
+        }
+        BatchProb& q = b->probs[i];
+        memset(&q, 0, sizeof q);
+        q.n = p.n;
+        q.n_pad = (p.n + 63) / 64 * 64;
+        q.k = p.degree;
+        q.bc_lo = p.bc[0];
+        q.bc_hi = p.bc[1];
+        q.lo = p.lo;
+        q.h = (p.hi - p.lo) / (double)p.n;
+        q.inv_h = 1.0 / q.h;
+        q.t_end = INFINITY;
+        q.off_ext = ext;
+        probs[i].offset = ext;
+        ext += 3LL * (p.degree + 1) * p.n;
+        q.off_int = (long long)off;
+        const size_t bytes = opt->precision == DG_PREC_FP64
+                                 ? 3 * (size_t)(p.degree + 1) * q.n_pad * 8
+                                 : 3 * (size_t)q.n_pad * 8 + 3 * (size_t)p.degree * q.n_pad * 4;
+        off += a256(bytes);
+    }
+    *total_elems = ext;
+    b->state_bytes = a256(off);
+    size_t w = 0;
+    b->off_probs = w;
+    w += a256(sizeof(BatchProb) * nprob);
+    b->off_order = w;
+    w += a256(sizeof(unsigned int) * nprob);
+    b->off_queue = w;
+    w += 256;
+    b->off_ctrl = w;
+    w += a256(sizeof(Ctrl) * nprob);
+    b->off_report = w;
+    w += a256(sizeof(BatchReport) * nprob);
+    b->off_backup = w;
+    w += b->state_bytes;
+    b->ws_bytes = w;
+    // longest-processing-time-first queue: cost ~ n (k+1)^2
+    b->order_natural.resize(nprob);
+    std::iota(b->order_natural.begin(), b->order_natural.end(), 0u);
+    b->order_lpt = b->order_natural;
+    std::stable_sort(b->order_lpt.begin(), b->order_lpt.end(), [&](unsigned x, unsigned y) {
+        const double cx = (double)b->probs[x].n * (b->probs[x].k + 1) * (b->probs[x].k + 1);
+        const double cy = (double)b->probs[y].n * (b->probs[y].k + 1) * (b->probs[y].k + 1);
+        return cx > cy;
+    });
+    int dev = 0;
+    hipDeviceProp_t prop;
+    b->cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        b->cus = prop.multiProcessorCount;
+    b->grid = 2 * b->cus;
+    b->use_lpt = 1;
+    b->st = static_cast<hipStream_t>(opt->stream);
+    *out = b;
+    return DG_OK;
+}
+
+int dg_batch_destroy(dg_batch* b)
+{
+    if (!b) return DG_ERR_ARG;
+    delete b;
+    return DG_OK;
+}
+
+int dg_batch_buffer_sizes(const dg_batch* b, size_t* state_bytes, size_t* workspace_bytes)
+{
+    if (!b) return DG_ERR_ARG;
+    if (state_bytes) *state_bytes = b->state_bytes;
+    if (workspace_bytes) *workspace_bytes = b->ws_bytes;
+    return DG_OK;
+}
+
+int dg_batch_bind(dg_batch* b, void* u_n, void* u_a, void* u_b, void* workspace)
+{
+    if (!b || !u_n || !u_a || !u_b || !workspace) return DG_ERR_ARG;
+    void* ptrs[4] = {u_n, u_a, u_b, workspace};
+    for (void* p : ptrs)
+        if (((uintptr_t)p) & 255) return DG_ERR_ARG;
+    b->u[0] = u_n;
+    b->u[1] = u_a;
+    b->u[2] = u_b;
+    b->ws = static_cast<unsigned char*>(workspace);
+    DG_HIP(hipStreamSynchronize(b->st));
+    DG_HIP(hipMemcpy(b->ws + b->off_probs, b->probs.data(), sizeof(BatchProb) * b->nprob,
+                     hipMemcpyHostToDevice));
+    int rc = upload_order(b, b->use_lpt);
+    if (rc) return rc;
+    DG_HIP(hipMemset(b->ws + b->off_report, 0, sizeof(BatchReport) * b->nprob));
+    b->bound = true;
+    return DG_OK;
+}
+
+int dg_batch_set_state(dg_batch* b, const double* packed_dev)
+{
+    if (!b || !packed_dev) return DG_ERR_ARG;
+    if (!b->bound) return DG_ERR_STATE;
+    const BatchArgs a = batch_args(b, 0);
+    if (b->opt.precision == DG_PREC_MIXED)
+        DG_HIP(launch_batch_convert<float>(1, a, packed_dev, b->nprob, b->st));
+    else
+        DG_HIP(launch_batch_convert<double>(1, a, packed_dev, b->nprob, b->st));
+    return DG_OK;
+}
+
+int dg_batch_get_state(dg_batch* b, double* packed_dev)
+{
+    if (!b || !packed_dev) return DG_ERR_ARG;
+    if (!b->bound) return DG_ERR_STATE;
+    const BatchArgs a = batch_args(b, 0);
+    if (b->opt.precision == DG_PREC_MIXED)
+        DG_HIP(launch_batch_convert<float>(0, a, packed_dev, b->nprob, b->st));
+    else
+        DG_HIP(launch_batch_convert<double>(0, a, packed_dev, b->nprob, b->st));
+    return DG_OK;
+}
+
+int dg_batch_run(dg_batch* b, const double* t_end, int64_t steps, dg_report* per_problem)
+{
+    if (!b || steps < 0) return DG_ERR_ARG;
+    if (!b->bound) return DG_ERR_STATE;
+    DG_HIP(hipStreamSynchronize(b->st));
+    if (t_end) {
+        for (int i = 0; i < b->nprob; ++i) b->probs[i].t_end = t_end[i];
+        DG_HIP(hipMemcpy(b->ws + b->off_probs, b->probs.data(), sizeof(BatchProb) * b->nprob,
+                         hipMemcpyHostToDevice));
+    }
+    int rc = reset_run(b);
+    if (!rc) rc = launch(b, steps);
+    if (rc) return rc;
+    std::vector<BatchReport> rep(b->nprob);
+    DG_HIP(hipMemcpyAsync(rep.data(), b->ws + b->off_report, sizeof(BatchReport) * b->nprob,
+                          hipMemcpyDeviceToHost, b->st));
+    DG_HIP(hipStreamSynchronize(b->st));
+    int status = DG_OK;
+    for (int i = 0; i < b->nprob; ++i) {
+        if (rep[i].status && status == DG_OK) status = rep[i].status;
+        if (!per_problem) continue;
+        dg_report& r = per_problem[i];
+        memset(&r, 0, sizeof r);
+        r.steps = rep[i].steps;
+        r.t = rep[i].t;
+        r.dt_min = rep[i].dt_min;
+        r.dt_max = rep[i].dt_max;
+        for (int v = 0; v < 3; ++v) {
+            r.ledger[v] = rep[i].ledger[v];
+            r.boundary_flux[v] = rep[i].bflux[v];
+        }
+        r.min_rho = r.min_p = r.max_exponent = NAN;
+        r.status = rep[i].status;
+        r.first_bad_cell = rep[i].status ? rep[i].first_bad : -1;
+    }
+    return status;
+}
+
+// Autotuner: times `trial_steps` steps of the whole batch for every
+// candidate (persistent workgroups per compute unit x queue order), each
+// from the same saved state, keeps the fastest, restores the state and
+// writes a JSON summary to json (nullable, capacity cap).
+int dg_batch_tune(dg_batch* b, int64_t trial_steps, char* json, size_t cap)
+{
+    if (!b || trial_steps < 1) return DG_ERR_ARG;
+    if (!b->bound) return DG_ERR_STATE;
+    DG_HIP(hipStreamSynchronize(b->st));
+    DG_HIP(hipMemcpy(b->ws + b->off_backup, b->u[0], b->state_bytes, hipMemcpyDeviceToDevice));
+    const int factors[4] = {1, 2, 4, 8};
+    struct Cand {
+        int factor, lpt;
+        float ms;
+    };
+    std::vector<Cand> cands;
+    hipEvent_t e0, e1;
+    DG_HIP(hipEventCreate(&e0));
+    DG_HIP(hipEventCreate(&e1));
+    int rc = DG_OK;
+    for (int lpt = 1; lpt >= 0 && rc == DG_OK; --lpt) {
+        rc = upload_order(b, lpt);
+        for (int f = 0; f < 4 && rc == DG_OK; ++f) {
+            b->grid = factors[f] * b->cus;
+            if (hipMemcpyAsync(b->u[0], b->ws + b->off_backup, b->state_bytes, hipMemcpyDeviceToDevice,
+                               b->st) != hipSuccess)
+                rc = DG_ERR_DEVICE;
+            if (!rc) rc = reset_run(b);
+            if (!rc && hipEventRecord(e0, b->st) != hipSuccess) rc = DG_ERR_DEVICE;
+            if (!rc) rc = launch(b, trial_steps);
+            if (!rc && hipEventRecord(e1, b->st) != hipSuccess) rc = DG_ERR_DEVICE;
+            if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = DG_ERR_DEVICE;
+            float ms = 0.f;
+            if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = DG_ERR_DEVICE;
+            cands.push_back({factors[f], lpt, ms});
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (hipMemcpy(b->u[0], b->ws + b->off_backup, b->state_bytes, hipMemcpyDeviceToDevice) != hipSuccess)
+        rc = DG_ERR_DEVICE;
+    if (rc) return rc;
+    const Cand* best = &cands[0];
+    for (const Cand& c : cands)
+        if (c.ms < best->ms) best = &c;
+    b->grid = best->factor * b->cus;
+    rc = upload_order(b, best->lpt);
+    if (json && cap) {
+        size_t used = 0;
+        auto put = [&](const char* fmt, auto... args) {
+            if (used < cap) {
+                int w = snprintf(json + used, cap - used, fmt, args...);
+                if (w > 0) used += (size_t)w;
+            }
+        };
+        put("{\"trial_steps\": %lld, \"candidates\": [", (long long)trial_steps);
+        for (size_t i = 0; i < cands.size(); ++i)
+            put("%s{\"wg_per_cu\": %d, \"order\": \"%s\", \"ms\": %.4f}", i ? ", " : "", cands[i].factor,
+                cands[i].lpt ? "lpt" : "natural", cands[i].ms);
+        put("], \"best\": {\"wg_per_cu\": %d, \"order\": \"%s\", \"ms\": %.4f}}", best->factor,
+            best->lpt ? "lpt" : "natural", best->ms);
+    }
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,279 @@
+// dg_batch_kernel.h — many independent 1D problems of different size and
+// degree in one persistent launch (gfx950).
+//
+// Each workgroup pulls whole problems from an atomic queue (the host orders
+// the queue longest-first, by cost n (k+1)^2 steps) and advances each one
+// through all of its time steps on its own: a CFL reduction over the
+// workgroup, then the three fused SSP-RK3 stage + jump-filter passes, each a
+// loop over the problem's 252-cell tiles with a workgroup barrier between
+// stages.  No grid-wide synchronisation is needed: a problem never leaves its
+// workgroup.
+// (included at the end of dg1d.hip: it reuses the 1D tile function)
+#include "dg_batch.h"
+
+namespace dg {
+
+namespace {
+
+__device__ __forceinline__ double block_max256(double v, double* red)
+{
+    v = wave_max(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double r = red[0];
+#pragma unroll
+    for (int i = 1; i < 4; ++i) r = (red[i] > r || red[i] != red[i]) ? red[i] : r;
+    __syncthreads();
+    return r;
+}
+
+// Deterministic block sum: fixed strided partial sums, fixed-order tree.
+__device__ __forceinline__ double block_sum256(double v, double* tree)
+{
+    tree[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) tree[threadIdx.x] += tree[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double r = tree[0];
+    __syncthreads();
+    return r;
+}
+
+template <typename TB>
+__device__ __forceinline__ StateView<TB> prob_view(void* base, const BatchProb& p, int k)
+{
+    StateView<TB> v;
+    unsigned char* b = static_cast<unsigned char*>(base) + p.off_int;
+    v.m0 = reinterpret_cast<double*>(b);
+    v.s0 = p.n_pad;
+    v.hi = reinterpret_cast<TB*>(v.m0 + 3 * p.n_pad);
+    v.sv = (int64_t)k * p.n_pad;
+    v.sl = p.n_pad;
+    return v;
+}
+
+template <int K, typename TB, int MODE>
+__device__ void solve_problem(const BatchArgs& b, const BatchProb& pr, unsigned int pidx,
+                              unsigned char* lds, double* red, double* tree, double* sflux)
+{
+    constexpr int TILE = MODE == 0 ? 254 : 252;
+    StateView<TB> A = prob_view<TB>(b.u[0], pr, K);
+    StateView<TB> B = prob_view<TB>(b.u[1], pr, K);
+    const StateView<TB> Cv = prob_view<TB>(b.u[2], pr, K);
+    const StateView<TB> A0 = A, B0 = B;
+    Ctrl* ctrl = &b.ctrl[pidx];
+    const int64_t n = pr.n;
+    const int64_t ntiles = (n + TILE - 1) / TILE;
+
+    Args1D<TB> a;
+    a.n = n;
+    a.inv_h = pr.inv_h;
+    a.periodic = pr.bc_lo == BC_PERIODIC;
+    a.bc_lo = pr.bc_lo;
+    a.bc_hi = pr.bc_hi;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) a.dir_lo[v] = a.dir_hi[v] = 0.0;
+    a.phys = b.phys;
+    a.dt_from_ctrl = 0;
+    a.check = 1;
+    a.ctrl = ctrl;
+    a.bflux = sflux;
+    a.alpha_acc = nullptr;
+    a.eta_acc = nullptr;
+    a.tcount = nullptr;
+    a.tcell = nullptr;
+    a.tdata = nullptr;
+    a.E_out = nullptr;
+    a.eta_out = nullptr;
+
+    // CFL quantity of the initial state
+    double lam = 0.0;
+    for (int64_t c = threadIdx.x; c < n; c += 256) {
+        double ub[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) ub[v] = A.m0[v * A.s0 + c];
+        const double l = Phys1D<EULER>::speed(ub, b.phys);
+        lam = (l > lam || l != l) ? l : lam;
+    }
+    double alpha = block_max256(lam, red);
+
+    double t = 0.0, dtmin = INFINITY, dtmax = 0.0;
+    double bfl[3] = {0.0, 0.0, 0.0};
+    long long steps = 0;
+    const double t_end = pr.t_end;
+    while (steps < b.steps && t < t_end) {
+        if (ctrl->status != 0) break;
+        double dt = b.cfl * pr.h / alpha;
+        if (!(dt > 0.0) || !isfinite(dt)) {
+            if (threadIdx.x == 0) latch_error(ctrl, -4, -1);
+            break;
+        }
+        bool last = false;
+        if (t + dt >= t_end) {
+            dt = t_end - t;
+            last = true;
+        }
+        double net[3] = {0.0, 0.0, 0.0};
+        for (int s = 0; s < 3; ++s) {
+            a.un = A;
+            a.us = s == 0 ? A : s == 1 ? B : Cv;
+            a.out = s == 1 ? Cv : B;
+            a.stage = s;
+            if (threadIdx.x < 8) sflux[threadIdx.x] = 0.0;
+            __syncthreads();
+            double lmax = 0.0;
+            for (int64_t tile = 0; tile < ntiles; ++tile) {
+                double l, e;
+                stage1d_tile<EULER, K, TB, MODE>(a, tile, dt, lds, &l, &e);
+                lmax = (l > lmax || l != l) ? l : lmax;
+                __syncthreads();  // the next tile reuses the LDS
+            }
+#pragma unroll
+            for (int v = 0; v < 3; ++v) net[v] += kStageWeight[s] * (sflux[4 + v] - sflux[v]);
+            if (s == 2) alpha = block_max256(lmax, red);
+        }
+#pragma unroll
+        for (int v = 0; v < 3; ++v) bfl[v] += dt * net[v];
+        t = last ? t_end : t + dt;
+        ++steps;
+        dtmin = dt < dtmin ? dt : dtmin;
+        dtmax = dt > dtmax ? dt : dtmax;
+        const StateView<TB> tmp = A;  // the step's output is in B
+        A = B;
+        B = tmp;
+    }
+    if (steps & 1) {
+        // the solution sits in the second buffer: copy it to the first
+        for (int64_t c = threadIdx.x; c < n; c += 256)
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                A0.m0[v * A0.s0 + c] = B0.m0[v * B0.s0 + c];
+#pragma unroll
+                for (int l = 1; l <= K; ++l)
+                    A0.hi[v * A0.sv + (l - 1) * A0.sl + c] = B0.hi[v * B0.sv + (l - 1) * B0.sl + c];
+            }
+        __syncthreads();
+    }
+    // FP64 ledger of the final state
+    double led[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        double acc = 0.0;
+        for (int64_t c = threadIdx.x; c < n; c += 256) acc += A0.m0[v * A0.s0 + c];
+        led[v] = pr.h * block_sum256(acc, tree);
+    }
+    if (threadIdx.x == 0) {
+        BatchReport& r = b.report[pidx];
+        r.steps = steps;
+        r.t = t;
+        r.dt_min = dtmin;
+        r.dt_max = dtmax;
+        for (int v = 0; v < 3; ++v) {
+            r.ledger[v] = led[v];
+            r.bflux[v] = bfl[v];
+        }
+        r.status = ctrl->status;
+        r.first_bad = ctrl->first_bad;
+    }
+}
+
+template <typename TB, int MODE>
+struct BatchLds {
+    static constexpr int a = Stage1DLds<EULER, 0, TB, MODE>::bytes;
+    static constexpr int b = Stage1DLds<EULER, 1, TB, MODE>::bytes;
+    static constexpr int c = Stage1DLds<EULER, 2, TB, MODE>::bytes;
+    static constexpr int d = Stage1DLds<EULER, 3, TB, MODE>::bytes;
+    static constexpr int ab = a > b ? a : b;
+    static constexpr int cd = c > d ? c : d;
+    static constexpr int bytes = ab > cd ? ab : cd;
+};
+
+}  // namespace
+
+template <typename TB, int MODE>
+__global__ __launch_bounds__(256) void batch1d_kernel(BatchArgs b)
+{
+    __shared__ __align__(16) unsigned char lds[BatchLds<TB, MODE>::bytes];
+    __shared__ double red[4];
+    __shared__ double tree[256];
+    __shared__ double sflux[8];
+    __shared__ unsigned int s_pi;
+    for (;;) {
+        if (threadIdx.x == 0) s_pi = atomicAdd(b.queue, 1u);
+        __syncthreads();
+        const unsigned int pi = s_pi;
+        __syncthreads();
+        if (pi >= (unsigned int)b.nprob) break;
+        const unsigned int p = b.order[pi];
+        const BatchProb pr = b.probs[p];
+        switch (pr.k) {
+        case 0: solve_problem<0, TB, MODE>(b, pr, p, lds, red, tree, sflux); break;
+        case 1: solve_problem<1, TB, MODE>(b, pr, p, lds, red, tree, sflux); break;
+        case 2: solve_problem<2, TB, MODE>(b, pr, p, lds, red, tree, sflux); break;
+        default: solve_problem<3, TB, MODE>(b, pr, p, lds, red, tree, sflux); break;
+        }
+        __syncthreads();
+    }
+}
+
+// FP64 exchange layout (problems packed back to back, [var][mode][cell])
+// <-> the internal per-problem blocks; one workgroup per problem.
+template <typename TB>
+__global__ __launch_bounds__(256) void batch_convert_kernel(int to_internal, BatchArgs b, double* ext)
+{
+    const BatchProb pr = b.probs[blockIdx.x];
+    const StateView<TB> v = prob_view<TB>(b.u[0], pr, pr.k);
+    const int K1 = pr.k + 1;
+    const long long total = 3LL * K1 * pr.n;
+    for (long long i = threadIdx.x; i < total; i += 256) {
+        const long long c = i % pr.n;
+        const int l = (int)((i / pr.n) % K1);
+        const int var = (int)(i / (pr.n * K1));
+        double* e = ext + pr.off_ext + i;
+        if (l == 0) {
+            double* p = v.m0 + var * v.s0 + c;
+            if (to_internal)
+                *p = *e;
+            else
+                *e = *p;
+        } else {
+            TB* p = v.hi + var * v.sv + (long long)(l - 1) * v.sl + c;
+            if (to_internal)
+                *p = (TB)*e;
+            else
+                *e = (double)*p;
+        }
+    }
+}
+
+template <typename TB>
+hipError_t launch_batch_convert(int to_internal, const BatchArgs& b, const double* ext, int nprob,
+                                hipStream_t st)
+{
+    hipLaunchKernelGGL((batch_convert_kernel<TB>), dim3(nprob), dim3(256), 0, st, to_internal, b,
+                       const_cast<double*>(ext));
+    return hipGetLastError();
+}
+template hipError_t launch_batch_convert<double>(int, const BatchArgs&, const double*, int, hipStream_t);
+template hipError_t launch_batch_convert<float>(int, const BatchArgs&, const double*, int, hipStream_t);
+
+hipError_t launch_batch1d(int mixed, int mode, const BatchArgs& b, int grid, hipStream_t st)
+{
+    if (mixed) {
+        if (mode == 0)
+            hipLaunchKernelGGL((batch1d_kernel<float, 0>), dim3(grid), dim3(256), 0, st, b);
+        else
+            hipLaunchKernelGGL((batch1d_kernel<float, 1>), dim3(grid), dim3(256), 0, st, b);
+    } else {
+        if (mode == 0)
+            hipLaunchKernelGGL((batch1d_kernel<double, 0>), dim3(grid), dim3(256), 0, st, b);
+        else
+            hipLaunchKernelGGL((batch1d_kernel<double, 1>), dim3(grid), dim3(256), 0, st, b);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dg
