@@ -98,6 +98,11 @@ typedef struct {
     double adv_speed[2];     /* advection velocity (DG_EQ_ADVECTION)              */
     int quad_points;         /* Gauss points per direction; 0 or degree+1         */
     void* stream;            /* hipStream_t; NULL = null stream                   */
+    int cf_mesh_factor;      /* 2D damping coefficient (c_fx, c_fy):
+                                0 (default): beta_x / (4 lambda H), beta_y / (4 lambda H),
+                                  so a one-dimensional state is filtered exactly as
+                                  by the 1D filter;
+                                1: times (h_x, h_y) as printed in Sec. 2.4 */
 } dg_options;
 
 /* Filled by dg_run / dg_report_read. */

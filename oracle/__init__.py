@@ -41,7 +41,7 @@ class Problem1D(C.Structure):
                 ("filter_dt", C.c_int), ("bc", C.c_int * 2), ("n", C.c_int64),
                 ("lo", C.c_double), ("hi", C.c_double), ("gamma", C.c_double),
                 ("adv_speed", C.c_double), ("cfl", C.c_double),
-                ("dirichlet", (C.c_double * 3) * 2)]
+                ("dirichlet", (C.c_double * 3) * 2), ("pp", C.c_int)]
 
 
 class Problem2D(C.Structure):
@@ -98,8 +98,9 @@ def nvars(eq: int, dim: int = 1) -> int:
 
 
 def problem1d(eq, k, n, lo, hi, bc=(PERIODIC, PERIODIC), filter=FILTER_JUMP, cfl=0.1,
-              gamma=1.4, adv_speed=1.0, nq=0, filter_dt=0, dirichlet=None) -> Problem1D:
+              gamma=1.4, adv_speed=1.0, nq=0, filter_dt=0, dirichlet=None, pp=0) -> Problem1D:
     P = Problem1D()
+    P.pp = pp
     P.eq, P.k, P.nq, P.filter, P.filter_dt = eq, k, nq, filter, filter_dt
     P.bc[0], P.bc[1] = bc
     P.n, P.lo, P.hi, P.gamma, P.adv_speed, P.cfl = n, lo, hi, gamma, adv_speed, cfl
@@ -112,7 +113,7 @@ def problem1d(eq, k, n, lo, hi, bc=(PERIODIC, PERIODIC), filter=FILTER_JUMP, cfl
 
 def problem2d(eq, k, nx, ny, xlo, xhi, ylo, yhi, bc=(PERIODIC,) * 4, filter=FILTER_JUMP,
               cfl=0.1, gamma=1.4, adv_speed=(1.0, 1.0), nq=0, filter_dt=0,
-              dirichlet=None, shock_x0=0.0, shock_speed=0.0, post=None, pre=None, cf_mesh=1,
+              dirichlet=None, shock_x0=0.0, shock_speed=0.0, post=None, pre=None, cf_mesh=0,
               basis=0, cf_scale=1.0) -> Problem2D:
     P = Problem2D()
     P.cf_mesh, P.basis, P.cf_scale = cf_mesh, basis, cf_scale

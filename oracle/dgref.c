@@ -332,7 +332,7 @@ int dgref_residual1d(const dgref_problem1d* P, const double* u, double* L, doubl
     double* fh = (double*)malloc(sizeof(double) * (size_t)nv * (size_t)(n + 1));
     if (!fh) return DGREF_ERR_ARG;
 
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= 4096)
     for (int64_t i = 0; i <= n; ++i) {
         double ul[MAXV], ur[MAXV], f[MAXV];
         iface1d(P, &B, u, i, 0, h, ul, ur);
@@ -340,7 +340,7 @@ int dgref_residual1d(const dgref_problem1d* P, const double* u, double* L, doubl
         for (int v = 0; v < nv; ++v) fh[(size_t)v * (size_t)(n + 1) + (size_t)i] = f[v];
     }
 
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= 4096)
     for (int64_t j = 0; j < n; ++j) {
         double fq[MAXQ][MAXV];
         for (int q = 0; q < B.nq; ++q) {
@@ -439,7 +439,7 @@ int dgref_exponents1d(const dgref_problem1d* P, double dt, const double* v, doub
     /* |[d^m u]| at every interface: jmp[(i*(k+1) + m)*nv + var] */
     double* jmp = (double*)malloc(sizeof(double) * (size_t)(n + 1) * (size_t)(k + 1) * nv);
     if (!jmp) return DGREF_ERR_ARG;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= 4096)
     for (int64_t i = 0; i <= n; ++i)
         for (int m = 0; m <= k; ++m) {
             double a[MAXV], b[MAXV];
@@ -448,7 +448,7 @@ int dgref_exponents1d(const dgref_problem1d* P, double dt, const double* v, doub
                 jmp[((size_t)i * (size_t)(k + 1) + (size_t)m) * nv + s] = fabs(b[s] - a[s]);
         }
 
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= 4096)
     for (int64_t j = 0; j < n; ++j) {
         /* ||[d^m u^(s)]||_{dK_j}: sum of the two interface jumps */
         double J[MAXK + 1][MAXV];
@@ -556,6 +556,115 @@ int dgref_hybrid1d(const dgref_problem1d* P, double dt, const double* v, double*
  * Reading of the damping duration: the split viscous problem is advanced
  * over the full step dt after every stage (filter_dt = 0); filter_dt = 1
  * uses the stage's own weight (1, 1/4, 2/3) of dt instead. */
+/* ------------------------------------------------------------------------ */
+/* Positivity-preserving limiter (Zhang and Shu; used after the filter in    */
+/* the paper's Sec. 3.2 examples with extreme positivity demands)            */
+/* ------------------------------------------------------------------------ */
+
+/* Test points of a cell: the Gauss-Lobatto points with N = ceil((k+3)/2)
+ * (they include both ends, where the fluxes are evaluated, and their rule
+ * is exact for degree k, so the cell average is a convex combination of
+ * the point values) and the Gauss points of the volume quadrature.
+ * Gauss-Lobatto nodes: +-1 and the roots of P_{N-1}'. */
+static int pp_points(const dgref_problem1d* P, double* xs)
+{
+    int N = (P->k + 4) / 2;
+    if (N < 2) N = 2;
+    int cnt = 0;
+    xs[cnt++] = -1.0;
+    xs[cnt++] = 1.0;
+    if (N == 3) xs[cnt++] = 0.0;
+    if (N == 4) {
+        xs[cnt++] = -sqrt(0.2);
+        xs[cnt++] = sqrt(0.2);
+    }
+    double xg[MAXQ], wg[MAXQ];
+    int nq = P->nq ? P->nq : P->k + 1;
+    dgref_gauss(nq, xg, wg);
+    for (int q = 0; q < nq; ++q) xs[cnt++] = xg[q];
+    return cnt;
+}
+
+static void point_state1d(const dgref_problem1d* P, const double* u, int64_t j, double xi,
+                          double* w)
+{
+    const int K1 = P->k + 1;
+    const int64_t n = P->n;
+    for (int v = 0; v < 3; ++v) {
+        double s = 0.0;
+        for (int l = 0; l < K1; ++l) s += U1(u, v, l, j) * dgref_legendre_deriv(l, 0, xi);
+        w[v] = s;
+    }
+}
+
+static double pressure_of(double gamma, const double* w)
+{
+    return (gamma - 1.0) * (w[2] - 0.5 * w[1] * w[1] / w[0]);
+}
+
+/* Limit cell j of u in place: scale the density's higher modes so the
+ * density at every test point is >= eps, then all higher modes so the
+ * pressure is >= eps (for each point the largest t in [0,1] with
+ * p(u_bar + t (u(x) - u_bar)) >= eps, found by bisection; p is concave along
+ * that segment).  eps = min(1e-13, rho_bar, p(u_bar)).  Cell averages are
+ * not changed. */
+static void pp_limit_cell(const dgref_problem1d* P, double* u, int64_t j)
+{
+    const int K1 = P->k + 1;
+    const int64_t n = P->n;
+    double ub[3];
+    for (int v = 0; v < 3; ++v) ub[v] = U1(u, v, 0, j);
+    double pb = pressure_of(P->gamma, ub);
+    if (!(ub[0] > 0.0) || !(pb > 0.0)) return; /* inadmissible average: not limitable */
+    double eps = 1e-13;
+    if (ub[0] < eps) eps = ub[0];
+    if (pb < eps) eps = pb;
+    double xs[16];
+    int np = pp_points(P, xs);
+    /* density */
+    double rmin = INFINITY;
+    for (int i = 0; i < np; ++i) {
+        double w[3];
+        point_state1d(P, u, j, xs[i], w);
+        if (w[0] < rmin) rmin = w[0];
+    }
+    if (rmin < eps) {
+        double th = (ub[0] - eps) / (ub[0] - rmin);
+        if (th < 0.0) th = 0.0;
+        for (int l = 1; l < K1; ++l) U1(u, 0, l, j) *= th;
+    }
+    /* pressure */
+    double theta = 1.0;
+    for (int i = 0; i < np; ++i) {
+        double w[3];
+        point_state1d(P, u, j, xs[i], w);
+        if (pressure_of(P->gamma, w) >= eps) continue;
+        double lo = 0.0, hi = 1.0;
+        for (int it = 0; it < 60; ++it) {
+            double mid = 0.5 * (lo + hi), wm[3];
+            for (int v = 0; v < 3; ++v) wm[v] = ub[v] + mid * (w[v] - ub[v]);
+            if (pressure_of(P->gamma, wm) >= eps)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        if (lo < theta) theta = lo;
+    }
+    if (theta < 1.0)
+        for (int v = 0; v < 3; ++v)
+            for (int l = 1; l < K1; ++l) U1(u, v, l, j) *= theta;
+}
+
+int dgref_pp_limit1d(const dgref_problem1d* P, double* u)
+{
+    int rc = check1d(P);
+    if (rc) return rc;
+    if (P->eq != DGREF_EULER) return DGREF_OK;
+#pragma omp parallel for schedule(static) if (P->n >= 4096)
+    for (int64_t j = 0; j < P->n; ++j) pp_limit_cell(P, u, j);
+    return DGREF_OK;
+}
+
 int dgref_post1d(const dgref_problem1d* P, int stage, double dt, const double* v,
                  double* out, int64_t* troubled)
 {
@@ -564,10 +673,14 @@ int dgref_post1d(const dgref_problem1d* P, int stage, double dt, const double* v
     if (rc) return rc;
     double tau = (P->filter_dt == 1) ? dt * stage_weight[stage] : dt;
     const size_t ndof = (size_t)dgref_nvars(P->eq, 1) * (size_t)(P->k + 1) * (size_t)P->n;
-    if (P->filter == DGREF_FILTER_JUMP) return dgref_filter1d(P, tau, v, out);
-    if (P->filter == DGREF_FILTER_HYBRID) return dgref_hybrid1d(P, tau, v, out, troubled);
-    if (out != v) memcpy(out, v, sizeof(double) * ndof);
-    return DGREF_OK;
+    if (P->filter == DGREF_FILTER_JUMP)
+        rc = dgref_filter1d(P, tau, v, out);
+    else if (P->filter == DGREF_FILTER_HYBRID)
+        rc = dgref_hybrid1d(P, tau, v, out, troubled);
+    else if (out != v)
+        memcpy(out, v, sizeof(double) * ndof);
+    if (!rc && P->pp) rc = dgref_pp_limit1d(P, out);
+    return rc;
 }
 
 /* One SSP-RK3 step with the post-stage operator after each stage (err_rk1,

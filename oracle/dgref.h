@@ -43,6 +43,7 @@ typedef struct {
     double adv_speed;    /* a in f(u) = a u (advection)                        */
     double cfl;          /* dt = cfl * h / alpha                               */
     double dirichlet[2][3]; /* prescribed boundary states (conserved vars)     */
+    int pp;              /* 1: positivity-preserving limiter after the filter   */
 } dgref_problem1d;
 
 typedef struct {
@@ -99,6 +100,7 @@ int dgref_hybrid1d(const dgref_problem1d* P, double dt, const double* v, double*
                    int64_t* troubled);
 int dgref_post1d(const dgref_problem1d* P, int stage, double dt, const double* v,
                  double* out, int64_t* troubled);
+int dgref_pp_limit1d(const dgref_problem1d* P, double* u);
 int dgref_step1d(const dgref_problem1d* P, double dt, double* u, double* bflux,
                  int64_t* troubled);
 int dgref_run1d(const dgref_problem1d* P, double t_end, int64_t max_steps, double* u,

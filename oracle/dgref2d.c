@@ -341,7 +341,7 @@ int dgref_residual2d(const dgref_problem2d* P, double t, const double* u, double
     ctx2d C;
     int rc = make_ctx(P, &C);
     if (rc) return rc;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (C.nx * C.ny >= 4096)
     for (int64_t jy = 0; jy < C.ny; ++jy)
         for (int64_t ix = 0; ix < C.nx; ++ix) {
             double Lc[MAXV][NMAX];
@@ -381,7 +381,7 @@ int dgref_stage2d(const dgref_problem2d* P, int stage, double t, double dt, cons
     if (stage < 0 || stage > 2) return DGREF_ERR_ARG;
     const double* src = stage == 0 ? un : us;
     const double ts = t + ct[stage] * dt;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (C.nx * C.ny >= 4096)
     for (int64_t jy = 0; jy < C.ny; ++jy)
         for (int64_t ix = 0; ix < C.nx; ++ix) {
             double Lc[MAXV][NMAX];
@@ -454,7 +454,12 @@ static void cell_jumps(const ctx2d* C, double t, const double* u, int64_t ix, in
 /* Damping exponents of one cell for every mode (p, q) (Sec. 2.3, mode-
  * dependent coefficient (para:damp22d)-(para:damp22d1); systems Sec. 2.4:
  * max over components; Euler (Sec. 2.4): (c_fx, c_fy) =
- * (hx beta_x, hy beta_y) / (4 lambda_pq H-bar)).  Reading for Q^k: the
+ * (m_x beta_x, m_y beta_y) / (4 lambda_pq H-bar)).  Reading of the mesh
+ * factors (m_x, m_y): the text prints (h_x, h_y), which makes the 2D
+ * exponent h times the 1D one for the same jumps; cf_mesh = 0 (default)
+ * takes (1, 1), with which the 2D filter of a state varying along one axis
+ * on square cells is exactly the 1D filter; cf_mesh = 1 takes the printed
+ * factors.  Reading for Q^k: the
  * sums over |alpha| = m run over alpha1, alpha2 <= k.  Em[m] receives the
  * exponent of mode index m; eta the hybrid indicator (Reading:
  * Jx/(2hx) + Jy/(2hy), max over components, which reduces to Algorithm 1's
@@ -521,7 +526,7 @@ int dgref_exponents2d(const dgref_problem2d* P, double t, double dt, const doubl
     int rc = make_ctx(P, &C);
     if (rc) return rc;
     const int L1 = 2 * C.k + 1;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (C.nx * C.ny >= 4096)
     for (int64_t jy = 0; jy < C.ny; ++jy)
         for (int64_t ix = 0; ix < C.nx; ++ix) {
             double Em[NMAX], e;
@@ -558,7 +563,7 @@ int dgref_post2d(const dgref_problem2d* P, int stage, double t, double dt, const
         free(eta);
         return DGREF_ERR_ARG;
     }
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (C.nx * C.ny >= 4096)
     for (int64_t jy = 0; jy < C.ny; ++jy)
         for (int64_t ix = 0; ix < C.nx; ++ix) {
             size_t cell = (size_t)jy * C.nx + ix;

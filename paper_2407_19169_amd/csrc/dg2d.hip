@@ -709,7 +709,7 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
         for (int l = 0; l < L1; ++l) {
             sx += Jx[l];
             sy += Jy[l];
-            const T sv = (T)a.hx * bx * sx + (T)a.hy * by * sy;
+            const T sv = (T)a.cfmx * bx * sx + (T)a.cfmy * by * sy;
             best[l] = (v == 0 || sv > best[l]) ? sv : best[l];
         }
         const T ev = jx0 * (T)(0.5 * a.inv_hx) + jy0_ * (T)(0.5 * a.inv_hy);

@@ -122,6 +122,8 @@ Args2D<TB> base_args2d(const dg_solver* s)
     a.check = s->eq == DG_EQ_EULER;
     a.ctrl = ctrl_of(s);
     a.tcap = s->ncell;
+    a.cfmx = s->opt.cf_mesh_factor ? a.hx : 1.0;
+    a.cfmy = s->opt.cf_mesh_factor ? a.hy : 1.0;
     // jump weights of the multi-index (a1, a2), m = a1 + a2: hx (m = 0),
     // m(m+1) hx^(m+1) (2/hx)^a1 (2/hy)^a2 (x edges); likewise with hy
     for (int a1 = 0; a1 < 4; ++a1)

@@ -105,7 +105,7 @@ __device__ void solve_problem(const BatchArgs& b, const BatchProb& pr, unsigned 
     long long steps = 0;
     const double t_end = pr.t_end;
     while (steps < b.steps && t < t_end) {
-        if (ctrl->status != 0) break;
+        if (ctrl->status == -4) break;  // non-finite: stop; positivity: report only
         double dt = b.cfl * pr.h / alpha;
         if (!(dt > 0.0) || !isfinite(dt)) {
             if (threadIdx.x == 0) latch_error(ctrl, -4, -1);

@@ -58,6 +58,7 @@ struct Args2D {
     double* E_out;            // nullable: per-cell exponents, (2k+1) per cell
     double* eta_out;
     double jsx[16], jsy[16];  // jump weights per multi-index a1*4+a2 (see filter2d)
+    double cfmx, cfmy;        // mesh factors of (c_fx, c_fy): (hx, hy) as printed, or (1, 1)
 };
 
 template <typename TB>

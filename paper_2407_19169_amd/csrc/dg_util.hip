@@ -36,7 +36,9 @@ __global__ void step_ctrl_kernel(Ctrl* c, int finalize_only)
         c->active = 0;
     }
     if (finalize_only || c->done) return;
-    if (c->status != 0 || !(c->t < c->t_end) || c->steps >= c->max_steps) {
+    // a positivity violation is reported but does not stop the run; a
+    // non-finite value does
+    if (c->status == -4 || !(c->t < c->t_end) || c->steps >= c->max_steps) {
         c->done = 1;
         return;
     }

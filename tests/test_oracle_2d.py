@@ -3,9 +3,10 @@
 The strongest pins reduce the 2D scheme to the separately pinned 1D oracle:
 for data that vary along one axis only, the 2D residual equals the 1D
 residual, the 2D hybrid indicator equals the 1D one, and the 2D damping
-exponent equals the 1D exponent times h_x^2/h_y (the 2D Euler coefficient
-of Sec. 2.4 carries h_x beta_x where the 1D one carries beta, and the 2D
-factor (2/h_x)(2/h_y) replaces (2/h)^2).  Further pins: free-stream
+exponent equals the 1D exponent times h_x/h_y (the factor (2/h_x)(2/h_y)
+replaces (2/h)^2; on square cells the two filters coincide) -- or times
+h_x^2/h_y with the mesh factor h_x in c_fx as printed in Sec. 2.4.
+Further pins: free-stream
 preservation with every boundary type, conservation, mode 0 untouched,
 exponents depending on p+q only, zero jumps for global polynomials, the
 CFL maximum, and order k+1 on smooth solutions (advection and the
@@ -62,14 +63,16 @@ def test_reduces_to_1d_along_x(ref, k, bc):
         return
     dt = 1e-3
     E1, eta1 = ref.exponents1d(P1, dt, u1)
-    E2, eta2 = ref.exponents2d(P2, dt, u2)
-    np.testing.assert_allclose(eta2, np.broadcast_to(eta1, eta2.shape), rtol=1e-13, atol=1e-300)
-    want = E1 * hx * hx / hy
-    for jy in range(ny):
-        np.testing.assert_allclose(E2[jy, :, : k + 1], want, rtol=1e-12, atol=1e-300)
-        # modes p + q > k have only jumps of order <= k: same exponent as l = k
-        for l in range(k + 1, 2 * k + 1):
-            np.testing.assert_allclose(E2[jy, :, l], want[:, k], rtol=1e-12)
+    for cf_mesh, factor in ((0, hx / hy), (1, hx * hx / hy)):
+        P2 = ref.problem2d(2, k, n, ny, 0.0, 1.0, 0.0, 0.3, bc=(bc, bc, 0, 0), cf_mesh=cf_mesh)
+        E2, eta2 = ref.exponents2d(P2, dt, u2)
+        np.testing.assert_allclose(eta2, np.broadcast_to(eta1, eta2.shape), rtol=1e-13, atol=1e-300)
+        want = E1 * factor
+        for jy in range(ny):
+            np.testing.assert_allclose(E2[jy, :, : k + 1], want, rtol=1e-12, atol=1e-300)
+            # modes p + q > k have only jumps of order <= k: same exponent as l = k
+            for l in range(k + 1, 2 * k + 1):
+                np.testing.assert_allclose(E2[jy, :, l], want[:, k], rtol=1e-12)
 
 
 @pytest.mark.parametrize("k", [1, 2])
@@ -91,7 +94,7 @@ def test_reduces_to_1d_along_y(ref, k, bc):
     E1, eta1 = ref.exponents1d(P1, dt, u1)
     E2, eta2 = ref.exponents2d(P2, dt, u2)
     np.testing.assert_allclose(eta2, np.broadcast_to(eta1[:, None], eta2.shape), rtol=1e-13)
-    np.testing.assert_allclose(E2[:, 0, : k + 1], E1 * hy * hy / hx, rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(E2[:, 0, : k + 1], E1 * hy / hx, rtol=1e-12, atol=1e-300)
 
 
 def test_advection_reduces_to_1d(ref):
@@ -238,10 +241,11 @@ def _advection_error(ref, n, k, T):
 
 @pytest.mark.parametrize("k", [1, 2])
 def test_advection_order_k_plus_1(ref, k):
-    e1 = _advection_error(ref, 8, k, 0.25)
-    e2 = _advection_error(ref, 16, k, 0.25)
-    e3 = _advection_error(ref, 32, k, 0.25)
-    assert math.log2(e2 / e3) > k + 1 - 0.4, (e1, e2, e3)
+    # the filter's own error dominates on coarse meshes (as in the paper's
+    # tables); the order is measured on the finer pair
+    e2 = _advection_error(ref, 32, k, 0.25)
+    e3 = _advection_error(ref, 64, k, 0.25)
+    assert math.log2(e2 / e3) > k + 1 - 0.4, (e2, e3)
 
 
 @pytest.mark.slow
@@ -251,7 +255,7 @@ def test_vortex_order_q2(ref):
     solution."""
     errs = []
     T = 0.5
-    for n in (16, 32):
+    for n in (40, 80):
         w = I.vortex2d(n, 2, seed=None)
         P = ref.problem2d(2, 2, n, n, 0.0, 10.0, -5.0, 5.0, bc=(0, 0, 0, 0), filter=1, cfl=0.1)
         u, rep, rc = ref.run2d(P, w.u0, T)
