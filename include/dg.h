@@ -103,6 +103,15 @@ typedef struct {
                                   so a one-dimensional state is filtered exactly as
                                   by the 1D filter;
                                 1: times (h_x, h_y) as printed in Sec. 2.4 */
+    int positivity;          /* 1D Euler: 1 = Zhang-Shu positivity-preserving limiter
+                                after the post-stage operator (Sec. 3.2 uses it for
+                                extreme cases): density and pressure kept positive at
+                                each cell's Gauss-Lobatto and Gauss points.  A step
+                                whose stage leaves an inadmissible cell average is
+                                undone and retried with half the time step (at most
+                                40 times; then the run stops with DG_ERR_POSITIVITY).
+                                Positivity reports then concern cell averages only.
+                                0 = off.  Other equations / 2D: DG_ERR_UNSUPPORTED. */
 } dg_options;
 
 /* Filled by dg_run / dg_report_read. */
@@ -117,6 +126,7 @@ typedef struct {
     double max_exponent;     /* largest damping exponent applied                  */
     int status;              /* first error latched on the device (dg_status)     */
     int64_t first_bad_cell;  /* cell index of that error, -1 if none              */
+    int64_t restarts;        /* steps retried with half dt (positivity limiter)   */
 } dg_report;
 
 typedef struct dg_solver dg_solver;

@@ -61,7 +61,7 @@ class Report(C.Structure):
                 ("boundary_flux", C.c_double * 4), ("troubled_cells", C.c_int64),
                 ("min_rho", C.c_double), ("min_p", C.c_double),
                 ("max_exponent", C.c_double), ("status", C.c_int),
-                ("first_bad_cell", C.c_int64)]
+                ("first_bad_cell", C.c_int64), ("restarts", C.c_int64)]
 
 
 _lib = None
@@ -191,6 +191,22 @@ def post1d(P: Problem1D, stage: int, dt: float, v: np.ndarray):
     _chk(lib().dgref_post1d(C.byref(P), stage, C.c_double(dt), _ptr(v), _ptr(out), C.byref(tr)),
          "post1d")
     return out, tr.value
+
+
+def pp_limit1d(P: Problem1D, u: np.ndarray):
+    """Positivity-preserving limiter (Zhang and Shu) on every cell of u."""
+    u = np.array(u, dtype=np.float64, order="C", copy=True)
+    _chk(lib().dgref_pp_limit1d(C.byref(P), _ptr(u)), "pp_limit1d")
+    return u
+
+
+def step1d_rc(P: Problem1D, dt: float, u: np.ndarray, bflux: np.ndarray | None = None):
+    """One step; returns (new state or None when rejected, return code)."""
+    u = np.array(u, dtype=np.float64, order="C", copy=True)
+    bf = np.zeros(4) if bflux is None else bflux
+    tr = C.c_int64(0)
+    rc = lib().dgref_step1d(C.byref(P), C.c_double(dt), _ptr(u), _ptr(bf), C.byref(tr))
+    return u, rc
 
 
 def step1d(P: Problem1D, dt: float, u: np.ndarray):

@@ -565,34 +565,40 @@ int dgref_hybrid1d(const dgref_problem1d* P, double dt, const double* v, double*
  * (they include both ends, where the fluxes are evaluated, and their rule
  * is exact for degree k, so the cell average is a convex combination of
  * the point values) and the Gauss points of the volume quadrature.
- * Gauss-Lobatto nodes: +-1 and the roots of P_{N-1}'. */
-static int pp_points(const dgref_problem1d* P, double* xs)
+ * Gauss-Lobatto nodes: +-1 and the roots of P_{N-1}' (0 for N = 3,
+ * +-sqrt(1/5) for N = 4).  V[i][l] = P_l at point i, taken from the same
+ * tables the DG operator evaluates its traces and quadrature values with,
+ * so a point value here is bitwise the value the fluxes will see. */
+static int pp_points(const dgref_problem1d* P, double V[16][MAXK + 1])
 {
-    int N = (P->k + 4) / 2;
-    if (N < 2) N = 2;
+    dgref_basis B;
+    if (dgref_make_basis(P->k, P->nq, &B)) return 0;
+    const int K1 = P->k + 1;
+    const int N = (P->k + 4) / 2 < 2 ? 2 : (P->k + 4) / 2;
     int cnt = 0;
-    xs[cnt++] = -1.0;
-    xs[cnt++] = 1.0;
-    if (N == 3) xs[cnt++] = 0.0;
-    if (N == 4) {
-        xs[cnt++] = -sqrt(0.2);
-        xs[cnt++] = sqrt(0.2);
+    for (int side = 0; side < 2; ++side, ++cnt)
+        for (int l = 0; l < K1; ++l) V[cnt][l] = B.tr[side][l][0];
+    if (N == 3) {
+        for (int l = 0; l < K1; ++l) V[cnt][l] = dgref_legendre_deriv(l, 0, 0.0);
+        ++cnt;
     }
-    double xg[MAXQ], wg[MAXQ];
-    int nq = P->nq ? P->nq : P->k + 1;
-    dgref_gauss(nq, xg, wg);
-    for (int q = 0; q < nq; ++q) xs[cnt++] = xg[q];
+    if (N == 4)
+        for (int sgn = -1; sgn <= 1; sgn += 2, ++cnt)
+            for (int l = 0; l < K1; ++l)
+                V[cnt][l] = (double)legendre_deriv_ld(l, 0, (long double)sgn * sqrtl(0.2L));
+    for (int q = 0; q < B.nq; ++q, ++cnt)
+        for (int l = 0; l < K1; ++l) V[cnt][l] = B.phi[q][l];
     return cnt;
 }
 
-static void point_state1d(const dgref_problem1d* P, const double* u, int64_t j, double xi,
-                          double* w)
+static void point_state1d(const dgref_problem1d* P, const double* u, int64_t j,
+                          const double* Vi, double* w)
 {
     const int K1 = P->k + 1;
     const int64_t n = P->n;
     for (int v = 0; v < 3; ++v) {
         double s = 0.0;
-        for (int l = 0; l < K1; ++l) s += U1(u, v, l, j) * dgref_legendre_deriv(l, 0, xi);
+        for (int l = 0; l < K1; ++l) s += U1(u, v, l, j) * Vi[l];
         w[v] = s;
     }
 }
@@ -602,12 +608,52 @@ static double pressure_of(double gamma, const double* w)
     return (gamma - 1.0) * (w[2] - 0.5 * w[1] * w[1] / w[0]);
 }
 
+/* The pressure as the flux and the wave speed evaluate it. */
+static double pressure_flux(double gamma, const double* w)
+{
+    const double vel = w[1] / w[0];
+    return (gamma - 1.0) * (w[2] - 0.5 * w[1] * vel);
+}
+
+/* Point value w and the sums wa of the magnitudes of its terms. */
+static void point_state_abs1d(const dgref_problem1d* P, const double* u, int64_t j,
+                              const double* Vi, double* w, double* wa)
+{
+    const int K1 = P->k + 1;
+    const int64_t n = P->n;
+    for (int v = 0; v < 3; ++v) {
+        double s = 0.0, sa = 0.0;
+        for (int l = 0; l < K1; ++l) {
+            s += U1(u, v, l, j) * Vi[l];
+            sa += fabs(U1(u, v, l, j) * Vi[l]);
+        }
+        w[v] = s;
+        wa[v] = sa;
+    }
+}
+
+/* Rounding margin of the pressure at a point (8 units of roundoff times
+ * the magnitudes that cancel in E - m^2 / (2 rho)): near vacuum the point
+ * pressure is the small difference of two large numbers, so a value below
+ * this margin has no reliable sign. */
+static double pp_margin(const double* w, const double* wa)
+{
+    const double ur = 0x1p-52;
+    const double kin = 0.5 * w[1] * w[1] / w[0];
+    return 8.0 * ur * (wa[2] + fabs(w[1]) * wa[1] / w[0] + kin * wa[0] / w[0]);
+}
+
 /* Limit cell j of u in place: scale the density's higher modes so the
- * density at every test point is >= eps, then all higher modes so the
- * pressure is >= eps (for each point the largest t in [0,1] with
- * p(u_bar + t (u(x) - u_bar)) >= eps, found by bisection; p is concave along
- * that segment).  eps = min(1e-13, rho_bar, p(u_bar)).  Cell averages are
- * not changed. */
+ * density at every test point is >= eps_r, then all higher modes so the
+ * pressure at each point is >= eps_p (for each point the largest t in
+ * [0,1] with p(u_bar + t (u(x) - u_bar)) >= eps_p, found by bisection; p is
+ * concave along that segment).  eps = min(1e-13, rho_bar, p(u_bar)) as in
+ * Zhang and Shu; here eps_r = max(eps, 8 u sum_l |rho_l P_l|) and eps_p =
+ * max(eps, the rounding margin of the point's pressure), which equal eps
+ * in exact arithmetic.  Cell averages are not changed.  The scaled cell is
+ * then checked point by point in the arithmetic of the fluxes, its higher
+ * modes halved until density and pressure are positive there (dropped after
+ * 50 halvings; with the margins this does not occur in practice). */
 static void pp_limit_cell(const dgref_problem1d* P, double* u, int64_t j)
 {
     const int K1 = P->k + 1;
@@ -619,31 +665,40 @@ static void pp_limit_cell(const dgref_problem1d* P, double* u, int64_t j)
     double eps = 1e-13;
     if (ub[0] < eps) eps = ub[0];
     if (pb < eps) eps = pb;
-    double xs[16];
-    int np = pp_points(P, xs);
+    double V[16][MAXK + 1];
+    int np = pp_points(P, V);
     /* density */
-    double rmin = INFINITY;
+    double rmin = INFINITY, eps_r = eps;
     for (int i = 0; i < np; ++i) {
-        double w[3];
-        point_state1d(P, u, j, xs[i], w);
+        double w[3], wa[3];
+        point_state_abs1d(P, u, j, V[i], w, wa);
         if (w[0] < rmin) rmin = w[0];
+        double m = 8.0 * 0x1p-52 * wa[0];
+        if (m > eps_r) eps_r = m;
     }
-    if (rmin < eps) {
-        double th = (ub[0] - eps) / (ub[0] - rmin);
+    if (eps_r > ub[0]) eps_r = ub[0];
+    if (rmin < eps_r) {
+        double th = (ub[0] - eps_r) / (ub[0] - rmin);
         if (th < 0.0) th = 0.0;
         for (int l = 1; l < K1; ++l) U1(u, 0, l, j) *= th;
     }
     /* pressure */
     double theta = 1.0;
     for (int i = 0; i < np; ++i) {
-        double w[3];
-        point_state1d(P, u, j, xs[i], w);
-        if (pressure_of(P->gamma, w) >= eps) continue;
+        double w[3], wa[3];
+        point_state_abs1d(P, u, j, V[i], w, wa);
+        double eps_p = eps;
+        if (w[0] > 0.0) {
+            double m = pp_margin(w, wa);
+            if (m > eps_p) eps_p = m;
+        }
+        if (eps_p > pb) eps_p = pb;
+        if (pressure_of(P->gamma, w) >= eps_p) continue;
         double lo = 0.0, hi = 1.0;
         for (int it = 0; it < 60; ++it) {
             double mid = 0.5 * (lo + hi), wm[3];
             for (int v = 0; v < 3; ++v) wm[v] = ub[v] + mid * (w[v] - ub[v]);
-            if (pressure_of(P->gamma, wm) >= eps)
+            if (pressure_of(P->gamma, wm) >= eps_p)
                 lo = mid;
             else
                 hi = mid;
@@ -653,6 +708,19 @@ static void pp_limit_cell(const dgref_problem1d* P, double* u, int64_t j)
     if (theta < 1.0)
         for (int v = 0; v < 3; ++v)
             for (int l = 1; l < K1; ++l) U1(u, v, l, j) *= theta;
+    /* positivity in the fluxes' own arithmetic */
+    for (int halving = 0; halving <= 50; ++halving) {
+        int ok = 1;
+        for (int i = 0; i < np && ok; ++i) {
+            double w[3];
+            point_state1d(P, u, j, V[i], w);
+            ok = w[0] > 0.0 && pressure_flux(P->gamma, w) > 0.0;
+        }
+        if (ok) return;
+        const double f = halving < 50 ? 0.5 : 0.0;
+        for (int v = 0; v < 3; ++v)
+            for (int l = 1; l < K1; ++l) U1(u, v, l, j) *= f;
+    }
 }
 
 int dgref_pp_limit1d(const dgref_problem1d* P, double* u)
@@ -686,6 +754,23 @@ int dgref_post1d(const dgref_problem1d* P, int stage, double dt, const double* v
 /* One SSP-RK3 step with the post-stage operator after each stage (err_rk1,
  * err_rk2).  bflux (nullable) accumulates dt * sum_s b_s (fhat_right -
  * fhat_left) with the effective weights b = (1/6, 1/6, 2/3). */
+static int averages_admissible(const dgref_problem1d* P, const double* u)
+{
+    const int K1 = P->k + 1;
+    const int64_t n = P->n;
+    for (int64_t j = 0; j < n; ++j) {
+        double w[3] = {U1(u, 0, 0, j), U1(u, 1, 0, j), U1(u, 2, 0, j)};
+        if (!(w[0] > 0.0) || !(pressure_of(P->gamma, w) > 0.0)) return 0;
+    }
+    return 1;
+}
+
+/* One SSP-RK3 step with the post-stage operator after every stage.  With
+ * the positivity limiter, a stage whose cell averages leave the admissible
+ * set (the CFL bound of the positivity argument failed for the stage
+ * states) rejects the step: DGREF_ERR_POSITIVITY is returned and u, bflux
+ * and troubled are left untouched, so the caller can retry with a smaller
+ * dt. */
 int dgref_step1d(const dgref_problem1d* P, double dt, double* u, double* bflux,
                  int64_t* troubled)
 {
@@ -695,6 +780,10 @@ int dgref_step1d(const dgref_problem1d* P, double dt, double* u, double* bflux,
     const int nv = dgref_nvars(P->eq, 1);
     const int64_t n = P->n;
     const size_t ndof = (size_t)nv * (size_t)(P->k + 1) * (size_t)n;
+    double bf0[MAXV] = {0.0, 0.0, 0.0, 0.0};
+    int64_t tr0 = troubled ? *troubled : 0;
+    if (bflux)
+        for (int v = 0; v < nv; ++v) bf0[v] = bflux[v];
     double* un = (double*)malloc(sizeof(double) * ndof);
     double* us = (double*)malloc(sizeof(double) * ndof);
     double* w = (double*)malloc(sizeof(double) * ndof);
@@ -710,8 +799,16 @@ int dgref_step1d(const dgref_problem1d* P, double dt, double* u, double* bflux,
                 bflux[v] += dt * b[s] *
                             (fh[(size_t)v * (size_t)(n + 1) + (size_t)n] - fh[(size_t)v * (size_t)(n + 1)]);
         rc = dgref_post1d(P, s, dt, w, us, troubled);
+        if (!rc && P->pp && P->eq == DGREF_EULER && !averages_admissible(P, us))
+            rc = DGREF_ERR_POSITIVITY;
     }
-    if (!rc) memcpy(u, us, sizeof(double) * ndof);
+    if (!rc) {
+        memcpy(u, us, sizeof(double) * ndof);
+    } else {
+        if (bflux)
+            for (int v = 0; v < nv; ++v) bflux[v] = bf0[v];
+        if (troubled) *troubled = tr0;
+    }
 done:
     free(un);
     free(us);
@@ -758,7 +855,17 @@ int dgref_check1d(const dgref_problem1d* P, const double* u, double* min_rho, do
             double p = (P->gamma - 1.0) * (uq[2] - 0.5 * uq[1] * uq[1] / uq[0]);
             if (uq[0] < mr) mr = uq[0];
             if (p < mp) mp = p;
-            if ((!(uq[0] > 0.0) || !(p > 0.0)) && status == DGREF_OK) {
+            if ((!(uq[0] > 0.0) || !(p > 0.0)) && status == DGREF_OK && !P->pp) {
+                status = DGREF_ERR_POSITIVITY;
+                bad = j;
+            }
+        }
+        /* with the positivity limiter, point values sit at its margin eps
+         * up to rounding: only an inadmissible cell average is an error */
+        if (P->pp && status == DGREF_OK) {
+            double w[3] = {U1(u, 0, 0, j), U1(u, 1, 0, j), U1(u, 2, 0, j)};
+            double pb = (P->gamma - 1.0) * (w[2] - 0.5 * w[1] * w[1] / w[0]);
+            if (!(w[0] > 0.0) || !(pb > 0.0)) {
                 status = DGREF_ERR_POSITIVITY;
                 bad = j;
             }
@@ -790,9 +897,21 @@ int dgref_run1d(const dgref_problem1d* P, double t_end, int64_t max_steps, doubl
         double alpha = dgref_max_wavespeed1d(P, u);
         if (!isfinite(alpha)) { rc = DGREF_ERR_NONFINITE; break; }
         double dt = P->cfl * h / alpha;
+        /* a time step too small to advance t ends the run */
+        if (!(t + dt > t)) { rc = DGREF_ERR_NONFINITE; break; }
         int last = 0;
         if (t + dt >= t_end) { dt = t_end - t; last = 1; }
         rc = dgref_step1d(P, dt, u, r.boundary_flux, &r.troubled_cells);
+        /* positivity limiter: a rejected step is retried with half the time
+         * step (Zhang and Shu's remedy when a stage violates the CFL bound
+         * of the positivity argument) */
+        for (int tries = 0; rc == DGREF_ERR_POSITIVITY && P->pp && tries < DGREF_MAX_RETRIES;
+             ++tries) {
+            dt *= 0.5;
+            last = 0;
+            r.restarts++;
+            rc = dgref_step1d(P, dt, u, r.boundary_flux, &r.troubled_cells);
+        }
         if (rc) break;
         t = last ? t_end : t + dt;
         r.steps++;

@@ -76,7 +76,11 @@ typedef struct {
     double max_exponent;       /* largest damping exponent applied             */
     int status;
     int64_t first_bad_cell;
+    int64_t restarts;          /* steps retried with half dt (positivity limiter) */
 } dgref_report;
+
+/* retries of one step with halved dt before the run stops */
+#define DGREF_MAX_RETRIES 40
 
 int dgref_nvars(int eq, int dim);
 int dgref_num_threads(void);   /* OpenMP threads the cell loops use */

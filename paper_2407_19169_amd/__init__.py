@@ -39,7 +39,8 @@ class dg_mesh(C.Structure):
 class dg_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("filter", C.c_int), ("cfl", C.c_double),
                 ("gamma", C.c_double), ("adv_speed", C.c_double * 2),
-                ("quad_points", C.c_int), ("stream", C.c_void_p), ("cf_mesh_factor", C.c_int)]
+                ("quad_points", C.c_int), ("stream", C.c_void_p), ("cf_mesh_factor", C.c_int),
+                ("positivity", C.c_int)]
 
 
 class dg_report(C.Structure):
@@ -48,7 +49,7 @@ class dg_report(C.Structure):
                 ("boundary_flux", C.c_double * 4), ("troubled_cells", C.c_int64),
                 ("min_rho", C.c_double), ("min_p", C.c_double),
                 ("max_exponent", C.c_double), ("status", C.c_int),
-                ("first_bad_cell", C.c_int64)]
+                ("first_bad_cell", C.c_int64), ("restarts", C.c_int64)]
 
 
 class dg_problem1d(C.Structure):
@@ -136,9 +137,11 @@ def make_mesh(dim, n, lo, hi, bc, dirichlet=None, shock_x0=0.0, shock_speed=0.0,
 
 
 def make_options(precision=DG_PREC_FP64, filter=DG_FILTER_JUMP, cfl=0.1, gamma=1.4,
-                 adv_speed=(1.0, 0.0), quad_points=0, stream=None, cf_mesh_factor=0) -> dg_options:
+                 adv_speed=(1.0, 0.0), quad_points=0, stream=None, cf_mesh_factor=0,
+                 positivity=0) -> dg_options:
     o = dg_options()
     o.cf_mesh_factor = cf_mesh_factor
+    o.positivity = positivity
     o.precision, o.filter, o.cfl, o.gamma = precision, filter, cfl, gamma
     o.adv_speed[0], o.adv_speed[1] = adv_speed
     o.quad_points = quad_points

@@ -85,6 +85,197 @@ __device__ __forceinline__ T combine_t(int stage, T un, T adv)
                       : (T)(1.0 / 3.0) * un + (T)(2.0 / 3.0) * adv;
 }
 
+// ------------------------------------------------ positivity limiter --
+// Zhang and Shu's positivity-preserving limiter for the Euler equations,
+// applied after the filter (the paper's Sec. 3.2 examples with extreme
+// positivity demands).  Test points of a cell: the N-point Gauss-Lobatto
+// nodes, N = ceil((k+3)/2) (both ends, and the centre for N = 3), followed
+// by the K+1 Gauss points of the volume rule.
+template <int K>
+struct PPPoints {
+    static constexpr int N = (K + 4) / 2;
+    static constexpr int NP = (N == 3 ? 3 : 2) + K + 1;
+};
+
+// P_l at test point i.
+template <int K>
+__device__ __forceinline__ constexpr double pp_leg(int i, int l)
+{
+    constexpr int N = PPPoints<K>::N;
+    return i == 0 ? ((l & 1) ? -1.0 : 1.0)
+         : i == 1 ? 1.0
+         : (N == 3 && i == 2) ? (l == 0 ? 1.0 : l == 2 ? -0.5 : 0.0)
+         : leg_at(K + 1, i - (N == 3 ? 3 : 2), l);
+}
+
+template <int K, typename TB>
+__device__ __forceinline__ void pp_point(const double (&u0)[3], const TB (&uh)[3][K > 0 ? K : 1],
+                                         int i, double (&w)[3])
+{
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        double s = u0[v];
+#pragma unroll
+        for (int l = 1; l <= K; ++l) s += (double)uh[v][l - 1] * pp_leg<K>(i, l);
+        w[v] = s;
+    }
+}
+
+// Point value and the sums of the magnitudes of its terms.
+template <int K, typename TB>
+__device__ __forceinline__ void pp_point_abs(const double (&u0)[3], const TB (&uh)[3][K > 0 ? K : 1],
+                                             int i, double (&w)[3], double (&wa)[3])
+{
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        double s = u0[v], sa = fabs(u0[v]);
+#pragma unroll
+        for (int l = 1; l <= K; ++l) {
+            const double t = (double)uh[v][l - 1] * pp_leg<K>(i, l);
+            s += t;
+            sa += fabs(t);
+        }
+        w[v] = s;
+        wa[v] = sa;
+    }
+}
+
+__device__ __forceinline__ double pp_pressure(double gamma, const double (&w)[3])
+{
+    return (gamma - 1.0) * (w[2] - 0.5 * w[1] * w[1] / w[0]);
+}
+
+// Rounding margin of the pressure at a point (8 units of roundoff of the
+// arithmetic the fluxes use, times the magnitudes that cancel in
+// E - m^2 / (2 rho)): below it the point pressure has no reliable sign.
+template <typename TB>
+__device__ __forceinline__ double pp_margin(const double (&w)[3], const double (&wa)[3])
+{
+    constexpr double ur = sizeof(TB) == 4 ? 0x1p-23 : 0x1p-52;
+    const double kin = 0.5 * w[1] * w[1] / w[0];
+    return 8.0 * ur * (wa[2] + fabs(w[1]) * wa[1] / w[0] + kin * wa[0] / w[0]);
+}
+
+// Limit one cell in place: scale the density's modes >= 1 so the density
+// at every test point is >= eps_r, then all modes >= 1 so the pressure is
+// >= eps_p (largest admissible t in [0, 1] on the segment from the average
+// to each point value, by 60 bisection steps; the pressure is concave
+// along it).  FP64 modes: eps = min(1e-13, rho_bar, p_bar) as in Zhang and
+// Shu, raised to the rounding margins of the point values (8 u sum |rho_l
+// P_l| for the density, pp_margin for the pressure), which vanish in exact
+// arithmetic.  FP32 modes (mixed precision): the margins use FP32's unit
+// roundoff, which also covers rounding the limited modes to FP32.  The
+// average is never changed; an inadmissible average is left for the
+// caller's check.
+template <int K, typename TB>
+__device__ __forceinline__ void pp_limit(double (&u0)[3], TB (&uh)[3][K > 0 ? K : 1], double gamma)
+{
+    if constexpr (K > 0) {
+        constexpr int NP = PPPoints<K>::NP;
+        constexpr bool kFP32 = sizeof(TB) == 4;
+        const double pb = pp_pressure(gamma, u0);
+        if (!(u0[0] > 0.0) || !(pb > 0.0)) return;
+        double eps = 1e-13;
+        if (u0[0] < eps) eps = u0[0];
+        if (pb < eps) eps = pb;
+        double eps_r = eps;
+        const double eps_p = eps;
+        constexpr double ur = kFP32 ? 0x1p-23 : 0x1p-52;
+        double rmin = INFINITY;
+        for (int i = 0; i < NP; ++i) {
+            double w[3], wa[3];
+            pp_point_abs<K, TB>(u0, uh, i, w, wa);
+            if (w[0] < rmin) rmin = w[0];
+            const double m = 8.0 * ur * wa[0];
+            if (m > eps_r) eps_r = m;
+        }
+        if (eps_r > u0[0]) eps_r = u0[0];
+        if (rmin < eps_r) {
+            double th = (u0[0] - eps_r) / (u0[0] - rmin);
+            if (th < 0.0) th = 0.0;
+#pragma unroll
+            for (int l = 0; l < K; ++l) uh[0][l] = (TB)((double)uh[0][l] * th);
+        }
+        double theta = 1.0;
+        for (int i = 0; i < NP; ++i) {
+            double w[3], wa[3];
+            pp_point_abs<K, TB>(u0, uh, i, w, wa);
+            double eps_i = eps_p;
+            if (w[0] > 0.0) {
+                const double m = pp_margin<TB>(w, wa);
+                if (m > eps_i) eps_i = m;
+            }
+            if (eps_i > pb) eps_i = pb;
+            if (pp_pressure(gamma, w) >= eps_i) continue;
+            double lo = 0.0, hi = 1.0;
+            for (int it = 0; it < 60; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                double wm[3];
+#pragma unroll
+                for (int v = 0; v < 3; ++v) wm[v] = u0[v] + mid * (w[v] - u0[v]);
+                if (pp_pressure(gamma, wm) >= eps_i)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            if (lo < theta) theta = lo;
+        }
+        if (theta < 1.0) {
+#pragma unroll
+            for (int v = 0; v < 3; ++v)
+#pragma unroll
+                for (int l = 0; l < K; ++l) uh[v][l] = (TB)((double)uh[v][l] * theta);
+        }
+        // Positivity in the fluxes' own arithmetic (precision TB, pressure
+        // as the flux computes it): near vacuum the point values of the
+        // scaled coefficients can differ in sign from the segment values
+        // by rounding, so the modes >= 1 are halved until every test point
+        // is positive (dropped after 50 halvings).
+        for (int halving = 0; halving <= 50; ++halving) {
+            bool ok = true;
+            for (int i = 0; i < NP && ok; ++i) {
+                TB w[3];
+#pragma unroll
+                for (int v = 0; v < 3; ++v) {
+                    TB s = (TB)u0[v];
+#pragma unroll
+                    for (int l = 1; l <= K; ++l) s += uh[v][l - 1] * (TB)pp_leg<K>(i, l);
+                    w[v] = s;
+                }
+                const TB vel = w[1] / w[0];
+                const TB pr = ((TB)gamma - (TB)1) * (w[2] - (TB)0.5 * w[1] * vel);
+                ok = w[0] > (TB)0 && pr > (TB)0;
+            }
+            if (ok) break;
+            const TB f = halving < 50 ? (TB)0.5 : (TB)0;
+#pragma unroll
+            for (int v = 0; v < 3; ++v)
+#pragma unroll
+                for (int l = 0; l < K; ++l) uh[v][l] *= f;
+        }
+    }
+}
+
+__device__ __forceinline__ bool pp_admissible(const double (&u0)[3], double gamma)
+{
+    return u0[0] > 0.0 && pp_pressure(gamma, u0) > 0.0;
+}
+
+// Limiter (Euler with the limiter on) + average check of one own output
+// cell; returns the CFL quantity of its average.
+template <int EQ, int K, typename TB, int NV>
+__device__ __forceinline__ double finish_cell(const Args1D<TB>& a, int64_t c, double (&v0)[NV],
+                                              TB (&vh)[NV][K > 0 ? K : 1], bool limit)
+{
+    if constexpr (EQ == EULER) {
+        if (a.pp && limit) {
+            pp_limit<K, TB>(v0, vh, a.phys.gamma);
+            if (!pp_admissible(v0, a.phys.gamma) && a.reject) atomicOr(a.reject, 1);
+        }
+    }
+    return (double)Phys1D<EQ>::speed(v0, a.phys);
+}
+
 }  // namespace
 
 // -------------------------------------------------------------------------
@@ -184,7 +375,9 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
         double pl = Phys1D<EULER>::pressure(dl, a.phys), pr = Phys1D<EULER>::pressure(dr, a.phys);
         if (!(dl[0] > 0.0) || !(dr[0] > 0.0) || !(pl > 0.0) || !(pr > 0.0)) {
             bool fin = isfinite(dl[0]) && isfinite(dr[0]) && isfinite(pl) && isfinite(pr);
-            latch_error(a.ctrl, fin ? -5 : -4, cc);
+            // with the positivity limiter the traces sit at its margin up
+            // to rounding; the limiter and the step rejection own positivity
+            if (!fin || !a.pp) latch_error(a.ctrl, fin ? -5 : -4, cc);
         }
     }
     __syncthreads();
@@ -283,8 +476,12 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
 
     const bool own = valid && c >= 0 && c < n && tid >= HALO && tid < 256 - HALO;
 
+    double lam = 0.0;
     if constexpr (MODE == 0) {
-        if (own) store_cell<K, NV, TB>(a.out, c, v0, vh);
+        if (own) {
+            lam = finish_cell<EQ, K, TB, NV>(a, c, v0, vh, true);
+            store_cell<K, NV, TB>(a.out, c, v0, vh);
+        }
         *eta_out = 0.0;
     } else {
         // ---- jump filter on the unfiltered output (needs neighbours) ----
@@ -379,8 +576,11 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
 #pragma unroll
                     for (int v = 0; v < NV; ++v) vh[v][l - 1] *= f;
                 }
+                lam = finish_cell<EQ, K, TB, NV>(a, c, v0, vh, true);
                 store_cell<K, NV, TB>(a.out, c, v0, vh);
             } else {
+                // troubled cells are limited after the blend (pass B)
+                lam = finish_cell<EQ, K, TB, NV>(a, c, v0, vh, !(eta > (T)1));
                 store_cell<K, NV, TB>(a.out, c, v0, vh);
                 if (eta > (T)1) {
                     unsigned int slot = atomicAdd(a.tcount, 1u);
@@ -398,14 +598,16 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
         }
         *eta_out = (double)eta_own;
     }
-    // CFL quantity of the output's cell average (FP64)
-    *lam_out = own ? (double)P::speed(v0, a.phys) : 0.0;
+    // CFL quantity of the output (FP64): its cell average, and with the
+    // positivity limiter also the test points
+    *lam_out = lam;
 }
 
 template <int EQ, int K, typename TB, int MODE>
 __global__ __launch_bounds__(256) void stage1d_kernel(Args1D<TB> a)
 {
-    if (a.ctrl && a.dt_from_ctrl && a.ctrl->done) return;
+    // a finished run, or a step already rejected by the positivity limiter
+    if (a.ctrl && a.dt_from_ctrl && (a.ctrl->done || a.ctrl->reject)) return;
     const double dt = a.dt_from_ctrl ? a.ctrl->dt : a.dt_host;
     __shared__ __align__(16) unsigned char lds[Stage1DLds<EQ, K, TB, MODE>::bytes];
     double lam, eta;
@@ -423,14 +625,15 @@ __global__ __launch_bounds__(256) void stage1d_kernel(Args1D<TB> a)
 }
 
 // Hybrid pass B: u^l <- [omega + (1 - omega) exp(-E^l)] u^l for troubled
-// cells (eta > 1), omega = (M - eta) / (M - 1), M = max eta.
+// cells (eta > 1), omega = (M - eta) / (M - 1), M = max eta; then, with the
+// positivity limiter on, the limiter on the blended cell.
 template <int K, int NV, typename TB>
 __global__ __launch_bounds__(256) void blend1d_kernel(StateView<TB> out, const unsigned int* count,
                                                       const long long* tcell, const double* tdata,
                                                       const unsigned long long* eta_bits,
-                                                      const Ctrl* ctrl, int from_ctrl)
+                                                      const Ctrl* ctrl, int from_ctrl, PPArgs pp)
 {
-    if (from_ctrl && ctrl->done) return;
+    if (from_ctrl && (ctrl->done || ctrl->reject)) return;
     const unsigned int cnt = *count;
     const double M = __longlong_as_double((long long)*eta_bits);
     for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
@@ -443,6 +646,16 @@ __global__ __launch_bounds__(256) void blend1d_kernel(StateView<TB> out, const u
             const TB f = (TB)(w + (1.0 - w) * exp(-rec[l]));
 #pragma unroll
             for (int v = 0; v < NV; ++v) out.hi[v * out.sv + (l - 1) * out.sl + c] *= f;
+        }
+        if constexpr (NV == 3) {
+            if (pp.on) {
+                double v0[3];
+                TB vh[3][K > 0 ? K : 1];
+                load_cell<K, 3, TB>(out, c, v0, vh);
+                pp_limit<K, TB>(v0, vh, pp.phys.gamma);
+                if (!pp_admissible(v0, pp.phys.gamma) && pp.reject) atomicOr(pp.reject, 1);
+                store_cell<K, 3, TB>(out, c, v0, vh);
+            }
         }
     }
 }
@@ -571,6 +784,7 @@ __global__ __launch_bounds__(256) void filter1d_kernel(Args1D<TB> a)
 #pragma unroll
             for (int v = 0; v < NV; ++v) vh[v][l - 1] *= f;
         }
+        finish_cell<EQ, K, TB, NV>(a, c, v0, vh, true);
         store_cell<K, NV, TB>(a.out, c, v0, vh);
     } else {
         a.eta_out[c] = (double)eta;
@@ -584,7 +798,7 @@ template <int K, int NV, typename TB>
 __global__ __launch_bounds__(256) void blend_all1d_kernel(StateView<TB> w, StateView<TB> out, int64_t n,
                                                           const double* E, const double* eta,
                                                           const unsigned long long* eta_bits,
-                                                          unsigned int* tcount)
+                                                          unsigned int* tcount, PPArgs pp)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
@@ -592,8 +806,9 @@ __global__ __launch_bounds__(256) void blend_all1d_kernel(StateView<TB> w, State
     double v0[NV];
     TB vh[NV][KH];
     load_cell<K, NV, TB>(w, c, v0, vh);
-    const double M = __longlong_as_double((long long)*eta_bits);
-    const double e = eta[c];
+    // eta == nullptr: no hybrid blend (the limiter alone, after a plain stage)
+    const double M = eta ? __longlong_as_double((long long)*eta_bits) : 0.0;
+    const double e = eta ? eta[c] : 0.0;
     if (e > 1.0) {
         atomicAdd(tcount, 1u);
         const double om = (M - e) / (M - 1.0);
@@ -602,6 +817,12 @@ __global__ __launch_bounds__(256) void blend_all1d_kernel(StateView<TB> w, State
             const TB f = (TB)(om + (1.0 - om) * exp(-E[c * (K + 1) + l]));
 #pragma unroll
             for (int v = 0; v < NV; ++v) vh[v][l - 1] *= f;
+        }
+    }
+    if constexpr (NV == 3) {
+        if (pp.on) {
+            pp_limit<K, TB>(v0, vh, pp.phys.gamma);
+            if (!pp_admissible(v0, pp.phys.gamma) && pp.reject) atomicOr(pp.reject, 1);
         }
     }
     store_cell<K, NV, TB>(out, c, v0, vh);
@@ -685,7 +906,7 @@ template <typename TB>
 hipError_t launch_blend1d(int nv, int k, StateView<TB> out, const unsigned int* count,
                           const long long* tcell, const double* tdata,
                           const unsigned long long* eta_bits, const Ctrl* ctrl, int from_ctrl,
-                          int64_t max_entries, hipStream_t st)
+                          int64_t max_entries, PPArgs pp, hipStream_t st)
 {
     unsigned g = (unsigned)((max_entries + 255) / 256);
     if (g > 1024) g = 1024;
@@ -693,7 +914,7 @@ hipError_t launch_blend1d(int nv, int k, StateView<TB> out, const unsigned int* 
 #define DG_CASE(NV_, K_)                                                                            \
     if (nv == NV_ && k == K_) {                                                                     \
         hipLaunchKernelGGL((blend1d_kernel<K_, NV_, TB>), dim3(g), dim3(256), 0, st, out, count,      \
-                           tcell, tdata, eta_bits, ctrl, from_ctrl);                                \
+                           tcell, tdata, eta_bits, ctrl, from_ctrl, pp);                            \
         return hipGetLastError();                                                                   \
     }
     DG_CASE(1, 0) DG_CASE(1, 1) DG_CASE(1, 2) DG_CASE(1, 3)
@@ -706,13 +927,13 @@ template <typename TB>
 hipError_t launch_blend_all1d(int nv, int k, StateView<TB> w, StateView<TB> out, int64_t n,
                               const double* E, const double* eta,
                               const unsigned long long* eta_bits, unsigned int* tcount,
-                              hipStream_t st)
+                              PPArgs pp, hipStream_t st)
 {
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
 #define DG_CASE(NV_, K_)                                                                           \
     if (nv == NV_ && k == K_) {                                                                    \
         hipLaunchKernelGGL((blend_all1d_kernel<K_, NV_, TB>), grid, block, 0, st, w, out, n, E, eta, \
-                           eta_bits, tcount);                                                      \
+                           eta_bits, tcount, pp);                                                  \
         return hipGetLastError();                                                                  \
     }
     DG_CASE(1, 0) DG_CASE(1, 1) DG_CASE(1, 2) DG_CASE(1, 3)
@@ -741,10 +962,10 @@ hipError_t launch_maxwave1d(int eq, StateView<TB> u, int64_t n, PhysParams phys,
     template hipError_t launch_blend1d<TB>(int, int, StateView<TB>, const unsigned int*,            \
                                            const long long*, const double*,                        \
                                            const unsigned long long*, const Ctrl*, int, int64_t,   \
-                                           hipStream_t);                                           \
+                                           PPArgs, hipStream_t);                                   \
     template hipError_t launch_blend_all1d<TB>(int, int, StateView<TB>, StateView<TB>, int64_t,     \
                                                const double*, const double*,                       \
-                                               const unsigned long long*, unsigned int*,           \
+                                               const unsigned long long*, unsigned int*, PPArgs,   \
                                                hipStream_t);                                       \
     template hipError_t launch_maxwave1d<TB>(int, StateView<TB>, int64_t, PhysParams,               \
                                              unsigned long long*, Ctrl*, hipStream_t);

@@ -92,7 +92,19 @@ Args1D<TB> base_args(const dg_solver* s)
     a.phys.a[1] = s->opt.adv_speed[1];
     a.check = s->eq == DG_EQ_EULER;
     a.ctrl = ctrl_of(s);
+    a.pp = s->opt.positivity;
+    a.reject = &ctrl_of(s)->reject;
     return a;
+}
+
+template <typename TB>
+PPArgs pp_args(const dg_solver* s)
+{
+    PPArgs p;
+    p.on = s->opt.positivity;
+    p.phys = base_args<TB>(s).phys;
+    p.reject = &ctrl_of(s)->reject;
+    return p;
 }
 
 template <typename TB>
@@ -156,6 +168,7 @@ int stage_impl(dg_solver* s, int stage, double dt)
     a.out = view_of<TB>(s, s->ws + s->off_w);
     a.stage = stage;
     a.dt_host = dt;
+    a.pp = 0;  // the limiter belongs to the post-stage operator
     DG_HIP(launch_stage1d<TB>(s->eq, s->k, a, 0, s->user_st));
     return DG_OK;
 }
@@ -167,6 +180,11 @@ int filter_impl(dg_solver* s, int stage, double dt)
     if (s->opt.filter == DG_FILTER_NONE) {
         DG_HIP(hipMemcpyAsync(target, s->ws + s->off_w, s->state_bytes, hipMemcpyDeviceToDevice,
                               s->user_st));
+        if (s->opt.positivity) {
+            const StateView<TB> t = view_of<TB>(s, target);
+            DG_HIP(launch_blend_all1d<TB>(s->nv, s->k, t, t, s->ncell, nullptr, nullptr, nullptr,
+                                          nullptr, pp_args<TB>(s), s->user_st));
+        }
         return DG_OK;
     }
     if (s->dim == 2) {
@@ -219,7 +237,7 @@ int filter_impl(dg_solver* s, int stage, double dt)
     a.eta_acc = eta_bits;
     DG_HIP(launch_filter1d<TB>(s->eq, s->k, a, 2, s->user_st));
     DG_HIP(launch_blend_all1d<TB>(s->nv, s->k, a.us, a.out, s->ncell, a.E_out, a.eta_out, eta_bits,
-                                  tcount, s->user_st));
+                                  tcount, pp_args<TB>(s), s->user_st));
     return DG_OK;
 }
 
@@ -304,8 +322,12 @@ int record_steps(dg_solver* s, int G, hipStream_t st)
             DG_HIP(launch_stage1d<TB>(s->eq, s->k, a, fmode, st));
             if (fmode == 2)
                 DG_HIP(launch_blend1d<TB>(s->nv, s->k, a.out, &c->tcount[stage], tcell, tdata,
-                                          &c->eta_bits[stage], c, 1, s->ncell, st));
+                                          &c->eta_bits[stage], c, 1, s->ncell,
+                                          pp_args<TB>(s), st));
         }
+        // positivity limiter: a rejected step is undone (u^n copied over its
+        // output) and retried with half dt by the next step control
+        if (s->opt.positivity) DG_HIP(launch_restore(c, A, B, s->state_bytes, st));
     }
     return DG_OK;
 }
@@ -350,7 +372,7 @@ int report_impl(dg_solver* s, dg_report* rep)
     DG_HIP(launch_ledger<TB>(s->nv, s->ncell, view_of<TB>(s, s->u[0]), vol, aux, st));
     if (s->dim == 1)
         DG_HIP(launch_check1d<TB>(s->eq, s->k, view_of<TB>(s, s->u[0]), s->ncell,
-                                  base_args<TB>(s).phys, ctrl_of(s), aux + 4, st));
+                                  base_args<TB>(s).phys, ctrl_of(s), aux + 4, s->opt.positivity, st));
     Ctrl c;
     double hv[6];
     DG_HIP(hipMemcpyAsync(&c, ctrl_of(s), sizeof c, hipMemcpyDeviceToHost, st));
@@ -372,6 +394,7 @@ int report_impl(dg_solver* s, dg_report* rep)
         rep->status = c.status;
         rep->first_bad_cell = c.status ? c.first_bad : -1;
         rep->steps = c.steps;
+        rep->restarts = c.restarts;
     }
     return c.status;
 }
@@ -388,6 +411,8 @@ int run_impl(dg_solver* s, double t_end, int64_t max_steps, dg_report* rep)
     c.max_steps = steps0 + max_steps;
     c.done = 0;
     c.active = 0;
+    c.reject = 0;
+    c.retries = 0;
     c.dt_min = INFINITY;
     c.dt_max = 0.0;
     c.alpha_bits = 0;
@@ -399,26 +424,31 @@ int run_impl(dg_solver* s, double t_end, int64_t max_steps, dg_report* rep)
     }
     int rc = maxwave_impl<TB>(s, &ctrl_of(s)->alpha_bits, st);
     if (rc) return rc;
-    // Replays: when the step limit binds, all replays are launched at
-    // once; otherwise batches double in size between control reads.
-    const long long need = (max_steps + s->graph_steps - 1) / s->graph_steps;
-    long long launched = 0, batch = 1;
-    int done = 0;
-    while (!done) {
-        long long nb = batch;
-        if (launched + nb > need) nb = need - launched;
-        if (nb <= 0) break;
+    // Replays: batches double in size between control reads, never beyond
+    // the replays the remaining step budget needs.  With the positivity
+    // limiter a rejected step is retried, so the budget is re-read.
+    const long long restarts0 = c.restarts;
+    long long batch = 1, completed = 0;
+    for (;;) {
+        const long long rem = max_steps - completed;
+        if (rem <= 0) break;
+        long long nb = (rem + s->graph_steps - 1) / s->graph_steps;
+        if (nb > batch) nb = batch;
         for (long long r = 0; r < nb; ++r) DG_HIP(hipGraphLaunch(s->graph, st));
-        launched += nb;
-        DG_HIP(hipMemcpyAsync(&done, &ctrl_of(s)->done, sizeof done, hipMemcpyDeviceToHost, st));
+        Ctrl cr;
+        DG_HIP(hipMemcpyAsync(&cr, ctrl_of(s), sizeof cr, hipMemcpyDeviceToHost, st));
         DG_HIP(hipStreamSynchronize(st));
-        if (launched >= need) break;
+        if (cr.done) break;
+        // the last step of a replay has run but is finalised by the next
+        // step control, unless it was rejected
+        completed = cr.steps - steps0 + ((cr.active && !cr.reject) ? 1 : 0);
         batch = batch < 64 ? batch * 2 : 64;
     }
     DG_HIP(launch_step_ctrl(ctrl_of(s), 1, st));
     DG_HIP(hipMemcpyAsync(&c, ctrl_of(s), sizeof c, hipMemcpyDeviceToHost, st));
     DG_HIP(hipStreamSynchronize(st));
-    if ((c.steps - steps0) & 1)
+    // every executed step (finalised or rejected) swaps the buffer roles
+    if ((c.steps - steps0 + c.restarts - restarts0) & 1)
         DG_HIP(hipMemcpyAsync(s->u[0], s->u[1], s->state_bytes, hipMemcpyDeviceToDevice, st));
     return report_impl<TB>(s, rep);
 }
@@ -542,6 +572,8 @@ int dg_create(const dg_mesh* mesh, int degree, int equation, const dg_options* o
     if (opt->precision != DG_PREC_FP64 && opt->precision != DG_PREC_MIXED) return DG_ERR_ARG;
     if (opt->filter < 0 || opt->filter > 2) return DG_ERR_ARG;
     if (opt->quad_points != 0 && opt->quad_points != degree + 1) return DG_ERR_UNSUPPORTED;
+    if (opt->positivity != 0 && opt->positivity != 1) return DG_ERR_ARG;
+    if (opt->positivity && (equation != DG_EQ_EULER || mesh->dim != 1)) return DG_ERR_UNSUPPORTED;
     if (!(opt->cfl > 0.0)) return DG_ERR_ARG;
     if (equation == DG_EQ_EULER && !(opt->gamma > 1.0)) return DG_ERR_ARG;
     for (int d = 0; d < mesh->dim; ++d) {

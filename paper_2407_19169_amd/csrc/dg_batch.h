@@ -20,6 +20,7 @@ struct BatchReport {
     double ledger[3], bflux[3];
     int status, pad;
     long long first_bad;
+    long long restarts;     // steps retried with half dt (positivity limiter)
 };
 
 struct BatchArgs {
@@ -33,6 +34,7 @@ struct BatchArgs {
     long long steps;
     double cfl;
     PhysParams phys;
+    int pp;                 // positivity-preserving limiter after the filter
 };
 
 hipError_t launch_batch1d(int mixed, int mode, const BatchArgs& b, int grid, hipStream_t st);

@@ -53,6 +53,7 @@ BatchArgs batch_args(const dg_batch* b, long long steps)
     a.nprob = b->nprob;
     a.steps = steps;
     a.cfl = b->opt.cfl;
+    a.pp = b->opt.positivity;
     a.phys.gamma = b->opt.gamma;
     return a;
 }
@@ -93,6 +94,7 @@ int dg_batch_create(int nprob, dg_problem1d* probs, int equation, const dg_optio
     if (nprob < 1 || !probs || !opt || !total_elems) return DG_ERR_ARG;
     if (equation != DG_EQ_EULER) return DG_ERR_UNSUPPORTED;
     if (opt->filter == DG_FILTER_HYBRID) return DG_ERR_UNSUPPORTED;
+    if (opt->positivity != 0 && opt->positivity != 1) return DG_ERR_ARG;
     if (opt->precision != DG_PREC_FP64 && opt->precision != DG_PREC_MIXED) return DG_ERR_ARG;
     if (!(opt->cfl > 0.0) || !(opt->gamma > 1.0)) return DG_ERR_ARG;
     dg_batch* b = new (std::nothrow) dg_batch();
@@ -261,6 +263,7 @@ int dg_batch_run(dg_batch* b, const double* t_end, int64_t steps, dg_report* per
         r.min_rho = r.min_p = r.max_exponent = NAN;
         r.status = rep[i].status;
         r.first_bad_cell = rep[i].status ? rep[i].first_bad : -1;
+        r.restarts = rep[i].restarts;
     }
     return status;
 }

@@ -57,7 +57,8 @@ __device__ __forceinline__ StateView<TB> prob_view(void* base, const BatchProb& 
 
 template <int K, typename TB, int MODE>
 __device__ void solve_problem(const BatchArgs& b, const BatchProb& pr, unsigned int pidx,
-                              unsigned char* lds, double* red, double* tree, double* sflux)
+                              unsigned char* lds, double* red, double* tree, double* sflux,
+                              int* sreject)
 {
     constexpr int TILE = MODE == 0 ? 254 : 252;
     StateView<TB> A = prob_view<TB>(b.u[0], pr, K);
@@ -88,6 +89,8 @@ __device__ void solve_problem(const BatchArgs& b, const BatchProb& pr, unsigned 
     a.tdata = nullptr;
     a.E_out = nullptr;
     a.eta_out = nullptr;
+    a.pp = b.pp;
+    a.reject = sreject;
 
     // CFL quantity of the initial state
     double lam = 0.0;
@@ -102,20 +105,27 @@ __device__ void solve_problem(const BatchArgs& b, const BatchProb& pr, unsigned 
 
     double t = 0.0, dtmin = INFINITY, dtmax = 0.0;
     double bfl[3] = {0.0, 0.0, 0.0};
-    long long steps = 0;
+    long long steps = 0, restarts = 0;
+    int retries = 0;
     const double t_end = pr.t_end;
+    double dt = 0.0;
+    bool last = false, retry = false;
     while (steps < b.steps && t < t_end) {
         if (ctrl->status == -4) break;  // non-finite: stop; positivity: report only
-        double dt = b.cfl * pr.h / alpha;
-        if (!(dt > 0.0) || !isfinite(dt)) {
-            if (threadIdx.x == 0) latch_error(ctrl, -4, -1);
-            break;
+        if (!retry) {
+            dt = b.cfl * pr.h / alpha;
+            // a non-finite step, or one too small to advance t, ends the run
+            if (!(dt > 0.0) || !isfinite(dt) || !(t + dt > t)) {
+                if (threadIdx.x == 0) latch_error(ctrl, -4, -1);
+                break;
+            }
+            last = false;
+            if (t + dt >= t_end) {
+                dt = t_end - t;
+                last = true;
+            }
         }
-        bool last = false;
-        if (t + dt >= t_end) {
-            dt = t_end - t;
-            last = true;
-        }
+        retry = false;
         double net[3] = {0.0, 0.0, 0.0};
         for (int s = 0; s < 3; ++s) {
             a.un = A;
@@ -123,6 +133,7 @@ __device__ void solve_problem(const BatchArgs& b, const BatchProb& pr, unsigned 
             a.out = s == 1 ? Cv : B;
             a.stage = s;
             if (threadIdx.x < 8) sflux[threadIdx.x] = 0.0;
+            if (threadIdx.x == 0) *sreject = 0;
             __syncthreads();
             double lmax = 0.0;
             for (int64_t tile = 0; tile < ntiles; ++tile) {
@@ -131,10 +142,29 @@ __device__ void solve_problem(const BatchArgs& b, const BatchProb& pr, unsigned 
                 lmax = (l > lmax || l != l) ? l : lmax;
                 __syncthreads();  // the next tile reuses the LDS
             }
+            if (*sreject) {
+                // positivity limiter: this stage left an inadmissible cell
+                // average; u^n (buffer A) is untouched, so the step is
+                // simply run again with half the time step
+                retry = true;
+                break;
+            }
 #pragma unroll
             for (int v = 0; v < 3; ++v) net[v] += kStageWeight[s] * (sflux[4 + v] - sflux[v]);
             if (s == 2) alpha = block_max256(lmax, red);
         }
+        if (retry) {
+            __syncthreads();  // every lane has read the flag before it is cleared
+            if (++retries > kMaxRetries) {
+                if (threadIdx.x == 0) latch_error(ctrl, -5, -1);
+                break;
+            }
+            ++restarts;
+            dt *= 0.5;
+            last = false;
+            continue;
+        }
+        retries = 0;
 #pragma unroll
         for (int v = 0; v < 3; ++v) bfl[v] += dt * net[v];
         t = last ? t_end : t + dt;
@@ -177,6 +207,7 @@ __device__ void solve_problem(const BatchArgs& b, const BatchProb& pr, unsigned 
         }
         r.status = ctrl->status;
         r.first_bad = ctrl->first_bad;
+        r.restarts = restarts;
     }
 }
 
@@ -200,6 +231,7 @@ __global__ __launch_bounds__(256) void batch1d_kernel(BatchArgs b)
     __shared__ double red[4];
     __shared__ double tree[256];
     __shared__ double sflux[8];
+    __shared__ int sreject;
     __shared__ unsigned int s_pi;
     for (;;) {
         if (threadIdx.x == 0) s_pi = atomicAdd(b.queue, 1u);
@@ -210,10 +242,10 @@ __global__ __launch_bounds__(256) void batch1d_kernel(BatchArgs b)
         const unsigned int p = b.order[pi];
         const BatchProb pr = b.probs[p];
         switch (pr.k) {
-        case 0: solve_problem<0, TB, MODE>(b, pr, p, lds, red, tree, sflux); break;
-        case 1: solve_problem<1, TB, MODE>(b, pr, p, lds, red, tree, sflux); break;
-        case 2: solve_problem<2, TB, MODE>(b, pr, p, lds, red, tree, sflux); break;
-        default: solve_problem<3, TB, MODE>(b, pr, p, lds, red, tree, sflux); break;
+        case 0: solve_problem<0, TB, MODE>(b, pr, p, lds, red, tree, sflux, &sreject); break;
+        case 1: solve_problem<1, TB, MODE>(b, pr, p, lds, red, tree, sflux, &sreject); break;
+        case 2: solve_problem<2, TB, MODE>(b, pr, p, lds, red, tree, sflux, &sreject); break;
+        default: solve_problem<3, TB, MODE>(b, pr, p, lds, red, tree, sflux, &sreject); break;
         }
         __syncthreads();
     }

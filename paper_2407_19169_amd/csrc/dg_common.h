@@ -164,11 +164,17 @@ struct Ctrl {
     int last;                        // the scheduled step ends exactly at t_end
     int done;                        // no further step will run
     int status;                      // first error code latched (dg_status)
-    int pad;
+    int reject;                      // positivity limiter: a stage left a bad cell average
     long long first_bad;             // cell index of that error
     double bflux[4];                 // boundary-flux ledger (FP64)
     double bstage[3][8];             // per-stage boundary fluxes: lo[4], hi[4]
+    long long restarts;              // steps retried with half dt (positivity limiter)
+    int retries;                     // consecutive retries of the current step
+    int pad;
 };
+
+// Retries of one step with halved dt (positivity limiter) before a run stops.
+constexpr int kMaxRetries = 40;
 
 // atomicMax/atomicMin over doubles through their bit patterns; valid for
 // non-negative values (IEEE-754 order equals unsigned order there) and

@@ -31,6 +31,16 @@ struct Args1D {
     double* tdata;                  // (eta, E^1..E^k) per entry
     double* E_out;                  // nullable: per-cell exponents
     double* eta_out;                // per-cell eta (unfused hybrid)
+    int pp;                         // Euler: positivity-preserving limiter after the filter
+    int* reject;                    // pp: set when an output cell average is inadmissible
+};
+
+// Positivity limiter inputs of the blend kernels (hybrid pass B and the
+// per-call blend): the limiter runs after the blend.
+struct PPArgs {
+    int on;
+    PhysParams phys;
+    int* reject;                    // nullable: set on an inadmissible cell average
 };
 
 template <typename TB>
@@ -83,18 +93,19 @@ template <typename TB>
 hipError_t launch_blend1d(int nv, int k, StateView<TB> out, const unsigned int* count,
                           const long long* tcell, const double* tdata,
                           const unsigned long long* eta_bits, const Ctrl* ctrl, int from_ctrl,
-                          int64_t max_entries, hipStream_t st);
+                          int64_t max_entries, PPArgs pp, hipStream_t st);
 template <typename TB>
 hipError_t launch_blend_all1d(int nv, int k, StateView<TB> w, StateView<TB> out, int64_t n,
                               const double* E, const double* eta,
                               const unsigned long long* eta_bits, unsigned int* tcount,
-                              hipStream_t st);
+                              PPArgs pp, hipStream_t st);
 template <typename TB>
 hipError_t launch_maxwave1d(int eq, StateView<TB> u, int64_t n, PhysParams phys,
                             unsigned long long* acc, Ctrl* err, hipStream_t st);
 
 // step control (dg_util.hip)
 hipError_t launch_step_ctrl(Ctrl* c, int finalize_only, hipStream_t st);
+hipError_t launch_restore(const Ctrl* c, const void* src, void* dst, size_t bytes, hipStream_t st);
 template <typename TB>
 hipError_t launch_convert(int to_internal, int nv, int nmodes, int64_t ncell, const double* fp64,
                           StateView<TB> v, hipStream_t st);
@@ -103,6 +114,6 @@ hipError_t launch_ledger(int nv, int64_t ncell, StateView<TB> u, double cell_vol
                          hipStream_t st);
 template <typename TB>
 hipError_t launch_check1d(int eq, int k, StateView<TB> u, int64_t n, PhysParams phys, Ctrl* c,
-                          double* minvals, hipStream_t st);
+                          double* minvals, int pp, hipStream_t st);
 
 }  // namespace dg

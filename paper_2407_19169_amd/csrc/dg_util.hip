@@ -19,7 +19,35 @@ __global__ void step_ctrl_kernel(Ctrl* c, int finalize_only)
         }
         return;
     }
+    if (c->reject) {
+        // positivity limiter: the step that just ran left an inadmissible
+        // cell average; its output was replaced by u^n (restore kernel), so
+        // it is run again with half the time step
+        c->reject = 0;
+        if (c->active && !c->done) {
+            if (++c->retries > kMaxRetries) {
+                if (c->status == 0) {
+                    c->status = -5;
+                    c->first_bad = -1;
+                }
+                c->active = 0;
+                c->done = 1;
+                return;
+            }
+            c->restarts += 1;
+            c->dt *= 0.5;
+            c->last = 0;
+            c->alpha_bits = 0;
+            for (int s = 0; s < 3; ++s) {
+                c->tcount[s] = 0;
+                c->eta_bits[s] = 0;
+                for (int v = 0; v < 8; ++v) c->bstage[s][v] = 0.0;
+            }
+            return;
+        }
+    }
     if (c->active) {
+        c->retries = 0;
         const double dt = c->dt;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -44,7 +72,8 @@ __global__ void step_ctrl_kernel(Ctrl* c, int finalize_only)
     }
     const double alpha = __longlong_as_double((long long)c->alpha_bits);
     double dt = c->cfl_num / alpha;
-    if (!(dt > 0.0) || !isfinite(dt)) {
+    // a non-finite step, or one too small to advance t, ends the run
+    if (!(dt > 0.0) || !isfinite(dt) || !(c->t + dt > c->t)) {
         if (c->status == 0) {
             c->status = -4;
             c->first_bad = -1;
@@ -71,6 +100,29 @@ __global__ void step_ctrl_kernel(Ctrl* c, int finalize_only)
 hipError_t launch_step_ctrl(Ctrl* c, int finalize_only, hipStream_t st)
 {
     hipLaunchKernelGGL(step_ctrl_kernel, dim3(1), dim3(64), 0, st, c, finalize_only);
+    return hipGetLastError();
+}
+
+// Positivity limiter: when the step just run was rejected, copy its input
+// state (u^n) over its output buffer, so the retry finds u^n where the next
+// step reads its input.  A no-op otherwise.
+__global__ __launch_bounds__(256) void restore_kernel(const Ctrl* c, const uint4* src, uint4* dst,
+                                                      size_t n16)
+{
+    if (!c->reject || !c->active || c->done) return;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_restore(const Ctrl* c, const void* src, void* dst, size_t bytes, hipStream_t st)
+{
+    const size_t n16 = bytes / 16;
+    size_t g = (n16 + 255) / 256;
+    if (g > 2048) g = 2048;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(restore_kernel, dim3((unsigned)g), dim3(256), 0, st, c,
+                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
     return hipGetLastError();
 }
 
@@ -149,7 +201,7 @@ hipError_t launch_ledger(int nv, int64_t ncell, StateView<TB> u, double cell_vol
 // latches DG_ERR_POSITIVITY, a NaN latches DG_ERR_NONFINITE).
 template <int K, typename TB>
 __global__ __launch_bounds__(256) void check1d_kernel(StateView<TB> u, int64_t n, PhysParams phys,
-                                                      Ctrl* c, unsigned long long* minvals)
+                                                      Ctrl* c, unsigned long long* minvals, int pp)
 {
     constexpr int Q = K + 1;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -176,6 +228,9 @@ __global__ __launch_bounds__(256) void check1d_kernel(StateView<TB> u, int64_t n
             mr = w[0] < mr ? w[0] : mr;
             mp = p < mp ? p : mp;
         }
+        // with the positivity limiter, point values sit at its margin up to
+        // rounding: only an inadmissible cell average is an error
+        if (pp) bad = !(u0[0] > 0.0) || !(Phys1D<EULER>::pressure(u0, phys) > 0.0);
         if (nonfin)
             latch_error(c, -4, j);
         else if (bad)
@@ -198,16 +253,16 @@ __global__ __launch_bounds__(256) void check1d_kernel(StateView<TB> u, int64_t n
 
 template <typename TB>
 hipError_t launch_check1d(int eq, int k, StateView<TB> u, int64_t n, PhysParams phys, Ctrl* c,
-                          double* minvals, hipStream_t st)
+                          double* minvals, int pp, hipStream_t st)
 {
     if (eq != EULER) return hipSuccess;
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
     unsigned long long* mv = reinterpret_cast<unsigned long long*>(minvals);
     switch (k) {
-    case 0: hipLaunchKernelGGL((check1d_kernel<0, TB>), grid, block, 0, st, u, n, phys, c, mv); break;
-    case 1: hipLaunchKernelGGL((check1d_kernel<1, TB>), grid, block, 0, st, u, n, phys, c, mv); break;
-    case 2: hipLaunchKernelGGL((check1d_kernel<2, TB>), grid, block, 0, st, u, n, phys, c, mv); break;
-    default: hipLaunchKernelGGL((check1d_kernel<3, TB>), grid, block, 0, st, u, n, phys, c, mv); break;
+    case 0: hipLaunchKernelGGL((check1d_kernel<0, TB>), grid, block, 0, st, u, n, phys, c, mv, pp); break;
+    case 1: hipLaunchKernelGGL((check1d_kernel<1, TB>), grid, block, 0, st, u, n, phys, c, mv, pp); break;
+    case 2: hipLaunchKernelGGL((check1d_kernel<2, TB>), grid, block, 0, st, u, n, phys, c, mv, pp); break;
+    default: hipLaunchKernelGGL((check1d_kernel<3, TB>), grid, block, 0, st, u, n, phys, c, mv, pp); break;
     }
     return hipGetLastError();
 }
@@ -217,7 +272,7 @@ hipError_t launch_check1d(int eq, int k, StateView<TB> u, int64_t n, PhysParams 
                                            hipStream_t);                                           \
     template hipError_t launch_ledger<TB>(int, int64_t, StateView<TB>, double, double*, hipStream_t); \
     template hipError_t launch_check1d<TB>(int, int, StateView<TB>, int64_t, PhysParams, Ctrl*,    \
-                                           double*, hipStream_t);
+                                           double*, int, hipStream_t);
 DG_INST(double)
 DG_INST(float)
 #undef DG_INST
