@@ -58,6 +58,94 @@ def run_gpu(dg, torch, w, precision: int, steps: int, warmup: int):
     return s, rep, wall
 
 
+def _timed_run(dg, torch, s, steps: int, warmup: int):
+    if warmup:
+        dg.dg_run(s.h, 1e30, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = dg.dg_run(s.h, 1e30, steps)
+    torch.cuda.synchronize()
+    return rep, time.perf_counter() - t0
+
+
+def sweep_1d(dg, torch, I, sizes, steps: int):
+    """Fused stage + jump filter on HBM-sized 1D states (Shu-Osher profile
+    on n cells, P2): step throughput and the fused kernel's bandwidth."""
+    out = []
+    for n in sizes:
+        w = I.shu_osher(n, 2)
+        ndof = 3 * (w.k + 1) * n
+        for prec in (dg.DG_PREC_FP64, dg.DG_PREC_MIXED):
+            mesh = dg.make_mesh(1, (n,), (w.lo,), (w.hi,), (dg.DG_BC_OUTFLOW, dg.DG_BC_OUTFLOW))
+            opt = dg.make_options(precision=prec, filter=dg.DG_FILTER_JUMP, cfl=w.cfl)
+            s = dg.Solver(mesh, w.k, dg.DG_EQ_EULER, opt)
+            s.set_state(w.u0)
+            rep, wall = _timed_run(dg, torch, s, steps, 2)
+            durs = [dg.dg_time_kernel(s.h, st, rep.dt_max, 20) for st in range(3)]
+            avg = sum(durs) / 3.0
+            b = bytes_per_dof_update(w.k, prec) * ndof
+            gbs = b / (avg * 1e-6) / 1e9
+            out.append({"cells": n, "precision": "fp64" if prec == 0 else "mixed",
+                        "dof_updates_per_s": ndof * 3 * steps / wall,
+                        "ms_per_step": 1e3 * wall / steps,
+                        "fused_kernel_us": round(avg, 2), "fused_kernel_GBps": round(gbs, 1),
+                        "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+            log(f"1D sweep n={n} {out[-1]['precision']}: {out[-1]['dof_updates_per_s']:.3e} "
+                f"DOF-updates/s, fused kernel {avg:.1f} us = {gbs:.0f} GB/s")
+            s.close()
+        del w
+    return out
+
+
+def bench_2d(dg, torch, I, w, mesh, prec: int, filt: int, steps: int):
+    """A 2D workload: step throughput and, per stage, the residual and filter
+    kernel times against the stage's algorithmic bytes."""
+    ndof = 4 * (w.k + 1) ** 2 * w.nx * w.ny
+    opt = dg.make_options(precision=prec, filter=filt, cfl=w.cfl)
+    s = dg.Solver(mesh, w.k, dg.DG_EQ_EULER, opt)
+    s.set_state(w.u0)
+    rep, wall = _timed_run(dg, torch, s, steps, 2)
+    res = [dg.dg_time_kernel(s.h, st, rep.dt_max, 10) for st in range(3)]
+    fil = [dg.dg_time_kernel(s.h, 3 + st, rep.dt_max, 10) for st in range(3)]
+    s.close()
+    nm = (w.k + 1) ** 2
+    per_dof = 8.0 if prec == 0 else (8.0 + 4.0 * (nm - 1)) / nm
+    b = 8.0 / 3.0 * per_dof * ndof
+    stage_us = (sum(res) + sum(fil)) / 3.0
+    gbs = b / (stage_us * 1e-6) / 1e9
+    return {"dofs": ndof, "precision": "fp64" if prec == 0 else "mixed", "status": rep.status,
+            "dof_updates_per_s": ndof * 3 * steps / wall, "ms_per_step": 1e3 * wall / steps,
+            "residual_kernel_us": round(sum(res) / 3, 2), "filter_kernel_us": round(sum(fil) / 3, 2),
+            "stage_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def bench_batch(dg, torch, I, steps: int):
+    """4096 seeded Riemann problems (256..8192 cells, P1-P3), mixed
+    precision, jump filter + positivity limiter, one persistent launch."""
+    spec = I.batched_riemann_spec(4096, 4001)
+    states = I.batched_riemann_states(spec)
+    probs = [(int(spec.n[i]), int(spec.k[i]), -1.0, 1.0, dg.DG_BC_OUTFLOW, dg.DG_BC_OUTFLOW)
+             for i in range(len(spec.n))]
+    ndof = int(sum(3 * (k + 1) * n for n, k, *_ in probs))
+    b = dg.Batch(probs, dg.make_options(precision=dg.DG_PREC_MIXED, filter=dg.DG_FILTER_JUMP,
+                                         cfl=0.1, positivity=1))
+    b.set_state(states)
+    tune = json.loads(b.tune(3))
+    b.set_state(states)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = b.run(steps, check=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    done = sum(int(r.steps) for r in reps)
+    upd = sum(3 * (k + 1) * n * int(r.steps) * 3 for (n, k, *_), r in zip(probs, reps))
+    b.close()
+    return {"problems": len(probs), "dofs": ndof, "steps_requested": steps,
+            "steps_done": done, "failed": sum(1 for r in reps if r.status == -4),
+            "retries": sum(int(r.restarts) for r in reps),
+            "dof_updates_per_s": upd / wall, "wall_s": wall, "schedule": tune.get("best")}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +155,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--sweep", default="1000000,4000000,16000000",
+                    help="1D cell counts of the HBM sweep (comma separated, empty: skip; "
+                         "multiples of 10 keep the initial shock on a cell interface)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -116,6 +207,33 @@ def main() -> int:
             "ratio_vs_fp64": vm / value}
         log(f"mixed: {vm:.4e} DOF-updates/s")
         sm.close()
+        sizes = [int(x) for x in args.sweep.split(",") if x]
+        if sizes:
+            variants["sweep_1d_fused_jump_filter"] = sweep_1d(dg, torch, I, sizes, 20)
+        wv = I.vortex2d(1024, 2, seed=3001)
+        mesh = dg.make_mesh(2, (1024, 1024), (0.0, -5.0), (10.0, 5.0), (0, 0, 0, 0))
+        for prec in (dg.DG_PREC_FP64, dg.DG_PREC_MIXED):
+            r = bench_2d(dg, torch, I, wv, mesh, prec, dg.DG_FILTER_JUMP, 20)
+            variants[f"vortex2d_1024_q2_{r['precision']}"] = r
+            log(f"vortex 1024^2 Q2 {r['precision']}: {r['dof_updates_per_s']:.3e} DOF-updates/s, "
+                f"stage {r['stage_GBps']} GB/s")
+        del wv
+        wd = I.double_mach(4096, 1024, 3)
+        post, pre = I.conserved2d(*wd.extra["post"]), I.conserved2d(1.4, 0.0, 0.0, 1.0)
+        speed = wd.extra["shock_speed"] / np.sin(np.pi / 3)
+        meshd = dg.make_mesh(2, (4096, 1024), (0.0, 0.0), (4.0, 1.0),
+                             (dg.DG_BC_DIRICHLET, dg.DG_BC_OUTFLOW, 4, 5),
+                             dirichlet=[list(post)] * 4, shock_x0=1 / 6, shock_speed=speed,
+                             post=list(post), pre=list(pre))
+        r = bench_2d(dg, torch, I, wd, meshd, dg.DG_PREC_MIXED, dg.DG_FILTER_JUMP, 10)
+        variants["double_mach_4096x1024_q3_mixed"] = r
+        log(f"double Mach 4096x1024 Q3 mixed: {r['dof_updates_per_s']:.3e} DOF-updates/s, "
+            f"stage {r['stage_GBps']} GB/s")
+        del wd
+        rb = bench_batch(dg, torch, I, 200)
+        variants["batched_riemann_4096_mixed_pp"] = rb
+        log(f"batched 4096 problems: {rb['dof_updates_per_s']:.3e} DOF-updates/s, "
+            f"{rb['failed']} failed, {rb['retries']} retries")
 
     cpu = None
     if not args.no_cpu_baseline:

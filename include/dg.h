@@ -189,9 +189,10 @@ int dg_report_read(dg_solver* s, dg_report* rep);
  * buffer of ncells*(Lmax+1) doubles. */
 int dg_last_exponents(dg_solver* s, double* E_dev);
 
-/* Measurement hook: launch a kernel of dg_run `reps` times on the solver's
- * run stream with time step dt and return its average duration in
- * microseconds from HIP events recorded around each launch.  1D: `stage`
+/* Measurement hook: launch a kernel of dg_run `reps` times back to back on
+ * the solver's run stream with time step dt and return its average
+ * duration in microseconds from HIP events recorded before the first and
+ * after the last launch (after one untimed warm-up launch).  1D: `stage`
  * 0..2 selects the fused stage(+filter / hybrid pass A) kernel of that RK
  * stage (reads u_n, u_a, u_b; writes u_a or u_b).  2D: 0..2 the residual
  * kernel of that stage (writes the workspace), 3..5 the filter kernel

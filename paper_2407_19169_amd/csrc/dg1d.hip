@@ -584,11 +584,13 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
                 store_cell<K, NV, TB>(a.out, c, v0, vh);
                 if (eta > (T)1) {
                     unsigned int slot = atomicAdd(a.tcount, 1u);
-                    a.tcell[slot] = c;
-                    double* rec = a.tdata + (size_t)slot * K1;
-                    rec[0] = (double)eta;
+                    if ((long long)slot < a.tcap) {
+                        a.tcell[slot] = c;
+                        double* rec = a.tdata + (size_t)slot * K1;
+                        rec[0] = (double)eta;
 #pragma unroll
-                    for (int l = 1; l <= K; ++l) rec[l] = (double)E[l];
+                        for (int l = 1; l <= K; ++l) rec[l] = (double)E[l];
+                    }
                 }
             }
             if (a.E_out) {
@@ -631,10 +633,12 @@ template <int K, int NV, typename TB>
 __global__ __launch_bounds__(256) void blend1d_kernel(StateView<TB> out, const unsigned int* count,
                                                       const long long* tcell, const double* tdata,
                                                       const unsigned long long* eta_bits,
-                                                      const Ctrl* ctrl, int from_ctrl, PPArgs pp)
+                                                      const Ctrl* ctrl, int from_ctrl, long long cap,
+                                                      PPArgs pp)
 {
     if (from_ctrl && (ctrl->done || ctrl->reject)) return;
-    const unsigned int cnt = *count;
+    unsigned int cnt = *count;
+    if ((long long)cnt > cap) cnt = (unsigned int)cap;
     const double M = __longlong_as_double((long long)*eta_bits);
     for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
         const long long c = tcell[i];
@@ -914,7 +918,7 @@ hipError_t launch_blend1d(int nv, int k, StateView<TB> out, const unsigned int* 
 #define DG_CASE(NV_, K_)                                                                            \
     if (nv == NV_ && k == K_) {                                                                     \
         hipLaunchKernelGGL((blend1d_kernel<K_, NV_, TB>), dim3(g), dim3(256), 0, st, out, count,      \
-                           tcell, tdata, eta_bits, ctrl, from_ctrl, pp);                            \
+                           tcell, tdata, eta_bits, ctrl, from_ctrl, (long long)max_entries, pp);   \
         return hipGetLastError();                                                                   \
     }
     DG_CASE(1, 0) DG_CASE(1, 1) DG_CASE(1, 2) DG_CASE(1, 3)

@@ -94,6 +94,7 @@ Args1D<TB> base_args(const dg_solver* s)
     a.ctrl = ctrl_of(s);
     a.pp = s->opt.positivity;
     a.reject = &ctrl_of(s)->reject;
+    a.tcap = s->ncell;
     return a;
 }
 
@@ -459,6 +460,34 @@ bool is_fp64(const dg_solver* s) { return s->opt.precision == DG_PREC_FP64; }
 // dg_run: A = u_n read-only, outputs to u_a / u_b).  The hybrid list and
 // the CFL accumulator point into the aux scratch, whose counters are
 // cleared by a one-thread kernel before each timed launch.
+// Average duration of `reps` back-to-back launches of one kernel on the run
+// stream, from HIP events recorded before the first and after the last
+// launch (one warm-up launch first; the scratch control block's per-step
+// accumulators are cleared before the timed launches, and the troubled
+// lists saturate at their capacity).
+template <typename F>
+int time_launches(dg_solver* s, Ctrl* scratch, int reps, F launch, double* avg_us)
+{
+    hipStream_t st = s->run_st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = DG_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = DG_ERR_DEVICE;
+    if (rc == DG_OK && launch_step_ctrl(scratch, 2, st) != hipSuccess) rc = DG_ERR_DEVICE;
+    if (rc == DG_OK && launch() != hipSuccess) rc = DG_ERR_DEVICE;
+    if (rc == DG_OK && launch_step_ctrl(scratch, 2, st) != hipSuccess) rc = DG_ERR_DEVICE;
+    if (rc == DG_OK && hipEventRecord(e0, st) != hipSuccess) rc = DG_ERR_DEVICE;
+    for (int r = 0; r < reps && rc == DG_OK; ++r)
+        if (launch() != hipSuccess) rc = DG_ERR_DEVICE;
+    if (rc == DG_OK && hipEventRecord(e1, st) != hipSuccess) rc = DG_ERR_DEVICE;
+    if (rc == DG_OK && hipEventSynchronize(e1) != hipSuccess) rc = DG_ERR_DEVICE;
+    float ms = 0.f;
+    if (rc == DG_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = DG_ERR_DEVICE;
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (rc == DG_OK) *avg_us = 1000.0 * ms / reps;
+    return rc;
+}
+
 template <typename TB>
 int time_impl(dg_solver* s, int stage, double dt, int reps, double* avg_us)
 {
@@ -488,27 +517,11 @@ int time_impl(dg_solver* s, int stage, double dt, int reps, double* avg_us)
         f.tcount = &scratch->tcount[0];
         f.tcell = reinterpret_cast<long long*>(s->ws + s->off_tcell);
         f.tdata = reinterpret_cast<double*>(s->ws + s->off_tdata);
-        hipEvent_t e0, e1;
-        DG_HIP(hipEventCreate(&e0));
-        DG_HIP(hipEventCreate(&e1));
-        double total_ms = 0.0;
-        int rc = DG_OK;
-        for (int r = 0; r < reps && rc == DG_OK; ++r) {
-            if (launch_step_ctrl(scratch, 2, st) != hipSuccess) rc = DG_ERR_DEVICE;
-            if (hipEventRecord(e0, st) != hipSuccess) rc = DG_ERR_DEVICE;
-            hipError_t e = which < 3 ? launch_stage2d<TB>(s->eq, s->k, a, st)
-                                     : launch_filter2d<TB>(s->eq, s->k, f, fmode == 1 ? 1 : 2, st);
-            if (e != hipSuccess) rc = DG_ERR_DEVICE;
-            if (hipEventRecord(e1, st) != hipSuccess) rc = DG_ERR_DEVICE;
-            if (hipEventSynchronize(e1) != hipSuccess) rc = DG_ERR_DEVICE;
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = DG_ERR_DEVICE;
-            total_ms += ms;
-        }
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
-        *avg_us = 1000.0 * total_ms / reps;
-        return rc;
+        auto launch = [&]() {
+            return which < 3 ? launch_stage2d<TB>(s->eq, s->k, a, st)
+                             : launch_filter2d<TB>(s->eq, s->k, f, fmode == 1 ? 1 : 2, st);
+        };
+        return time_launches(s, scratch, reps, launch, avg_us);
     }
     Args1D<TB> a = base_args<TB>(s);
     a.un = view_of<TB>(s, s->u[0]);
@@ -523,25 +536,8 @@ int time_impl(dg_solver* s, int stage, double dt, int reps, double* avg_us)
     a.tcount = &scratch->tcount[stage];
     a.tcell = reinterpret_cast<long long*>(s->ws + s->off_tcell);
     a.tdata = reinterpret_cast<double*>(s->ws + s->off_tdata);
-    hipEvent_t e0, e1;
-    DG_HIP(hipEventCreate(&e0));
-    DG_HIP(hipEventCreate(&e1));
-    double total_ms = 0.0;
-    int rc = DG_OK;
-    for (int r = 0; r < reps && rc == DG_OK; ++r) {
-        if (launch_step_ctrl(scratch, 2, st) != hipSuccess) rc = DG_ERR_DEVICE;
-        if (hipEventRecord(e0, st) != hipSuccess) rc = DG_ERR_DEVICE;
-        if (launch_stage1d<TB>(s->eq, s->k, a, fmode, st) != hipSuccess) rc = DG_ERR_DEVICE;
-        if (hipEventRecord(e1, st) != hipSuccess) rc = DG_ERR_DEVICE;
-        if (hipEventSynchronize(e1) != hipSuccess) rc = DG_ERR_DEVICE;
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = DG_ERR_DEVICE;
-        total_ms += ms;
-    }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    *avg_us = 1000.0 * total_ms / reps;
-    return rc;
+    auto launch = [&]() { return launch_stage1d<TB>(s->eq, s->k, a, fmode, st); };
+    return time_launches(s, scratch, reps, launch, avg_us);
 }
 
 }  // namespace

@@ -29,6 +29,7 @@ struct Args1D {
     unsigned int* tcount;           // hybrid pass A: troubled list
     long long* tcell;
     double* tdata;                  // (eta, E^1..E^k) per entry
+    long long tcap;                 // capacity of the troubled list (entries)
     double* E_out;                  // nullable: per-cell exponents
     double* eta_out;                // per-cell eta (unfused hybrid)
     int pp;                         // Euler: positivity-preserving limiter after the filter
