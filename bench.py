@@ -146,6 +146,41 @@ def bench_batch(dg, torch, I, steps: int):
             "dof_updates_per_s": upd / wall, "wall_s": wall, "schedule": tune.get("best")}
 
 
+def _dmr_mesh(dg, I, np, nx, ny, k):
+    wd = I.double_mach(nx, ny, k)
+    post, pre = I.conserved2d(*wd.extra["post"]), I.conserved2d(1.4, 0.0, 0.0, 1.0)
+    speed = wd.extra["shock_speed"] / np.sin(np.pi / 3)
+    mesh = dg.make_mesh(2, (nx, ny), (0.0, 0.0), (4.0, 1.0),
+                        (dg.DG_BC_DIRICHLET, dg.DG_BC_OUTFLOW, 4, 5),
+                        dirichlet=[list(post)] * 4, shock_x0=1 / 6, shock_speed=speed,
+                        post=list(post), pre=list(pre))
+    return wd, mesh
+
+
+def run_only(args, dg, torch, I, np) -> int:
+    if args.only == "sweep":
+        r = sweep_1d(dg, torch, I, [int(x) for x in args.sweep.split(",") if x], args.steps)
+    elif args.only == "vortex":
+        wv = I.vortex2d(1024, 2, seed=3001)
+        mesh = dg.make_mesh(2, (1024, 1024), (0.0, -5.0), (10.0, 5.0), (0, 0, 0, 0))
+        r = [bench_2d(dg, torch, I, wv, mesh, p, dg.DG_FILTER_JUMP, args.steps) for p in (0, 1)]
+    elif args.only == "dmr":
+        wd, mesh = _dmr_mesh(dg, I, np, 4096, 1024, 3)
+        r = bench_2d(dg, torch, I, wd, mesh, dg.DG_PREC_MIXED, dg.DG_FILTER_JUMP, args.steps)
+    elif args.only == "copy":
+        # reference for hardware traffic counters: a plain 1 GiB device copy
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        r = {"bytes_read_per_copy": x.numel() * 8, "bytes_written_per_copy": y.numel() * 8}
+    else:
+        r = bench_batch(dg, torch, I, args.steps)
+    print(json.dumps({"only": args.only, "result": r}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,6 +190,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--only", choices=["sweep", "vortex", "dmr", "batch", "copy"], default=None,
+                    help="run one supplementary workload alone and print its figures "
+                         "(for profiler runs); no headline line")
     ap.add_argument("--sweep", default="1000000,4000000,16000000",
                     help="1D cell counts of the HBM sweep (comma separated, empty: skip; "
                          "multiples of 10 keep the initial shock on a cell interface)")
@@ -172,6 +210,8 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.only:
+        return run_only(args, dg, torch, I, np)
     w = I.shu_osher(args.cells, 2)
     ndof = 3 * (w.k + 1) * w.n
     log(f"workload: Shu-Osher {w.n} cells P{w.k} hybrid, {ndof} DOFs; warmup {args.warmup}, "
@@ -218,13 +258,7 @@ def main() -> int:
             log(f"vortex 1024^2 Q2 {r['precision']}: {r['dof_updates_per_s']:.3e} DOF-updates/s, "
                 f"stage {r['stage_GBps']} GB/s")
         del wv
-        wd = I.double_mach(4096, 1024, 3)
-        post, pre = I.conserved2d(*wd.extra["post"]), I.conserved2d(1.4, 0.0, 0.0, 1.0)
-        speed = wd.extra["shock_speed"] / np.sin(np.pi / 3)
-        meshd = dg.make_mesh(2, (4096, 1024), (0.0, 0.0), (4.0, 1.0),
-                             (dg.DG_BC_DIRICHLET, dg.DG_BC_OUTFLOW, 4, 5),
-                             dirichlet=[list(post)] * 4, shock_x0=1 / 6, shock_speed=speed,
-                             post=list(post), pre=list(pre))
+        wd, meshd = _dmr_mesh(dg, I, np, 4096, 1024, 3)
         r = bench_2d(dg, torch, I, wd, meshd, dg.DG_PREC_MIXED, dg.DG_FILTER_JUMP, 10)
         variants["double_mach_4096x1024_q3_mixed"] = r
         log(f"double Mach 4096x1024 Q3 mixed: {r['dof_updates_per_s']:.3e} DOF-updates/s, "

@@ -73,6 +73,12 @@ struct Phys1D<ADV> {
     __device__ static T speed(const T* u, const PhysParams& p) { return fabs((T)p.a[0]); }
     template <typename T>
     __device__ static T enthalpy(const T* u, const PhysParams& p) { return (T)1; }
+    template <typename T>
+    __device__ static T flux_speed(const T* u, T* f, const PhysParams& p)
+    {
+        flux(u, f, p);
+        return speed(u, p);
+    }
 };
 
 template <>
@@ -84,6 +90,12 @@ struct Phys1D<BURGERS> {
     __device__ static T speed(const T* u, const PhysParams& p) { return fabs(u[0]); }
     template <typename T>
     __device__ static T enthalpy(const T* u, const PhysParams& p) { return (T)1; }
+    template <typename T>
+    __device__ static T flux_speed(const T* u, T* f, const PhysParams& p)
+    {
+        flux(u, f, p);
+        return speed(u, p);
+    }
 };
 
 template <>
@@ -116,6 +128,18 @@ struct Phys1D<EULER> {
         T pr = ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * u[1] / u[0]);
         return (u[2] + pr) / u[0];
     }
+    // flux and speed of one state sharing the velocity and pressure (the
+    // same expressions as flux() and speed(), so the same values)
+    template <typename T>
+    __device__ static T flux_speed(const T* u, T* f, const PhysParams& p)
+    {
+        T vel = u[1] / u[0];
+        T pr = ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * vel);
+        f[0] = u[1];
+        f[1] = u[1] * vel + pr;
+        f[2] = vel * (u[2] + pr);
+        return fabs(vel) + tsqrt<T>((T)p.gamma * pr / u[0]);
+    }
 };
 
 // Local Lax-Friedrichs flux: 1/2 (f(a) + f(b)) - 1/2 max(|f'(a)|, |f'(b)|) (b - a).
@@ -124,9 +148,8 @@ __device__ __forceinline__ void llf1d(const T* ul, const T* ur, T* fh, const Phy
 {
     constexpr int NV = Phys1D<EQ>::NV;
     T fl[NV], fr[NV];
-    Phys1D<EQ>::flux(ul, fl, p);
-    Phys1D<EQ>::flux(ur, fr, p);
-    T al = Phys1D<EQ>::speed(ul, p), ar = Phys1D<EQ>::speed(ur, p);
+    const T al = Phys1D<EQ>::flux_speed(ul, fl, p);
+    const T ar = Phys1D<EQ>::flux_speed(ur, fr, p);
     T alpha = al > ar ? al : ar;
 #pragma unroll
     for (int v = 0; v < NV; ++v) fh[v] = (T)0.5 * (fl[v] + fr[v]) - (T)0.5 * alpha * (ur[v] - ul[v]);
@@ -179,9 +202,14 @@ constexpr int kMaxRetries = 40;
 // atomicMax/atomicMin over doubles through their bit patterns; valid for
 // non-negative values (IEEE-754 order equals unsigned order there) and
 // propagates NaN (its bit pattern exceeds every finite one).
+// The atomic is issued only when v exceeds the value already there (read
+// from L2, coherent across the device): thousands of workgroups reducing
+// into one address otherwise serialise on it.  Within a reduction the
+// stored value only grows, so a skipped update can never lose the maximum.
 __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* p, double v)
 {
-    atomicMax(p, (unsigned long long)__double_as_longlong(v));
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    if (b > __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(p, b);
 }
 
 // Wavefront (64 lanes) maximum.
