@@ -2,19 +2,20 @@
 // kernels for gfx950 (arXiv:2407.19169, Sec. 2.3 two-dimensional scheme and
 // filter, Sec. 2.4 systems, Sec. 3 Algorithm 1).
 //
-// Mapping: 16x16 cells per 256-thread workgroup, one thread per cell,
-// x-fastest SoA mode planes (each plane load is a coalesced row access).
-// The LDS tile has an 18x18 slot grid: the 16x16 own cells plus a ring of 64
-// neighbours, filled by global cell coordinate (wrapped when periodic,
-// flagged when outside the domain), so ragged tiles need no special case.
-//   stage2d:  traces of each cell's right/top edges (and the ring's facing
-//             edges) go to LDS; each edge flux is evaluated once per tile at
-//             the Q Gauss points of the edge; the LDS is then reused for the
-//             fluxes; volume quadrature by partial sum factorisation.
-//   filter2d: one variable at a time, the modes of the tile + ring are staged
-//             in LDS; the jumps of every mixed derivative at the two corners
-//             of each edge are sum-factorised contractions of the two cells'
-//             modes with the derivative values P_p^(a)(+-1).
+// Mapping: one lane per (cell, variable), the variables of a cell in
+// adjacent lanes; 16 x (256 / (16 NV)) cells per 256-thread workgroup (16x4
+// for Euler); x-fastest SoA mode planes.  Tiles are staged in LDS with the
+// neighbour cells they need, found by global cell coordinate (wrapped when
+// periodic, flagged when outside the domain), so ragged tiles need no
+// special case.
+//   stage2d:  each lane publishes its variable's edge traces; every
+//             (edge, Gauss point) flux is evaluated once per tile; the volume
+//             fluxes are shared among the lanes of a cell, one Gauss point of
+//             the current row per lane.
+//   filter2d: the jumps of every mixed derivative at the two corners of each
+//             edge are sum-factorised contractions of the two cells' modes
+//             with the derivative values P_p^(a)(+-1), per variable; the
+//             maximum over the variables is taken inside the cell's lanes.
 #include "dg_kernels.h"
 
 namespace dg {
@@ -179,87 +180,101 @@ __device__ __forceinline__ T combine2_t(int stage, T un, T adv)
                       : (T)(1.0 / 3.0) * un + (T)(2.0 / 3.0) * adv;
 }
 
-// modes of one cell: u0 (FP64 mode 0) and uh[v][m-1] for m = p*K1+q >= 1
-template <int NV, int NM, typename TB>
-__device__ __forceinline__ void load_cell2d(const StateView<TB>& s, int64_t c, double (&u0)[NV],
-                                            TB (&uh)[NV][NM > 1 ? NM - 1 : 1])
-{
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        u0[v] = s.m0[v * s.s0 + c];
-#pragma unroll
-        for (int m = 1; m < NM; ++m) uh[v][m - 1] = s.hi[v * s.sv + (m - 1) * s.sl + c];
-    }
-}
-
 // P_l^(m)(+-1) as a compile-time constant: side 0 -> -1, side 1 -> +1
 __device__ __forceinline__ constexpr double dtr(int l, int m, int side)
 {
     return side ? dtrace_r(l, m) : dtrace_l(l, m);
 }
 
-// Values of a cell's polynomial at the Q Gauss points of one face (FACE 0
-// left xi=-1, 1 right xi=+1, 2 bottom eta=-1, 3 top eta=+1): first the sum
-// across the face, then the along-face Legendre series.  Own cells and the
-// tile's ring cells both use this routine, so the two workgroups that
-// evaluate a tile-boundary edge flux see bitwise identical traces (the
+// Values of one variable's polynomial at the Q Gauss points of one face
+// (FACE 0 left xi=-1, 1 right xi=+1, 2 bottom eta=-1, 3 top eta=+1): first
+// the sum across the face, then the along-face Legendre series.  Own cells
+// and the tile's ring cells both use this routine, so the two workgroups
+// that evaluate a tile-boundary edge flux see bitwise identical traces (the
 // FP64 mode-0 update then telescopes exactly).
-template <int FACE, int NV, int K, typename TB, typename T>
-__device__ __forceinline__ void face_trace(const double (&u0)[NV],
-                                           const TB (&uh)[NV][(K + 1) * (K + 1) > 1 ? (K + 1) * (K + 1) - 1 : 1],
-                                           T (&tr)[K + 1][NV])
+template <int FACE, int K, typename T>
+__device__ __forceinline__ void face_trace_var(const T (&um)[(K + 1) * (K + 1)], T (&tr)[K + 1])
 {
     constexpr int K1 = K + 1;
     constexpr bool xface = FACE < 2;
     constexpr bool plus = (FACE & 1) != 0;
+    T c[K1];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        T c[K1];
+    for (int o = 0; o < K1; ++o) {
+        T sum = (T)0;
 #pragma unroll
-        for (int o = 0; o < K1; ++o) {
-            T s = (T)0;
-#pragma unroll
-            for (int n = 0; n < K1; ++n) {
-                const int p = xface ? n : o, q = xface ? o : n;
-                const T val = (p == 0 && q == 0) ? (T)u0[v] : (T)uh[v][p * K1 + q - 1];
-                s += (plus || !(n & 1)) ? val : -val;
-            }
-            c[o] = s;
+        for (int n = 0; n < K1; ++n) {
+            const T val = um[xface ? n * K1 + o : o * K1 + n];
+            sum += (plus || !(n & 1)) ? val : -val;
         }
+        c[o] = sum;
+    }
 #pragma unroll
-        for (int b = 0; b < K1; ++b) {
-            T s = (T)0;
+    for (int b = 0; b < K1; ++b) {
+        T sum = (T)0;
 #pragma unroll
-            for (int o = 0; o < K1; ++o) s += c[o] * (T)leg_at(K1, b, o);
-            tr[b][v] = s;
-        }
+        for (int o = 0; o < K1; ++o) sum += c[o] * (T)leg_at(K1, b, o);
+        tr[b] = sum;
     }
 }
 
-}  // namespace
+// Modes of variable v of cell c: FP64 mode 0 and the TB modes, all as T.
+template <int NM, typename TB, typename T>
+__device__ __forceinline__ void load_var2d(const StateView<TB>& s, int64_t c, int v, double& m0, T (&um)[NM])
+{
+    m0 = s.m0[v * s.s0 + c];
+    um[0] = (T)m0;
+#pragma unroll
+    for (int m = 1; m < NM; ++m) um[m] = s.hi[v * s.sv + (m - 1) * s.sl + c];
+}
 
-template <int EQ, int K, typename TB>
-__device__ __forceinline__ double stage2d_own_cell(const Args2D<TB>& a, int tid, int tx, int ty,
-                                                   int64_t ix, int64_t jy, int stage, double dt,
-                                                   const double (&u0)[Phys2D<EQ>::NV],
-                                                   const TB (&uh)[Phys2D<EQ>::NV][(K + 1) * (K + 1) > 1 ? (K + 1) * (K + 1) - 1 : 1],
-                                                   const TB* sFx, const TB* sFy);
+// Orders LDS writes before later LDS reads of other lanes of the same
+// wavefront (the lanes of one cell always share a wavefront).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace
 
 // -------------------------------------------------------------------------
 // Residual + Shu-Osher combination (no filter) -> a.out.  With alpha_acc the
 // kernel accumulates the CFL quantity max(lambda_x/hx + lambda_y/hy) of its
 // output's cell averages.
+// Mapping: one lane per (cell, variable), the NV lanes of a cell adjacent;
+// FX x FY cells per workgroup (16 x 4 for Euler).  Each lane evaluates its
+// variable's traces and point values; whole states at a point are gathered
+// inside the cell's lane group (a rotation transpose of shuffles), so every
+// flux is evaluated once: edge fluxes by (edge, point) work items over the
+// whole workgroup, volume fluxes with the NV lanes of a cell taking one
+// Gauss point of the current row each.
 // -------------------------------------------------------------------------
+template <int NV>
+struct StageTile {
+    static constexpr int FX = 16, FY = 256 / (16 * NV);
+    static constexpr int NVE = FY * (FX + 1);  // vertical edges (x = const)
+    static constexpr int NHE = FX * (FY + 1);  // horizontal edges
+};
+
 template <int EQ, int K, typename TB>
 __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
 {
     using P = Phys2D<EQ>;
     using T = TB;
-    constexpr int NV = P::NV, K1 = K + 1, NM = K1 * K1, Q = K1, NH = NM > 1 ? NM - 1 : 1;
-    constexpr int TS = Q * NV;                       // values of one edge trace / flux
-    constexpr int NTR = 17 * 16 + 16 + 16 * 17 + 16;  // trace slots
-    constexpr int NFL = 16 * 17 + 17 * 16;           // flux slots
-    __shared__ __align__(16) T lds[(NTR > NFL ? NTR : NFL) * TS];
+    constexpr int NV = P::NV, K1 = K + 1, NM = K1 * K1, Q = K1;
+    constexpr int FX = StageTile<NV>::FX, FY = StageTile<NV>::FY;
+    constexpr int NVE = StageTile<NV>::NVE, NHE = StageTile<NV>::NHE;
+    constexpr int TS = Q * NV;  // one edge: Q points x NV variables
+    // traces: lower side (the -x / -y cell) and upper side of every edge
+    // (vertical edges first), later reused for the edge fluxes
+    __shared__ __align__(16) T lds[2 * (NVE + NHE) * TS];
+    // per-cell exchange block of the volume term (point values, F1, F2)
+    __shared__ __align__(16) T sX[NV > 1 ? (256 / NV) * 3 * NV * NV : 1];
+    T* sLo = lds;
+    T* sHi = lds + (NVE + NHE) * TS;
+    T* sF = lds;
 
     if (a.dt_from_ctrl && a.ctrl->done) return;
     const double dt = a.dt_from_ctrl ? a.ctrl->dt : a.dt_host;
@@ -267,258 +282,243 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
     const int stage = a.stage;
     const double ts = t0 + (stage == 0 ? 0.0 : stage == 1 ? dt : 0.5 * dt);
 
-    // trace regions: R[ty][0..16] right traces of slot cols 0..16, Lr[ty]
-    // left trace of slot col 17, Tt[tx][0..16] top traces of slot rows 0..16,
-    // Br[tx] bottom trace of slot row 17.
-    T* sR = lds;
-    T* sLr = sR + 16 * 17 * TS;
-    T* sT = sLr + 16 * TS;
-    T* sBr = sT + 16 * 17 * TS;
-    // flux regions (after the traces are consumed): Fx[ty][e], e = 0..16 the
-    // vertical edges of row ty; Fy[tx][e] the horizontal edges of column tx.
-    T* sFx = lds;
-    T* sFy = lds + 16 * 17 * TS;
-
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    const int64_t ix0 = (int64_t)blockIdx.x * 16, jy0 = (int64_t)blockIdx.y * 16;
+    const int tid = threadIdx.x, v = tid % NV, cidx = tid / NV, base = tid - v;
+    const int tx = cidx % FX, ty = cidx / FX;
+    const int64_t ix0 = (int64_t)blockIdx.x * FX, jy0 = (int64_t)blockIdx.y * FY;
     const int64_t ix = ix0 + tx, jy = jy0 + ty;
     const bool px = a.bc[0] == BC_PERIODIC, py = a.bc[2] == BC_PERIODIC;
     const int64_t cx = slot_index(ix, a.nx, px), cy = slot_index(jy, a.ny, py);
     const bool loadable = cx >= 0 && cy >= 0;
     const bool own = ix < a.nx && jy < a.ny;
+    // edge slots: vertical edge e (0..FX) of row r -> r*(FX+1)+e;
+    // horizontal edge e (0..FY) of column c -> NVE + c*(FY+1)+e
+    auto vslot = [&](int r, int e) { return r * (FX + 1) + e; };
+    auto hslot = [&](int c, int e) { return NVE + c * (FY + 1) + e; };
 
-    double u0[NV];
-    T uh[NV][NH];
+    // ---- phase 1: own traces (and the ring's facing traces) to LDS ----
+    double m0v = 0.0;
+    T um[NM];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        u0[v] = 0.0;
+    for (int m = 0; m < NM; ++m) um[m] = (T)0;
+    if (loadable) load_var2d<NM, TB, T>(a.us, cy * a.nx + cx, v, m0v, um);
+    if (loadable) {
+        T tr[Q];
+        face_trace_var<0, K, T>(um, tr);  // left face: upper side of vertical edge tx
 #pragma unroll
-        for (int m = 0; m < NH; ++m) uh[v][m] = (T)0;
+        for (int b = 0; b < Q; ++b) sHi[vslot(ty, tx) * TS + b * NV + v] = tr[b];
+        face_trace_var<1, K, T>(um, tr);  // right face: lower side of edge tx+1
+#pragma unroll
+        for (int b = 0; b < Q; ++b) sLo[vslot(ty, tx + 1) * TS + b * NV + v] = tr[b];
+        face_trace_var<2, K, T>(um, tr);  // bottom face: upper side of horizontal edge ty
+#pragma unroll
+        for (int b = 0; b < Q; ++b) sHi[hslot(tx, ty) * TS + b * NV + v] = tr[b];
+        face_trace_var<3, K, T>(um, tr);  // top face: lower side of edge ty+1
+#pragma unroll
+        for (int b = 0; b < Q; ++b) sLo[hslot(tx, ty + 1) * TS + b * NV + v] = tr[b];
     }
-    if (loadable) load_cell2d<NV, NM, TB>(a.us, cy * a.nx + cx, u0, uh);
-    auto mode = [&](int v, int p, int q) -> T {
-        return (p == 0 && q == 0) ? (T)u0[v] : uh[v][p * K1 + q - 1];
-    };
-
-    // Edge traces at the Gauss points: u(+-1, eta_b) and u(xi_a, +-1).
-    T trL[Q][NV], trR[Q][NV], trB[Q][NV], trT[Q][NV];
-    face_trace<0, NV, K, TB, T>(u0, uh, trL);
-    face_trace<1, NV, K, TB, T>(u0, uh, trR);
-    face_trace<2, NV, K, TB, T>(u0, uh, trB);
-    face_trace<3, NV, K, TB, T>(u0, uh, trT);
-    (void)mode;
-#pragma unroll
-    for (int b = 0; b < Q; ++b)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            sR[(ty * 17 + tx + 1) * TS + b * NV + v] = trR[b][v];
-            sT[(tx * 17 + ty + 1) * TS + b * NV + v] = trT[b][v];
-        }
-
-    // Ring: 64 threads each load one neighbour cell of the tile and publish
-    // the trace of its edge that faces the tile.
-    if (tid < 64) {
-        const int g = tid >> 4, i = tid & 15;
-        const int64_t gx = g == 0 ? ix0 - 1 : g == 1 ? ix0 + 16 : ix0 + i;
-        const int64_t gy = g == 2 ? jy0 - 1 : g == 3 ? jy0 + 16 : jy0 + i;
+    constexpr int NRING = 2 * FY + 2 * FX;
+    if (tid < NRING * NV) {
+        const int r = tid / NV, rv = tid % NV;
+        int g, i;  // g: 0 left column, 1 right column, 2 bottom row, 3 top row
+        if (r < FY) { g = 0; i = r; }
+        else if (r < 2 * FY) { g = 1; i = r - FY; }
+        else if (r < 2 * FY + FX) { g = 2; i = r - 2 * FY; }
+        else { g = 3; i = r - 2 * FY - FX; }
+        const int64_t gx = g == 0 ? ix0 - 1 : g == 1 ? ix0 + FX : ix0 + i;
+        const int64_t gy = g == 2 ? jy0 - 1 : g == 3 ? jy0 + FY : jy0 + i;
         const int64_t hx_ = slot_index(gx, a.nx, px), hy_ = slot_index(gy, a.ny, py);
         if (hx_ >= 0 && hy_ >= 0) {
-            double w0[NV];
-            T wh[NV][NH];
-            load_cell2d<NV, NM, TB>(a.us, hy_ * a.nx + hx_, w0, wh);
-            // the face of the ring cell that faces the tile: g=0 right, 1 left,
-            // 2 top, 3 bottom
-            T* dst = g == 0 ? &sR[(i * 17 + 0) * TS]
-                   : g == 1 ? &sLr[i * TS]
-                   : g == 2 ? &sT[(i * 17 + 0) * TS]
-                            : &sBr[i * TS];
-            T tr[Q][NV];
-            if (g == 0)
-                face_trace<1, NV, K, TB, T>(w0, wh, tr);
-            else if (g == 1)
-                face_trace<0, NV, K, TB, T>(w0, wh, tr);
-            else if (g == 2)
-                face_trace<3, NV, K, TB, T>(w0, wh, tr);
-            else
-                face_trace<2, NV, K, TB, T>(w0, wh, tr);
+            double w0;
+            T wm[NM];
+            load_var2d<NM, TB, T>(a.us, hy_ * a.nx + hx_, rv, w0, wm);
+            T tr[Q];
+            T* dst;
+            if (g == 0) {
+                face_trace_var<1, K, T>(wm, tr);
+                dst = &sLo[vslot(i, 0) * TS];
+            } else if (g == 1) {
+                face_trace_var<0, K, T>(wm, tr);
+                dst = &sHi[vslot(i, FX) * TS];
+            } else if (g == 2) {
+                face_trace_var<3, K, T>(wm, tr);
+                dst = &sLo[hslot(i, 0) * TS];
+            } else {
+                face_trace_var<2, K, T>(wm, tr);
+                dst = &sHi[hslot(i, FY) * TS];
+            }
 #pragma unroll
-            for (int b = 0; b < Q; ++b)
-#pragma unroll
-                for (int v = 0; v < NV; ++v) dst[b * NV + v] = tr[b][v];
+            for (int b = 0; b < Q; ++b) dst[b * NV + rv] = tr[b];
         }
     }
     __syncthreads();
 
-    // Edge fluxes (LLF, normal +x / +y) at the Gauss points of the edges.
-    T fLx[Q][NV], fBy[Q][NV], fRx[Q][NV], fTy[Q][NV];
-    const bool need_r = loadable && (tx == 15 || (!px && ix == a.nx - 1));
-    const bool need_t = loadable && (ty == 15 || (!py && jy == a.ny - 1));
-    if (loadable) {
-        const bool lghost = !px && ix == 0, bghost = !py && jy == 0;
-        const bool rghost = !px && ix == a.nx - 1, tghost = !py && jy == a.ny - 1;
-        const double xl = a.xlo + (double)ix * a.hx, yb = a.ylo + (double)jy * a.hy;
+    // ---- phase 2: LLF flux at every (edge, Gauss point) of the tile ----
+    constexpr int NITEM = (NVE + NHE) * Q;
+    constexpr int PER = (NITEM + 255) / 256;
+    T fl[PER][NV];
 #pragma unroll
-        for (int b = 0; b < Q; ++b) {
-            const double yq = yb + 0.5 * a.hy * (1.0 + gl_node(Q, b));
-            const double xq = xl + 0.5 * a.hx * (1.0 + gl_node(Q, b));
-            T left[NV], bot[NV];
-            if (lghost)
-                ghost_state2d<NV, TB, T>(a, 0, xl, yq, ts, trL[b], left);
-            else
-#pragma unroll
-                for (int v = 0; v < NV; ++v) left[v] = sR[(ty * 17 + tx) * TS + b * NV + v];
-            llf2d<EQ, T>(left, trL[b], 0, fLx[b], a.phys);
-            if (bghost)
-                ghost_state2d<NV, TB, T>(a, 2, xq, yb, ts, trB[b], bot);
-            else
-#pragma unroll
-                for (int v = 0; v < NV; ++v) bot[v] = sT[(tx * 17 + ty) * TS + b * NV + v];
-            llf2d<EQ, T>(bot, trB[b], 1, fBy[b], a.phys);
-            if (need_r) {
-                T right[NV];
-                if (rghost)
-                    ghost_state2d<NV, TB, T>(a, 1, xl + a.hx, yq, ts, trR[b], right);
-                else
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) right[v] = sLr[ty * TS + b * NV + v];
-                llf2d<EQ, T>(trR[b], right, 0, fRx[b], a.phys);
-            }
-            if (need_t) {
-                T top[NV];
-                if (tghost)
-                    ghost_state2d<NV, TB, T>(a, 3, xq, yb + a.hy, ts, trT[b], top);
-                else
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) top[v] = sBr[tx * TS + b * NV + v];
-                llf2d<EQ, T>(trT[b], top, 1, fTy[b], a.phys);
-            }
+    for (int k = 0; k < PER; ++k) {
+        const int w = tid + 256 * k;
+        if (w >= NITEM) break;
+        const int es = w / Q, b = w % Q;
+        const bool vert = es < NVE;
+        int64_t glo, ghi;  // global coordinates of the lower and upper cells
+        int64_t other;     // the cell coordinate along the edge
+        if (vert) {
+            const int r = es / (FX + 1), e = es % (FX + 1);
+            glo = ix0 + e - 1;
+            ghi = ix0 + e;
+            other = jy0 + r;
+        } else {
+            const int c = (es - NVE) / (FY + 1), e = (es - NVE) % (FY + 1);
+            glo = jy0 + e - 1;
+            ghi = jy0 + e;
+            other = ix0 + c;
         }
-    }
-    __syncthreads();  // traces consumed; reuse the LDS for the fluxes
-    if (loadable) {
+        const int64_t nax = vert ? a.nx : a.ny, nal = vert ? a.ny : a.nx;
+        const bool per = vert ? px : py, per_o = vert ? py : px;
+        const bool lo_ok = slot_index(glo, nax, per) >= 0, hi_ok = slot_index(ghi, nax, per) >= 0;
+        const bool o_ok = slot_index(other, nal, per_o) >= 0;
+        T f[NV];
 #pragma unroll
-        for (int b = 0; b < Q; ++b)
+        for (int q = 0; q < NV; ++q) f[q] = (T)0;
+        if (o_ok && (lo_ok || hi_ok)) {
+            T ul[NV], ur[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                sFx[(ty * 17 + tx) * TS + b * NV + v] = fLx[b][v];
-                sFy[(tx * 17 + ty) * TS + b * NV + v] = fBy[b][v];
-                if (need_r) sFx[(ty * 17 + tx + 1) * TS + b * NV + v] = fRx[b][v];
-                if (need_t) sFy[(tx * 17 + ty + 1) * TS + b * NV + v] = fTy[b][v];
+            for (int q = 0; q < NV; ++q) {
+                ul[q] = sLo[es * TS + b * NV + q];
+                ur[q] = sHi[es * TS + b * NV + q];
             }
+            const double edge = vert ? a.xlo + (double)ghi * a.hx : a.ylo + (double)ghi * a.hy;
+            const double along = vert ? a.ylo + (double)other * a.hy + 0.5 * a.hy * (1.0 + gl_node(Q, b))
+                                      : a.xlo + (double)other * a.hx + 0.5 * a.hx * (1.0 + gl_node(Q, b));
+            const double xq = vert ? edge : along, yq = vert ? along : edge;
+            if (!lo_ok) ghost_state2d<NV, TB, T>(a, vert ? 0 : 2, xq, yq, ts, ur, ul);
+            if (!hi_ok) ghost_state2d<NV, TB, T>(a, vert ? 1 : 3, xq, yq, ts, ul, ur);
+            llf2d<EQ, T>(ul, ur, vert ? 0 : 1, f, a.phys);
+        }
+#pragma unroll
+        for (int q = 0; q < NV; ++q) fl[k][q] = f[q];
+    }
+    __syncthreads();  // traces consumed; the LDS now takes the fluxes
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int w = tid + 256 * k;
+        if (w >= NITEM) break;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) sF[(w / Q) * TS + (w % Q) * NV + q] = fl[k][q];
     }
     __syncthreads();
 
-    double lam_out = 0.0;
-    if (own) lam_out = stage2d_own_cell<EQ, K, TB>(a, tid, tx, ty, ix, jy, stage, dt, u0, uh, sFx, sFy);
-    // every lane reaches the wave reduction (no early exits above)
-    if (a.alpha_acc) {
-        const double z = wave_max(lam_out);
-        if ((tid & 63) == 0) atomic_max_nonneg(a.alpha_acc, z);
-    }
-}
-
-// Volume term, edge terms, residual and Shu-Osher combination of one own
-// cell (the fluxes of its four edges are in LDS); returns the CFL quantity
-// lambda_x/hx + lambda_y/hy of the output's cell average.
-template <int EQ, int K, typename TB>
-__device__ __forceinline__ double stage2d_own_cell(const Args2D<TB>& a, int tid, int tx, int ty,
-                                                   int64_t ix, int64_t jy, int stage, double dt,
-                                                   const double (&u0)[Phys2D<EQ>::NV],
-                                                   const TB (&uh)[Phys2D<EQ>::NV][(K + 1) * (K + 1) > 1 ? (K + 1) * (K + 1) - 1 : 1],
-                                                   const TB* sFx, const TB* sFy)
-{
-    using P = Phys2D<EQ>;
-    using T = TB;
-    constexpr int NV = P::NV, K1 = K + 1, NM = K1 * K1, Q = K1, NH = NM > 1 ? NM - 1 : 1;
-    constexpr int TS = Q * NV;
-    auto mode = [&](int v, int p, int q) -> T {
-        return (p == 0 && q == 0) ? (T)u0[v] : uh[v][p * K1 + q - 1];
-    };
+    // ---- phase 3: volume term, edge terms, combination (variable v) ----
     const int64_t cell = jy * a.nx + ix;
-
+    const T hy2 = (T)(0.5 * a.hy), hx2 = (T)(0.5 * a.hx);
+    T acc[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) acc[m] = (T)0;
     // Volume term: (hy/2) sum w_a w_b F1 P_p'(xi_a) P_q(eta_b)
     //            + (hx/2) sum w_a w_b F2 P_p(xi_a) P_q'(eta_b)
-    T acc[NV][NM];
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int m = 0; m < NM; ++m) acc[v][m] = (T)0;
-    const T hy2 = (T)(0.5 * a.hy), hx2 = (T)(0.5 * a.hx);
 #pragma unroll
     for (int qa = 0; qa < Q; ++qa) {
-        T col[NV][K1];  // sum_p u^{pq} P_p(xi_a)
+        T col[K1];  // sum_p u^{pq} P_p(xi_a)
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
+        for (int q = 0; q < K1; ++q) {
+            T sum = (T)0;
 #pragma unroll
-            for (int q = 0; q < K1; ++q) {
-                T s = (T)0;
+            for (int p = 0; p < K1; ++p) sum += um[p * K1 + q] * (T)leg_at(Q, qa, p);
+            col[q] = sum;
+        }
+        constexpr int NB = NV > Q ? NV : Q;
+        T uv[NB];  // this variable at the points (qa, b)
 #pragma unroll
-                for (int p = 0; p < K1; ++p) s += mode(v, p, q) * (T)leg_at(Q, qa, p);
-                col[v][q] = s;
+        for (int b = 0; b < NB; ++b) {
+            T sum = (T)0;
+            if (b < Q) {
+#pragma unroll
+                for (int q = 0; q < K1; ++q) sum += col[q] * (T)leg_at(Q, (b < Q ? b : 0), q);
             }
-        T t1[NV][K1], t2[NV][K1];  // sum_b w_b F1 P_q(eta_b), sum_b w_b F2 P_q'(eta_b)
+            uv[b] = sum;
+        }
+        T g1[NB], g2[NB];  // F1, F2 of this variable at the points (qa, b)
+        if constexpr (NV == 1) {
+            // scalar equations: the lane evaluates every point itself
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
+            for (int b = 0; b < Q; ++b) {
+                T u1[1] = {uv[b]}, h1[1], h2[1];
+                P::flux(u1, 0, h1, a.phys);
+                P::flux(u1, 1, h2, a.phys);
+                g1[b] = h1[0];
+                g2[b] = h2[0];
+            }
+        } else {
+            // lane v of the cell takes point (qa, v): the cell's lanes swap
+            // point values and fluxes through their LDS block
+            T* X = &sX[cidx * 3 * NV * NV];
 #pragma unroll
-            for (int q = 0; q < K1; ++q) t1[v][q] = t2[v][q] = (T)0;
-#pragma unroll
-        for (int qb = 0; qb < Q; ++qb) {
+            for (int b = 0; b < NV; ++b) X[b * NV + v] = uv[b];
+            wave_lds_sync();
             T uq[NV], f1[NV], f2[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                T s = (T)0;
-#pragma unroll
-                for (int q = 0; q < K1; ++q) s += col[v][q] * (T)leg_at(Q, qb, q);
-                uq[v] = s;
+            for (int q = 0; q < NV; ++q) {
+                uq[q] = X[v * NV + q];
+                f1[q] = f2[q] = (T)0;
             }
-            if (EQ == EULER && a.check) {
-                const T pr = Phys2D<EULER>::pressure(uq, a.phys);
-                if (!(uq[0] > (T)0) || !(pr > (T)0)) {
-                    const bool fin = isfinite((double)uq[0]) && isfinite((double)pr);
-                    latch_error(a.ctrl, fin ? -5 : -4, cell);
+            if (v < Q && own) {
+                if (EQ == EULER && a.check) {
+                    const T pr = Phys2D<EULER>::pressure(uq, a.phys);
+                    if (!(uq[0] > (T)0) || !(pr > (T)0)) {
+                        const bool fin = isfinite((double)uq[0]) && isfinite((double)pr);
+                        latch_error(a.ctrl, fin ? -5 : -4, cell);
+                    }
                 }
+                P::flux(uq, 0, f1, a.phys);
+                P::flux(uq, 1, f2, a.phys);
             }
-            P::flux(uq, 0, f1, a.phys);
-            P::flux(uq, 1, f2, a.phys);
-            const T wb = (T)gl_weight(Q, qb);
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
+            for (int q = 0; q < NV; ++q) {
+                X[NV * NV + v * NV + q] = f1[q];
+                X[2 * NV * NV + v * NV + q] = f2[q];
+            }
+            wave_lds_sync();
 #pragma unroll
-                for (int q = 0; q < K1; ++q) {
-                    t1[v][q] += wb * f1[v] * (T)leg_at(Q, qb, q);
-                    t2[v][q] += wb * f2[v] * (T)dleg_at(Q, qb, q);
-                }
+            for (int b = 0; b < NB; ++b) {
+                g1[b] = X[NV * NV + b * NV + v];
+                g2[b] = X[2 * NV * NV + b * NV + v];
+            }
+            wave_lds_sync();  // the block is rewritten by the next row
+        }
+        T t1[K1], t2[K1];  // sum_b w_b F1 P_q(eta_b), sum_b w_b F2 P_q'(eta_b)
+#pragma unroll
+        for (int q = 0; q < K1; ++q) t1[q] = t2[q] = (T)0;
+#pragma unroll
+        for (int b = 0; b < Q; ++b) {
+            const T wb = (T)gl_weight(Q, b);
+#pragma unroll
+            for (int q = 0; q < K1; ++q) {
+                t1[q] += wb * g1[b] * (T)leg_at(Q, b, q);
+                t2[q] += wb * g2[b] * (T)dleg_at(Q, b, q);
+            }
         }
         const T wa = (T)gl_weight(Q, qa);
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
+        for (int p = 0; p < K1; ++p)
 #pragma unroll
-            for (int p = 0; p < K1; ++p)
-#pragma unroll
-                for (int q = 0; q < K1; ++q)
-                    acc[v][p * K1 + q] += wa * (hy2 * (T)dleg_at(Q, qa, p) * t1[v][q] +
-                                                hx2 * (T)leg_at(Q, qa, p) * t2[v][q]);
+            for (int q = 0; q < K1; ++q)
+                acc[p * K1 + q] += wa * (hy2 * (T)dleg_at(Q, qa, p) * t1[q] + hx2 * (T)leg_at(Q, qa, p) * t2[q]);
     }
 
-    // Edge terms, residual, Shu-Osher combination.
-    double n0[NV];
-    T nh[NV][NH];
+    double v0 = 0.0;
+    if (own) {
+        double n0 = 0.0;
+        T nm[NM];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        n0[v] = 0.0;
-#pragma unroll
-        for (int m = 0; m < NH; ++m) nh[v][m] = (T)0;
-    }
-    if (stage > 0) load_cell2d<NV, NM, TB>(a.un, cell, n0, nh);
-    const T* FL = &sFx[(ty * 17 + tx) * TS];
-    const T* FR = &sFx[(ty * 17 + tx + 1) * TS];
-    const T* FB = &sFy[(tx * 17 + ty) * TS];
-    const T* FT = &sFy[(tx * 17 + ty + 1) * TS];
-    const double ivol = a.inv_hx * a.inv_hy;
-    double v0[NV];
-    T vh[NV][NH];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
+        for (int m = 0; m < NM; ++m) nm[m] = (T)0;
+        if (stage > 0) load_var2d<NM, TB, T>(a.un, cell, v, n0, nm);
+        const T* FL = &sF[vslot(ty, tx) * TS];
+        const T* FR = &sF[vslot(ty, tx + 1) * TS];
+        const T* FB = &sF[hslot(tx, ty) * TS];
+        const T* FT = &sF[hslot(tx, ty + 1) * TS];
+        const double ivol = a.inv_hx * a.inv_hy;
         // mode (0,0): -(hy/2) sum_b w_b (FR - FL) - (hx/2) sum_a w_a (FT - FB), in FP64
         double ex = 0.0, ey = 0.0;
 #pragma unroll
@@ -527,7 +527,8 @@ __device__ __forceinline__ double stage2d_own_cell(const Args2D<TB>& a, int tid,
             ey += gl_weight(Q, b) * ((double)FT[b * NV + v] - (double)FB[b * NV + v]);
         }
         const double L0 = -(0.5 * a.hy * ex + 0.5 * a.hx * ey) * ivol;
-        v0[v] = combine2(stage, n0[v], u0[v] + dt * L0);
+        v0 = combine2(stage, n0, m0v + dt * L0);
+        a.out.m0[v * a.out.s0 + cell] = v0;
 #pragma unroll
         for (int p = 0; p < K1; ++p)
 #pragma unroll
@@ -536,184 +537,244 @@ __device__ __forceinline__ double stage2d_own_cell(const Args2D<TB>& a, int tid,
                 T ex_ = (T)0, ey_ = (T)0;
 #pragma unroll
                 for (int b = 0; b < Q; ++b) {
-                    const T fl = (p & 1) ? -FL[b * NV + v] : FL[b * NV + v];
-                    ex_ += (T)gl_weight(Q, b) * (FR[b * NV + v] - fl) * (T)leg_at(Q, b, q);
+                    const T fl_ = (p & 1) ? -FL[b * NV + v] : FL[b * NV + v];
+                    ex_ += (T)gl_weight(Q, b) * (FR[b * NV + v] - fl_) * (T)leg_at(Q, b, q);
                     const T fb = (q & 1) ? -FB[b * NV + v] : FB[b * NV + v];
                     ey_ += (T)gl_weight(Q, b) * (FT[b * NV + v] - fb) * (T)leg_at(Q, b, p);
                 }
-                const T r = acc[v][p * K1 + q] - hy2 * ex_ - hx2 * ey_;
+                const T r = acc[p * K1 + q] - hy2 * ex_ - hx2 * ey_;
                 const T L = (T)((2 * p + 1) * (2 * q + 1)) * (T)ivol * r;
-                const int m = p * K1 + q - 1;
-                vh[v][m] = combine2_t<T>(stage, nh[v][m], uh[v][m] + (T)dt * L);
+                const int m = p * K1 + q;
+                a.out.hi[v * a.out.sv + (m - 1) * a.out.sl + cell] =
+                    combine2_t<T>(stage, nm[m], um[m] + (T)dt * L);
             }
     }
-    // store
+    // CFL quantity of the output's cell average (all variables of the cell)
+    if (a.alpha_acc) {
+        double w0[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        a.out.m0[v * a.out.s0 + cell] = v0[v];
-#pragma unroll
-        for (int m = 1; m < NM; ++m) a.out.hi[v * a.out.sv + (m - 1) * a.out.sl + cell] = vh[v][m - 1];
+        for (int q = 0; q < NV; ++q) w0[q] = NV > 1 ? __shfl(v0, base + q, 64) : v0;
+        const double lam = own ? P::speed(w0, 0, a.phys) * a.inv_hx + P::speed(w0, 1, a.phys) * a.inv_hy
+                               : 0.0;
+        const double z = wave_max(lam);
+        if ((tid & 63) == 0) atomic_max_nonneg(a.alpha_acc, z);
     }
-    (void)tid;
-    return P::speed(v0, 0, a.phys) * a.inv_hx + P::speed(v0, 1, a.phys) * a.inv_hy;
 }
 
 // -------------------------------------------------------------------------
 // Jump filter (MODE 1: filtered copy of a.us into a.out) or hybrid pass A
 // (MODE 2: records of the troubled cells of a.us, and max eta).
-//   E^l = dt / (hx hy H) * max_v [hx beta_x Sx^l_v + hy beta_y Sy^l_v],
+//   E^l = dt / (hx hy H) * max_v [cfmx beta_x Sx^l_v + cfmy beta_y Sy^l_v],
 //   Sx^l = sum_{|a| <= l} jsx[a] * Jx^a (edge-averaged |[d^a u]| in reference
 //   derivatives; jsx[0] = hx, jsx[a] = m(m+1) hx^(m+1) (2/hx)^a1 (2/hy)^a2).
+// Mapping: one lane per (cell, variable); the NV lanes of a cell are
+// adjacent, so the maximum over the variables is a reduction inside a group
+// of NV lanes.  A workgroup covers FX x FY cells (16 x 4 for Euler) and
+// stages their modes and those of the four face-neighbour rows/columns in
+// LDS; each lane keeps only its own variable's modes in registers.
 // -------------------------------------------------------------------------
+template <int NV>
+struct FilterTile {
+    static constexpr int FX = 16, FY = 256 / (16 * NV);
+    static constexpr int SX = FX + 2, SY = FY + 2;
+};
+
 template <int EQ, int K, typename TB, int MODE>
 __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
 {
     using P = Phys2D<EQ>;
     using T = TB;
     constexpr int NV = P::NV, K1 = K + 1, NM = K1 * K1, L1 = 2 * K + 1;
-    __shared__ __align__(16) T sM[18 * 18 * NM];
+    constexpr int FX = FilterTile<NV>::FX, FY = FilterTile<NV>::FY;
+    constexpr int SX = FilterTile<NV>::SX, SY = FilterTile<NV>::SY;
+    constexpr int STRIDE = NM * NV + 1;  // T words per slot, padded against bank conflicts
+    __shared__ __align__(16) T sM[SX * SY * STRIDE];
 
     if (a.dt_from_ctrl && a.ctrl->done) return;
     const double dt = a.dt_from_ctrl ? a.ctrl->dt : a.dt_host;
     const double t0 = a.dt_from_ctrl ? a.ctrl->t : a.t_host;
     const double tf = t0 + (a.stage == 1 ? 0.5 : 1.0) * dt;  // time the stage output stands for
 
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    const int64_t ix0 = (int64_t)blockIdx.x * 16, jy0 = (int64_t)blockIdx.y * 16;
+    const int tid = threadIdx.x, v = tid % NV, cidx = tid / NV;
+    const int tx = cidx % FX, ty = cidx / FX;
+    const int64_t ix0 = (int64_t)blockIdx.x * FX, jy0 = (int64_t)blockIdx.y * FY;
     const int64_t ix = ix0 + tx, jy = jy0 + ty;
     const bool px = a.bc[0] == BC_PERIODIC, py = a.bc[2] == BC_PERIODIC;
     const int64_t cx = slot_index(ix, a.nx, px), cy = slot_index(jy, a.ny, py);
     const bool loadable = cx >= 0 && cy >= 0;
     const bool own = ix < a.nx && jy < a.ny;
-    // ring slot of this thread (tid < 64)
-    const int g = tid >> 4, gi = tid & 15;
-    const int64_t rgx = g == 0 ? ix0 - 1 : g == 1 ? ix0 + 16 : ix0 + gi;
-    const int64_t rgy = g == 2 ? jy0 - 1 : g == 3 ? jy0 + 16 : jy0 + gi;
-    const int64_t rcx = slot_index(rgx, a.nx, px), rcy = slot_index(rgy, a.ny, py);
-    const int rslot = g == 0 ? (gi + 1) * 18 + 0 : g == 1 ? (gi + 1) * 18 + 17 : g == 2 ? 0 * 18 + gi + 1
-                                                                                        : 17 * 18 + gi + 1;
-    const int oslot = (ty + 1) * 18 + tx + 1;
+    const int oslot = (ty + 1) * SX + tx + 1;
+
+    // own modes of variable v: registers and LDS
+    double m0v = 0.0;
+    T um[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) um[m] = (T)0;
+    if (loadable) {
+        const int64_t c = cy * a.nx + cx;
+        m0v = a.us.m0[v * a.us.s0 + c];
+        um[0] = (T)m0v;
+#pragma unroll
+        for (int m = 1; m < NM; ++m) um[m] = a.us.hi[v * a.us.sv + (m - 1) * a.us.sl + c];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) sM[oslot * STRIDE + m * NV + v] = um[m];
+    }
+    // face-neighbour ring: left/right columns and bottom/top rows of the tile
+    constexpr int NRING = 2 * FY + 2 * FX;
+    if (tid < NRING * NV) {
+        const int r = tid / NV, rv = tid % NV;
+        int sx, sy;
+        if (r < FY) {
+            sx = 0;
+            sy = r + 1;
+        } else if (r < 2 * FY) {
+            sx = FX + 1;
+            sy = r - FY + 1;
+        } else if (r < 2 * FY + FX) {
+            sx = r - 2 * FY + 1;
+            sy = 0;
+        } else {
+            sx = r - 2 * FY - FX + 1;
+            sy = FY + 1;
+        }
+        const int64_t gx = slot_index(ix0 + sx - 1, a.nx, px), gy = slot_index(jy0 + sy - 1, a.ny, py);
+        if (gx >= 0 && gy >= 0) {
+            const int64_t c = gy * a.nx + gx;
+            const int slot = sy * SX + sx;
+            sM[slot * STRIDE + rv] = (T)a.us.m0[rv * a.us.s0 + c];
+#pragma unroll
+            for (int m = 1; m < NM; ++m)
+                sM[slot * STRIDE + m * NV + rv] = a.us.hi[rv * a.us.sv + (m - 1) * a.us.sl + c];
+        }
+    }
+    __syncthreads();
+
     const bool lin = slot_index(ix - 1, a.nx, px) >= 0, rin = slot_index(ix + 1, a.nx, px) >= 0;
     const bool bin = slot_index(jy - 1, a.ny, py) >= 0, tin = slot_index(jy + 1, a.ny, py) >= 0;
     const double xl = a.xlo + (double)ix * a.hx, yb = a.ylo + (double)jy * a.hy;
 
-    T best[L1];
-#pragma unroll
-    for (int l = 0; l < L1; ++l) best[l] = (T)0;
-    T eta = (T)0;
-    double ub[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) ub[v] = loadable ? a.us.m0[v * a.us.s0 + cy * a.nx + cx] : 1.0;
+    // cell-average state (all variables) for beta_x, beta_y and H
     T ubt[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) ubt[v] = (T)ub[v];
+    for (int w = 0; w < NV; ++w) ubt[w] = loadable ? sM[oslot * STRIDE + w] : (T)1;
     const T bx = P::speed(ubt, 0, a.phys), by = P::speed(ubt, 1, a.phys);
     const T H = P::enthalpy(ubt, a.phys);
 
-    for (int v = 0; v < NV; ++v) {
-        __syncthreads();
-        if (loadable) {
-            const int64_t c = cy * a.nx + cx;
-            sM[oslot * NM] = (T)a.us.m0[v * a.us.s0 + c];
+    T Jx[L1], Jy[L1];  // weighted sums per derivative order m = a1 + a2 (variable v)
 #pragma unroll
-            for (int m = 1; m < NM; ++m) sM[oslot * NM + m] = a.us.hi[v * a.us.sv + (m - 1) * a.us.sl + c];
-        }
-        if (tid < 64 && rcx >= 0 && rcy >= 0) {
-            const int64_t c = rcy * a.nx + rcx;
-            sM[rslot * NM] = (T)a.us.m0[v * a.us.s0 + c];
+    for (int m = 0; m < L1; ++m) Jx[m] = Jy[m] = (T)0;
+    T jx0 = (T)0, jy0_ = (T)0;
+    if (own) {
+        // DIR 0: vertical faces (x = const), DIR 1: horizontal faces.  The
+        // face side is a run-time loop index (keeps one face live at a time).
 #pragma unroll
-            for (int m = 1; m < NM; ++m) sM[rslot * NM + m] = a.us.hi[v * a.us.sv + (m - 1) * a.us.sl + c];
-        }
-        __syncthreads();
-        if (!own) continue;
-        const T* U0 = &sM[oslot * NM];
-        T Jx[L1], Jy[L1];  // weighted sums per derivative order m = a1 + a2
+        for (int dir = 0; dir < 2; ++dir) {
+#pragma unroll 1
+            for (int side = 0; side < 2; ++side) {
+                const bool inside = dir == 0 ? (side ? rin : lin) : (side ? tin : bin);
+                const int nslot = oslot + (dir == 0 ? (side ? 1 : -1) : (side ? SX : -SX));
+                const T* UN = &sM[nslot * STRIDE + v];
+                // across-face derivative values P_n^(a)(end): +1 end for
+                // side 1, -1 end for side 0 (sign (-1)^(n+a)); the neighbour
+                // sees the opposite end
+                auto across = [&](int n, int al, int sd) -> T {
+                    const double r = dtrace_r(n, al);
+                    return (T)((sd || !((n + al) & 1)) ? r : -r);
+                };
+                // D[al][o] = sum_n (nb - own) u^{..} P_n^(al)(end), n the
+                // across-face index, o the along-face index
+                T D[K1][K1];
 #pragma unroll
-        for (int m = 0; m < L1; ++m) Jx[m] = Jy[m] = (T)0;
-        T jx0 = (T)0, jy0_ = (T)0;
-        // vertical faces: side 0 (left, neighbour slot -1) and 1 (right, +1)
+                for (int al = 0; al < K1; ++al)
 #pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const bool inside = side ? rin : lin;
-            const T* UN = &sM[(oslot + (side ? 1 : -1)) * NM];
-            // G[a1][q] = sum_p u^{pq} P_p^(a1)(end): own at its `side` end,
-            // neighbour at the opposite end
-            T D[K1][K1];  // D[a1][q] = G_nb - G_own (or G_own if ghost)
+                    for (int o = 0; o < K1; ++o) {
+                        T go = (T)0, gn = (T)0;
 #pragma unroll
-            for (int a1 = 0; a1 < K1; ++a1)
-#pragma unroll
-                for (int q = 0; q < K1; ++q) {
-                    T go = (T)0, gn = (T)0;
-#pragma unroll
-                    for (int p = (a1 > 0 ? a1 : 0); p < K1; ++p) {
-                        go += U0[p * K1 + q] * (T)dtr(p, a1, side);
-                        if (inside) gn += UN[p * K1 + q] * (T)dtr(p, a1, 1 - side);
+                        for (int n = (al > 0 ? al : 0); n < K1; ++n) {
+                            const int m = dir == 0 ? n * K1 + o : o * K1 + n;
+                            go += um[m] * across(n, al, side);
+                            if (inside) gn += UN[m * NV] * across(n, al, 1 - side);
+                        }
+                        D[al][o] = inside ? gn - go : go;
                     }
-                    D[a1][q] = inside ? gn - go : go;
+                // outside the domain: the ghost at the two corners of this face
+                int gk[2] = {0, 0};
+                bool grf[2] = {false, false};
+                T gst[2] = {(T)0, (T)0};
+                if (!inside) {
+                    const int fside = 2 * dir + side;
+#pragma unroll
+                    for (int cc = 0; cc < 2; ++cc) {
+                        const double xc = dir == 0 ? xl + (side ? a.hx : 0.0) : xl + (cc ? a.hx : 0.0);
+                        const double yc = dir == 0 ? yb + (cc ? a.hy : 0.0) : yb + (side ? a.hy : 0.0);
+                        bool rf;
+                        gk[cc] = boundary_kind(a, fside, xc, yc, tf, &rf);
+                        grf[cc] = rf;
+                        gst[cc] = gk[cc] ? (T)boundary_state(a, fside, gk[cc], v) : (T)0;
+                    }
                 }
-            const double xf = xl + (side ? a.hx : 0.0);
 #pragma unroll
-            for (int cyc = 0; cyc < 2; ++cyc) {
-                const double yc = yb + (cyc ? a.hy : 0.0);
+                for (int cc = 0; cc < 2; ++cc)
 #pragma unroll
-                for (int a1 = 0; a1 < K1; ++a1)
+                    for (int al = 0; al < K1; ++al)
 #pragma unroll
-                    for (int a2 = 0; a2 < K1; ++a2) {
-                        T s = (T)0;
+                        for (int bl = 0; bl < K1; ++bl) {
+                            // al: across-face derivative order, bl: along-face
+                            T sum = (T)0;
 #pragma unroll
-                        for (int q = (a2 > 0 ? a2 : 0); q < K1; ++q) s += D[a1][q] * (T)dtr(q, a2, cyc);
-                        T j = inside ? fabs(s) : ghost_jump2d<TB, T>(a, side, xf, yc, tf, a1, a2, v, s);
-                        Jx[a1 + a2] += (T)(0.5 * a.jsx[a1 * 4 + a2]) * j;
-                        if (a1 == 0 && a2 == 0) jx0 += (T)0.5 * j;
-                    }
+                            for (int o = (bl > 0 ? bl : 0); o < K1; ++o)
+                                sum += D[al][o] * (T)dtr(o, bl, cc);
+                            T j = fabs(sum);
+                            if (!inside) {
+                                if (gk[cc])
+                                    j = (al == 0 && bl == 0) ? fabs(gst[cc] - sum) : fabs(sum);
+                                else if (grf[cc])
+                                    j = (((al & 1) != 0) != (v == 1 + dir)) ? (T)2 * fabs(sum) : (T)0;
+                                else
+                                    j = (T)0;
+                            }
+                            const int a1 = dir == 0 ? al : bl, a2 = dir == 0 ? bl : al;
+                            if (dir == 0) {
+                                Jx[a1 + a2] += (T)(0.5 * a.jsx[a1 * 4 + a2]) * j;
+                                if (al == 0 && bl == 0) jx0 += (T)0.5 * j;
+                            } else {
+                                Jy[a1 + a2] += (T)(0.5 * a.jsy[a1 * 4 + a2]) * j;
+                                if (al == 0 && bl == 0) jy0_ += (T)0.5 * j;
+                            }
+                        }
             }
         }
-        // horizontal faces: side 0 (bottom, slot -18) and 1 (top, +18)
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const bool inside = side ? tin : bin;
-            const T* UN = &sM[(oslot + (side ? 18 : -18)) * NM];
-            T D[K1][K1];  // D[p][a2]
-#pragma unroll
-            for (int p = 0; p < K1; ++p)
-#pragma unroll
-                for (int a2 = 0; a2 < K1; ++a2) {
-                    T go = (T)0, gn = (T)0;
-#pragma unroll
-                    for (int q = (a2 > 0 ? a2 : 0); q < K1; ++q) {
-                        go += U0[p * K1 + q] * (T)dtr(q, a2, side);
-                        if (inside) gn += UN[p * K1 + q] * (T)dtr(q, a2, 1 - side);
-                    }
-                    D[p][a2] = inside ? gn - go : go;
-                }
-            const double yf = yb + (side ? a.hy : 0.0);
-#pragma unroll
-            for (int cxc = 0; cxc < 2; ++cxc) {
-                const double xc = xl + (cxc ? a.hx : 0.0);
-#pragma unroll
-                for (int a1 = 0; a1 < K1; ++a1)
-#pragma unroll
-                    for (int a2 = 0; a2 < K1; ++a2) {
-                        T s = (T)0;
-#pragma unroll
-                        for (int p = (a1 > 0 ? a1 : 0); p < K1; ++p) s += D[p][a2] * (T)dtr(p, a1, cxc);
-                        T j = inside ? fabs(s) : ghost_jump2d<TB, T>(a, 2 + side, xc, yf, tf, a1, a2, v, s);
-                        Jy[a1 + a2] += (T)(0.5 * a.jsy[a1 * 4 + a2]) * j;
-                        if (a1 == 0 && a2 == 0) jy0_ += (T)0.5 * j;
-                    }
-            }
-        }
-        // running partial sums over the derivative order and max over vars
+    }
+    // running partial sums over the derivative order, then the maximum over
+    // the variables (in variable order, as a sequential loop would take it)
+    T best[L1];
+    {
         T sx = (T)0, sy = (T)0;
+        const int base = tid - v;
 #pragma unroll
         for (int l = 0; l < L1; ++l) {
             sx += Jx[l];
             sy += Jy[l];
             const T sv = (T)a.cfmx * bx * sx + (T)a.cfmy * by * sy;
-            best[l] = (v == 0 || sv > best[l]) ? sv : best[l];
+            T bl = sv;
+#pragma unroll
+            for (int w = 0; w < NV; ++w) {
+                const T o = NV > 1 ? __shfl(sv, base + w, 64) : sv;
+                bl = (w == 0 || o > bl) ? o : bl;
+            }
+            best[l] = bl;
         }
+    }
+    T eta;
+    {
         const T ev = jx0 * (T)(0.5 * a.inv_hx) + jy0_ * (T)(0.5 * a.inv_hy);
-        eta = (v == 0 || ev > eta) ? ev : eta;
+        const int base = tid - v;
+        eta = ev;
+#pragma unroll
+        for (int w = 0; w < NV; ++w) {
+            const T o = NV > 1 ? __shfl(ev, base + w, 64) : ev;
+            eta = (w == 0 || o > eta) ? o : eta;
+        }
     }
     if (MODE == 2) {
         // max eta over the grid: every lane reaches the wave reduction
@@ -727,7 +788,7 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
     E[0] = (T)0;
 #pragma unroll
     for (int l = 1; l < L1; ++l) E[l] = coef * best[l];
-    if (a.E_out) {
+    if (a.E_out && v == 0) {
 #pragma unroll
         for (int l = 0; l < L1; ++l) a.E_out[cell * L1 + l] = (double)E[l];
     }
@@ -735,28 +796,27 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
         T f[L1];
 #pragma unroll
         for (int l = 1; l < L1; ++l) f[l] = texp<T>(-E[l]);
+        a.out.m0[v * a.out.s0 + cell] = m0v;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            a.out.m0[v * a.out.s0 + cell] = a.us.m0[v * a.us.s0 + cell];
+        for (int p = 0; p < K1; ++p)
 #pragma unroll
-            for (int p = 0; p < K1; ++p)
-#pragma unroll
-                for (int q = 0; q < K1; ++q) {
-                    if (p == 0 && q == 0) continue;
-                    const int m = p * K1 + q - 1;
-                    a.out.hi[v * a.out.sv + m * a.out.sl + cell] = a.us.hi[v * a.us.sv + m * a.us.sl + cell] * f[p + q];
-                }
-        }
+            for (int q = 0; q < K1; ++q) {
+                if (p == 0 && q == 0) continue;
+                const int m = p * K1 + q;
+                a.out.hi[v * a.out.sv + (m - 1) * a.out.sl + cell] = um[m] * f[p + q];
+            }
     } else {
-        if (a.eta_out) a.eta_out[cell] = (double)eta;
-        if (eta > (T)1) {
-            const unsigned int slot = atomicAdd(a.tcount, 1u);
-            if ((long long)slot < a.tcap) {
-                a.tcell[slot] = cell;
-                double* rec = a.tdata + (size_t)slot * L1;
-                rec[0] = (double)eta;
+        if (v == 0) {
+            if (a.eta_out) a.eta_out[cell] = (double)eta;
+            if (eta > (T)1) {
+                const unsigned int slot = atomicAdd(a.tcount, 1u);
+                if ((long long)slot < a.tcap) {
+                    a.tcell[slot] = cell;
+                    double* rec = a.tdata + (size_t)slot * L1;
+                    rec[0] = (double)eta;
 #pragma unroll
-                for (int l = 1; l < L1; ++l) rec[l] = (double)E[l];
+                    for (int l = 1; l < L1; ++l) rec[l] = (double)E[l];
+                }
             }
         }
     }
@@ -820,7 +880,9 @@ __global__ __launch_bounds__(256) void maxwave2d_kernel(StateView<TB> u, int64_t
 template <typename TB>
 hipError_t launch_stage2d(int eq, int k, const Args2D<TB>& a, hipStream_t st)
 {
-    dim3 grid((unsigned)((a.nx + 15) / 16), (unsigned)((a.ny + 15) / 16)), block(256);
+    const int fx = eq == ADV ? StageTile<1>::FX : StageTile<4>::FX;
+    const int fy = eq == ADV ? StageTile<1>::FY : StageTile<4>::FY;
+    dim3 grid((unsigned)((a.nx + fx - 1) / fx), (unsigned)((a.ny + fy - 1) / fy)), block(256);
 #define DG_CASE(E_, K_)                                                                   \
     if (eq == E_ && k == K_) {                                                            \
         hipLaunchKernelGGL((stage2d_kernel<E_, K_, TB>), grid, block, 0, st, a);          \
@@ -835,7 +897,9 @@ hipError_t launch_stage2d(int eq, int k, const Args2D<TB>& a, hipStream_t st)
 template <typename TB>
 hipError_t launch_filter2d(int eq, int k, const Args2D<TB>& a, int mode, hipStream_t st)
 {
-    dim3 grid((unsigned)((a.nx + 15) / 16), (unsigned)((a.ny + 15) / 16)), block(256);
+    const int fx = eq == ADV ? FilterTile<1>::FX : FilterTile<4>::FX;
+    const int fy = eq == ADV ? FilterTile<1>::FY : FilterTile<4>::FY;
+    dim3 grid((unsigned)((a.nx + fx - 1) / fx), (unsigned)((a.ny + fy - 1) / fy)), block(256);
 #define DG_CASE(E_, K_)                                                                        \
     if (eq == E_ && k == K_) {                                                                 \
         if (mode == 1)                                                                         \
