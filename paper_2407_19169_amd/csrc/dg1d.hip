@@ -273,7 +273,22 @@ __device__ __forceinline__ double finish_cell(const Args1D<TB>& a, int64_t c, do
             if (!pp_admissible(v0, a.phys.gamma) && a.reject) atomicOr(a.reject, 1);
         }
     }
-    return (double)Phys1D<EQ>::speed(v0, a.phys);
+    // the CFL quantity is only reduced after the last stage of a step
+    return (a.alpha_acc || a.want_lam) ? (double)Phys1D<EQ>::speed(v0, a.phys) : 0.0;
+}
+
+// Positivity and finiteness of the two states of an interface flux (the
+// pressures are those the flux computed).  With the positivity limiter the
+// traces sit at its margin up to rounding: only non-finite values latch.
+template <typename TB, typename T>
+__device__ __forceinline__ void trace_check(const Args1D<TB>& a, const T* ul, const T* ur, T pl, T pr,
+                                            int64_t cell)
+{
+    if (!(ul[0] > (T)0) || !(ur[0] > (T)0) || !(pl > (T)0) || !(pr > (T)0)) {
+        const bool fin = isfinite((double)ul[0]) && isfinite((double)ur[0]) && isfinite((double)pl) &&
+                         isfinite((double)pr);
+        if (!fin || !a.pp) latch_error(a.ctrl, fin ? -5 : -4, cell);
+    }
 }
 
 }  // namespace
@@ -358,8 +373,9 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
         sTrR[v * 256 + tid] = sr;
     }
 
-    // Positivity (Euler) of the stage input at the traces, in FP64.
-    if (EQ == EULER && valid && a.check) {
+    // Positivity (Euler) of the stage input at the traces, in FP64.  The
+    // FP64 path checks the pressures its interface fluxes compute instead.
+    if (EQ == EULER && valid && a.check && sizeof(T) != 8) {
         double dl[NV], dr[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -392,7 +408,9 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
 #pragma unroll
             for (int v = 0; v < NV; ++v) left[v] = sTrR[v * 256 + tid - 1];
         }
-        llf1d<EQ, T>(left, tl, fL, a.phys);
+        T pl, pr;
+        llf1d<EQ, T>(left, tl, fL, a.phys, &pl, &pr);
+        if (EQ == EULER && a.check && sizeof(T) == 8) trace_check(a, left, tl, pl, pr, cc);
 #pragma unroll
         for (int v = 0; v < NV; ++v) sF[v * 256 + tid] = fL[v];
     }
@@ -410,9 +428,10 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
     }
     if (have_res) {
         if (!a.periodic && c == n - 1) {
-            T right[NV];
+            T right[NV], pl, pr;
             ghost_state<NV, T>(a.bc_hi, a.dir_hi, tr, right);
-            llf1d<EQ, T>(tr, right, fR, a.phys);
+            llf1d<EQ, T>(tr, right, fR, a.phys, &pl, &pr);
+            if (EQ == EULER && a.check && sizeof(T) == 8) trace_check(a, tr, right, pl, pr, cc);
         } else {
 #pragma unroll
             for (int v = 0; v < NV; ++v) fR[v] = sF[v * 256 + tid + 1];
@@ -442,11 +461,10 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
                 for (int l = 1; l <= K; ++l) s += uh[v][l - 1] * (T)leg_at(Q, q, l);
                 uq[v] = s;
             }
-            P::flux(uq, fq, a.phys);
+            const T pq = P::flux_pressure(uq, fq, a.phys);
             if (EQ == EULER && a.check && valid) {
-                double p = Phys1D<EULER>::pressure(uq, a.phys);
-                if (!(uq[0] > (T)0) || !(p > 0.0)) {
-                    bool fin = isfinite((double)uq[0]) && isfinite(p);
+                if (!(uq[0] > (T)0) || !(pq > (T)0)) {
+                    bool fin = isfinite((double)uq[0]) && isfinite((double)pq);
                     latch_error(a.ctrl, fin ? -5 : -4, cc);
                 }
             }
@@ -605,42 +623,20 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
     *lam_out = lam;
 }
 
-template <int EQ, int K, typename TB, int MODE>
-__global__ __launch_bounds__(256) void stage1d_kernel(Args1D<TB> a)
-{
-    // a finished run, or a step already rejected by the positivity limiter
-    if (a.ctrl && a.dt_from_ctrl && (a.ctrl->done || a.ctrl->reject)) return;
-    const double dt = a.dt_from_ctrl ? a.ctrl->dt : a.dt_host;
-    __shared__ __align__(16) unsigned char lds[Stage1DLds<EQ, K, TB, MODE>::bytes];
-    double lam, eta;
-    stage1d_tile<EQ, K, TB, MODE>(a, (int64_t)blockIdx.x, dt, lds, &lam, &eta);
-    if (MODE == 2) {
-        // max eta over the domain (wave reduction, one atomic per wave)
-        const double e = wave_max(eta);
-        if ((threadIdx.x & 63) == 0) atomic_max_nonneg(a.eta_acc, e);
-    }
-    if (a.alpha_acc) {
-        // CFL reduction of the output's cell averages (next step)
-        const double l = wave_max(lam);
-        if ((threadIdx.x & 63) == 0) atomic_max_nonneg(a.alpha_acc, l);
-    }
-}
-
-// Hybrid pass B: u^l <- [omega + (1 - omega) exp(-E^l)] u^l for troubled
-// cells (eta > 1), omega = (M - eta) / (M - 1), M = max eta; then, with the
-// positivity limiter on, the limiter on the blended cell.
+// Hybrid pass B over entries i0, i0+stride, ... of the troubled list:
+// u^l <- [omega + (1 - omega) exp(-E^l)] u^l, omega = (M - eta) / (M - 1),
+// M = max eta; then, with the positivity limiter on, the limiter on the
+// blended cell.
 template <int K, int NV, typename TB>
-__global__ __launch_bounds__(256) void blend1d_kernel(StateView<TB> out, const unsigned int* count,
-                                                      const long long* tcell, const double* tdata,
-                                                      const unsigned long long* eta_bits,
-                                                      const Ctrl* ctrl, int from_ctrl, long long cap,
-                                                      PPArgs pp)
+__device__ __forceinline__ void blend_entries(StateView<TB> out, const unsigned int* count,
+                                              const long long* tcell, const double* tdata,
+                                              const unsigned long long* eta_bits, long long cap,
+                                              const PPArgs& pp, unsigned int i0, unsigned int stride)
 {
-    if (from_ctrl && (ctrl->done || ctrl->reject)) return;
     unsigned int cnt = *count;
     if ((long long)cnt > cap) cnt = (unsigned int)cap;
     const double M = __longlong_as_double((long long)*eta_bits);
-    for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
+    for (unsigned int i = i0; i < cnt; i += stride) {
         const long long c = tcell[i];
         const double* rec = tdata + (size_t)i * (K + 1);
         const double eta = rec[0];
@@ -662,6 +658,66 @@ __global__ __launch_bounds__(256) void blend1d_kernel(StateView<TB> out, const u
             }
         }
     }
+}
+
+template <int EQ, int K, typename TB, int MODE>
+__global__ __launch_bounds__(256) void stage1d_kernel(Args1D<TB> a)
+{
+    // a finished run, or a step already rejected by the positivity limiter
+    if (a.ctrl && a.dt_from_ctrl && (a.ctrl->done || a.ctrl->reject)) return;
+    const double dt = a.dt_from_ctrl ? a.ctrl->dt : a.dt_host;
+    __shared__ __align__(16) unsigned char lds[Stage1DLds<EQ, K, TB, MODE>::bytes];
+    double lam, eta;
+    stage1d_tile<EQ, K, TB, MODE>(a, (int64_t)blockIdx.x, dt, lds, &lam, &eta);
+    if (MODE == 2) {
+        // max eta over the domain (wave reduction, one atomic per wave)
+        const double e = wave_max(eta);
+        if ((threadIdx.x & 63) == 0) atomic_max_nonneg(a.eta_acc, e);
+    }
+    if (a.alpha_acc) {
+        // CFL reduction of the output's cell averages (next step)
+        const double l = wave_max(lam);
+        if ((threadIdx.x & 63) == 0) atomic_max_nonneg(a.alpha_acc, l);
+    }
+    if (a.tail) {
+        // The last workgroup to finish runs the hybrid pass B over the whole
+        // troubled list and/or the step control, so neither needs a launch
+        // of its own: every other workgroup has published its output, list
+        // entries and reductions before counting itself in.
+        __shared__ unsigned int s_last;
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) s_last = atomicAdd(&a.ctrl->arrive, 1u) == gridDim.x - 1;
+        __syncthreads();
+        if (s_last) {
+            __threadfence();
+            if constexpr (MODE == 2) {
+                if (a.tail & 1) {
+                    const PPArgs pp{a.pp, a.phys, a.reject};
+                    blend_entries<K, Phys1D<EQ>::NV, TB>(a.out, a.tcount, a.tcell, a.tdata, a.eta_acc, a.tcap,
+                                                        pp, threadIdx.x, blockDim.x);
+                }
+            }
+            if (threadIdx.x == 0) {
+                a.ctrl->arrive = 0;
+                if (a.tail & 2) step_ctrl_body(a.ctrl, 0);
+            }
+        }
+    }
+}
+
+// Hybrid pass B as a kernel of its own (per-call path and the dg_run graph
+// with the positivity limiter on).
+template <int K, int NV, typename TB>
+__global__ __launch_bounds__(256) void blend1d_kernel(StateView<TB> out, const unsigned int* count,
+                                                      const long long* tcell, const double* tdata,
+                                                      const unsigned long long* eta_bits,
+                                                      const Ctrl* ctrl, int from_ctrl, long long cap,
+                                                      PPArgs pp)
+{
+    if (from_ctrl && (ctrl->done || ctrl->reject)) return;
+    blend_entries<K, NV, TB>(out, count, tcell, tdata, eta_bits, cap, pp,
+                             blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 // Unfused filter / hybrid (per-call API): reads the unfiltered stage output

@@ -132,6 +132,7 @@ __device__ void solve_problem(const BatchArgs& b, const BatchProb& pr, unsigned 
             a.us = s == 0 ? A : s == 1 ? B : Cv;
             a.out = s == 1 ? Cv : B;
             a.stage = s;
+            a.want_lam = s == 2;
             if (threadIdx.x < 8) sflux[threadIdx.x] = 0.0;
             if (threadIdx.x == 0) *sreject = 0;
             __syncthreads();

@@ -74,10 +74,17 @@ struct Phys1D<ADV> {
     template <typename T>
     __device__ static T enthalpy(const T* u, const PhysParams& p) { return (T)1; }
     template <typename T>
-    __device__ static T flux_speed(const T* u, T* f, const PhysParams& p)
+    __device__ static T flux_speed(const T* u, T* f, const PhysParams& p, T* pr_out = nullptr)
     {
         flux(u, f, p);
+        if (pr_out) *pr_out = (T)1;
         return speed(u, p);
+    }
+    template <typename T>
+    __device__ static T flux_pressure(const T* u, T* f, const PhysParams& p)
+    {
+        flux(u, f, p);
+        return (T)1;
     }
 };
 
@@ -91,10 +98,17 @@ struct Phys1D<BURGERS> {
     template <typename T>
     __device__ static T enthalpy(const T* u, const PhysParams& p) { return (T)1; }
     template <typename T>
-    __device__ static T flux_speed(const T* u, T* f, const PhysParams& p)
+    __device__ static T flux_speed(const T* u, T* f, const PhysParams& p, T* pr_out = nullptr)
     {
         flux(u, f, p);
+        if (pr_out) *pr_out = (T)1;
         return speed(u, p);
+    }
+    template <typename T>
+    __device__ static T flux_pressure(const T* u, T* f, const PhysParams& p)
+    {
+        flux(u, f, p);
+        return (T)1;
     }
 };
 
@@ -129,27 +143,41 @@ struct Phys1D<EULER> {
         return (u[2] + pr) / u[0];
     }
     // flux and speed of one state sharing the velocity and pressure (the
-    // same expressions as flux() and speed(), so the same values)
+    // same expressions as flux() and speed(), so the same values); the
+    // pressure is returned in *pr_out
     template <typename T>
-    __device__ static T flux_speed(const T* u, T* f, const PhysParams& p)
+    __device__ static T flux_speed(const T* u, T* f, const PhysParams& p, T* pr_out = nullptr)
     {
         T vel = u[1] / u[0];
         T pr = ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * vel);
         f[0] = u[1];
         f[1] = u[1] * vel + pr;
         f[2] = vel * (u[2] + pr);
+        if (pr_out) *pr_out = pr;
         return fabs(vel) + tsqrt<T>((T)p.gamma * pr / u[0]);
+    }
+    // flux of one state, returning the pressure it used
+    template <typename T>
+    __device__ static T flux_pressure(const T* u, T* f, const PhysParams& p)
+    {
+        T vel = u[1] / u[0];
+        T pr = ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * vel);
+        f[0] = u[1];
+        f[1] = u[1] * vel + pr;
+        f[2] = vel * (u[2] + pr);
+        return pr;
     }
 };
 
 // Local Lax-Friedrichs flux: 1/2 (f(a) + f(b)) - 1/2 max(|f'(a)|, |f'(b)|) (b - a).
 template <int EQ, typename T>
-__device__ __forceinline__ void llf1d(const T* ul, const T* ur, T* fh, const PhysParams& p)
+__device__ __forceinline__ void llf1d(const T* ul, const T* ur, T* fh, const PhysParams& p,
+                                      T* pl = nullptr, T* pr = nullptr)
 {
     constexpr int NV = Phys1D<EQ>::NV;
     T fl[NV], fr[NV];
-    const T al = Phys1D<EQ>::flux_speed(ul, fl, p);
-    const T ar = Phys1D<EQ>::flux_speed(ur, fr, p);
+    const T al = Phys1D<EQ>::flux_speed(ul, fl, p, pl);
+    const T ar = Phys1D<EQ>::flux_speed(ur, fr, p, pr);
     T alpha = al > ar ? al : ar;
 #pragma unroll
     for (int v = 0; v < NV; ++v) fh[v] = (T)0.5 * (fl[v] + fr[v]) - (T)0.5 * alpha * (ur[v] - ul[v]);
@@ -193,7 +221,7 @@ struct Ctrl {
     double bstage[3][8];             // per-stage boundary fluxes: lo[4], hi[4]
     long long restarts;              // steps retried with half dt (positivity limiter)
     int retries;                     // consecutive retries of the current step
-    int pad;
+    unsigned int arrive;             // workgroups of the running stage kernel that finished
 };
 
 // Retries of one step with halved dt (positivity limiter) before a run stops.

@@ -32,6 +32,9 @@ struct Args1D {
     long long tcap;                 // capacity of the troubled list (entries)
     double* E_out;                  // nullable: per-cell exponents
     double* eta_out;                // per-cell eta (unfused hybrid)
+    int want_lam;                   // return the CFL quantity without alpha_acc (batch)
+    int tail;                       // work of the last workgroup to finish (dg_run graph):
+                                    // bit 0 hybrid pass B, bit 1 step control
     int pp;                         // Euler: positivity-preserving limiter after the filter
     int* reject;                    // pp: set when an output cell average is inadmissible
 };
@@ -103,6 +106,99 @@ hipError_t launch_blend_all1d(int nv, int k, StateView<TB> w, StateView<TB> out,
 template <typename TB>
 hipError_t launch_maxwave1d(int eq, StateView<TB> u, int64_t n, PhysParams phys,
                             unsigned long long* acc, Ctrl* err, hipStream_t st);
+
+// Finalise the step that just ran (advance t, ledger, dt statistics) and,
+// unless finalize_only, schedule the next one: dt = cfl_num / alpha from the
+// CFL maximum accumulated by the previous step's last stage, clamped so the
+// run ends exactly at t_end.  Called by one thread, from step_ctrl_kernel or
+// from the last workgroup of the last stage kernel of a step.
+__device__ inline void step_ctrl_body(Ctrl* c, int finalize_only)
+{
+    if (finalize_only == 2) {  // clear the per-step accumulators only
+        c->alpha_bits = 0;
+        for (int s = 0; s < 3; ++s) {
+            c->tcount[s] = 0;
+            c->eta_bits[s] = 0;
+        }
+        return;
+    }
+    if (c->reject) {
+        // positivity limiter: the step that just ran left an inadmissible
+        // cell average; its output was replaced by u^n (restore kernel), so
+        // it is run again with half the time step
+        c->reject = 0;
+        if (c->active && !c->done) {
+            if (++c->retries > kMaxRetries) {
+                if (c->status == 0) {
+                    c->status = -5;
+                    c->first_bad = -1;
+                }
+                c->active = 0;
+                c->done = 1;
+                return;
+            }
+            c->restarts += 1;
+            c->dt *= 0.5;
+            c->last = 0;
+            c->alpha_bits = 0;
+            for (int s = 0; s < 3; ++s) {
+                c->tcount[s] = 0;
+                c->eta_bits[s] = 0;
+                for (int v = 0; v < 8; ++v) c->bstage[s][v] = 0.0;
+            }
+            return;
+        }
+    }
+    if (c->active) {
+        c->retries = 0;
+        const double dt = c->dt;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double net = kStageWeight[0] * (c->bstage[0][4 + v] - c->bstage[0][v]) +
+                         kStageWeight[1] * (c->bstage[1][4 + v] - c->bstage[1][v]) +
+                         kStageWeight[2] * (c->bstage[2][4 + v] - c->bstage[2][v]);
+            c->bflux[v] += dt * net;
+        }
+        c->t = c->last ? c->t_end : c->t + dt;
+        c->steps += 1;
+        if (dt < c->dt_min) c->dt_min = dt;
+        if (dt > c->dt_max) c->dt_max = dt;
+        c->troubled += (long long)c->tcount[0] + c->tcount[1] + c->tcount[2];
+        c->active = 0;
+    }
+    if (finalize_only || c->done) return;
+    // a positivity violation is reported but does not stop the run; a
+    // non-finite value does
+    if (c->status == -4 || !(c->t < c->t_end) || c->steps >= c->max_steps) {
+        c->done = 1;
+        return;
+    }
+    const double alpha = __longlong_as_double((long long)c->alpha_bits);
+    double dt = c->cfl_num / alpha;
+    // a non-finite step, or one too small to advance t, ends the run
+    if (!(dt > 0.0) || !isfinite(dt) || !(c->t + dt > c->t)) {
+        if (c->status == 0) {
+            c->status = -4;
+            c->first_bad = -1;
+        }
+        c->done = 1;
+        return;
+    }
+    int last = 0;
+    if (c->t + dt >= c->t_end) {
+        dt = c->t_end - c->t;
+        last = 1;
+    }
+    c->dt = dt;
+    c->last = last;
+    c->active = 1;
+    c->alpha_bits = 0;
+    for (int s = 0; s < 3; ++s) {
+        c->tcount[s] = 0;
+        c->eta_bits[s] = 0;
+        for (int v = 0; v < 8; ++v) c->bstage[s][v] = 0.0;
+    }
+}
 
 // step control (dg_util.hip)
 hipError_t launch_step_ctrl(Ctrl* c, int finalize_only, hipStream_t st);

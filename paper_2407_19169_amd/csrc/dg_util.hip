@@ -4,97 +4,11 @@
 
 namespace dg {
 
-// Finalise the step that just ran (advance t, ledger, dt statistics) and,
-// unless finalize_only, schedule the next one: dt = cfl_num / alpha from the
-// CFL maximum accumulated by the previous step's last stage, clamped so the
-// run ends exactly at t_end.  One thread; runs between the stage kernels.
+// One thread; runs between the stage kernels.
 __global__ void step_ctrl_kernel(Ctrl* c, int finalize_only)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    if (finalize_only == 2) {  // clear the per-step accumulators only
-        c->alpha_bits = 0;
-        for (int s = 0; s < 3; ++s) {
-            c->tcount[s] = 0;
-            c->eta_bits[s] = 0;
-        }
-        return;
-    }
-    if (c->reject) {
-        // positivity limiter: the step that just ran left an inadmissible
-        // cell average; its output was replaced by u^n (restore kernel), so
-        // it is run again with half the time step
-        c->reject = 0;
-        if (c->active && !c->done) {
-            if (++c->retries > kMaxRetries) {
-                if (c->status == 0) {
-                    c->status = -5;
-                    c->first_bad = -1;
-                }
-                c->active = 0;
-                c->done = 1;
-                return;
-            }
-            c->restarts += 1;
-            c->dt *= 0.5;
-            c->last = 0;
-            c->alpha_bits = 0;
-            for (int s = 0; s < 3; ++s) {
-                c->tcount[s] = 0;
-                c->eta_bits[s] = 0;
-                for (int v = 0; v < 8; ++v) c->bstage[s][v] = 0.0;
-            }
-            return;
-        }
-    }
-    if (c->active) {
-        c->retries = 0;
-        const double dt = c->dt;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            double net = kStageWeight[0] * (c->bstage[0][4 + v] - c->bstage[0][v]) +
-                         kStageWeight[1] * (c->bstage[1][4 + v] - c->bstage[1][v]) +
-                         kStageWeight[2] * (c->bstage[2][4 + v] - c->bstage[2][v]);
-            c->bflux[v] += dt * net;
-        }
-        c->t = c->last ? c->t_end : c->t + dt;
-        c->steps += 1;
-        if (dt < c->dt_min) c->dt_min = dt;
-        if (dt > c->dt_max) c->dt_max = dt;
-        c->troubled += (long long)c->tcount[0] + c->tcount[1] + c->tcount[2];
-        c->active = 0;
-    }
-    if (finalize_only || c->done) return;
-    // a positivity violation is reported but does not stop the run; a
-    // non-finite value does
-    if (c->status == -4 || !(c->t < c->t_end) || c->steps >= c->max_steps) {
-        c->done = 1;
-        return;
-    }
-    const double alpha = __longlong_as_double((long long)c->alpha_bits);
-    double dt = c->cfl_num / alpha;
-    // a non-finite step, or one too small to advance t, ends the run
-    if (!(dt > 0.0) || !isfinite(dt) || !(c->t + dt > c->t)) {
-        if (c->status == 0) {
-            c->status = -4;
-            c->first_bad = -1;
-        }
-        c->done = 1;
-        return;
-    }
-    int last = 0;
-    if (c->t + dt >= c->t_end) {
-        dt = c->t_end - c->t;
-        last = 1;
-    }
-    c->dt = dt;
-    c->last = last;
-    c->active = 1;
-    c->alpha_bits = 0;
-    for (int s = 0; s < 3; ++s) {
-        c->tcount[s] = 0;
-        c->eta_bits[s] = 0;
-        for (int v = 0; v < 8; ++v) c->bstage[s][v] = 0.0;
-    }
+    step_ctrl_body(c, finalize_only);
 }
 
 hipError_t launch_step_ctrl(Ctrl* c, int finalize_only, hipStream_t st)
