@@ -679,31 +679,6 @@ __global__ __launch_bounds__(256) void stage1d_kernel(Args1D<TB> a)
         const double l = wave_max(lam);
         if ((threadIdx.x & 63) == 0) atomic_max_nonneg(a.alpha_acc, l);
     }
-    if (a.tail) {
-        // The last workgroup to finish runs the hybrid pass B over the whole
-        // troubled list and/or the step control, so neither needs a launch
-        // of its own: every other workgroup has published its output, list
-        // entries and reductions before counting itself in.
-        __shared__ unsigned int s_last;
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) s_last = atomicAdd(&a.ctrl->arrive, 1u) == gridDim.x - 1;
-        __syncthreads();
-        if (s_last) {
-            __threadfence();
-            if constexpr (MODE == 2) {
-                if (a.tail & 1) {
-                    const PPArgs pp{a.pp, a.phys, a.reject};
-                    blend_entries<K, Phys1D<EQ>::NV, TB>(a.out, a.tcount, a.tcell, a.tdata, a.eta_acc, a.tcap,
-                                                        pp, threadIdx.x, blockDim.x);
-                }
-            }
-            if (threadIdx.x == 0) {
-                a.ctrl->arrive = 0;
-                if (a.tail & 2) step_ctrl_body(a.ctrl, 0);
-            }
-        }
-    }
 }
 
 // Hybrid pass B as a kernel of its own (per-call path and the dg_run graph

@@ -258,10 +258,6 @@ int maxwave_impl(dg_solver* s, unsigned long long* acc, hipStream_t st)
 
 // Record G fused steps (rotation A->B, (B,A)->C, (C,A)->B; then the mirror)
 // on the capture stream.
-// 1D runs without the positivity limiter fold the hybrid pass B and the step
-// control into the tail of the stage kernels (see stage1d_kernel).
-bool fused_tail(const dg_solver* s) { return s->dim == 1 && !s->opt.positivity; }
-
 template <typename TB>
 int record_steps(dg_solver* s, int G, hipStream_t st)
 {
@@ -273,7 +269,7 @@ int record_steps(dg_solver* s, int G, hipStream_t st)
         void* A = (i % 2 == 0) ? s->u[0] : s->u[1];
         void* B = (i % 2 == 0) ? s->u[1] : s->u[0];
         void* Cb = s->u[2];
-        if (!fused_tail(s)) DG_HIP(launch_step_ctrl(c, 0, st));
+        DG_HIP(launch_step_ctrl(c, 0, st));
         if (s->dim == 2) {
             for (int stage = 0; stage < 3; ++stage) {
                 void* target = stage == 1 ? Cb : B;
@@ -324,9 +320,8 @@ int record_steps(dg_solver* s, int G, hipStream_t st)
             a.tcount = &c->tcount[stage];
             a.tcell = tcell;
             a.tdata = tdata;
-            if (fused_tail(s)) a.tail = (fmode == 2 ? 1 : 0) | (stage == 2 ? 2 : 0);
             DG_HIP(launch_stage1d<TB>(s->eq, s->k, a, fmode, st));
-            if (fmode == 2 && !fused_tail(s))
+            if (fmode == 2)
                 DG_HIP(launch_blend1d<TB>(s->nv, s->k, a.out, &c->tcount[stage], tcell, tdata,
                                           &c->eta_bits[stage], c, 1, s->ncell,
                                           pp_args<TB>(s), st));
@@ -430,9 +425,6 @@ int run_impl(dg_solver* s, double t_end, int64_t max_steps, dg_report* rep)
     }
     int rc = maxwave_impl<TB>(s, &ctrl_of(s)->alpha_bits, st);
     if (rc) return rc;
-    // with the fused tail the graph's steps do not schedule themselves: the
-    // first step is scheduled here, each later one by its predecessor
-    if (fused_tail(s)) DG_HIP(launch_step_ctrl(ctrl_of(s), 0, st));
     // Replays: batches double in size between control reads, never beyond
     // the replays the remaining step budget needs.  With the positivity
     // limiter a rejected step is retried, so the budget is re-read.
@@ -448,13 +440,12 @@ int run_impl(dg_solver* s, double t_end, int64_t max_steps, dg_report* rep)
         DG_HIP(hipMemcpyAsync(&cr, ctrl_of(s), sizeof cr, hipMemcpyDeviceToHost, st));
         DG_HIP(hipStreamSynchronize(st));
         if (cr.done) break;
-        // without the fused tail the last step of a replay has run but is
-        // finalised by the next step control, unless it was rejected; with
-        // it, an active step is scheduled but has not run
-        completed = cr.steps - steps0 + ((!fused_tail(s) && cr.active && !cr.reject) ? 1 : 0);
+        // the last step of a replay has run but is finalised by the next
+        // step control, unless it was rejected
+        completed = cr.steps - steps0 + ((cr.active && !cr.reject) ? 1 : 0);
         batch = batch < 64 ? batch * 2 : 64;
     }
-    if (!fused_tail(s)) DG_HIP(launch_step_ctrl(ctrl_of(s), 1, st));
+    DG_HIP(launch_step_ctrl(ctrl_of(s), 1, st));
     DG_HIP(hipMemcpyAsync(&c, ctrl_of(s), sizeof c, hipMemcpyDeviceToHost, st));
     DG_HIP(hipStreamSynchronize(st));
     // every executed step (finalised or rejected) swaps the buffer roles

@@ -221,7 +221,7 @@ struct Ctrl {
     double bstage[3][8];             // per-stage boundary fluxes: lo[4], hi[4]
     long long restarts;              // steps retried with half dt (positivity limiter)
     int retries;                     // consecutive retries of the current step
-    unsigned int arrive;             // workgroups of the running stage kernel that finished
+    int pad;
 };
 
 // Retries of one step with halved dt (positivity limiter) before a run stops.

@@ -33,8 +33,6 @@ struct Args1D {
     double* E_out;                  // nullable: per-cell exponents
     double* eta_out;                // per-cell eta (unfused hybrid)
     int want_lam;                   // return the CFL quantity without alpha_acc (batch)
-    int tail;                       // work of the last workgroup to finish (dg_run graph):
-                                    // bit 0 hybrid pass B, bit 1 step control
     int pp;                         // Euler: positivity-preserving limiter after the filter
     int* reject;                    // pp: set when an output cell average is inadmissible
 };
@@ -110,8 +108,7 @@ hipError_t launch_maxwave1d(int eq, StateView<TB> u, int64_t n, PhysParams phys,
 // Finalise the step that just ran (advance t, ledger, dt statistics) and,
 // unless finalize_only, schedule the next one: dt = cfl_num / alpha from the
 // CFL maximum accumulated by the previous step's last stage, clamped so the
-// run ends exactly at t_end.  Called by one thread, from step_ctrl_kernel or
-// from the last workgroup of the last stage kernel of a step.
+// run ends exactly at t_end.  Called by one thread (step_ctrl_kernel).
 __device__ inline void step_ctrl_body(Ctrl* c, int finalize_only)
 {
     if (finalize_only == 2) {  // clear the per-step accumulators only
