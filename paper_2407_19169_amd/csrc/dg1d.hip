@@ -1,7 +1,9 @@
 // dg1d.hip — 1D RKDG stage, jump filter, hybrid limiter and CFL kernels
 // for gfx950 (arXiv:2407.19169, Sec. 2.1, 2.4, Sec. 3 and Algorithm 1).
 //
-// Mapping: one thread per cell, 256-thread workgroups (4 wave64), state in
+// Mapping: one thread per cell; the stage kernel runs 256-thread workgroups
+// (4 wave64) on large grids and single-wavefront tiles on small ones, the
+// other kernels 256-thread workgroups.  State lives in
 // structure-of-arrays planes so every load/store of a mode plane is one
 // coalesced 64-lane access.  A workgroup stages its cells' interface traces
 // in LDS, so each interface flux is evaluated once per tile.  The fused
@@ -303,20 +305,20 @@ __device__ __forceinline__ void trace_check(const Args1D<TB>& a, const T* ul, co
 // With a.alpha != 0 the kernel also accumulates max |f'(u-bar)| of its
 // output into ctrl->alpha_bits (the next step's CFL reduction).
 // -------------------------------------------------------------------------
-template <int EQ, int K, typename TB, int MODE>
+template <int EQ, int K, typename TB, int MODE, int BS = 256>
 struct Stage1DLds {
     static constexpr int NV = Phys1D<EQ>::NV;
     // phase 1 (traces, fluxes) and phase 2 (derivative traces) alias
-    static constexpr int PH1 = 2 * NV * 256 * (int)sizeof(TB);
-    static constexpr int PH2 = NV * 256 * 8 + 2 * (K + 1) * NV * 256 * (int)sizeof(TB);
+    static constexpr int PH1 = 2 * NV * BS * (int)sizeof(TB);
+    static constexpr int PH2 = NV * BS * 8 + 2 * (K + 1) * NV * BS * (int)sizeof(TB);
     static constexpr int bytes = MODE == 0 ? PH1 : (PH1 > PH2 ? PH1 : PH2);
 };
 
-// One 256-cell tile (tile index blk) of the stage; `lds` provides
+// One BS-cell tile (tile index blk) of the stage; `lds` provides
 // Stage1DLds::bytes of shared memory.  Returns, per thread, the CFL
 // quantity of its output cell (*lam_out, 0 for halo / outside lanes) and
 // its hybrid indicator (*eta_out); reductions are left to the caller.
-template <int EQ, int K, typename TB, int MODE>
+template <int EQ, int K, typename TB, int MODE, int BS = 256>
 __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, double dt,
                                              unsigned char* lds, double* lam_out, double* eta_out)
 {
@@ -326,12 +328,12 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
     constexpr int K1 = K + 1;
     constexpr int KH = K > 0 ? K : 1;
     constexpr int HALO = MODE == 0 ? 1 : 2;
-    constexpr int TILE = 256 - 2 * HALO;
+    constexpr int TILE = BS - 2 * HALO;
     constexpr int Q = K + 1;
 
     const int stage = a.stage;
-    T* sTrR = reinterpret_cast<T*>(lds);                 // [NV][256] right trace
-    T* sF = sTrR + NV * 256;                             // [NV][256] flux at left interface
+    T* sTrR = reinterpret_cast<T*>(lds);                 // [NV][BS] right trace
+    T* sF = sTrR + NV * BS;                             // [NV][BS] flux at left interface
 
     const int tid = threadIdx.x;
     const int64_t c = blk * TILE + tid - HALO;
@@ -370,7 +372,7 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
         }
         tl[v] = sl;
         tr[v] = sr;
-        sTrR[v * 256 + tid] = sr;
+        sTrR[v * BS + tid] = sr;
     }
 
     // Positivity (Euler) of the stage input at the traces, in FP64.  The
@@ -406,13 +408,13 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
             ghost_state<NV, T>(a.bc_lo, a.dir_lo, tl, left);
         } else {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) left[v] = sTrR[v * 256 + tid - 1];
+            for (int v = 0; v < NV; ++v) left[v] = sTrR[v * BS + tid - 1];
         }
         T pl, pr;
         llf1d<EQ, T>(left, tl, fL, a.phys, &pl, &pr);
         if (EQ == EULER && a.check && sizeof(T) == 8) trace_check(a, left, tl, pl, pr, cc);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sF[v * 256 + tid] = fL[v];
+        for (int v = 0; v < NV; ++v) sF[v * BS + tid] = fL[v];
     }
     __syncthreads();
 
@@ -434,10 +436,10 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
             if (EQ == EULER && a.check && sizeof(T) == 8) trace_check(a, tr, right, pl, pr, cc);
         } else {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) fR[v] = sF[v * 256 + tid + 1];
+            for (int v = 0; v < NV; ++v) fR[v] = sF[v * BS + tid + 1];
         }
         // Boundary fluxes for the conservation ledger (one writer each).
-        if (a.bflux && !a.periodic && tid >= HALO && tid < 256 - HALO) {
+        if (a.bflux && !a.periodic && tid >= HALO && tid < BS - HALO) {
             if (c == 0)
 #pragma unroll
                 for (int v = 0; v < NV; ++v) a.bflux[v] = (double)fL[v];
@@ -492,7 +494,7 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
         }
     }
 
-    const bool own = valid && c >= 0 && c < n && tid >= HALO && tid < 256 - HALO;
+    const bool own = valid && c >= 0 && c < n && tid >= HALO && tid < BS - HALO;
 
     double lam = 0.0;
     if constexpr (MODE == 0) {
@@ -504,9 +506,9 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
     } else {
         // ---- jump filter on the unfiltered output (needs neighbours) ----
         __syncthreads();  // phase-1 LDS reads are complete
-        double* s0 = reinterpret_cast<double*>(lds);       // [NV][256] mode 0
-        T* sHR = reinterpret_cast<T*>(s0 + NV * 256);      // [K1][NV][256] right high-mode part
-        T* sHL = sHR + K1 * NV * 256;                      // [K1][NV][256] left high-mode part
+        double* s0 = reinterpret_cast<double*>(lds);       // [NV][BS] mode 0
+        T* sHR = reinterpret_cast<T*>(s0 + NV * BS);      // [K1][NV][BS] right high-mode part
+        T* sHL = sHR + K1 * NV * BS;                      // [K1][NV][BS] left high-mode part
         T hR[K1][NV], hL[K1][NV];
 #pragma unroll
         for (int m = 0; m <= K; ++m)
@@ -520,11 +522,11 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
                 }
                 hR[m][v] = r;
                 hL[m][v] = l_;
-                sHR[(m * NV + v) * 256 + tid] = r;
-                sHL[(m * NV + v) * 256 + tid] = l_;
+                sHR[(m * NV + v) * BS + tid] = r;
+                sHL[(m * NV + v) * BS + tid] = l_;
             }
 #pragma unroll
-        for (int v = 0; v < NV; ++v) s0[v * 256 + tid] = v0[v];
+        for (int v = 0; v < NV; ++v) s0[v * BS + tid] = v0[v];
         __syncthreads();
 
         T eta_own = (T)0;
@@ -541,16 +543,16 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
                         T inner = (m == 0 ? (T)v0[v] : (T)0) + hL[m][v];
                         jl = ghost_jump<T>(a.bc_lo, m, v, a.dir_lo[v], inner);
                     } else {
-                        T d = hL[m][v] - sHR[(m * NV + v) * 256 + tid - 1];
-                        if (m == 0) d += (T)(v0[v] - s0[v * 256 + tid - 1]);
+                        T d = hL[m][v] - sHR[(m * NV + v) * BS + tid - 1];
+                        if (m == 0) d += (T)(v0[v] - s0[v * BS + tid - 1]);
                         jl = fabs(d);
                     }
                     if (rbound) {
                         T inner = (m == 0 ? (T)v0[v] : (T)0) + hR[m][v];
                         jr = ghost_jump<T>(a.bc_hi, m, v, a.dir_hi[v], inner);
                     } else {
-                        T d = sHL[(m * NV + v) * 256 + tid + 1] - hR[m][v];
-                        if (m == 0) d += (T)(s0[v * 256 + tid + 1] - v0[v]);
+                        T d = sHL[(m * NV + v) * BS + tid + 1] - hR[m][v];
+                        if (m == 0) d += (T)(s0[v * BS + tid + 1] - v0[v]);
                         jr = fabs(d);
                     }
                     J[m][v] = jl + jr;
@@ -660,15 +662,15 @@ __device__ __forceinline__ void blend_entries(StateView<TB> out, const unsigned 
     }
 }
 
-template <int EQ, int K, typename TB, int MODE>
-__global__ __launch_bounds__(256) void stage1d_kernel(Args1D<TB> a)
+template <int EQ, int K, typename TB, int MODE, int BS>
+__global__ __launch_bounds__(BS) void stage1d_kernel(Args1D<TB> a)
 {
     // a finished run, or a step already rejected by the positivity limiter
     if (a.ctrl && a.dt_from_ctrl && (a.ctrl->done || a.ctrl->reject)) return;
     const double dt = a.dt_from_ctrl ? a.ctrl->dt : a.dt_host;
-    __shared__ __align__(16) unsigned char lds[Stage1DLds<EQ, K, TB, MODE>::bytes];
+    __shared__ __align__(16) unsigned char lds[Stage1DLds<EQ, K, TB, MODE, BS>::bytes];
     double lam, eta;
-    stage1d_tile<EQ, K, TB, MODE>(a, (int64_t)blockIdx.x, dt, lds, &lam, &eta);
+    stage1d_tile<EQ, K, TB, MODE, BS>(a, (int64_t)blockIdx.x, dt, lds, &lam, &eta);
     if (MODE == 2) {
         // max eta over the domain (wave reduction, one atomic per wave)
         const double e = wave_max(eta);
@@ -888,18 +890,28 @@ __global__ __launch_bounds__(256) void maxwave1d_kernel(StateView<TB> u, int64_t
 }
 
 // ------------------------------------------------------------ launchers --
+template <int EQ, int K, typename TB, int BS>
+static hipError_t launch_stage_bs(const Args1D<TB>& a, int mode, hipStream_t st)
+{
+    const int tile = mode == 0 ? BS - 2 : BS - 4;
+    dim3 grid((unsigned)((a.n + tile - 1) / tile)), block(BS);
+    if (mode == 0)
+        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 0, BS>), grid, block, 0, st, a);
+    else if (mode == 1)
+        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 1, BS>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 2, BS>), grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+// Small grids (under about a thousand 256-cell tiles) use one-wavefront
+// tiles: a single tile's dependent chain then bounds the stage, and smaller
+// tiles spread it over more compute units.
 template <int EQ, int K, typename TB>
 static hipError_t launch_stage(const Args1D<TB>& a, int mode, hipStream_t st)
 {
-    const int tile = mode == 0 ? 254 : 252;
-    dim3 grid((unsigned)((a.n + tile - 1) / tile)), block(256);
-    if (mode == 0)
-        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 0>), grid, block, 0, st, a);
-    else if (mode == 1)
-        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 1>), grid, block, 0, st, a);
-    else
-        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 2>), grid, block, 0, st, a);
-    return hipGetLastError();
+    if (a.n < 252 * 1024) return launch_stage_bs<EQ, K, TB, 64>(a, mode, st);
+    return launch_stage_bs<EQ, K, TB, 256>(a, mode, st);
 }
 
 template <int EQ, int K, typename TB>
