@@ -237,6 +237,20 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Tile of a 1D launch of `ntiles` workgroups over a grid `gx` tiles wide.
+// Workgroups are dispatched to the 8 XCDs round-robin by index, and each XCD
+// has its own L2; consecutive tiles in row-major order are therefore given
+// to one XCD, so the neighbour rows and columns a tile reads were mostly
+// fetched into the same L2 by the tiles around it.
+__device__ __forceinline__ void xcd_tile(int64_t gx, int64_t ntiles, int64_t& bx, int64_t& by)
+{
+    const int64_t p = blockIdx.x, q = ntiles >> 3, r = ntiles & 7;
+    const int64_t x = p & 7, k = p >> 3;
+    const int64_t l = x * q + (x < r ? x : r) + k;
+    bx = l % gx;
+    by = l / gx;
+}
+
 }  // namespace
 
 // -------------------------------------------------------------------------
@@ -268,13 +282,16 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
     constexpr int NVE = StageTile<NV>::NVE, NHE = StageTile<NV>::NHE;
     constexpr int TS = Q * NV;  // one edge: Q points x NV variables
     // traces: lower side (the -x / -y cell) and upper side of every edge
-    // (vertical edges first), later reused for the edge fluxes
-    __shared__ __align__(16) T lds[2 * (NVE + NHE) * TS];
-    // per-cell exchange block of the volume term (point values, F1, F2)
-    __shared__ __align__(16) T sX[NV > 1 ? (256 / NV) * 3 * NV * NV : 1];
+    // (vertical edges first); the lower half later takes the edge fluxes and
+    // the upper half the per-cell exchange blocks of the volume term (NV x NV
+    // values per cell: point values, then F1, then F2)
+    constexpr int HALF = (NVE + NHE) * TS;
+    constexpr int XB = NV > 1 ? (256 / NV) * NV * NV : 0;
+    __shared__ __align__(16) T lds[HALF + (HALF > XB ? HALF : XB)];
     T* sLo = lds;
-    T* sHi = lds + (NVE + NHE) * TS;
+    T* sHi = lds + HALF;
     T* sF = lds;
+    T* sX = lds + HALF;
 
     if (a.dt_from_ctrl && a.ctrl->done) return;
     const double dt = a.dt_from_ctrl ? a.ctrl->dt : a.dt_host;
@@ -284,7 +301,9 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
 
     const int tid = threadIdx.x, v = tid % NV, cidx = tid / NV, base = tid - v;
     const int tx = cidx % FX, ty = cidx / FX;
-    const int64_t ix0 = (int64_t)blockIdx.x * FX, jy0 = (int64_t)blockIdx.y * FY;
+    int64_t tbx, tby;
+    xcd_tile((a.nx + FX - 1) / FX, gridDim.x, tbx, tby);
+    const int64_t ix0 = tbx * FX, jy0 = tby * FY;
     const int64_t ix = ix0 + tx, jy = jy0 + ty;
     const bool px = a.bc[0] == BC_PERIODIC, py = a.bc[2] == BC_PERIODIC;
     const int64_t cx = slot_index(ix, a.nx, px), cy = slot_index(jy, a.ny, py);
@@ -301,6 +320,14 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
 #pragma unroll
     for (int m = 0; m < NM; ++m) um[m] = (T)0;
     if (loadable) load_var2d<NM, TB, T>(a.us, cy * a.nx + cx, v, m0v, um);
+    // u^n of the own cell for the combination, fetched now so that its
+    // latency overlaps the flux phases
+    const int64_t cell = jy * a.nx + ix;
+    double n0 = 0.0;
+    T nm[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) nm[m] = (T)0;
+    if (own && stage > 0) load_var2d<NM, TB, T>(a.un, cell, v, n0, nm);
     if (loadable) {
         T tr[Q];
         face_trace_var<0, K, T>(um, tr);  // left face: upper side of vertical edge tx
@@ -411,7 +438,6 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
     __syncthreads();
 
     // ---- phase 3: volume term, edge terms, combination (variable v) ----
-    const int64_t cell = jy * a.nx + ix;
     const T hy2 = (T)(0.5 * a.hy), hx2 = (T)(0.5 * a.hx);
     T acc[NM];
 #pragma unroll
@@ -453,7 +479,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
         } else {
             // lane v of the cell takes point (qa, v): the cell's lanes swap
             // point values and fluxes through their LDS block
-            T* X = &sX[cidx * 3 * NV * NV];
+            T* X = &sX[cidx * NV * NV];
 #pragma unroll
             for (int b = 0; b < NV; ++b) X[b * NV + v] = uv[b];
             wave_lds_sync();
@@ -463,6 +489,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
                 uq[q] = X[v * NV + q];
                 f1[q] = f2[q] = (T)0;
             }
+            wave_lds_sync();  // the block is rewritten with F1
             if (v < Q && own) {
                 if (EQ == EULER && a.check) {
                     const T pr = Phys2D<EULER>::pressure(uq, a.phys);
@@ -475,16 +502,16 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
                 P::flux(uq, 1, f2, a.phys);
             }
 #pragma unroll
-            for (int q = 0; q < NV; ++q) {
-                X[NV * NV + v * NV + q] = f1[q];
-                X[2 * NV * NV + v * NV + q] = f2[q];
-            }
+            for (int q = 0; q < NV; ++q) X[v * NV + q] = f1[q];
             wave_lds_sync();
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                g1[b] = X[NV * NV + b * NV + v];
-                g2[b] = X[2 * NV * NV + b * NV + v];
-            }
+            for (int b = 0; b < NB; ++b) g1[b] = X[b * NV + v];
+            wave_lds_sync();  // then with F2
+#pragma unroll
+            for (int q = 0; q < NV; ++q) X[v * NV + q] = f2[q];
+            wave_lds_sync();
+#pragma unroll
+            for (int b = 0; b < NB; ++b) g2[b] = X[b * NV + v];
             wave_lds_sync();  // the block is rewritten by the next row
         }
         T t1[K1], t2[K1];  // sum_b w_b F1 P_q(eta_b), sum_b w_b F2 P_q'(eta_b)
@@ -509,11 +536,6 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
 
     double v0 = 0.0;
     if (own) {
-        double n0 = 0.0;
-        T nm[NM];
-#pragma unroll
-        for (int m = 0; m < NM; ++m) nm[m] = (T)0;
-        if (stage > 0) load_var2d<NM, TB, T>(a.un, cell, v, n0, nm);
         const T* FL = &sF[vslot(ty, tx) * TS];
         const T* FR = &sF[vslot(ty, tx + 1) * TS];
         const T* FB = &sF[hslot(tx, ty) * TS];
@@ -597,7 +619,9 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
 
     const int tid = threadIdx.x, v = tid % NV, cidx = tid / NV;
     const int tx = cidx % FX, ty = cidx / FX;
-    const int64_t ix0 = (int64_t)blockIdx.x * FX, jy0 = (int64_t)blockIdx.y * FY;
+    int64_t tbx, tby;
+    xcd_tile((a.nx + FX - 1) / FX, gridDim.x, tbx, tby);
+    const int64_t ix0 = tbx * FX, jy0 = tby * FY;
     const int64_t ix = ix0 + tx, jy = jy0 + ty;
     const bool px = a.bc[0] == BC_PERIODIC, py = a.bc[2] == BC_PERIODIC;
     const int64_t cx = slot_index(ix, a.nx, px), cy = slot_index(jy, a.ny, py);
@@ -882,7 +906,7 @@ hipError_t launch_stage2d(int eq, int k, const Args2D<TB>& a, hipStream_t st)
 {
     const int fx = eq == ADV ? StageTile<1>::FX : StageTile<4>::FX;
     const int fy = eq == ADV ? StageTile<1>::FY : StageTile<4>::FY;
-    dim3 grid((unsigned)((a.nx + fx - 1) / fx), (unsigned)((a.ny + fy - 1) / fy)), block(256);
+    dim3 grid((unsigned)(((a.nx + fx - 1) / fx) * ((a.ny + fy - 1) / fy))), block(256);
 #define DG_CASE(E_, K_)                                                                   \
     if (eq == E_ && k == K_) {                                                            \
         hipLaunchKernelGGL((stage2d_kernel<E_, K_, TB>), grid, block, 0, st, a);          \
@@ -899,7 +923,7 @@ hipError_t launch_filter2d(int eq, int k, const Args2D<TB>& a, int mode, hipStre
 {
     const int fx = eq == ADV ? FilterTile<1>::FX : FilterTile<4>::FX;
     const int fy = eq == ADV ? FilterTile<1>::FY : FilterTile<4>::FY;
-    dim3 grid((unsigned)((a.nx + fx - 1) / fx), (unsigned)((a.ny + fy - 1) / fy)), block(256);
+    dim3 grid((unsigned)(((a.nx + fx - 1) / fx) * ((a.ny + fy - 1) / fy))), block(256);
 #define DG_CASE(E_, K_)                                                                        \
     if (eq == E_ && k == K_) {                                                                 \
         if (mode == 1)                                                                         \

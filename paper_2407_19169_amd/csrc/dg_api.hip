@@ -37,7 +37,12 @@ struct dg_solver {
 namespace {
 
 constexpr size_t kCtrlBytes = 4096;
-constexpr size_t kAuxBytes = 4096;
+// aux scratch: [0..3] ledger, [4..5] minima, [8..10] per-call counters,
+// [16..) a second control block; from byte 4096 the ledger's partial sums.
+constexpr size_t kAuxLedgerOff = 512;  // in doubles
+constexpr size_t kAuxBytes = 4096 + 4 * kLedgerParts * sizeof(double);
+static_assert(16 * sizeof(double) + sizeof(Ctrl) <= kAuxLedgerOff * sizeof(double),
+              "the second control block overlaps the ledger partials");
 constexpr int kGraphSteps = 16;  // even: the three state buffers rotate with period 2
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -370,7 +375,8 @@ int report_impl(dg_solver* s, dg_report* rep)
     DG_HIP(hipStreamSynchronize(st));
     DG_HIP(hipMemcpy(aux + 4, init, sizeof init, hipMemcpyHostToDevice));
     const double vol = s->dim == 1 ? s->h[0] : s->h[0] * s->h[1];
-    DG_HIP(launch_ledger<TB>(s->nv, s->ncell, view_of<TB>(s, s->u[0]), vol, aux, st));
+    DG_HIP(launch_ledger<TB>(s->nv, s->ncell, view_of<TB>(s, s->u[0]), vol, aux, aux + kAuxLedgerOff,
+                             st));
     if (s->dim == 1)
         DG_HIP(launch_check1d<TB>(s->eq, s->k, view_of<TB>(s, s->u[0]), s->ncell,
                                   base_args<TB>(s).phys, ctrl_of(s), aux + 4, s->opt.positivity, st));

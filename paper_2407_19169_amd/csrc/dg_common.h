@@ -240,6 +240,13 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* p, double 
     if (b > __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(p, b);
 }
 
+// The minimum counterpart (the stored value only falls within a reduction).
+__device__ __forceinline__ void atomic_min_nonneg(unsigned long long* p, double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    if (b < __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(p, b);
+}
+
 // Wavefront (64 lanes) maximum.
 __device__ __forceinline__ double wave_max(double v)
 {

@@ -203,9 +203,12 @@ hipError_t launch_restore(const Ctrl* c, const void* src, void* dst, size_t byte
 template <typename TB>
 hipError_t launch_convert(int to_internal, int nv, int nmodes, int64_t ncell, const double* fp64,
                           StateView<TB> v, hipStream_t st);
+// Conservation ledger: out[v] = cell volume x sum of the cell averages of
+// variable v; part holds nv x kLedgerParts doubles of partial sums.
+constexpr int kLedgerParts = 256;
 template <typename TB>
 hipError_t launch_ledger(int nv, int64_t ncell, StateView<TB> u, double cell_volume, double* out,
-                         hipStream_t st);
+                         double* part, hipStream_t st);
 template <typename TB>
 hipError_t launch_check1d(int eq, int k, StateView<TB> u, int64_t n, PhysParams phys, Ctrl* c,
                           double* minvals, int pp, hipStream_t st);

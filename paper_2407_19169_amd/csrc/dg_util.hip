@@ -81,20 +81,40 @@ hipError_t launch_convert(int to_internal, int nv, int nmodes, int64_t ncell, co
     return hipGetLastError();
 }
 
-// Deterministic FP64 sum over cells of the cell averages of each variable:
-// one workgroup per variable, fixed strided partial sums, fixed-order tree.
+// Deterministic FP64 sum over cells of the cell averages of each variable,
+// in two passes with a fixed partition: kLedgerParts workgroups per variable
+// each sum one contiguous chunk (fixed strided partial sums, fixed-order LDS
+// tree), then one workgroup per variable sums the partials in a fixed-order
+// tree.  The result does not depend on scheduling.
 template <typename TB>
-__global__ __launch_bounds__(1024) void ledger_kernel(int64_t ncell, StateView<TB> u, double vol,
-                                                      double* out)
+__global__ __launch_bounds__(256) void ledger_part_kernel(int64_t ncell, StateView<TB> u,
+                                                          double* part)
 {
-    __shared__ double s[1024];
-    const int var = blockIdx.x;
+    __shared__ double s[256];
+    const int var = blockIdx.y;
+    const int64_t chunk = (ncell + kLedgerParts - 1) / kLedgerParts;
+    const int64_t c0 = (int64_t)blockIdx.x * chunk;
+    const int64_t c1 = c0 + chunk < ncell ? c0 + chunk : ncell;
     const double* p = u.m0 + var * u.s0;
     double acc = 0.0;
-    for (int64_t c = threadIdx.x; c < ncell; c += 1024) acc += p[c];
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += 256) acc += p[c];
     s[threadIdx.x] = acc;
     __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[var * kLedgerParts + blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(kLedgerParts) void ledger_sum_kernel(const double* part, double vol,
+                                                                  double* out)
+{
+    __shared__ double s[kLedgerParts];
+    const int var = blockIdx.x;
+    s[threadIdx.x] = part[var * kLedgerParts + threadIdx.x];
+    __syncthreads();
+    for (int w = kLedgerParts / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
         __syncthreads();
     }
@@ -103,9 +123,12 @@ __global__ __launch_bounds__(1024) void ledger_kernel(int64_t ncell, StateView<T
 
 template <typename TB>
 hipError_t launch_ledger(int nv, int64_t ncell, StateView<TB> u, double cell_volume, double* out,
-                         hipStream_t st)
+                         double* part, hipStream_t st)
 {
-    hipLaunchKernelGGL((ledger_kernel<TB>), dim3(nv), dim3(1024), 0, st, ncell, u, cell_volume, out);
+    hipLaunchKernelGGL((ledger_part_kernel<TB>), dim3(kLedgerParts, nv), dim3(256), 0, st, ncell, u,
+                       part);
+    hipLaunchKernelGGL(ledger_sum_kernel, dim3(nv), dim3(kLedgerParts), 0, st, part, cell_volume,
+                       out);
     return hipGetLastError();
 }
 
@@ -159,9 +182,21 @@ __global__ __launch_bounds__(256) void check1d_kernel(StateView<TB> u, int64_t n
         mr = a < mr ? a : mr;
         mp = b < mp ? b : mp;
     }
+    // workgroup minimum, then one (skippable) atomic per workgroup
+    __shared__ double sm[2][4];
+    const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        atomicMin(&minvals[0], (unsigned long long)__double_as_longlong(mr));
-        atomicMin(&minvals[1], (unsigned long long)__double_as_longlong(mp));
+        sm[0][wv] = mr;
+        sm[1][wv] = mp;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 4; ++i) {
+            mr = sm[0][i] < mr ? sm[0][i] : mr;
+            mp = sm[1][i] < mp ? sm[1][i] : mp;
+        }
+        atomic_min_nonneg(&minvals[0], mr);
+        atomic_min_nonneg(&minvals[1], mp);
     }
 }
 
@@ -184,7 +219,8 @@ hipError_t launch_check1d(int eq, int k, StateView<TB> u, int64_t n, PhysParams 
 #define DG_INST(TB)                                                                                \
     template hipError_t launch_convert<TB>(int, int, int, int64_t, const double*, StateView<TB>,   \
                                            hipStream_t);                                           \
-    template hipError_t launch_ledger<TB>(int, int64_t, StateView<TB>, double, double*, hipStream_t); \
+    template hipError_t launch_ledger<TB>(int, int64_t, StateView<TB>, double, double*, double*,  \
+                                          hipStream_t);                                           \
     template hipError_t launch_check1d<TB>(int, int, StateView<TB>, int64_t, PhysParams, Ctrl*,    \
                                            double*, int, hipStream_t);
 DG_INST(double)
