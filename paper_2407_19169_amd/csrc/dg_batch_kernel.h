@@ -225,8 +225,17 @@ struct BatchLds {
 
 }  // namespace
 
+// Register budget of the mixed form: 3 waves per SIMD (168 VGPRs; its LDS
+// allows 4 workgroups per CU), one register under what the compiler picks
+// by itself.  The FP64 form is left free: a budget of 2 waves spills.
+template <typename TB>
+struct BatchWaves {
+    static constexpr int value = sizeof(TB) == 4 ? 3 : 1;
+};
+
 template <typename TB, int MODE>
-__global__ __launch_bounds__(256) void batch1d_kernel(BatchArgs b)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BatchWaves<TB>::value)))
+void batch1d_kernel(BatchArgs b)
 {
     __shared__ __align__(16) unsigned char lds[BatchLds<TB, MODE>::bytes];
     __shared__ double red[4];
