@@ -158,6 +158,37 @@ __device__ __forceinline__ double pp_margin(const double (&w)[3], const double (
     return 8.0 * ur * (wa[2] + fabs(w[1]) * wa[1] / w[0] + kin * wa[0] / w[0]);
 }
 
+// True when the limiter provably leaves the cell unchanged: since |P_l| <= 1
+// on [-1, 1], rho_bar - sum_l |rho_l| bounds the density and
+// (gamma - 1) (E_lo - M_hi^2 / (2 rho_lo)) the pressure from below at every
+// point of the cell; both exceed twice the largest threshold and rounding
+// margin the limiter could apply there (the margins' 8 units of roundoff
+// also cover the rounding of the point values and of the verification in
+// the modes' precision), so no test point is limited and the verification
+// passes at once.
+template <int K, typename TB>
+__device__ __forceinline__ bool pp_clear(const double (&u0)[3], const TB (&uh)[3][K > 0 ? K : 1],
+                                         double gamma)
+{
+    constexpr double ur = sizeof(TB) == 4 ? 0x1p-23 : 0x1p-52;
+    double sa[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        double t = 0.0;
+#pragma unroll
+        for (int l = 0; l < K; ++l) t += fabs((double)uh[v][l]);
+        sa[v] = t;
+    }
+    const double rlo = u0[0] - sa[0], sr = fabs(u0[0]) + sa[0];
+    if (!(rlo > 2.0 * (1e-13 + 8.0 * ur * sr))) return false;
+    const double mhi = fabs(u0[1]) + sa[1];
+    const double elo = u0[2] - sa[2], se = fabs(u0[2]) + sa[2];
+    const double kin = 0.5 * mhi * mhi / rlo;
+    const double plo = (gamma - 1.0) * (elo - kin);
+    const double mmax = 8.0 * ur * (se + 2.0 * kin + kin * sr / rlo);
+    return plo > 2.0 * (1e-13 + mmax);
+}
+
 // Limit one cell in place: scale the density's modes >= 1 so the density
 // at every test point is >= eps_r, then all modes >= 1 so the pressure is
 // >= eps_p (largest admissible t in [0, 1] on the segment from the average
@@ -173,6 +204,7 @@ template <int K, typename TB>
 __device__ __forceinline__ void pp_limit(double (&u0)[3], TB (&uh)[3][K > 0 ? K : 1], double gamma)
 {
     if constexpr (K > 0) {
+        if (pp_clear<K, TB>(u0, uh, gamma)) return;
         constexpr int NP = PPPoints<K>::NP;
         constexpr bool kFP32 = sizeof(TB) == 4;
         const double pb = pp_pressure(gamma, u0);

@@ -55,7 +55,7 @@ __device__ __forceinline__ StateView<TB> prob_view(void* base, const BatchProb& 
     return v;
 }
 
-template <int K, typename TB, int MODE>
+template <int K, typename TB, int MODE, int PP>
 __device__ void solve_problem(const BatchArgs& b, const BatchProb& pr, unsigned int pidx,
                               unsigned char* lds, double* red, double* tree, double* sflux,
                               int* sreject)
@@ -89,7 +89,7 @@ __device__ void solve_problem(const BatchArgs& b, const BatchProb& pr, unsigned 
     a.tdata = nullptr;
     a.E_out = nullptr;
     a.eta_out = nullptr;
-    a.pp = b.pp;
+    a.pp = PP;  // compile-time, so the limiter's code exists only where it runs
     a.reject = sreject;
 
     // CFL quantity of the initial state
@@ -226,15 +226,15 @@ struct BatchLds {
 }  // namespace
 
 // Register budget of the mixed form: 3 waves per SIMD (168 VGPRs; its LDS
-// allows 4 workgroups per CU), one register under what the compiler picks
-// by itself.  The FP64 form is left free: a budget of 2 waves spills.
-template <typename TB>
+// allows 4 workgroups per CU) without the positivity limiter, 2 with it (a
+// budget of 3 spills, and measured slower).  The FP64 form is left free.
+template <typename TB, int PP>
 struct BatchWaves {
-    static constexpr int value = sizeof(TB) == 4 ? 3 : 1;
+    static constexpr int value = sizeof(TB) == 4 ? (PP ? 2 : 3) : 1;
 };
 
-template <typename TB, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BatchWaves<TB>::value)))
+template <typename TB, int MODE, int PP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BatchWaves<TB, PP>::value)))
 void batch1d_kernel(BatchArgs b)
 {
     __shared__ __align__(16) unsigned char lds[BatchLds<TB, MODE>::bytes];
@@ -252,10 +252,10 @@ void batch1d_kernel(BatchArgs b)
         const unsigned int p = b.order[pi];
         const BatchProb pr = b.probs[p];
         switch (pr.k) {
-        case 0: solve_problem<0, TB, MODE>(b, pr, p, lds, red, tree, sflux, &sreject); break;
-        case 1: solve_problem<1, TB, MODE>(b, pr, p, lds, red, tree, sflux, &sreject); break;
-        case 2: solve_problem<2, TB, MODE>(b, pr, p, lds, red, tree, sflux, &sreject); break;
-        default: solve_problem<3, TB, MODE>(b, pr, p, lds, red, tree, sflux, &sreject); break;
+        case 0: solve_problem<0, TB, MODE, PP>(b, pr, p, lds, red, tree, sflux, &sreject); break;
+        case 1: solve_problem<1, TB, MODE, PP>(b, pr, p, lds, red, tree, sflux, &sreject); break;
+        case 2: solve_problem<2, TB, MODE, PP>(b, pr, p, lds, red, tree, sflux, &sreject); break;
+        default: solve_problem<3, TB, MODE, PP>(b, pr, p, lds, red, tree, sflux, &sreject); break;
         }
         __syncthreads();
     }
@@ -302,19 +302,25 @@ hipError_t launch_batch_convert(int to_internal, const BatchArgs& b, const doubl
 template hipError_t launch_batch_convert<double>(int, const BatchArgs&, const double*, int, hipStream_t);
 template hipError_t launch_batch_convert<float>(int, const BatchArgs&, const double*, int, hipStream_t);
 
+template <typename TB>
+static void launch_batch_tb(int mode, const BatchArgs& b, int grid, hipStream_t st)
+{
+    if (mode == 0 && !b.pp)
+        hipLaunchKernelGGL((batch1d_kernel<TB, 0, 0>), dim3(grid), dim3(256), 0, st, b);
+    else if (mode == 0)
+        hipLaunchKernelGGL((batch1d_kernel<TB, 0, 1>), dim3(grid), dim3(256), 0, st, b);
+    else if (!b.pp)
+        hipLaunchKernelGGL((batch1d_kernel<TB, 1, 0>), dim3(grid), dim3(256), 0, st, b);
+    else
+        hipLaunchKernelGGL((batch1d_kernel<TB, 1, 1>), dim3(grid), dim3(256), 0, st, b);
+}
+
 hipError_t launch_batch1d(int mixed, int mode, const BatchArgs& b, int grid, hipStream_t st)
 {
-    if (mixed) {
-        if (mode == 0)
-            hipLaunchKernelGGL((batch1d_kernel<float, 0>), dim3(grid), dim3(256), 0, st, b);
-        else
-            hipLaunchKernelGGL((batch1d_kernel<float, 1>), dim3(grid), dim3(256), 0, st, b);
-    } else {
-        if (mode == 0)
-            hipLaunchKernelGGL((batch1d_kernel<double, 0>), dim3(grid), dim3(256), 0, st, b);
-        else
-            hipLaunchKernelGGL((batch1d_kernel<double, 1>), dim3(grid), dim3(256), 0, st, b);
-    }
+    if (mixed)
+        launch_batch_tb<float>(mode, b, grid, st);
+    else
+        launch_batch_tb<double>(mode, b, grid, st);
     return hipGetLastError();
 }
 
