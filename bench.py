@@ -25,6 +25,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the headline stage kernel (20000 cells, P2, FP64,
+# hybrid pass A), from rocprofv3 FETCH_SIZE and WRITE_SIZE over the
+# back-to-back timing launches, each scaled by what the counter reads for a
+# plain 1 GiB device copy (FETCH x2.0, WRITE x1.0); the summary with the
+# commands is profiles/stage1d_headline_traffic.md.  Set to None when that
+# kernel changes until the counters are taken again.
+HEADLINE_TRAFFIC_BYTES = (1671.0 * 2.0 + 1407.7 * 1.0) * 1024
 METRIC = "DOF-updates/s per RK stage and % HBM roofline, FP32 vs FP64, batched vs single"
 
 
@@ -139,11 +146,17 @@ def bench_batch(dg, torch, I, steps: int):
     wall = time.perf_counter() - t0
     done = sum(int(r.steps) for r in reps)
     upd = sum(3 * (k + 1) * n * int(r.steps) * 3 for (n, k, *_), r in zip(probs, reps))
+    # algorithmic bytes: 8/3 state passes per stage at each problem's own
+    # mixed-precision bytes per DOF (retried steps not counted)
+    nbytes = sum(3 * (k + 1) * n * int(r.steps) * 3 * bytes_per_dof_update(k, 1)
+                 for (n, k, *_), r in zip(probs, reps))
     b.close()
+    gbs = nbytes / wall / 1e9
     return {"problems": len(probs), "dofs": ndof, "steps_requested": steps,
             "steps_done": done, "failed": sum(1 for r in reps if r.status == -4),
             "retries": sum(int(r.restarts) for r in reps),
-            "dof_updates_per_s": upd / wall, "wall_s": wall, "schedule": tune.get("best")}
+            "dof_updates_per_s": upd / wall, "wall_s": wall, "algorithmic_GBps": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "schedule": tune.get("best")}
 
 
 def _dmr_mesh(dg, I, np, nx, ny, k):
@@ -230,7 +243,8 @@ def main() -> int:
     bytes_launch = bytes_per_dof_update(w.k, 0) * ndof
     achieved = bytes_launch / (avg_us * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": None if HEADLINE_TRAFFIC_BYTES is None else int(HEADLINE_TRAFFIC_BYTES),
                 "kernel": "stage1d_kernel<EULER,2,double,2> (fused residual + RK + hybrid pass A)",
                 "avg_launch_us": round(avg_us, 3),
                 "per_stage_us": [round(d, 3) for d in durs],
@@ -266,8 +280,8 @@ def main() -> int:
         del wd
         rb = bench_batch(dg, torch, I, 200)
         variants["batched_riemann_4096_mixed_pp"] = rb
-        log(f"batched 4096 problems: {rb['dof_updates_per_s']:.3e} DOF-updates/s, "
-            f"{rb['failed']} failed, {rb['retries']} retries")
+        log(f"batched 4096 problems: {rb['dof_updates_per_s']:.3e} DOF-updates/s "
+            f"({rb['algorithmic_GBps']} GB/s), {rb['failed']} failed, {rb['retries']} retries")
 
     cpu = None
     if not args.no_cpu_baseline:
