@@ -112,6 +112,14 @@ typedef struct {
                                 40 times; then the run stops with DG_ERR_POSITIVITY).
                                 Positivity reports then concern cell averages only.
                                 0 = off.  Other equations / 2D: DG_ERR_UNSUPPORTED. */
+    int basis;               /* 2D space (Sec. 2.3): 0 = Q^k tensor product (modes
+                                p, q <= k); 1 = P^k total degree (p + q <= k), the
+                                paper's own space.  Both keep the Q^k layout; with P^k
+                                the modes p + q > k are zero: dg_set_state drops them
+                                (the L2 projection onto P^k, the basis being
+                                orthogonal) and the residual keeps them at zero.  1D:
+                                both values name the same space.  Other values:
+                                DG_ERR_ARG. */
 } dg_options;
 
 /* Filled by dg_run / dg_report_read. */

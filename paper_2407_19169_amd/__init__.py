@@ -40,7 +40,7 @@ class dg_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("filter", C.c_int), ("cfl", C.c_double),
                 ("gamma", C.c_double), ("adv_speed", C.c_double * 2),
                 ("quad_points", C.c_int), ("stream", C.c_void_p), ("cf_mesh_factor", C.c_int),
-                ("positivity", C.c_int)]
+                ("positivity", C.c_int), ("basis", C.c_int)]
 
 
 class dg_report(C.Structure):
@@ -138,10 +138,11 @@ def make_mesh(dim, n, lo, hi, bc, dirichlet=None, shock_x0=0.0, shock_speed=0.0,
 
 def make_options(precision=DG_PREC_FP64, filter=DG_FILTER_JUMP, cfl=0.1, gamma=1.4,
                  adv_speed=(1.0, 0.0), quad_points=0, stream=None, cf_mesh_factor=0,
-                 positivity=0) -> dg_options:
+                 positivity=0, basis=0) -> dg_options:
     o = dg_options()
     o.cf_mesh_factor = cf_mesh_factor
     o.positivity = positivity
+    o.basis = basis
     o.precision, o.filter, o.cfl, o.gamma = precision, filter, cfl, gamma
     o.adv_speed[0], o.adv_speed[1] = adv_speed
     o.quad_points = quad_points

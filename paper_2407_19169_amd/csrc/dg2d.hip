@@ -568,7 +568,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
                 const T L = (T)((2 * p + 1) * (2 * q + 1)) * (T)ivol * r;
                 const int m = p * K1 + q;
                 a.out.hi[v * a.out.sv + (m - 1) * a.out.sl + cell] =
-                    combine2_t<T>(stage, nm[m], um[m] + (T)dt * L);
+                    (a.pk && p + q > K) ? (T)0 : combine2_t<T>(stage, nm[m], um[m] + (T)dt * L);
             }
     }
     // CFL quantity of the output's cell average (all variables of the cell)
@@ -877,6 +877,28 @@ __global__ __launch_bounds__(256) void blend2d_kernel(StateView<TB> out, const u
     }
 }
 
+template <typename TB>
+__global__ __launch_bounds__(256) void pk_project2d_kernel(StateView<TB> u, int nv, int k, int64_t ncell)
+{
+    const int K1 = k + 1;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
+         c += (int64_t)gridDim.x * blockDim.x)
+        for (int v = 0; v < nv; ++v)
+            for (int p = 0; p <= k; ++p)
+                for (int q = k + 1 - p; q <= k; ++q)
+                    u.hi[v * u.sv + (int64_t)(p * K1 + q - 1) * u.sl + c] = (TB)0;
+}
+
+template <typename TB>
+hipError_t launch_pk_project2d(int nv, int k, StateView<TB> u, int64_t ncell, hipStream_t st)
+{
+    int64_t g = (ncell + 255) / 256;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL((pk_project2d_kernel<TB>), dim3((unsigned)g), dim3(256), 0, st, u, nv, k, ncell);
+    return hipGetLastError();
+}
+
 template <int EQ, typename TB>
 __global__ __launch_bounds__(256) void maxwave2d_kernel(StateView<TB> u, int64_t ncell, double ihx,
                                                         double ihy, PhysParams phys,
@@ -983,6 +1005,7 @@ hipError_t launch_maxwave2d(int eq, StateView<TB> u, int64_t nx, int64_t ny, dou
                                            const long long*, const double*,                      \
                                            const unsigned long long*, const Ctrl*, int, int64_t, \
                                            hipStream_t);                                         \
+    template hipError_t launch_pk_project2d<TB>(int, int, StateView<TB>, int64_t, hipStream_t);   \
     template hipError_t launch_maxwave2d<TB>(int, StateView<TB>, int64_t, int64_t, double, double, \
                                              PhysParams, unsigned long long*, Ctrl*, hipStream_t);
 DG_INST(double)

@@ -140,6 +140,7 @@ Args2D<TB> base_args2d(const dg_solver* s)
     a.check = s->eq == DG_EQ_EULER;
     a.ctrl = ctrl_of(s);
     a.tcap = s->ncell;
+    a.pk = s->opt.basis == 1;
     a.cfmx = s->opt.cf_mesh_factor ? a.hx : 1.0;
     a.cfmy = s->opt.cf_mesh_factor ? a.hy : 1.0;
     // jump weights of the multi-index (a1, a2), m = a1 + a2: hx (m = 0),
@@ -575,6 +576,7 @@ int dg_create(const dg_mesh* mesh, int degree, int equation, const dg_options* o
     if (opt->filter < 0 || opt->filter > 2) return DG_ERR_ARG;
     if (opt->quad_points != 0 && opt->quad_points != degree + 1) return DG_ERR_UNSUPPORTED;
     if (opt->positivity != 0 && opt->positivity != 1) return DG_ERR_ARG;
+    if (opt->basis != 0 && opt->basis != 1) return DG_ERR_ARG;
     if (opt->positivity && (equation != DG_EQ_EULER || mesh->dim != 1)) return DG_ERR_UNSUPPORTED;
     if (!(opt->cfl > 0.0)) return DG_ERR_ARG;
     if (equation == DG_EQ_EULER && !(opt->gamma > 1.0)) return DG_ERR_ARG;
@@ -691,6 +693,14 @@ int dg_set_state(dg_solver* s, const double* modes_dev)
     } else {
         DG_HIP(launch_convert<float>(1, s->nv, s->nmodes, s->ncell, modes_dev,
                                      view_of<float>(s, s->u[0]), s->user_st));
+    }
+    if (s->dim == 2 && s->opt.basis == 1 && s->k > 0) {
+        if (is_fp64(s))
+            DG_HIP(launch_pk_project2d<double>(s->nv, s->k, view_of<double>(s, s->u[0]), s->ncell,
+                                               s->user_st));
+        else
+            DG_HIP(launch_pk_project2d<float>(s->nv, s->k, view_of<float>(s, s->u[0]), s->ncell,
+                                              s->user_st));
     }
     return DG_OK;
 }

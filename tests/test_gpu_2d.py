@@ -264,3 +264,94 @@ def test_full_size_double_mach_sampled_step(dg, ref):
                 want = _patch_step(ref, P, w.u0, int(jy), ix + dx, dt)
                 err = np.max(np.abs(got[:, :, jy, ix + dx] - want)) / np.max(np.abs(want[:, 0]))
                 assert err <= tol, (prec, jy, ix + dx, err)
+
+
+# ---- P^k (total degree, the paper's 2D space): basis = 1 on both sides ----
+def _pk_mask(k):
+    return np.array([1.0 if p + q <= k else 0.0 for p in range(k + 1) for q in range(k + 1)])
+
+
+@pytest.mark.parametrize("k,nx,ny,bcs", [(1, 16, 16, (0, 0, 0, 0)), (2, 31, 17, (3, 1, 4, 5)),
+                                         (3, 18, 35, (2, 2, 1, 1))])
+def test_pk_stage_and_filter_per_call(dg, ref, k, nx, ny, bcs):
+    """P^k: one residual stage plus one filter / hybrid application per call,
+    FP64, relative L-infinity <= 1e-13; modes with p + q > k stay zero."""
+    import torch
+
+    mask = _pk_mask(k)[None, :, None, None]
+    un, ua, ub = (random_euler2d(s, k, ny, nx) * mask for s in (1, 2, 3))
+    dt = 0.05 / nx
+    kw = _mesh_kwargs(bcs)
+    box = (0.0, 1.0, 0.0, 0.8)
+    mesh = dg.make_mesh(2, (nx, ny), (box[0], box[2]), (box[1], box[3]), bcs, **kw)
+    for filt in (0, 1, 2):
+        s = dg.Solver(mesh, k, 2, dg.make_options(filter=filt, cfl=0.1, basis=1))
+        P = ref.problem2d(2, k, nx, ny, *box, bc=bcs, filter=filt, cfl=0.1,
+                          dirichlet=kw["dirichlet"], shock_x0=kw["shock_x0"],
+                          shock_speed=kw["shock_speed"], post=kw["post"], pre=kw["pre"], basis=1)
+        for stage, us in ((0, un), (1, ua), (2, ub)):
+            s.set_state(un)
+            if stage:
+                dg.buffer_view(s, stage).copy_(torch.as_tensor(us))
+            dg.dg_stage(s.h, stage, dt)
+            dg.dg_jump_filter(s.h, stage, dt)
+            torch.cuda.synchronize()
+            got = dg.buffer_view(s, {0: 1, 1: 2, 2: 0}[stage]).cpu().numpy()
+            w = ref.stage2d(P, stage, dt, un, us, t=0.0)
+            tf = (1.0, 0.5, 1.0)[stage] * dt
+            want, _ = ref.post2d(P, stage, dt, w, t=tf)
+            assert np.all(got[:, _pk_mask(k) == 0.0] == 0.0)
+            for v in range(4):
+                err = rel_linf(got[v], want[v])
+                assert err <= 1e-13, (k, filt, stage, v, err)
+        s.close()
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_pk_vortex_run_parity(dg, ref, k):
+    """P^k vortex (seeded centre), 40x40, jump filter, 60 steps: FP64 within
+    1e-10 of the oracle's P^k run.  dg_set_state receives the Q^k
+    projection and keeps its P^k part."""
+    w = I.vortex2d(40, k, seed=3001)
+    mesh = dg.make_mesh(2, (w.nx, w.ny), (w.xlo, w.ylo), (w.xhi, w.yhi), w.bc)
+    s = dg.Solver(mesh, k, 2, dg.make_options(filter=1, cfl=w.cfl, basis=1))
+    s.set_state(w.u0)
+    rep = dg.dg_run(s.h, 1e30, 60)
+    got = s.get_state().cpu().numpy()
+    s.close()
+    P = ref.problem2d(2, k, w.nx, w.ny, w.xlo, w.xhi, w.ylo, w.yhi, bc=w.bc, filter=1, cfl=w.cfl,
+                      basis=1)
+    u0 = w.u0 * _pk_mask(k)[None, :, None, None]
+    want, orep, rc = ref.run2d(P, u0, 1e30, 60)
+    assert rc == 0 and rep.steps == orep.steps == 60
+    assert np.all(got[:, _pk_mask(k) == 0.0] == 0.0)
+    for v in range(4):
+        assert rel_linf(got[v], want[v]) <= 1e-10, v
+
+
+def test_pk_mixed_quadrant_hybrid(dg, ref):
+    """P^2 four-quadrant Riemann problem, 32x32, hybrid, mixed precision, 30
+    steps: cell averages within 1e-6 (relative L1) of the FP64 oracle."""
+    w = I.quadrant2d(32, 2, seed=3002)
+    mesh = dg.make_mesh(2, (w.nx, w.ny), (w.xlo, w.ylo), (w.xhi, w.yhi), w.bc)
+    s = dg.Solver(mesh, 2, 2, dg.make_options(precision=1, filter=2, cfl=w.cfl, basis=1))
+    s.set_state(w.u0)
+    rep = dg.dg_run(s.h, 1e30, 30)
+    got = s.get_state().cpu().numpy()
+    s.close()
+    P = ref.problem2d(2, 2, w.nx, w.ny, w.xlo, w.xhi, w.ylo, w.yhi, bc=w.bc, filter=2, cfl=w.cfl,
+                      basis=1)
+    want, orep, rc = ref.run2d(P, w.u0 * _pk_mask(2)[None, :, None, None], 1e30, 30)
+    assert rc == 0 and rep.status == 0 and rep.steps == 30
+    assert np.all(got[:, _pk_mask(2) == 0.0] == 0.0)
+    for v in range(4):
+        l1 = np.sum(np.abs(got[v, 0] - want[v, 0])) / np.sum(np.abs(want[v, 0]))
+        print(f"P2 mixed hybrid quadrant: var {v} relative L1 {l1:.3e}")
+        assert l1 < 1e-6, (v, l1)
+
+
+def test_basis_option_checked(dg):
+    mesh = dg.make_mesh(2, (8, 8), (0.0, 0.0), (1.0, 1.0), (0, 0, 0, 0))
+    with pytest.raises(dg.DGError) as e:
+        dg.Solver(mesh, 2, 2, dg.make_options(basis=2))
+    assert e.value.code == dg.DG_ERR_ARG
