@@ -104,23 +104,25 @@ def sweep_1d(dg, torch, I, sizes, steps: int):
     return out
 
 
-def bench_2d(dg, torch, I, w, mesh, prec: int, filt: int, steps: int):
+def bench_2d(dg, torch, I, w, mesh, prec: int, filt: int, steps: int, basis: int = 0):
     """A 2D workload: step throughput and, per stage, the residual and filter
-    kernel times against the stage's algorithmic bytes."""
-    ndof = 4 * (w.k + 1) ** 2 * w.nx * w.ny
-    opt = dg.make_options(precision=prec, filter=filt, cfl=w.cfl)
+    kernel times against the stage's algorithmic bytes.  basis 1: the P^k
+    space (the modes p + q <= k are the DOFs)."""
+    nm = (w.k + 1) ** 2 if basis == 0 else (w.k + 1) * (w.k + 2) // 2
+    ndof = 4 * nm * w.nx * w.ny
+    opt = dg.make_options(precision=prec, filter=filt, cfl=w.cfl, basis=basis)
     s = dg.Solver(mesh, w.k, dg.DG_EQ_EULER, opt)
     s.set_state(w.u0)
     rep, wall = _timed_run(dg, torch, s, steps, 2)
     res = [dg.dg_time_kernel(s.h, st, rep.dt_max, 10) for st in range(3)]
     fil = [dg.dg_time_kernel(s.h, 3 + st, rep.dt_max, 10) for st in range(3)]
     s.close()
-    nm = (w.k + 1) ** 2
     per_dof = 8.0 if prec == 0 else (8.0 + 4.0 * (nm - 1)) / nm
     b = 8.0 / 3.0 * per_dof * ndof
     stage_us = (sum(res) + sum(fil)) / 3.0
     gbs = b / (stage_us * 1e-6) / 1e9
-    return {"dofs": ndof, "precision": "fp64" if prec == 0 else "mixed", "status": rep.status,
+    return {"dofs": ndof, "space": "Q^k" if basis == 0 else "P^k",
+            "precision": "fp64" if prec == 0 else "mixed", "status": rep.status,
             "dof_updates_per_s": ndof * 3 * steps / wall, "ms_per_step": 1e3 * wall / steps,
             "residual_kernel_us": round(sum(res) / 3, 2), "filter_kernel_us": round(sum(fil) / 3, 2),
             "stage_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
@@ -176,10 +178,12 @@ def run_only(args, dg, torch, I, np) -> int:
     elif args.only == "vortex":
         wv = I.vortex2d(1024, 2, seed=3001)
         mesh = dg.make_mesh(2, (1024, 1024), (0.0, -5.0), (10.0, 5.0), (0, 0, 0, 0))
-        r = [bench_2d(dg, torch, I, wv, mesh, p, dg.DG_FILTER_JUMP, args.steps) for p in (0, 1)]
+        r = [bench_2d(dg, torch, I, wv, mesh, p, dg.DG_FILTER_JUMP, args.steps, basis=b)
+             for p in (0, 1) for b in (0, 1)]
     elif args.only == "dmr":
         wd, mesh = _dmr_mesh(dg, I, np, 4096, 1024, 3)
-        r = bench_2d(dg, torch, I, wd, mesh, dg.DG_PREC_MIXED, dg.DG_FILTER_JUMP, args.steps)
+        r = [bench_2d(dg, torch, I, wd, mesh, dg.DG_PREC_MIXED, dg.DG_FILTER_JUMP, args.steps, basis=b)
+             for b in (0, 1)]
     elif args.only == "copy":
         # reference for hardware traffic counters: a plain 1 GiB device copy
         x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
@@ -271,12 +275,17 @@ def main() -> int:
             variants[f"vortex2d_1024_q2_{r['precision']}"] = r
             log(f"vortex 1024^2 Q2 {r['precision']}: {r['dof_updates_per_s']:.3e} DOF-updates/s, "
                 f"stage {r['stage_GBps']} GB/s")
+        r = bench_2d(dg, torch, I, wv, mesh, dg.DG_PREC_MIXED, dg.DG_FILTER_JUMP, 20, basis=1)
+        variants["vortex2d_1024_p2_mixed"] = r
+        log(f"vortex 1024^2 P2 mixed: {r['dof_updates_per_s']:.3e} DOF-updates/s, "
+            f"stage {r['stage_GBps']} GB/s")
         del wv
         wd, meshd = _dmr_mesh(dg, I, np, 4096, 1024, 3)
-        r = bench_2d(dg, torch, I, wd, meshd, dg.DG_PREC_MIXED, dg.DG_FILTER_JUMP, 10)
-        variants["double_mach_4096x1024_q3_mixed"] = r
-        log(f"double Mach 4096x1024 Q3 mixed: {r['dof_updates_per_s']:.3e} DOF-updates/s, "
-            f"stage {r['stage_GBps']} GB/s")
+        for basis, name in ((0, "q3"), (1, "p3")):
+            r = bench_2d(dg, torch, I, wd, meshd, dg.DG_PREC_MIXED, dg.DG_FILTER_JUMP, 10, basis=basis)
+            variants[f"double_mach_4096x1024_{name}_mixed"] = r
+            log(f"double Mach 4096x1024 {name.upper()} mixed: {r['dof_updates_per_s']:.3e} "
+                f"DOF-updates/s, stage {r['stage_GBps']} GB/s")
         del wd
         rb = bench_batch(dg, torch, I, 200)
         variants["batched_riemann_4096_mixed_pp"] = rb

@@ -238,6 +238,9 @@ class Solver:
         dg_bind(self.h, *self._ptrs)
         self.nv = (3 if mesh.dim == 1 else 4) if equation == DG_EQ_EULER else 1
         self.nmodes = (degree + 1) if mesh.dim == 1 else (degree + 1) ** 2
+        # modes stored per variable: the 2D P^k space keeps p + q <= k only
+        self.nmodes_stored = ((degree + 1) * (degree + 2) // 2
+                              if mesh.dim == 2 and options.basis == 1 and degree > 0 else self.nmodes)
         self.ncell = mesh.n[0] if mesh.dim == 1 else mesh.n[0] * mesh.n[1]
 
     def shape(self):
@@ -278,14 +281,24 @@ class Solver:
 
 def buffer_view(solver: Solver, i: int):
     """FP64-layout view of state buffer i (0 = u_n, 1 = u_a, 2 = u_b) of a
-    DG_PREC_FP64 solver (the caller owns these buffers)."""
+    DG_PREC_FP64 solver (the caller owns these buffers).  The mode axis has
+    the stored modes: for the 2D P^k space the modes p + q <= k in p-major
+    order (`pk_modes`)."""
     torch = solver.torch
     t = solver._raw[i]
     off = solver._ptrs[i] - t.data_ptr()
+    shape = list(solver.shape())
+    shape[1] = solver.nmodes_stored
     nel = 1
-    for d in solver.shape():
+    for d in shape:
         nel *= d
-    return t[off:off + nel * 8].view(torch.float64).view(solver.shape())
+    return t[off:off + nel * 8].view(torch.float64).view(shape)
+
+
+def pk_modes(k: int):
+    """Q^k mode indices p*(k+1)+q of the P^k modes (p + q <= k), in the order
+    the device stores them."""
+    return [p * (k + 1) + q for p in range(k + 1) for q in range(k + 1) if p + q <= k]
 
 
 # ----------------------------------------------------------------- batch --

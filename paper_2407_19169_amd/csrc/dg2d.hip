@@ -218,14 +218,32 @@ __device__ __forceinline__ void face_trace_var(const T (&um)[(K + 1) * (K + 1)],
     }
 }
 
-// Modes of variable v of cell c: FP64 mode 0 and the TB modes, all as T.
-template <int NM, typename TB, typename T>
-__device__ __forceinline__ void load_var2d(const StateView<TB>& s, int64_t c, int v, double& m0, T (&um)[NM])
+// Storage plane of mode m = p (k+1) + q: the Q^k space keeps every mode at
+// plane m; the P^k space (PK) keeps only the modes p + q <= k, in p-major
+// order, and the others are zero by construction.
+template <int K, bool PK>
+__device__ __forceinline__ constexpr bool mode_kept(int m)
 {
+    return !PK || m / (K + 1) + m % (K + 1) <= K;
+}
+template <int K, bool PK>
+__device__ __forceinline__ constexpr int mode_plane(int m)
+{
+    return PK ? (m / (K + 1)) * (K + 1) - (m / (K + 1)) * (m / (K + 1) - 1) / 2 + m % (K + 1) : m;
+}
+
+// Modes of variable v of cell c: FP64 mode 0 and the TB modes, all as T
+// (the modes the space leaves out as zeros).
+template <int K, bool PK, typename TB, typename T>
+__device__ __forceinline__ void load_var2d(const StateView<TB>& s, int64_t c, int v, double& m0,
+                                           T (&um)[(K + 1) * (K + 1)])
+{
+    constexpr int NM = (K + 1) * (K + 1);
     m0 = s.m0[v * s.s0 + c];
     um[0] = (T)m0;
 #pragma unroll
-    for (int m = 1; m < NM; ++m) um[m] = s.hi[v * s.sv + (m - 1) * s.sl + c];
+    for (int m = 1; m < NM; ++m)
+        um[m] = mode_kept<K, PK>(m) ? (T)s.hi[v * s.sv + (mode_plane<K, PK>(m) - 1) * s.sl + c] : (T)0;
 }
 
 // Orders LDS writes before later LDS reads of other lanes of the same
@@ -272,7 +290,7 @@ struct StageTile {
     static constexpr int NHE = FX * (FY + 1);  // horizontal edges
 };
 
-template <int EQ, int K, typename TB>
+template <int EQ, int K, typename TB, bool PK>
 __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
 {
     using P = Phys2D<EQ>;
@@ -319,7 +337,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
     T um[NM];
 #pragma unroll
     for (int m = 0; m < NM; ++m) um[m] = (T)0;
-    if (loadable) load_var2d<NM, TB, T>(a.us, cy * a.nx + cx, v, m0v, um);
+    if (loadable) load_var2d<K, PK, TB, T>(a.us, cy * a.nx + cx, v, m0v, um);
     // u^n of the own cell for the combination, fetched now so that its
     // latency overlaps the flux phases
     const int64_t cell = jy * a.nx + ix;
@@ -327,7 +345,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
     T nm[NM];
 #pragma unroll
     for (int m = 0; m < NM; ++m) nm[m] = (T)0;
-    if (own && stage > 0) load_var2d<NM, TB, T>(a.un, cell, v, n0, nm);
+    if (own && stage > 0) load_var2d<K, PK, TB, T>(a.un, cell, v, n0, nm);
     if (loadable) {
         T tr[Q];
         face_trace_var<0, K, T>(um, tr);  // left face: upper side of vertical edge tx
@@ -357,7 +375,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
         if (hx_ >= 0 && hy_ >= 0) {
             double w0;
             T wm[NM];
-            load_var2d<NM, TB, T>(a.us, hy_ * a.nx + hx_, rv, w0, wm);
+            load_var2d<K, PK, TB, T>(a.us, hy_ * a.nx + hx_, rv, w0, wm);
             T tr[Q];
             T* dst;
             if (g == 0) {
@@ -555,7 +573,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
         for (int p = 0; p < K1; ++p)
 #pragma unroll
             for (int q = 0; q < K1; ++q) {
-                if (p == 0 && q == 0) continue;
+                if ((p == 0 && q == 0) || (PK && p + q > K)) continue;
                 T ex_ = (T)0, ey_ = (T)0;
 #pragma unroll
                 for (int b = 0; b < Q; ++b) {
@@ -567,8 +585,8 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
                 const T r = acc[p * K1 + q] - hy2 * ex_ - hx2 * ey_;
                 const T L = (T)((2 * p + 1) * (2 * q + 1)) * (T)ivol * r;
                 const int m = p * K1 + q;
-                a.out.hi[v * a.out.sv + (m - 1) * a.out.sl + cell] =
-                    (a.pk && p + q > K) ? (T)0 : combine2_t<T>(stage, nm[m], um[m] + (T)dt * L);
+                a.out.hi[v * a.out.sv + (mode_plane<K, PK>(m) - 1) * a.out.sl + cell] =
+                    combine2_t<T>(stage, nm[m], um[m] + (T)dt * L);
             }
     }
     // CFL quantity of the output's cell average (all variables of the cell)
@@ -601,7 +619,7 @@ struct FilterTile {
     static constexpr int SX = FX + 2, SY = FY + 2;
 };
 
-template <int EQ, int K, typename TB, int MODE>
+template <int EQ, int K, typename TB, int MODE, bool PK>
 __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
 {
     using P = Phys2D<EQ>;
@@ -636,10 +654,7 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
     for (int m = 0; m < NM; ++m) um[m] = (T)0;
     if (loadable) {
         const int64_t c = cy * a.nx + cx;
-        m0v = a.us.m0[v * a.us.s0 + c];
-        um[0] = (T)m0v;
-#pragma unroll
-        for (int m = 1; m < NM; ++m) um[m] = a.us.hi[v * a.us.sv + (m - 1) * a.us.sl + c];
+        load_var2d<K, PK, TB, T>(a.us, c, v, m0v, um);
 #pragma unroll
         for (int m = 0; m < NM; ++m) sM[oslot * STRIDE + m * NV + v] = um[m];
     }
@@ -668,7 +683,9 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
             sM[slot * STRIDE + rv] = (T)a.us.m0[rv * a.us.s0 + c];
 #pragma unroll
             for (int m = 1; m < NM; ++m)
-                sM[slot * STRIDE + m * NV + rv] = a.us.hi[rv * a.us.sv + (m - 1) * a.us.sl + c];
+                sM[slot * STRIDE + m * NV + rv] =
+                    mode_kept<K, PK>(m) ? (T)a.us.hi[rv * a.us.sv + (mode_plane<K, PK>(m) - 1) * a.us.sl + c]
+                                        : (T)0;
         }
     }
     __syncthreads();
@@ -716,6 +733,7 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
 #pragma unroll
                         for (int n = (al > 0 ? al : 0); n < K1; ++n) {
                             const int m = dir == 0 ? n * K1 + o : o * K1 + n;
+                            if (!mode_kept<K, PK>(m)) continue;
                             go += um[m] * across(n, al, side);
                             if (inside) gn += UN[m * NV] * across(n, al, 1 - side);
                         }
@@ -825,9 +843,9 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
         for (int p = 0; p < K1; ++p)
 #pragma unroll
             for (int q = 0; q < K1; ++q) {
-                if (p == 0 && q == 0) continue;
+                if ((p == 0 && q == 0) || (PK && p + q > K)) continue;
                 const int m = p * K1 + q;
-                a.out.hi[v * a.out.sv + (m - 1) * a.out.sl + cell] = um[m] * f[p + q];
+                a.out.hi[v * a.out.sv + (mode_plane<K, PK>(m) - 1) * a.out.sl + cell] = um[m] * f[p + q];
             }
     } else {
         if (v == 0) {
@@ -847,7 +865,7 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
 }
 
 // Hybrid pass B over the troubled list: u^{pq} <- [w + (1 - w) exp(-E^{p+q})] u^{pq}.
-template <int K, int NV, typename TB>
+template <int K, int NV, typename TB, bool PK>
 __global__ __launch_bounds__(256) void blend2d_kernel(StateView<TB> out, const unsigned int* count,
                                                       const long long* tcell, const double* tdata,
                                                       const unsigned long long* eta_bits,
@@ -871,31 +889,60 @@ __global__ __launch_bounds__(256) void blend2d_kernel(StateView<TB> out, const u
             for (int p = 0; p < K1; ++p)
 #pragma unroll
                 for (int q = 0; q < K1; ++q) {
-                    if (p == 0 && q == 0) continue;
-                    out.hi[v * out.sv + (p * K1 + q - 1) * out.sl + c] *= f[p + q];
+                    if ((p == 0 && q == 0) || (PK && p + q > K)) continue;
+                    out.hi[v * out.sv + (mode_plane<K, PK>(p * K1 + q) - 1) * out.sl + c] *= f[p + q];
                 }
     }
 }
 
+// P^k exchange conversion: the FP64 exchange layout [var][p (k+1) + q][cell]
+// (every Q^k mode) <-> the compact internal P^k planes.  To the device the
+// modes p + q > k are dropped (the L2 projection onto P^k, the Legendre
+// basis being orthogonal); from the device they are written as zeros.
 template <typename TB>
-__global__ __launch_bounds__(256) void pk_project2d_kernel(StateView<TB> u, int nv, int k, int64_t ncell)
+__global__ __launch_bounds__(256) void convert_pk2d_kernel(int to_internal, int k, int64_t ncell,
+                                                           int64_t total, const double* ext_in,
+                                                           double* ext_out, StateView<TB> v)
 {
-    const int K1 = k + 1;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
-         c += (int64_t)gridDim.x * blockDim.x)
-        for (int v = 0; v < nv; ++v)
-            for (int p = 0; p <= k; ++p)
-                for (int q = k + 1 - p; q <= k; ++q)
-                    u.hi[v * u.sv + (int64_t)(p * K1 + q - 1) * u.sl + c] = (TB)0;
+    const int K1 = k + 1, NM = K1 * K1;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = i % ncell;
+        const int64_t rest = i / ncell;
+        const int m = (int)(rest % NM);
+        const int var = (int)(rest / NM);
+        const int p = m / K1, q = m % K1;
+        if (p + q > k) {
+            if (!to_internal) ext_out[i] = 0.0;
+            continue;
+        }
+        const int plane = p * K1 - p * (p - 1) / 2 + q;
+        if (plane == 0) {
+            double* d = v.m0 + var * v.s0 + c;
+            if (to_internal)
+                *d = ext_in[i];
+            else
+                ext_out[i] = *d;
+        } else {
+            TB* d = v.hi + var * v.sv + (int64_t)(plane - 1) * v.sl + c;
+            if (to_internal)
+                *d = (TB)ext_in[i];
+            else
+                ext_out[i] = (double)*d;
+        }
+    }
 }
 
 template <typename TB>
-hipError_t launch_pk_project2d(int nv, int k, StateView<TB> u, int64_t ncell, hipStream_t st)
+hipError_t launch_convert_pk2d(int to_internal, int nv, int k, int64_t ncell, const double* ext,
+                               StateView<TB> v, hipStream_t st)
 {
-    int64_t g = (ncell + 255) / 256;
+    const int64_t total = (int64_t)nv * (k + 1) * (k + 1) * ncell;
+    int64_t g = (total + 255) / 256;
     if (g > 65536) g = 65536;
     if (g < 1) g = 1;
-    hipLaunchKernelGGL((pk_project2d_kernel<TB>), dim3((unsigned)g), dim3(256), 0, st, u, nv, k, ncell);
+    hipLaunchKernelGGL((convert_pk2d_kernel<TB>), dim3((unsigned)g), dim3(256), 0, st, to_internal, k,
+                       ncell, total, ext, const_cast<double*>(ext), v);
     return hipGetLastError();
 }
 
@@ -931,7 +978,10 @@ hipError_t launch_stage2d(int eq, int k, const Args2D<TB>& a, hipStream_t st)
     dim3 grid((unsigned)(((a.nx + fx - 1) / fx) * ((a.ny + fy - 1) / fy))), block(256);
 #define DG_CASE(E_, K_)                                                                   \
     if (eq == E_ && k == K_) {                                                            \
-        hipLaunchKernelGGL((stage2d_kernel<E_, K_, TB>), grid, block, 0, st, a);          \
+        if (a.pk)                                                                         \
+            hipLaunchKernelGGL((stage2d_kernel<E_, K_, TB, (K_ > 0)>), grid, block, 0, st, a); \
+        else                                                                              \
+            hipLaunchKernelGGL((stage2d_kernel<E_, K_, TB, false>), grid, block, 0, st, a); \
         return hipGetLastError();                                                         \
     }
     DG_CASE(ADV, 0) DG_CASE(ADV, 1) DG_CASE(ADV, 2) DG_CASE(ADV, 3)
@@ -948,10 +998,14 @@ hipError_t launch_filter2d(int eq, int k, const Args2D<TB>& a, int mode, hipStre
     dim3 grid((unsigned)(((a.nx + fx - 1) / fx) * ((a.ny + fy - 1) / fy))), block(256);
 #define DG_CASE(E_, K_)                                                                        \
     if (eq == E_ && k == K_) {                                                                 \
-        if (mode == 1)                                                                         \
-            hipLaunchKernelGGL((filter2d_kernel<E_, K_, TB, 1>), grid, block, 0, st, a);       \
+        if (mode == 1 && a.pk)                                                                 \
+            hipLaunchKernelGGL((filter2d_kernel<E_, K_, TB, 1, (K_ > 0)>), grid, block, 0, st, a); \
+        else if (mode == 1)                                                                    \
+            hipLaunchKernelGGL((filter2d_kernel<E_, K_, TB, 1, false>), grid, block, 0, st, a); \
+        else if (a.pk)                                                                         \
+            hipLaunchKernelGGL((filter2d_kernel<E_, K_, TB, 2, (K_ > 0)>), grid, block, 0, st, a); \
         else                                                                                   \
-            hipLaunchKernelGGL((filter2d_kernel<E_, K_, TB, 2>), grid, block, 0, st, a);       \
+            hipLaunchKernelGGL((filter2d_kernel<E_, K_, TB, 2, false>), grid, block, 0, st, a); \
         return hipGetLastError();                                                              \
     }
     DG_CASE(ADV, 0) DG_CASE(ADV, 1) DG_CASE(ADV, 2) DG_CASE(ADV, 3)
@@ -964,15 +1018,21 @@ template <typename TB>
 hipError_t launch_blend2d(int nv, int k, StateView<TB> out, int64_t ncell, const unsigned int* count,
                           const long long* tcell, const double* tdata,
                           const unsigned long long* eta_bits, const Ctrl* ctrl, int from_ctrl,
-                          int64_t max_entries, hipStream_t st)
+                          int64_t max_entries, int pk, hipStream_t st)
 {
     unsigned g = (unsigned)((max_entries + 255) / 256);
     if (g > 2048) g = 2048;
     if (g < 1) g = 1;
 #define DG_CASE(NV_, K_)                                                                          \
     if (nv == NV_ && k == K_) {                                                                   \
-        hipLaunchKernelGGL((blend2d_kernel<K_, NV_, TB>), dim3(g), dim3(256), 0, st, out, count,  \
-                           tcell, tdata, eta_bits, ctrl, from_ctrl, (long long)max_entries);      \
+        if (pk)                                                                                   \
+            hipLaunchKernelGGL((blend2d_kernel<K_, NV_, TB, (K_ > 0)>), dim3(g), dim3(256), 0, st, \
+                               out, count, tcell, tdata, eta_bits, ctrl, from_ctrl,              \
+                               (long long)max_entries);                                           \
+        else                                                                                      \
+            hipLaunchKernelGGL((blend2d_kernel<K_, NV_, TB, false>), dim3(g), dim3(256), 0, st,   \
+                               out, count, tcell, tdata, eta_bits, ctrl, from_ctrl,              \
+                               (long long)max_entries);                                           \
         return hipGetLastError();                                                                 \
     }
     DG_CASE(1, 0) DG_CASE(1, 1) DG_CASE(1, 2) DG_CASE(1, 3)
@@ -1004,8 +1064,9 @@ hipError_t launch_maxwave2d(int eq, StateView<TB> u, int64_t nx, int64_t ny, dou
     template hipError_t launch_blend2d<TB>(int, int, StateView<TB>, int64_t, const unsigned int*, \
                                            const long long*, const double*,                      \
                                            const unsigned long long*, const Ctrl*, int, int64_t, \
-                                           hipStream_t);                                         \
-    template hipError_t launch_pk_project2d<TB>(int, int, StateView<TB>, int64_t, hipStream_t);   \
+                                           int, hipStream_t);                                    \
+    template hipError_t launch_convert_pk2d<TB>(int, int, int, int64_t, const double*,           \
+                                                StateView<TB>, hipStream_t);                      \
     template hipError_t launch_maxwave2d<TB>(int, StateView<TB>, int64_t, int64_t, double, double, \
                                              PhysParams, unsigned long long*, Ctrl*, hipStream_t);
 DG_INST(double)

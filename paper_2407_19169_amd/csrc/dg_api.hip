@@ -20,7 +20,8 @@ using namespace dg;
 struct dg_solver {
     dg_mesh mesh;
     dg_options opt;
-    int k, eq, dim, nv, nmodes, lmax;
+    int k, eq, dim, nv, nmodes, lmax;  // nmodes: modes stored per variable
+    int pk;                            // 2D P^k space in compact planes
     int64_t ncell, n_pad;
     double h[2], inv_h[2];
     size_t state_bytes, ws_bytes;
@@ -140,7 +141,7 @@ Args2D<TB> base_args2d(const dg_solver* s)
     a.check = s->eq == DG_EQ_EULER;
     a.ctrl = ctrl_of(s);
     a.tcap = s->ncell;
-    a.pk = s->opt.basis == 1;
+    a.pk = s->pk;
     a.cfmx = s->opt.cf_mesh_factor ? a.hx : 1.0;
     a.cfmy = s->opt.cf_mesh_factor ? a.hy : 1.0;
     // jump weights of the multi-index (a1, a2), m = a1 + a2: hx (m = 0),
@@ -223,7 +224,7 @@ int filter_impl(dg_solver* s, int stage, double dt)
         a.eta_out = reinterpret_cast<double*>(s->ws + s->off_eta);
         DG_HIP(launch_filter2d<TB>(s->eq, s->k, a, 2, s->user_st));
         DG_HIP(launch_blend2d<TB>(s->nv, s->k, a.out, s->ncell, tcount, a.tcell, a.tdata, eta_bits,
-                                  ctrl_of(s), 0, s->ncell, s->user_st));
+                                  ctrl_of(s), 0, s->ncell, s->pk, s->user_st));
         return DG_OK;
     }
     Args1D<TB> a = base_args<TB>(s);
@@ -307,7 +308,7 @@ int record_steps(dg_solver* s, int G, hipStream_t st)
                         f.tdata = tdata;
                         DG_HIP(launch_filter2d<TB>(s->eq, s->k, f, 2, st));
                         DG_HIP(launch_blend2d<TB>(s->nv, s->k, f.out, s->ncell, &c->tcount[stage], tcell,
-                                                  tdata, &c->eta_bits[stage], c, 1, s->ncell, st));
+                                                  tdata, &c->eta_bits[stage], c, 1, s->ncell, s->pk, st));
                     }
                 }
             }
@@ -605,7 +606,11 @@ int dg_create(const dg_mesh* mesh, int degree, int equation, const dg_options* o
     s->eq = equation;
     s->dim = mesh->dim;
     s->nv = (equation == DG_EQ_EULER) ? (mesh->dim == 1 ? 3 : 4) : 1;
-    s->nmodes = mesh->dim == 1 ? degree + 1 : (degree + 1) * (degree + 1);
+    // stored modes: P^k keeps the (k+1)(k+2)/2 modes p + q <= k (compact planes)
+    s->pk = mesh->dim == 2 && opt->basis == 1 && degree > 0;
+    s->nmodes = mesh->dim == 1 ? degree + 1
+              : s->pk ? (degree + 1) * (degree + 2) / 2
+                      : (degree + 1) * (degree + 1);
     s->lmax = mesh->dim == 1 ? degree : 2 * degree;
     s->ncell = mesh->dim == 1 ? mesh->n[0] : mesh->n[0] * mesh->n[1];
     s->n_pad = (s->ncell + 63) / 64 * 64;
@@ -687,20 +692,19 @@ int dg_set_state(dg_solver* s, const double* modes_dev)
 {
     if (!s || !modes_dev) return DG_ERR_ARG;
     if (!s->bound) return DG_ERR_STATE;
-    if (is_fp64(s)) {
+    if (s->pk) {
+        if (is_fp64(s))
+            DG_HIP(launch_convert_pk2d<double>(1, s->nv, s->k, s->ncell, modes_dev,
+                                               view_of<double>(s, s->u[0]), s->user_st));
+        else
+            DG_HIP(launch_convert_pk2d<float>(1, s->nv, s->k, s->ncell, modes_dev,
+                                              view_of<float>(s, s->u[0]), s->user_st));
+    } else if (is_fp64(s)) {
         DG_HIP(hipMemcpyAsync(s->u[0], modes_dev, (size_t)s->nv * s->nmodes * s->ncell * sizeof(double),
                               hipMemcpyDeviceToDevice, s->user_st));
     } else {
         DG_HIP(launch_convert<float>(1, s->nv, s->nmodes, s->ncell, modes_dev,
                                      view_of<float>(s, s->u[0]), s->user_st));
-    }
-    if (s->dim == 2 && s->opt.basis == 1 && s->k > 0) {
-        if (is_fp64(s))
-            DG_HIP(launch_pk_project2d<double>(s->nv, s->k, view_of<double>(s, s->u[0]), s->ncell,
-                                               s->user_st));
-        else
-            DG_HIP(launch_pk_project2d<float>(s->nv, s->k, view_of<float>(s, s->u[0]), s->ncell,
-                                              s->user_st));
     }
     return DG_OK;
 }
@@ -709,7 +713,14 @@ int dg_get_state(dg_solver* s, double* modes_dev)
 {
     if (!s || !modes_dev) return DG_ERR_ARG;
     if (!s->bound) return DG_ERR_STATE;
-    if (is_fp64(s)) {
+    if (s->pk) {
+        if (is_fp64(s))
+            DG_HIP(launch_convert_pk2d<double>(0, s->nv, s->k, s->ncell, modes_dev,
+                                               view_of<double>(s, s->u[0]), s->user_st));
+        else
+            DG_HIP(launch_convert_pk2d<float>(0, s->nv, s->k, s->ncell, modes_dev,
+                                              view_of<float>(s, s->u[0]), s->user_st));
+    } else if (is_fp64(s)) {
         DG_HIP(hipMemcpyAsync(modes_dev, s->u[0], (size_t)s->nv * s->nmodes * s->ncell * sizeof(double),
                               hipMemcpyDeviceToDevice, s->user_st));
     } else {

@@ -71,7 +71,7 @@ struct Args2D {
     double* eta_out;
     double jsx[16], jsy[16];  // jump weights per multi-index a1*4+a2 (see filter2d)
     double cfmx, cfmy;        // mesh factors of (c_fx, c_fy): (hx, hy) as printed, or (1, 1)
-    int pk;                   // P^k space: modes with p + q > k stay zero
+    int pk;                   // P^k space: compact planes of the modes p + q <= k
 };
 
 template <typename TB>
@@ -82,10 +82,12 @@ template <typename TB>
 hipError_t launch_blend2d(int nv, int k, StateView<TB> out, int64_t ncell, const unsigned int* count,
                           const long long* tcell, const double* tdata,
                           const unsigned long long* eta_bits, const Ctrl* ctrl, int from_ctrl,
-                          int64_t max_entries, hipStream_t st);
-// P^k projection of a Q^k-layout state: zero the modes with p + q > k.
+                          int64_t max_entries, int pk, hipStream_t st);
+// FP64 exchange layout (every Q^k mode) <-> compact internal P^k planes
+// (modes p + q <= k in p-major order); zeros for the other modes on the way out.
 template <typename TB>
-hipError_t launch_pk_project2d(int nv, int k, StateView<TB> u, int64_t ncell, hipStream_t st);
+hipError_t launch_convert_pk2d(int to_internal, int nv, int k, int64_t ncell, const double* ext,
+                               StateView<TB> v, hipStream_t st);
 template <typename TB>
 hipError_t launch_maxwave2d(int eq, StateView<TB> u, int64_t nx, int64_t ny, double inv_hx,
                             double inv_hy, PhysParams phys, unsigned long long* acc, Ctrl* err,
