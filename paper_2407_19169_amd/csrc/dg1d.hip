@@ -662,14 +662,13 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
 // M = max eta; then, with the positivity limiter on, the limiter on the
 // blended cell.
 template <int K, int NV, typename TB>
-__device__ __forceinline__ void blend_entries(StateView<TB> out, const unsigned int* count,
-                                              const long long* tcell, const double* tdata,
-                                              const unsigned long long* eta_bits, long long cap,
-                                              const PPArgs& pp, unsigned int i0, unsigned int stride)
+__device__ __forceinline__ void blend_entries(StateView<TB> out, unsigned int cnt, const long long* tcell,
+                                              const double* tdata, unsigned long long eta_bits,
+                                              long long cap, const PPArgs& pp, unsigned int i0,
+                                              unsigned int stride)
 {
-    unsigned int cnt = *count;
     if ((long long)cnt > cap) cnt = (unsigned int)cap;
-    const double M = __longlong_as_double((long long)*eta_bits);
+    const double M = __longlong_as_double((long long)eta_bits);
     for (unsigned int i = i0; i < cnt; i += stride) {
         const long long c = tcell[i];
         const double* rec = tdata + (size_t)i * (K + 1);
@@ -698,8 +697,14 @@ template <int EQ, int K, typename TB, int MODE, int BS>
 __global__ __launch_bounds__(BS) void stage1d_kernel(Args1D<TB> a)
 {
     // a finished run, or a step already rejected by the positivity limiter
-    if (a.ctrl && a.dt_from_ctrl && (a.ctrl->done || a.ctrl->reject)) return;
-    const double dt = a.dt_from_ctrl ? a.ctrl->dt : a.dt_host;
+    // (flags and dt fetched together: one memory round trip)
+    int stop = 0;
+    double dt = a.dt_host;
+    if (a.dt_from_ctrl) {
+        stop = a.ctrl->done | a.ctrl->reject;
+        dt = a.ctrl->dt;
+    }
+    if (stop) return;
     __shared__ __align__(16) unsigned char lds[Stage1DLds<EQ, K, TB, MODE, BS>::bytes];
     double lam, eta;
     stage1d_tile<EQ, K, TB, MODE, BS>(a, (int64_t)blockIdx.x, dt, lds, &lam, &eta);
@@ -724,9 +729,14 @@ __global__ __launch_bounds__(256) void blend1d_kernel(StateView<TB> out, const u
                                                       const Ctrl* ctrl, int from_ctrl, long long cap,
                                                       PPArgs pp)
 {
-    if (from_ctrl && (ctrl->done || ctrl->reject)) return;
-    blend_entries<K, NV, TB>(out, count, tcell, tdata, eta_bits, cap, pp,
-                             blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+    // the control flags, the list length and the maximum are fetched
+    // together (one memory round trip) before anything depends on them
+    const int stop = from_ctrl ? (ctrl->done | ctrl->reject) : 0;
+    const unsigned int cnt = *count;
+    const unsigned long long eb = *eta_bits;
+    if (stop) return;
+    blend_entries<K, NV, TB>(out, cnt, tcell, tdata, eb, cap, pp, blockIdx.x * blockDim.x + threadIdx.x,
+                             gridDim.x * blockDim.x);
 }
 
 // Unfused filter / hybrid (per-call API): reads the unfiltered stage output

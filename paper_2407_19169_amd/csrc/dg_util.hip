@@ -4,11 +4,15 @@
 
 namespace dg {
 
-// One thread; runs between the stage kernels.
+// One thread; runs between the stage kernels.  The control block is read
+// into registers in one burst of loads, updated there and written back, so
+// its dependent branches cost no memory round trips.
 __global__ void step_ctrl_kernel(Ctrl* c, int finalize_only)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    step_ctrl_body(c, finalize_only);
+    Ctrl l = *c;
+    step_ctrl_body(&l, finalize_only);
+    *c = l;
 }
 
 hipError_t launch_step_ctrl(Ctrl* c, int finalize_only, hipStream_t st)
