@@ -340,9 +340,10 @@ __device__ __forceinline__ void trace_check(const Args1D<TB>& a, const T* ul, co
 template <int EQ, int K, typename TB, int MODE, int BS = 256>
 struct Stage1DLds {
     static constexpr int NV = Phys1D<EQ>::NV;
-    // phase 1 (traces, fluxes) and phase 2 (derivative traces) alias
+    // phase 1 (traces, fluxes) and phase 2 (mode 0, right derivative
+    // traces, later the left-interface jumps) alias
     static constexpr int PH1 = 2 * NV * BS * (int)sizeof(TB);
-    static constexpr int PH2 = NV * BS * 8 + 2 * (K + 1) * NV * BS * (int)sizeof(TB);
+    static constexpr int PH2 = NV * BS * 8 + (K + 1) * NV * BS * (int)sizeof(TB);
     static constexpr int bytes = MODE == 0 ? PH1 : (PH1 > PH2 ? PH1 : PH2);
 };
 
@@ -451,7 +452,7 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
     __syncthreads();
 
     // Residual and Shu-Osher combination -> unfiltered output (v0, vh).
-    const bool have_res = valid && tid >= 1 && tid <= 254;
+    const bool have_res = valid && tid >= 1 && tid <= BS - 2;
     double v0[NV];
     T vh[NV][KH];
 #pragma unroll
@@ -540,7 +541,7 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
         __syncthreads();  // phase-1 LDS reads are complete
         double* s0 = reinterpret_cast<double*>(lds);       // [NV][BS] mode 0
         T* sHR = reinterpret_cast<T*>(s0 + NV * BS);      // [K1][NV][BS] right high-mode part
-        T* sHL = sHR + K1 * NV * BS;                      // [K1][NV][BS] left high-mode part
+        T* sJ = sHR;                                      // then: jumps at the left interface
         T hR[K1][NV], hL[K1][NV];
 #pragma unroll
         for (int m = 0; m <= K; ++m)
@@ -555,39 +556,58 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
                 hR[m][v] = r;
                 hL[m][v] = l_;
                 sHR[(m * NV + v) * BS + tid] = r;
-                sHL[(m * NV + v) * BS + tid] = l_;
             }
 #pragma unroll
         for (int v = 0; v < NV; ++v) s0[v * BS + tid] = v0[v];
+        __syncthreads();
+
+        // |[d^m u]| at the left interface of lanes 1..BS-2 (the own cells and
+        // the first halo lane on the right): each interface jump is formed
+        // once, by the cell to its right, and handed to its left neighbour
+        // through LDS
+        const bool lbound = !a.periodic && c == 0, rbound = !a.periodic && c == n - 1;
+        const bool jlane = tid >= 1 && tid <= BS - 2;
+        T jl[K1][NV];
+#pragma unroll
+        for (int m = 0; m <= K; ++m)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                jl[m][v] = (T)0;
+                if (!jlane) continue;
+                if (lbound) {
+                    T inner = (m == 0 ? (T)v0[v] : (T)0) + hL[m][v];
+                    jl[m][v] = ghost_jump<T>(a.bc_lo, m, v, a.dir_lo[v], inner);
+                } else {
+                    T d = hL[m][v] - sHR[(m * NV + v) * BS + tid - 1];
+                    if (m == 0) d += (T)(v0[v] - s0[v * BS + tid - 1]);
+                    jl[m][v] = fabs(d);
+                }
+            }
+        __syncthreads();  // the right traces are consumed
+        if (jlane) {
+#pragma unroll
+            for (int m = 0; m <= K; ++m)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sJ[(m * NV + v) * BS + tid] = jl[m][v];
+        }
         __syncthreads();
 
         T eta_own = (T)0;
         if (own) {
             // S[l][v] = sum_{m<=l} m(m+1) 2^m (|[d^m]|_left + |[d^m]|_right)
             T J[K1][NV];
-            const bool lbound = !a.periodic && c == 0, rbound = !a.periodic && c == n - 1;
 #pragma unroll
             for (int m = 0; m <= K; ++m)
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
-                    T jl, jr;
-                    if (lbound) {
-                        T inner = (m == 0 ? (T)v0[v] : (T)0) + hL[m][v];
-                        jl = ghost_jump<T>(a.bc_lo, m, v, a.dir_lo[v], inner);
-                    } else {
-                        T d = hL[m][v] - sHR[(m * NV + v) * BS + tid - 1];
-                        if (m == 0) d += (T)(v0[v] - s0[v * BS + tid - 1]);
-                        jl = fabs(d);
-                    }
+                    T jr;
                     if (rbound) {
                         T inner = (m == 0 ? (T)v0[v] : (T)0) + hR[m][v];
                         jr = ghost_jump<T>(a.bc_hi, m, v, a.dir_hi[v], inner);
                     } else {
-                        T d = sHL[(m * NV + v) * BS + tid + 1] - hR[m][v];
-                        if (m == 0) d += (T)(s0[v * BS + tid + 1] - v0[v]);
-                        jr = fabs(d);
+                        jr = sJ[(m * NV + v) * BS + tid + 1];
                     }
-                    J[m][v] = jl + jr;
+                    J[m][v] = jl[m][v] + jr;
                 }
             // beta_j = |f'(u-bar_j)|, H-bar_j from the cell average; the
             // exponent sigma_j^l dt = beta dt / (h H) * max_s S^l_s (the
@@ -697,14 +717,8 @@ template <int EQ, int K, typename TB, int MODE, int BS>
 __global__ __launch_bounds__(BS) void stage1d_kernel(Args1D<TB> a)
 {
     // a finished run, or a step already rejected by the positivity limiter
-    // (flags and dt fetched together: one memory round trip)
-    int stop = 0;
-    double dt = a.dt_host;
-    if (a.dt_from_ctrl) {
-        stop = a.ctrl->done | a.ctrl->reject;
-        dt = a.ctrl->dt;
-    }
-    if (stop) return;
+    if (a.ctrl && a.dt_from_ctrl && (a.ctrl->done || a.ctrl->reject)) return;
+    const double dt = a.dt_from_ctrl ? a.ctrl->dt : a.dt_host;
     __shared__ __align__(16) unsigned char lds[Stage1DLds<EQ, K, TB, MODE, BS>::bytes];
     double lam, eta;
     stage1d_tile<EQ, K, TB, MODE, BS>(a, (int64_t)blockIdx.x, dt, lds, &lam, &eta);

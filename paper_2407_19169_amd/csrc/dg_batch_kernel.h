@@ -56,7 +56,7 @@ __device__ __forceinline__ StateView<TB> prob_view(void* base, const BatchProb& 
 }
 
 template <int K, typename TB, int MODE, int PP>
-__device__ void solve_problem(const BatchArgs& b, const BatchProb& pr, unsigned int pidx,
+__device__ __forceinline__ void solve_problem(const BatchArgs& b, const BatchProb& pr, unsigned int pidx,
                               unsigned char* lds, double* red, double* tree, double* sflux,
                               int* sreject)
 {
@@ -230,7 +230,7 @@ struct BatchLds {
 // budget of 3 spills, and measured slower).  The FP64 form is left free.
 template <typename TB, int PP>
 struct BatchWaves {
-    static constexpr int value = sizeof(TB) == 4 ? (PP ? 2 : 3) : 1;
+    static constexpr int value = sizeof(TB) == 4 ? 3 : 1;
 };
 
 template <typename TB, int MODE, int PP>
