@@ -300,3 +300,32 @@ def test_nonfinite_state_is_reported(dg, ref):
     assert rep.status in (dg.DG_ERR_POSITIVITY, dg.DG_ERR_NONFINITE)
     assert rep.first_bad_cell >= 0
     s.close()
+
+
+@pytest.mark.parametrize("filt,prec", [(1, 0), (2, 0), (1, 1)])
+def test_large_grid_tiles_run_parity(dg, ref, filt, prec):
+    """300000 cells (above the size where dg_run switches from 64- to
+    256-lane stage tiles), Shu-Osher profile, P2, 12 steps: FP64 within 1e-10
+    of the oracle everywhere; mixed cell averages within 1e-6 (relative L1)
+    and the ledger closed to FP64 roundoff."""
+    n = 300000
+    w = I.shu_osher(n, 2)
+    s = _solver(dg, 2, 2, n, -5.0, 5.0, (1, 1), filt, prec=prec)
+    s.set_state(w.u0)
+    rep = dg.dg_run(s.h, 1e30, 12)
+    got = s.get_state().cpu().numpy()
+    s.close()
+    P = _oracle(ref, 2, 2, n, -5.0, 5.0, (1, 1), filt)
+    want, orep, rc = ref.run1d(P, w.u0, 1e30, 12)
+    assert rc == 0 and rep.steps == orep.steps == 12
+    h = 10.0 / n
+    for v in range(3):
+        if prec == 0:
+            assert rel_linf(got[v], want[v]) <= 1e-10, v
+        else:
+            l1 = np.sum(np.abs(got[v, 0] - want[v, 0])) / np.sum(np.abs(want[v, 0]))
+            assert l1 < 1e-6, (v, l1)
+        q0 = h * w.u0[v, 0].sum()
+        assert abs(rep.ledger[v] + rep.boundary_flux[v] - q0) < 1e-12 * max(1.0, abs(q0))
+    if filt == 2:
+        assert rep.troubled_cells == orep.troubled_cells
