@@ -79,6 +79,11 @@ typedef enum { DG_FILTER_NONE = 0, DG_FILTER_JUMP = 1, DG_FILTER_HYBRID = 2 } dg
  * stored, and volume, flux and filter arithmetic run, in FP32. */
 typedef enum { DG_PREC_FP64 = 0, DG_PREC_MIXED = 1 } dg_precision;
 
+/* Interface flux (Sec. 3: the computations use local Lax-Friedrichs; HLL
+ * and HLLC are named there as alternatives).  HLL / HLLC: Euler only, with
+ * Davis's wave-speed estimates; HLLC restores the contact wave. */
+typedef enum { DG_FLUX_LLF = 0, DG_FLUX_HLL = 1, DG_FLUX_HLLC = 2 } dg_flux;
+
 typedef struct {
     int dim;                 /* 1 or 2                                            */
     int64_t n[2];            /* cells along x (and y); uniform mesh               */
@@ -120,6 +125,9 @@ typedef struct {
                                 orthogonal) and the residual keeps them at zero.  1D:
                                 both values name the same space.  Other values:
                                 DG_ERR_ARG. */
+    int flux;                /* dg_flux; 0 = local Lax-Friedrichs.  HLL / HLLC with a
+                                scalar equation or a batch: DG_ERR_UNSUPPORTED; other
+                                values: DG_ERR_ARG. */
 } dg_options;
 
 /* Filled by dg_run / dg_report_read. */

@@ -23,14 +23,15 @@ _LIB_PATH = os.path.join(_HERE, "libdgref.so")
 ADVECTION, BURGERS, EULER = 0, 1, 2
 PERIODIC, OUTFLOW, REFLECT, DIRICHLET = 0, 1, 2, 3
 FILTER_NONE, FILTER_JUMP, FILTER_HYBRID = 0, 1, 2
+FLUX_LLF, FLUX_HLL, FLUX_HLLC = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
-    """Compile ``dgref.c`` with gcc into ``libdgref.so`` (FP64, OpenMP)."""
+    """Compile the oracle's C sources with gcc into ``libdgref.so`` (FP64, OpenMP)."""
     if force or not os.path.exists(_LIB_PATH):
         cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC", "-shared",
                "-o", _LIB_PATH + ".tmp", os.path.join(_HERE, "dgref.c"),
-               os.path.join(_HERE, "dgref2d.c"), "-lm"]
+               os.path.join(_HERE, "dgref2d.c"), os.path.join(_HERE, "dgref_hll.c"), "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
     return _LIB_PATH
@@ -41,7 +42,7 @@ class Problem1D(C.Structure):
                 ("filter_dt", C.c_int), ("bc", C.c_int * 2), ("n", C.c_int64),
                 ("lo", C.c_double), ("hi", C.c_double), ("gamma", C.c_double),
                 ("adv_speed", C.c_double), ("cfl", C.c_double),
-                ("dirichlet", (C.c_double * 3) * 2), ("pp", C.c_int)]
+                ("dirichlet", (C.c_double * 3) * 2), ("pp", C.c_int), ("flux", C.c_int)]
 
 
 class Problem2D(C.Structure):
@@ -52,7 +53,8 @@ class Problem2D(C.Structure):
                 ("adv_speed", C.c_double * 2), ("cfl", C.c_double),
                 ("dirichlet", (C.c_double * 4) * 4), ("shock_x0", C.c_double),
                 ("shock_speed", C.c_double), ("post", C.c_double * 4), ("pre", C.c_double * 4),
-                ("cf_mesh", C.c_int), ("basis", C.c_int), ("cf_scale", C.c_double)]
+                ("cf_mesh", C.c_int), ("basis", C.c_int), ("cf_scale", C.c_double),
+                ("flux", C.c_int)]
 
 
 class Report(C.Structure):
@@ -98,9 +100,11 @@ def nvars(eq: int, dim: int = 1) -> int:
 
 
 def problem1d(eq, k, n, lo, hi, bc=(PERIODIC, PERIODIC), filter=FILTER_JUMP, cfl=0.1,
-              gamma=1.4, adv_speed=1.0, nq=0, filter_dt=0, dirichlet=None, pp=0) -> Problem1D:
+              gamma=1.4, adv_speed=1.0, nq=0, filter_dt=0, dirichlet=None, pp=0,
+              flux=0) -> Problem1D:
     P = Problem1D()
     P.pp = pp
+    P.flux = flux
     P.eq, P.k, P.nq, P.filter, P.filter_dt = eq, k, nq, filter, filter_dt
     P.bc[0], P.bc[1] = bc
     P.n, P.lo, P.hi, P.gamma, P.adv_speed, P.cfl = n, lo, hi, gamma, adv_speed, cfl
@@ -114,9 +118,10 @@ def problem1d(eq, k, n, lo, hi, bc=(PERIODIC, PERIODIC), filter=FILTER_JUMP, cfl
 def problem2d(eq, k, nx, ny, xlo, xhi, ylo, yhi, bc=(PERIODIC,) * 4, filter=FILTER_JUMP,
               cfl=0.1, gamma=1.4, adv_speed=(1.0, 1.0), nq=0, filter_dt=0,
               dirichlet=None, shock_x0=0.0, shock_speed=0.0, post=None, pre=None, cf_mesh=0,
-              basis=0, cf_scale=1.0) -> Problem2D:
+              basis=0, cf_scale=1.0, flux=0) -> Problem2D:
     P = Problem2D()
     P.cf_mesh, P.basis, P.cf_scale = cf_mesh, basis, cf_scale
+    P.flux = flux
     P.shock_x0, P.shock_speed = shock_x0, shock_speed
     for v in range(4):
         P.post[v] = float(post[v]) if post is not None else 0.0
@@ -191,6 +196,22 @@ def post1d(P: Problem1D, stage: int, dt: float, v: np.ndarray):
     _chk(lib().dgref_post1d(C.byref(P), stage, C.c_double(dt), _ptr(v), _ptr(out), C.byref(tr)),
          "post1d")
     return out, tr.value
+
+
+def numflux1d(P: Problem1D, ul, ur) -> np.ndarray:
+    """The problem's interface flux between the states ul | ur."""
+    a, b = (np.ascontiguousarray(x, dtype=np.float64) for x in (ul, ur))
+    f = np.zeros_like(a)
+    _chk(lib().dgref_numflux1d(C.byref(P), _ptr(a), _ptr(b), _ptr(f)), "numflux1d")
+    return f
+
+
+def numflux2d(P: Problem2D, direction: int, ul, ur) -> np.ndarray:
+    """The problem's flux across a face of normal +x (0) / +y (1)."""
+    a, b = (np.ascontiguousarray(x, dtype=np.float64) for x in (ul, ur))
+    f = np.zeros_like(a)
+    _chk(lib().dgref_numflux2d(C.byref(P), int(direction), _ptr(a), _ptr(b), _ptr(f)), "numflux2d")
+    return f
 
 
 def pp_limit1d(P: Problem1D, u: np.ndarray):

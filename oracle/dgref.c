@@ -220,6 +220,22 @@ static void llf1d(int eq, double gamma, double a, const double* ul, const double
     for (int v = 0; v < nv; ++v) fh[v] = 0.5 * (fl[v] + fr[v]) - 0.5 * alpha * (ur[v] - ul[v]);
 }
 
+/* The interface flux the problem asks for: LLF, or HLL / HLLC (Euler). */
+static void numflux1d(const dgref_problem1d* P, const double* ul, const double* ur, double* fh)
+{
+    if (P->eq == DGREF_EULER && P->flux != DGREF_FLUX_LLF)
+        dgref_hll_flux(P->flux, 3, 0, P->gamma, ul, ur, fh);
+    else
+        llf1d(P->eq, P->gamma, P->adv_speed, ul, ur, fh);
+}
+
+int dgref_numflux1d(const dgref_problem1d* P, const double* ul, const double* ur, double* fh)
+{
+    if (!P || P->flux < DGREF_FLUX_LLF || P->flux > DGREF_FLUX_HLLC) return DGREF_ERR_ARG;
+    numflux1d(P, ul, ur, fh);
+    return DGREF_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* 1D helpers                                                               */
 /* ------------------------------------------------------------------------ */
@@ -336,7 +352,7 @@ int dgref_residual1d(const dgref_problem1d* P, const double* u, double* L, doubl
     for (int64_t i = 0; i <= n; ++i) {
         double ul[MAXV], ur[MAXV], f[MAXV];
         iface1d(P, &B, u, i, 0, h, ul, ur);
-        llf1d(P->eq, P->gamma, P->adv_speed, ul, ur, f);
+        numflux1d(P, ul, ur, f);
         for (int v = 0; v < nv; ++v) fh[(size_t)v * (size_t)(n + 1) + (size_t)i] = f[v];
     }
 

@@ -25,6 +25,9 @@ extern "C" {
 enum { DGREF_ADVECTION = 0, DGREF_BURGERS = 1, DGREF_EULER = 2 };
 enum { DGREF_PERIODIC = 0, DGREF_OUTFLOW = 1, DGREF_REFLECT = 2, DGREF_DIRICHLET = 3 };
 enum { DGREF_FILTER_NONE = 0, DGREF_FILTER_JUMP = 1, DGREF_FILTER_HYBRID = 2 };
+/* Interface fluxes: local Lax-Friedrichs (the paper's computations), and
+ * HLL / HLLC (named in Sec. 3 as alternatives; Euler only). */
+enum { DGREF_FLUX_LLF = 0, DGREF_FLUX_HLL = 1, DGREF_FLUX_HLLC = 2 };
 
 /* Status bits of a run. */
 enum { DGREF_OK = 0, DGREF_ERR_ARG = -1, DGREF_ERR_NONFINITE = -4, DGREF_ERR_POSITIVITY = -5 };
@@ -44,6 +47,7 @@ typedef struct {
     double cfl;          /* dt = cfl * h / alpha                               */
     double dirichlet[2][3]; /* prescribed boundary states (conserved vars)     */
     int pp;              /* 1: positivity-preserving limiter after the filter   */
+    int flux;            /* DGREF_FLUX_*: interface flux (HLL / HLLC: Euler)    */
 } dgref_problem1d;
 
 typedef struct {
@@ -64,6 +68,7 @@ typedef struct {
                       Sec. 2.4; 0: they do not (see the readings in the 2D part) */
     int basis;     /* 0: Q^k tensor product; 1: P^k total degree (p + q <= k) */
     double cf_scale; /* multiplies (c_fx, c_fy); 0 means 1 */
+    int flux;      /* DGREF_FLUX_*: interface flux (HLL / HLLC: Euler) */
 } dgref_problem2d;
 
 typedef struct {
@@ -105,6 +110,11 @@ int dgref_hybrid1d(const dgref_problem1d* P, double dt, const double* v, double*
 int dgref_post1d(const dgref_problem1d* P, int stage, double dt, const double* v,
                  double* out, int64_t* troubled);
 int dgref_pp_limit1d(const dgref_problem1d* P, double* u);
+/* The interface flux of P between the states ul (left) and ur (right);
+ * 2D: across a face of normal +x (dir 0) or +y (dir 1). */
+int dgref_numflux1d(const dgref_problem1d* P, const double* ul, const double* ur, double* fh);
+int dgref_numflux2d(const dgref_problem2d* P, int dir, const double* ul, const double* ur,
+                    double* fh);
 int dgref_step1d(const dgref_problem1d* P, double dt, double* u, double* bflux,
                  int64_t* troubled);
 int dgref_run1d(const dgref_problem1d* P, double t_end, int64_t max_steps, double* u,

@@ -114,6 +114,25 @@ static void llf2d(const dgref_problem2d* P, int dir, const double* ul, const dou
     for (int v = 0; v < nv; ++v) fh[v] = 0.5 * (fl[v] + fr[v]) - 0.5 * a * (ur[v] - ul[v]);
 }
 
+/* The interface flux the problem asks for: LLF, or HLL / HLLC (Euler). */
+static void numflux2d(const dgref_problem2d* P, int dir, const double* ul, const double* ur,
+                      double* fh)
+{
+    if (P->eq == DGREF_EULER && P->flux != DGREF_FLUX_LLF)
+        dgref_hll_flux(P->flux, 4, dir, P->gamma, ul, ur, fh);
+    else
+        llf2d(P, dir, ul, ur, fh);
+}
+
+int dgref_numflux2d(const dgref_problem2d* P, int dir, const double* ul, const double* ur,
+                    double* fh)
+{
+    if (!P || P->flux < DGREF_FLUX_LLF || P->flux > DGREF_FLUX_HLLC || dir < 0 || dir > 1)
+        return DGREF_ERR_ARG;
+    numflux2d(P, dir, ul, ur, fh);
+    return DGREF_OK;
+}
+
 /* --------------------------------------------------------- evaluation -- */
 /* u at reference point given P_p(xi) values px[p] and P_q(eta) values py[q]. */
 static void point_value(const ctx2d* C, const double* u, int64_t ix, int64_t jy, const double* px,
@@ -222,7 +241,7 @@ static int64_t nbr(int64_t i, int64_t n, int periodic)
 }
 
 /* --------------------------------------------------------- residual -- */
-/* LLF flux through the x-face at the left (side 0) or right (side 1) of
+/* Interface flux through the x-face at the left (side 0) or right (side 1) of
  * cell (ix, jy) at the edge Gauss point b. */
 static void xface_flux(const ctx2d* C, double t, const double* u, int64_t ix, int64_t jy, int side,
                        int b, double* fh)
@@ -244,9 +263,9 @@ static void xface_flux(const ctx2d* C, double t, const double* u, int64_t ix, in
     else
         ghost2d(P, side, x, y, t, uin, uout);
     if (side)
-        llf2d(P, 0, uin, uout, fh);
+        numflux2d(P, 0, uin, uout, fh);
     else
-        llf2d(P, 0, uout, uin, fh);
+        numflux2d(P, 0, uout, uin, fh);
 }
 
 static void yface_flux(const ctx2d* C, double t, const double* u, int64_t ix, int64_t jy, int side,
@@ -269,9 +288,9 @@ static void yface_flux(const ctx2d* C, double t, const double* u, int64_t ix, in
     else
         ghost2d(P, 2 + side, x, y, t, uin, uout);
     if (side)
-        llf2d(P, 1, uin, uout, fh);
+        numflux2d(P, 1, uin, uout, fh);
     else
-        llf2d(P, 1, uout, uin, fh);
+        numflux2d(P, 1, uout, uin, fh);
 }
 
 /* Residual of one cell (Sec. 2.3 scheme without the viscous term, with

@@ -17,4 +17,9 @@ typedef struct {
 
 int dgref_make_basis(int k, int nq, dgref_basis* B);
 
+/* HLL (kind 1) / HLLC (kind 2) Euler flux across a face of normal `dir`
+ * (dgref_hll.c); nv = 3 (1D) or 4 (2D). */
+void dgref_hll_flux(int kind, int nv, int dir, double gamma, const double* UL, const double* UR,
+                    double* F);
+
 #endif

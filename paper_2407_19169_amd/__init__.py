@@ -27,6 +27,7 @@ DG_BC_PERIODIC, DG_BC_OUTFLOW, DG_BC_REFLECT, DG_BC_DIRICHLET = 0, 1, 2, 3
 DG_BC_DMR_WALL, DG_BC_DMR_TOP = 4, 5
 DG_FILTER_NONE, DG_FILTER_JUMP, DG_FILTER_HYBRID = 0, 1, 2
 DG_PREC_FP64, DG_PREC_MIXED = 0, 1
+DG_FLUX_LLF, DG_FLUX_HLL, DG_FLUX_HLLC = 0, 1, 2
 
 
 class dg_mesh(C.Structure):
@@ -40,7 +41,7 @@ class dg_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("filter", C.c_int), ("cfl", C.c_double),
                 ("gamma", C.c_double), ("adv_speed", C.c_double * 2),
                 ("quad_points", C.c_int), ("stream", C.c_void_p), ("cf_mesh_factor", C.c_int),
-                ("positivity", C.c_int), ("basis", C.c_int)]
+                ("positivity", C.c_int), ("basis", C.c_int), ("flux", C.c_int)]
 
 
 class dg_report(C.Structure):
@@ -138,8 +139,9 @@ def make_mesh(dim, n, lo, hi, bc, dirichlet=None, shock_x0=0.0, shock_speed=0.0,
 
 def make_options(precision=DG_PREC_FP64, filter=DG_FILTER_JUMP, cfl=0.1, gamma=1.4,
                  adv_speed=(1.0, 0.0), quad_points=0, stream=None, cf_mesh_factor=0,
-                 positivity=0, basis=0) -> dg_options:
+                 positivity=0, basis=0, flux=DG_FLUX_LLF) -> dg_options:
     o = dg_options()
+    o.flux = flux
     o.cf_mesh_factor = cf_mesh_factor
     o.positivity = positivity
     o.basis = basis

@@ -351,7 +351,7 @@ struct Stage1DLds {
 // Stage1DLds::bytes of shared memory.  Returns, per thread, the CFL
 // quantity of its output cell (*lam_out, 0 for halo / outside lanes) and
 // its hybrid indicator (*eta_out); reductions are left to the caller.
-template <int EQ, int K, typename TB, int MODE, int BS = 256>
+template <int EQ, int K, typename TB, int MODE, int BS = 256, bool HLLX = false>
 __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, double dt,
                                              unsigned char* lds, double* lam_out, double* eta_out)
 {
@@ -444,7 +444,7 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
             for (int v = 0; v < NV; ++v) left[v] = sTrR[v * BS + tid - 1];
         }
         T pl, pr;
-        llf1d<EQ, T>(left, tl, fL, a.phys, &pl, &pr);
+        llf1d<EQ, T, HLLX>(left, tl, fL, a.phys, &pl, &pr);
         if (EQ == EULER && a.check && sizeof(T) == 8) trace_check(a, left, tl, pl, pr, cc);
 #pragma unroll
         for (int v = 0; v < NV; ++v) sF[v * BS + tid] = fL[v];
@@ -465,7 +465,7 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
         if (!a.periodic && c == n - 1) {
             T right[NV], pl, pr;
             ghost_state<NV, T>(a.bc_hi, a.dir_hi, tr, right);
-            llf1d<EQ, T>(tr, right, fR, a.phys, &pl, &pr);
+            llf1d<EQ, T, HLLX>(tr, right, fR, a.phys, &pl, &pr);
             if (EQ == EULER && a.check && sizeof(T) == 8) trace_check(a, tr, right, pl, pr, cc);
         } else {
 #pragma unroll
@@ -713,7 +713,7 @@ __device__ __forceinline__ void blend_entries(StateView<TB> out, unsigned int cn
     }
 }
 
-template <int EQ, int K, typename TB, int MODE, int BS>
+template <int EQ, int K, typename TB, int MODE, int BS, bool HLLX>
 __global__ __launch_bounds__(BS) void stage1d_kernel(Args1D<TB> a)
 {
     // a finished run, or a step already rejected by the positivity limiter
@@ -721,7 +721,7 @@ __global__ __launch_bounds__(BS) void stage1d_kernel(Args1D<TB> a)
     const double dt = a.dt_from_ctrl ? a.ctrl->dt : a.dt_host;
     __shared__ __align__(16) unsigned char lds[Stage1DLds<EQ, K, TB, MODE, BS>::bytes];
     double lam, eta;
-    stage1d_tile<EQ, K, TB, MODE, BS>(a, (int64_t)blockIdx.x, dt, lds, &lam, &eta);
+    stage1d_tile<EQ, K, TB, MODE, BS, HLLX>(a, (int64_t)blockIdx.x, dt, lds, &lam, &eta);
     if (MODE == 2) {
         // max eta over the domain (wave reduction, one atomic per wave)
         const double e = wave_max(eta);
@@ -946,18 +946,27 @@ __global__ __launch_bounds__(256) void maxwave1d_kernel(StateView<TB> u, int64_t
 }
 
 // ------------------------------------------------------------ launchers --
-template <int EQ, int K, typename TB, int BS>
-static hipError_t launch_stage_bs(const Args1D<TB>& a, int mode, hipStream_t st)
+template <int EQ, int K, typename TB, int BS, bool HLLX>
+static hipError_t launch_stage_fx(const Args1D<TB>& a, int mode, hipStream_t st)
 {
     const int tile = mode == 0 ? BS - 2 : BS - 4;
     dim3 grid((unsigned)((a.n + tile - 1) / tile)), block(BS);
     if (mode == 0)
-        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 0, BS>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 0, BS, HLLX>), grid, block, 0, st, a);
     else if (mode == 1)
-        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 1, BS>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 1, BS, HLLX>), grid, block, 0, st, a);
     else
-        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 2, BS>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 2, BS, HLLX>), grid, block, 0, st, a);
     return hipGetLastError();
+}
+
+// The HLL family of fluxes (Euler) has kernels of its own.
+template <int EQ, int K, typename TB, int BS>
+static hipError_t launch_stage_bs(const Args1D<TB>& a, int mode, hipStream_t st)
+{
+    if constexpr (EQ == EULER)
+        if (a.phys.flux != FLUX_LLF) return launch_stage_fx<EQ, K, TB, BS, true>(a, mode, st);
+    return launch_stage_fx<EQ, K, TB, BS, false>(a, mode, st);
 }
 
 // Small grids (under about a thousand 256-cell tiles) use one-wavefront

@@ -72,13 +72,20 @@ struct Phys2D<EULER> {
     }
 };
 
-template <int EQ, typename T>
+// Interface flux across a face of normal +dir: local Lax-Friedrichs (the
+// default) or, in Euler kernels compiled with HLLX, HLL / HLLC (p.flux).
+template <int EQ, typename T, bool HLLX = false>
 __device__ __forceinline__ void llf2d(const T* ul, const T* ur, int dir, T* fh, const PhysParams& p)
 {
     constexpr int NV = Phys2D<EQ>::NV;
     T fl[NV], fr[NV];
     Phys2D<EQ>::flux(ul, dir, fl, p);
     Phys2D<EQ>::flux(ur, dir, fr, p);
+    if constexpr (EQ == EULER && HLLX) {
+        hll_euler<NV, T>(p.flux, dir == 1, ul, ur, fl, fr, Phys2D<EULER>::pressure(ul, p),
+                         Phys2D<EULER>::pressure(ur, p), (T)p.gamma, fh);
+        return;
+    }
     const T al = Phys2D<EQ>::speed(ul, dir, p), ar = Phys2D<EQ>::speed(ur, dir, p);
     const T alpha = al > ar ? al : ar;
 #pragma unroll
@@ -290,7 +297,7 @@ struct StageTile {
     static constexpr int NHE = FX * (FY + 1);  // horizontal edges
 };
 
-template <int EQ, int K, typename TB, bool PK>
+template <int EQ, int K, typename TB, bool PK, bool HLLX>
 __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
 {
     using P = Phys2D<EQ>;
@@ -440,7 +447,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
             const double xq = vert ? edge : along, yq = vert ? along : edge;
             if (!lo_ok) ghost_state2d<NV, TB, T>(a, vert ? 0 : 2, xq, yq, ts, ur, ul);
             if (!hi_ok) ghost_state2d<NV, TB, T>(a, vert ? 1 : 3, xq, yq, ts, ul, ur);
-            llf2d<EQ, T>(ul, ur, vert ? 0 : 1, f, a.phys);
+            llf2d<EQ, T, HLLX>(ul, ur, vert ? 0 : 1, f, a.phys);
         }
 #pragma unroll
         for (int q = 0; q < NV; ++q) fl[k][q] = f[q];
@@ -978,10 +985,15 @@ hipError_t launch_stage2d(int eq, int k, const Args2D<TB>& a, hipStream_t st)
     dim3 grid((unsigned)(((a.nx + fx - 1) / fx) * ((a.ny + fy - 1) / fy))), block(256);
 #define DG_CASE(E_, K_)                                                                   \
     if (eq == E_ && k == K_) {                                                            \
-        if (a.pk)                                                                         \
-            hipLaunchKernelGGL((stage2d_kernel<E_, K_, TB, (K_ > 0)>), grid, block, 0, st, a); \
+        const bool hx = E_ == EULER && a.phys.flux != 0;                                  \
+        if (a.pk && hx)                                                                   \
+            hipLaunchKernelGGL((stage2d_kernel<E_, K_, TB, (K_ > 0), (E_ == EULER)>), grid, block, 0, st, a); \
+        else if (a.pk)                                                                    \
+            hipLaunchKernelGGL((stage2d_kernel<E_, K_, TB, (K_ > 0), false>), grid, block, 0, st, a); \
+        else if (hx)                                                                      \
+            hipLaunchKernelGGL((stage2d_kernel<E_, K_, TB, false, (E_ == EULER)>), grid, block, 0, st, a); \
         else                                                                              \
-            hipLaunchKernelGGL((stage2d_kernel<E_, K_, TB, false>), grid, block, 0, st, a); \
+            hipLaunchKernelGGL((stage2d_kernel<E_, K_, TB, false, false>), grid, block, 0, st, a); \
         return hipGetLastError();                                                         \
     }
     DG_CASE(ADV, 0) DG_CASE(ADV, 1) DG_CASE(ADV, 2) DG_CASE(ADV, 3)

@@ -94,6 +94,7 @@ Args1D<TB> base_args(const dg_solver* s)
         a.dir_hi[v] = s->mesh.dirichlet[1][v];
     }
     a.phys.gamma = s->opt.gamma;
+    a.phys.flux = s->opt.flux;
     a.phys.a[0] = s->opt.adv_speed[0];
     a.phys.a[1] = s->opt.adv_speed[1];
     a.check = s->eq == DG_EQ_EULER;
@@ -136,6 +137,7 @@ Args2D<TB> base_args2d(const dg_solver* s)
     a.shock_x0 = s->mesh.shock_x0;
     a.shock_speed = s->mesh.shock_speed;
     a.phys.gamma = s->opt.gamma;
+    a.phys.flux = s->opt.flux;
     a.phys.a[0] = s->opt.adv_speed[0];
     a.phys.a[1] = s->opt.adv_speed[1];
     a.check = s->eq == DG_EQ_EULER;
@@ -578,6 +580,8 @@ int dg_create(const dg_mesh* mesh, int degree, int equation, const dg_options* o
     if (opt->quad_points != 0 && opt->quad_points != degree + 1) return DG_ERR_UNSUPPORTED;
     if (opt->positivity != 0 && opt->positivity != 1) return DG_ERR_ARG;
     if (opt->basis != 0 && opt->basis != 1) return DG_ERR_ARG;
+    if (opt->flux < DG_FLUX_LLF || opt->flux > DG_FLUX_HLLC) return DG_ERR_ARG;
+    if (opt->flux != DG_FLUX_LLF && equation != DG_EQ_EULER) return DG_ERR_UNSUPPORTED;
     if (opt->positivity && (equation != DG_EQ_EULER || mesh->dim != 1)) return DG_ERR_UNSUPPORTED;
     if (!(opt->cfl > 0.0)) return DG_ERR_ARG;
     if (equation == DG_EQ_EULER && !(opt->gamma > 1.0)) return DG_ERR_ARG;

@@ -96,6 +96,8 @@ int dg_batch_create(int nprob, dg_problem1d* probs, int equation, const dg_optio
     if (opt->filter == DG_FILTER_HYBRID) return DG_ERR_UNSUPPORTED;
     if (opt->positivity != 0 && opt->positivity != 1) return DG_ERR_ARG;
     if (opt->basis != 0 && opt->basis != 1) return DG_ERR_ARG;  // 1D: the same space
+    if (opt->flux < DG_FLUX_LLF || opt->flux > DG_FLUX_HLLC) return DG_ERR_ARG;
+    if (opt->flux != DG_FLUX_LLF) return DG_ERR_UNSUPPORTED;
     if (opt->precision != DG_PREC_FP64 && opt->precision != DG_PREC_MIXED) return DG_ERR_ARG;
     if (!(opt->cfl > 0.0) || !(opt->gamma > 1.0)) return DG_ERR_ARG;
     dg_batch* b = new (std::nothrow) dg_batch();

@@ -54,7 +54,12 @@ __host__ __device__ constexpr double jump_weight(int m)
 struct PhysParams {
     double gamma;
     double a[2];   // advection velocity
+    int flux;      // numerical flux (Euler): FLUX_LLF, FLUX_HLL, FLUX_HLLC
 };
+
+// Numerical fluxes: Sec. 3 computes with the local Lax-Friedrichs flux and
+// names HLL and HLLC as alternatives that work with the filter as well.
+enum { FLUX_LLF = 0, FLUX_HLL = 1, FLUX_HLLC = 2 };
 
 template <typename T>
 __device__ __forceinline__ T tsqrt(T x) { return sqrt(x); }
@@ -169,15 +174,92 @@ struct Phys1D<EULER> {
     }
 };
 
-// Local Lax-Friedrichs flux: 1/2 (f(a) + f(b)) - 1/2 max(|f'(a)|, |f'(b)|) (b - a).
-template <int EQ, typename T>
+// HLL and HLLC fluxes of the Euler equations across a face (Harten, Lax
+// and van Leer; Toro, Spruce and Speares), from the two states, their
+// physical fluxes fl, fr and pressures.  1D (NV = 3): the normal momentum
+// is component 1; 2D (NV = 4): component 1 (x faces) or 2 (ydir), the
+// other momentum being tangential.  Wave speeds are Davis's estimates
+// S_L = min(u_L - c_L, u_R - c_R), S_R = max(u_L + c_L, u_R + c_R).  HLL:
+//   (S_R f_L - S_L f_R + S_L S_R (U_R - U_L)) / (S_R - S_L) for S_L < 0 < S_R;
+// HLLC: the contact speed
+//   S* = (p_R - p_L + m_L (S_L - u_L) - m_R (S_R - u_R)) / (rho_L (S_L - u_L) - rho_R (S_R - u_R)),
+// and on the side K that holds the face f_K + S_K (U*_K - U_K) with
+//   U*_K = rho_K (S_K - u_K) / (S_K - S*) (1, S* [normal], v_K [tangential],
+//          E_K / rho_K + (S* - u_K) (S* + p_K / (rho_K (S_K - u_K)))).
+// Outside the fan the upwind flux is taken.  (Selects only: the face
+// direction may be a run-time value.)
+template <int NV, typename T>
+__device__ __forceinline__ void hll_euler(int kind, bool ydir, const T* ul, const T* ur, const T* fl,
+                                          const T* fr, T pl, T pr, T gamma, T* fh)
+{
+    const bool y = NV == 4 && ydir;
+    const T mL = y ? ul[2] : ul[1], mR = y ? ur[2] : ur[1];
+    const T uL = mL / ul[0], uR = mR / ur[0];
+    const T cL = tsqrt<T>(gamma * pl / ul[0]), cR = tsqrt<T>(gamma * pr / ur[0]);
+    // fmin / fmax: a sound speed that is NaN (a state with negative
+    // pressure) leaves the bound to the other state
+    const T sL = fmin(uL - cL, uR - cR);
+    const T sR = fmax(uL + cL, uR + cR);
+    if (!(sL < (T)0)) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fh[v] = fl[v];
+        return;
+    }
+    if (!(sR > (T)0)) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fh[v] = fr[v];
+        return;
+    }
+    if (kind == FLUX_HLL) {
+        const T inv = (T)1 / (sR - sL);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fh[v] = (sR * fl[v] - sL * fr[v] + sL * sR * (ur[v] - ul[v])) * inv;
+        return;
+    }
+    const T dL = ul[0] * (sL - uL), dR = ur[0] * (sR - uR);
+    const T sS = (pr - pl + mL * (sL - uL) - mR * (sR - uR)) / (dL - dR);
+    const bool left = !(sS < (T)0);
+    T uK[NV], fK[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        uK[v] = left ? ul[v] : ur[v];
+        fK[v] = left ? fl[v] : fr[v];
+    }
+    const T sK = left ? sL : sR, unK = left ? uL : uR, pK = left ? pl : pr, dK = left ? dL : dR;
+    const T fac = dK / (sK - sS);
+    T us[NV];
+    us[0] = fac;
+    if constexpr (NV == 4) {
+        const T vt = (y ? uK[1] : uK[2]) / uK[0];
+        us[1] = y ? fac * vt : fac * sS;
+        us[2] = y ? fac * sS : fac * vt;
+    } else {
+        us[1] = fac * sS;
+    }
+    us[NV - 1] = fac * (uK[NV - 1] / uK[0] + (sS - unK) * (sS + pK / dK));
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fh[v] = fK[v] + sK * (us[v] - uK[v]);
+}
+
+// Interface flux.  Local Lax-Friedrichs (the default):
+// 1/2 (f(a) + f(b)) - 1/2 max(|f'(a)|, |f'(b)|) (b - a); Euler kernels
+// compiled with HLLX take HLL or HLLC (p.flux) instead.  (A run-time choice
+// in the default kernels would cost them registers.)
+template <int EQ, typename T, bool HLLX = false>
 __device__ __forceinline__ void llf1d(const T* ul, const T* ur, T* fh, const PhysParams& p,
                                       T* pl = nullptr, T* pr = nullptr)
 {
     constexpr int NV = Phys1D<EQ>::NV;
     T fl[NV], fr[NV];
-    const T al = Phys1D<EQ>::flux_speed(ul, fl, p, pl);
-    const T ar = Phys1D<EQ>::flux_speed(ur, fr, p, pr);
+    T pl_ = (T)0, pr_ = (T)0;
+    const T al = Phys1D<EQ>::flux_speed(ul, fl, p, &pl_);
+    const T ar = Phys1D<EQ>::flux_speed(ur, fr, p, &pr_);
+    if (pl) *pl = pl_;
+    if (pr) *pr = pr_;
+    if constexpr (EQ == EULER && HLLX) {
+        hll_euler<NV, T>(p.flux, false, ul, ur, fl, fr, pl_, pr_, (T)p.gamma, fh);
+        return;
+    }
     T alpha = al > ar ? al : ar;
 #pragma unroll
     for (int v = 0; v < NV; ++v) fh[v] = (T)0.5 * (fl[v] + fr[v]) - (T)0.5 * alpha * (ur[v] - ul[v]);

@@ -1,0 +1,214 @@
+"""GPU parity of the HLL and HLLC interface fluxes (Euler; Sec. 3 names
+them as alternatives to local Lax-Friedrichs) against the oracle's fluxes,
+through the C ABI: per call (one stage plus the post-stage operator, FP64,
+relative L-infinity <= 1e-13) and over short runs (FP64 <= 1e-10), in 1D and
+2D, plus the option's argument checks."""
+import math
+
+import numpy as np
+import pytest
+
+import dg_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_2407_19169_amd as dg
+
+    return dg
+
+
+def rel_linf(got, want):
+    return float(np.max(np.abs(np.asarray(got) - np.asarray(want))) / max(np.max(np.abs(want)), 1e-300))
+
+
+def _euler1d_state(k, n, seed):
+    rng = np.random.default_rng(seed)
+    u = np.zeros((3, k + 1, n))
+    rho = 0.5 + rng.random(n)
+    vel = rng.uniform(-1.5, 1.5, n)
+    p = 0.3 + rng.random(n)
+    u[0, 0], u[1, 0], u[2, 0] = rho, rho * vel, p / 0.4 + 0.5 * rho * vel * vel
+    if k > 0:
+        u[:, 1:] = 0.05 * rng.standard_normal((3, k, n)) * np.abs(u[:, :1])
+    return u
+
+
+@pytest.mark.parametrize("flux", [1, 2])
+@pytest.mark.parametrize("k,n,bc", [(1, 257, (1, 1)), (2, 300, (0, 0)), (3, 254, (2, 2))])
+def test_per_call_1d(dg, ref, flux, k, n, bc):
+    import torch
+
+    lo, hi = -1.0, 2.0
+    dt = 0.02 * (hi - lo) / n
+    un, ua, ub = (_euler1d_state(k, n, s) for s in (1, 2, 3))
+    for filt in (0, 1, 2):
+        mesh = dg.make_mesh(1, (n,), (lo,), (hi,), bc)
+        s = dg.Solver(mesh, k, 2, dg.make_options(filter=filt, cfl=0.1, flux=flux))
+        P = ref.problem1d(2, k, n, lo, hi, bc=bc, filter=filt, cfl=0.1, flux=flux)
+        for stage, us in ((0, un), (1, ua), (2, ub)):
+            s.set_state(un)
+            if stage:
+                dg.buffer_view(s, stage).copy_(torch.as_tensor(us))
+            dg.dg_stage(s.h, stage, dt)
+            dg.dg_jump_filter(s.h, stage, dt)
+            torch.cuda.synchronize()
+            got = dg.buffer_view(s, {0: 1, 1: 2, 2: 0}[stage]).cpu().numpy()
+            want, _ = ref.post1d(P, stage, dt, ref.stage1d(P, stage, dt, un, us))
+            assert rel_linf(got, want) <= 1e-13, (flux, k, n, filt, stage)
+        s.close()
+
+
+@pytest.mark.parametrize("flux", [1, 2])
+@pytest.mark.parametrize("filt", [1, 2])
+def test_lax_run_1d(dg, ref, flux, filt):
+    """Lax problem, 200 cells, P2, outflow, 40 steps."""
+    w = I.lax(200, 2)
+    mesh = dg.make_mesh(1, (200,), (-1.0,), (1.0,), (1, 1))
+    s = dg.Solver(mesh, 2, 2, dg.make_options(filter=filt, cfl=0.1, flux=flux))
+    s.set_state(w.u0)
+    rep = dg.dg_run(s.h, 1e30, 40)
+    got = s.get_state().cpu().numpy()
+    s.close()
+    P = ref.problem1d(2, 2, 200, -1.0, 1.0, bc=(1, 1), filter=filt, cfl=0.1, flux=flux)
+    want, orep, rc = ref.run1d(P, w.u0, 1e30, 40)
+    assert rc == 0 and rep.steps == orep.steps == 40
+    for v in range(3):
+        assert rel_linf(got[v], want[v]) <= 1e-10, v
+        q0 = 0.01 * w.u0[v, 0].sum()
+        assert abs(rep.ledger[v] + rep.boundary_flux[v] - q0) < 1e-12 * max(1.0, abs(q0))
+
+
+def test_shu_osher_mixed_hllc(dg, ref):
+    """Shu-Osher, 20000 cells, P2 hybrid, HLLC, mixed precision, 200 steps:
+    cell averages within 1e-6 (relative L1) of the FP64 oracle."""
+    w = I.shu_osher(20000, 2)
+    mesh = dg.make_mesh(1, (w.n,), (w.lo,), (w.hi,), (1, 1))
+    s = dg.Solver(mesh, 2, 2, dg.make_options(precision=1, filter=2, cfl=w.cfl, flux=2))
+    s.set_state(w.u0)
+    rep = dg.dg_run(s.h, 1e30, 200)
+    got = s.get_state().cpu().numpy()
+    s.close()
+    P = ref.problem1d(2, 2, w.n, w.lo, w.hi, bc=(1, 1), filter=2, cfl=w.cfl, flux=2)
+    want, orep, rc = ref.run1d(P, w.u0, 1e30, 200)
+    assert rc == 0 and rep.steps == 200
+    for v in range(3):
+        l1 = np.sum(np.abs(got[v, 0] - want[v, 0])) / np.sum(np.abs(want[v, 0]))
+        assert l1 < 1e-6, (v, l1)
+
+
+def _random_euler2d(seed, k, ny, nx, amp=0.05):
+    rng = np.random.default_rng(seed)
+    u = np.zeros((4, (k + 1) ** 2, ny, nx))
+    u[:, 0] = I.conserved2d(1 + 0.5 * rng.random((ny, nx)), rng.uniform(-1.5, 1.5, (ny, nx)),
+                            rng.uniform(-1.5, 1.5, (ny, nx)), 1 + 0.5 * rng.random((ny, nx)))
+    if k > 0:
+        u[:, 1:] = amp * rng.standard_normal((4, (k + 1) ** 2 - 1, ny, nx)) * np.abs(u[:, :1])
+    return u
+
+
+@pytest.mark.parametrize("flux", [1, 2])
+@pytest.mark.parametrize("k,nx,ny,bcs", [(1, 33, 20, (1, 1, 2, 2)), (2, 20, 13, (0, 0, 0, 0)),
+                                         (3, 18, 35, (2, 2, 1, 1))])
+def test_per_call_2d(dg, ref, flux, k, nx, ny, bcs):
+    import torch
+
+    un, ua, ub = (_random_euler2d(s, k, ny, nx) for s in (1, 2, 3))
+    dt = 0.05 / nx
+    box = (0.0, 1.0, 0.0, 0.8)
+    mesh = dg.make_mesh(2, (nx, ny), (box[0], box[2]), (box[1], box[3]), bcs)
+    for filt in (0, 1, 2):
+        s = dg.Solver(mesh, k, 2, dg.make_options(filter=filt, cfl=0.1, flux=flux))
+        P = ref.problem2d(2, k, nx, ny, *box, bc=bcs, filter=filt, cfl=0.1, flux=flux)
+        for stage, us in ((0, un), (1, ua), (2, ub)):
+            s.set_state(un)
+            if stage:
+                dg.buffer_view(s, stage).copy_(torch.as_tensor(us))
+            dg.dg_stage(s.h, stage, dt)
+            dg.dg_jump_filter(s.h, stage, dt)
+            torch.cuda.synchronize()
+            got = dg.buffer_view(s, {0: 1, 1: 2, 2: 0}[stage]).cpu().numpy()
+            w = ref.stage2d(P, stage, dt, un, us, t=0.0)
+            want, _ = ref.post2d(P, stage, dt, w, t=(1.0, 0.5, 1.0)[stage] * dt)
+            for v in range(4):
+                assert rel_linf(got[v], want[v]) <= 1e-13, (flux, k, filt, stage, v)
+        s.close()
+
+
+@pytest.mark.parametrize("flux", [1])
+def test_quadrant_hybrid_run_2d(dg, ref, flux):
+    """Four-quadrant Riemann problem, 32x32, Q2, hybrid, HLL, 30 steps.  (With
+    HLLC, less dissipative, this case reaches a negative pressure in the
+    oracle too: the 2D path has no positivity limiter.)"""
+    w = I.quadrant2d(32, 2, seed=3002)
+    mesh = dg.make_mesh(2, (w.nx, w.ny), (w.xlo, w.ylo), (w.xhi, w.yhi), w.bc)
+    s = dg.Solver(mesh, 2, 2, dg.make_options(filter=2, cfl=w.cfl, flux=flux))
+    s.set_state(w.u0)
+    rep = dg.dg_run(s.h, 1e30, 30)
+    got = s.get_state().cpu().numpy()
+    s.close()
+    P = ref.problem2d(2, 2, w.nx, w.ny, w.xlo, w.xhi, w.ylo, w.yhi, bc=w.bc, filter=2, cfl=w.cfl,
+                      flux=flux)
+    want, orep, rc = ref.run2d(P, w.u0, 1e30, 30)
+    assert rc == 0 and rep.steps == 30
+    for v in range(4):
+        assert rel_linf(got[v], want[v]) <= 1e-10, v
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_vortex_hllc_run_2d(dg, ref, k):
+    """Isentropic vortex (seeded centre), 40x40, jump filter, HLLC, 60 steps."""
+    w = I.vortex2d(40, k, seed=3001)
+    mesh = dg.make_mesh(2, (w.nx, w.ny), (w.xlo, w.ylo), (w.xhi, w.yhi), w.bc)
+    s = dg.Solver(mesh, k, 2, dg.make_options(filter=1, cfl=w.cfl, flux=2))
+    s.set_state(w.u0)
+    rep = dg.dg_run(s.h, 1e30, 60)
+    got = s.get_state().cpu().numpy()
+    s.close()
+    P = ref.problem2d(2, k, w.nx, w.ny, w.xlo, w.xhi, w.ylo, w.yhi, bc=w.bc, filter=1, cfl=w.cfl,
+                      flux=2)
+    want, orep, rc = ref.run2d(P, w.u0, 1e30, 60)
+    assert rc == 0 and rep.steps == orep.steps == 60
+    for v in range(4):
+        assert rel_linf(got[v], want[v]) <= 1e-10, v
+
+
+def test_double_mach_small_hllc_run(dg, ref):
+    """Double Mach reflection, 64x16, Q2, jump filter, HLLC, 20 steps, with
+    the moving top boundary and the reflecting wall."""
+    w = I.double_mach(64, 16, 2)
+    post, pre = I.conserved2d(*w.extra["post"]), I.conserved2d(1.4, 0.0, 0.0, 1.0)
+    speed = w.extra["shock_speed"] / math.sin(math.pi / 3)
+    mesh = dg.make_mesh(2, (64, 16), (0.0, 0.0), (4.0, 1.0), (3, 1, 4, 5),
+                        dirichlet=[list(post)] * 4, shock_x0=1 / 6, shock_speed=speed,
+                        post=list(post), pre=list(pre))
+    s = dg.Solver(mesh, 2, 2, dg.make_options(filter=1, cfl=0.1, flux=2))
+    s.set_state(w.u0)
+    rep = dg.dg_run(s.h, 1e30, 20)
+    got = s.get_state().cpu().numpy()
+    s.close()
+    P = ref.problem2d(2, 2, 64, 16, 0.0, 4.0, 0.0, 1.0, bc=(3, 1, 4, 5), filter=1, cfl=0.1,
+                      dirichlet=[list(post)] * 4, shock_x0=1 / 6, shock_speed=speed, post=post,
+                      pre=pre, flux=2)
+    want, orep, rc = ref.run2d(P, w.u0, 1e30, 20)
+    assert rc == 0 and rep.status == 0
+    for v in range(4):
+        assert rel_linf(got[v], want[v]) <= 1e-10, v
+
+
+def test_flux_option_checked(dg):
+    mesh = dg.make_mesh(1, (16,), (0.0,), (1.0,), (0, 0))
+    with pytest.raises(dg.DGError) as e:
+        dg.Solver(mesh, 2, dg.DG_EQ_BURGERS, dg.make_options(flux=dg.DG_FLUX_HLLC))
+    assert e.value.code == dg.DG_ERR_UNSUPPORTED
+    with pytest.raises(dg.DGError) as e:
+        dg.Solver(mesh, 2, dg.DG_EQ_EULER, dg.make_options(flux=3))
+    assert e.value.code == dg.DG_ERR_ARG
+    with pytest.raises(dg.DGError) as e:
+        dg.Batch([(64, 1, -1.0, 1.0, 1, 1)], dg.make_options(flux=dg.DG_FLUX_HLL))
+    assert e.value.code == dg.DG_ERR_UNSUPPORTED
