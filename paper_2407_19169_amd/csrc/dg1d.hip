@@ -351,7 +351,7 @@ struct Stage1DLds {
 // Stage1DLds::bytes of shared memory.  Returns, per thread, the CFL
 // quantity of its output cell (*lam_out, 0 for halo / outside lanes) and
 // its hybrid indicator (*eta_out); reductions are left to the caller.
-template <int EQ, int K, typename TB, int MODE, int BS = 256, bool HLLX = false>
+template <int EQ, int K, typename TB, int MODE, int BS = 256, bool HLLX = false, int NST = 1>
 __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, double dt,
                                              unsigned char* lds, double* lam_out, double* eta_out)
 {
@@ -360,11 +360,14 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
     constexpr int NV = P::NV;
     constexpr int K1 = K + 1;
     constexpr int KH = K > 0 ? K : 1;
-    constexpr int HALO = MODE == 0 ? 1 : 2;
+    // NST = 3: the whole SSP-RK3 step (MODE 0 or 1) in one pass; each stage
+    // consumes H1 lanes of halo on each side (the flux, and the filter's
+    // neighbour traces)
+    static_assert(NST == 1 || (NST == 3 && MODE != 2), "the hybrid needs a global max per stage");
+    constexpr int H1 = MODE == 0 ? 1 : 2;
+    constexpr int HALO = H1 * NST;
     constexpr int TILE = BS - 2 * HALO;
     constexpr int Q = K + 1;
-
-    const int stage = a.stage;
     T* sTrR = reinterpret_cast<T*>(lds);                 // [NV][BS] right trace
     T* sF = sTrR + NV * BS;                             // [NV][BS] flux at left interface
 
@@ -389,9 +392,32 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
         for (int l = 0; l < KH; ++l) uh[v][l] = nh[v][l] = (T)0;
     }
     if (valid) {
-        load_cell<K, NV, TB>(a.us, cc, u0, uh);
-        if (stage > 0) load_cell<K, NV, TB>(a.un, cc, n0, nh);
+        if (NST == 1) {
+            load_cell<K, NV, TB>(a.us, cc, u0, uh);
+            if (a.stage > 0) load_cell<K, NV, TB>(a.un, cc, n0, nh);
+        } else {
+            load_cell<K, NV, TB>(a.un, cc, n0, nh);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                u0[v] = n0[v];
+#pragma unroll
+                for (int l = 0; l < KH; ++l) uh[v][l] = nh[v][l];
+            }
+        }
     }
+    const bool own = valid && c >= 0 && c < n && tid >= HALO && tid < BS - HALO;
+    double lam = 0.0;
+    T eta_own = (T)0;
+#pragma unroll 1
+    for (int st = 0; st < NST; ++st) {
+    const int stage = NST == 1 ? a.stage : st;
+    // lanes whose stage input is valid, and those whose output will be
+    const int in_lo = st * H1, in_hi = BS - 1 - st * H1;
+    const bool last = st == NST - 1;
+    // lanes whose output this stage produces: the final stage's own cells;
+    // before it every valid lane in range (periodic halo lanes included)
+    const bool own_s = last ? own : (valid && tid >= in_lo + H1 && tid <= in_hi - H1);
+    if (st > 0) __syncthreads();  // the previous stage's LDS reads are complete
 
     // Interface traces u(x^+_{j-1/2}) (left end) and u(x^-_{j+1/2}) (right end).
     T tl[NV], tr[NV];
@@ -410,7 +436,7 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
 
     // Positivity (Euler) of the stage input at the traces, in FP64.  The
     // FP64 path checks the pressures its interface fluxes compute instead.
-    if (EQ == EULER && valid && a.check && sizeof(T) != 8) {
+    if (EQ == EULER && valid && a.check && sizeof(T) != 8 && tid >= in_lo && tid <= in_hi) {
         double dl[NV], dr[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -435,7 +461,7 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
 
     // Flux at the left interface of this cell (once per interface).
     T fL[NV], fR[NV];
-    if (valid && tid > 0) {
+    if (valid && tid > in_lo && tid <= in_hi) {
         T left[NV];
         if (!a.periodic && c == 0) {
             ghost_state<NV, T>(a.bc_lo, a.dir_lo, tl, left);
@@ -452,7 +478,7 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
     __syncthreads();
 
     // Residual and Shu-Osher combination -> unfiltered output (v0, vh).
-    const bool have_res = valid && tid >= 1 && tid <= BS - 2;
+    const bool have_res = valid && tid >= in_lo + 1 && tid <= in_hi - 1;
     double v0[NV];
     T vh[NV][KH];
 #pragma unroll
@@ -473,12 +499,13 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
         }
         // Boundary fluxes for the conservation ledger (one writer each).
         if (a.bflux && !a.periodic && tid >= HALO && tid < BS - HALO) {
+            double* bf = a.bflux + (NST == 1 ? 0 : 8 * st);
             if (c == 0)
 #pragma unroll
-                for (int v = 0; v < NV; ++v) a.bflux[v] = (double)fL[v];
+                for (int v = 0; v < NV; ++v) bf[v] = (double)fL[v];
             if (c == n - 1)
 #pragma unroll
-                for (int v = 0; v < NV; ++v) a.bflux[4 + v] = (double)fR[v];
+                for (int v = 0; v < NV; ++v) bf[4 + v] = (double)fR[v];
         }
         // Volume term: int f(u_h) P_l'(xi) dxi by the (K+1)-point Gauss rule.
         T vol[NV][KH];
@@ -527,15 +554,20 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
         }
     }
 
-    const bool own = valid && c >= 0 && c < n && tid >= HALO && tid < BS - HALO;
-
-    double lam = 0.0;
     if constexpr (MODE == 0) {
-        if (own) {
-            lam = finish_cell<EQ, K, TB, NV>(a, c, v0, vh, true);
-            store_cell<K, NV, TB>(a.out, c, v0, vh);
+        if (last) {
+            if (own) {
+                lam = finish_cell<EQ, K, TB, NV>(a, c, v0, vh, true);
+                store_cell<K, NV, TB>(a.out, c, v0, vh);
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                u0[v] = v0[v];
+#pragma unroll
+                for (int l = 0; l < KH; ++l) uh[v][l] = vh[v][l];
+            }
         }
-        *eta_out = 0.0;
     } else {
         // ---- jump filter on the unfiltered output (needs neighbours) ----
         __syncthreads();  // phase-1 LDS reads are complete
@@ -566,7 +598,7 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
         // once, by the cell to its right, and handed to its left neighbour
         // through LDS
         const bool lbound = !a.periodic && c == 0, rbound = !a.periodic && c == n - 1;
-        const bool jlane = tid >= 1 && tid <= BS - 2;
+        const bool jlane = tid >= in_lo + 2 && tid <= in_hi - 1;
         T jl[K1][NV];
 #pragma unroll
         for (int m = 0; m <= K; ++m)
@@ -592,8 +624,7 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
         }
         __syncthreads();
 
-        T eta_own = (T)0;
-        if (own) {
+        if (own_s) {
             // S[l][v] = sum_{m<=l} m(m+1) 2^m (|[d^m]|_left + |[d^m]|_right)
             T J[K1][NV];
 #pragma unroll
@@ -648,8 +679,17 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
 #pragma unroll
                     for (int v = 0; v < NV; ++v) vh[v][l - 1] *= f;
                 }
-                lam = finish_cell<EQ, K, TB, NV>(a, c, v0, vh, true);
-                store_cell<K, NV, TB>(a.out, c, v0, vh);
+                if (last) {
+                    lam = finish_cell<EQ, K, TB, NV>(a, c, v0, vh, true);
+                    store_cell<K, NV, TB>(a.out, c, v0, vh);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        u0[v] = v0[v];
+#pragma unroll
+                        for (int l = 0; l < KH; ++l) uh[v][l] = vh[v][l];
+                    }
+                }
             } else {
                 // troubled cells are limited after the blend (pass B)
                 lam = finish_cell<EQ, K, TB, NV>(a, c, v0, vh, !(eta > (T)1));
@@ -665,13 +705,14 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
                     }
                 }
             }
-            if (a.E_out) {
+            if (a.E_out && last) {
 #pragma unroll
                 for (int l = 0; l <= K; ++l) a.E_out[c * K1 + l] = (double)E[l];
             }
         }
-        *eta_out = (double)eta_own;
     }
+    }  // stages
+    *eta_out = (double)eta_own;
     // CFL quantity of the output (FP64): its cell average, and with the
     // positivity limiter also the test points
     *lam_out = lam;
@@ -713,7 +754,7 @@ __device__ __forceinline__ void blend_entries(StateView<TB> out, unsigned int cn
     }
 }
 
-template <int EQ, int K, typename TB, int MODE, int BS, bool HLLX>
+template <int EQ, int K, typename TB, int MODE, int BS, bool HLLX, int NST>
 __global__ __launch_bounds__(BS) void stage1d_kernel(Args1D<TB> a)
 {
     // a finished run, or a step already rejected by the positivity limiter
@@ -721,7 +762,7 @@ __global__ __launch_bounds__(BS) void stage1d_kernel(Args1D<TB> a)
     const double dt = a.dt_from_ctrl ? a.ctrl->dt : a.dt_host;
     __shared__ __align__(16) unsigned char lds[Stage1DLds<EQ, K, TB, MODE, BS>::bytes];
     double lam, eta;
-    stage1d_tile<EQ, K, TB, MODE, BS, HLLX>(a, (int64_t)blockIdx.x, dt, lds, &lam, &eta);
+    stage1d_tile<EQ, K, TB, MODE, BS, HLLX, NST>(a, (int64_t)blockIdx.x, dt, lds, &lam, &eta);
     if (MODE == 2) {
         // max eta over the domain (wave reduction, one atomic per wave)
         const double e = wave_max(eta);
@@ -946,37 +987,45 @@ __global__ __launch_bounds__(256) void maxwave1d_kernel(StateView<TB> u, int64_t
 }
 
 // ------------------------------------------------------------ launchers --
+// nst = 1: one RK stage (a.stage); nst = 3: the whole step (MODE 0 or 1).
 template <int EQ, int K, typename TB, int BS, bool HLLX>
-static hipError_t launch_stage_fx(const Args1D<TB>& a, int mode, hipStream_t st)
+static hipError_t launch_stage_fx(const Args1D<TB>& a, int mode, int nst, hipStream_t st)
 {
-    const int tile = mode == 0 ? BS - 2 : BS - 4;
+    const int tile = BS - 2 * nst * (mode == 0 ? 1 : 2);
     dim3 grid((unsigned)((a.n + tile - 1) / tile)), block(BS);
-    if (mode == 0)
-        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 0, BS, HLLX>), grid, block, 0, st, a);
+    if (nst == 3) {
+        if (mode == 0)
+            hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 0, BS, HLLX, 3>), grid, block, 0, st, a);
+        else if (mode == 1)
+            hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 1, BS, HLLX, 3>), grid, block, 0, st, a);
+        else
+            return hipErrorInvalidValue;
+    } else if (mode == 0)
+        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 0, BS, HLLX, 1>), grid, block, 0, st, a);
     else if (mode == 1)
-        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 1, BS, HLLX>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 1, BS, HLLX, 1>), grid, block, 0, st, a);
     else
-        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 2, BS, HLLX>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 2, BS, HLLX, 1>), grid, block, 0, st, a);
     return hipGetLastError();
 }
 
 // The HLL family of fluxes (Euler) has kernels of its own.
 template <int EQ, int K, typename TB, int BS>
-static hipError_t launch_stage_bs(const Args1D<TB>& a, int mode, hipStream_t st)
+static hipError_t launch_stage_bs(const Args1D<TB>& a, int mode, int nst, hipStream_t st)
 {
     if constexpr (EQ == EULER)
-        if (a.phys.flux != FLUX_LLF) return launch_stage_fx<EQ, K, TB, BS, true>(a, mode, st);
-    return launch_stage_fx<EQ, K, TB, BS, false>(a, mode, st);
+        if (a.phys.flux != FLUX_LLF) return launch_stage_fx<EQ, K, TB, BS, true>(a, mode, nst, st);
+    return launch_stage_fx<EQ, K, TB, BS, false>(a, mode, nst, st);
 }
 
 // Small grids (under about a thousand 256-cell tiles) use one-wavefront
 // tiles: a single tile's dependent chain then bounds the stage, and smaller
 // tiles spread it over more compute units.
 template <int EQ, int K, typename TB>
-static hipError_t launch_stage(const Args1D<TB>& a, int mode, hipStream_t st)
+static hipError_t launch_stage(const Args1D<TB>& a, int mode, int nst, hipStream_t st)
 {
-    if (a.n < 252 * 1024) return launch_stage_bs<EQ, K, TB, 64>(a, mode, st);
-    return launch_stage_bs<EQ, K, TB, 256>(a, mode, st);
+    if (a.n < 252 * 1024) return launch_stage_bs<EQ, K, TB, 64>(a, mode, nst, st);
+    return launch_stage_bs<EQ, K, TB, 256>(a, mode, nst, st);
 }
 
 template <int EQ, int K, typename TB>
@@ -991,10 +1040,10 @@ static hipError_t launch_filter(const Args1D<TB>& a, int mode, hipStream_t st)
 }
 
 template <typename TB>
-hipError_t launch_stage1d(int eq, int k, const Args1D<TB>& a, int mode, hipStream_t st)
+hipError_t launch_stage1d(int eq, int k, const Args1D<TB>& a, int mode, hipStream_t st, int nst)
 {
 #define DG_CASE(E_, K_) \
-    if (eq == E_ && k == K_) return launch_stage<E_, K_, TB>(a, mode, st);
+    if (eq == E_ && k == K_) return launch_stage<E_, K_, TB>(a, mode, nst, st);
     DG_CASE(ADV, 0) DG_CASE(ADV, 1) DG_CASE(ADV, 2) DG_CASE(ADV, 3)
     DG_CASE(BURGERS, 0) DG_CASE(BURGERS, 1) DG_CASE(BURGERS, 2) DG_CASE(BURGERS, 3)
     DG_CASE(EULER, 0) DG_CASE(EULER, 1) DG_CASE(EULER, 2) DG_CASE(EULER, 3)
@@ -1069,7 +1118,7 @@ hipError_t launch_maxwave1d(int eq, StateView<TB> u, int64_t n, PhysParams phys,
 }
 
 #define DG_INST(TB)                                                                                 \
-    template hipError_t launch_stage1d<TB>(int, int, const Args1D<TB>&, int, hipStream_t);          \
+    template hipError_t launch_stage1d<TB>(int, int, const Args1D<TB>&, int, hipStream_t, int);     \
     template hipError_t launch_filter1d<TB>(int, int, const Args1D<TB>&, int, hipStream_t);         \
     template hipError_t launch_blend1d<TB>(int, int, StateView<TB>, const unsigned int*,            \
                                            const long long*, const double*,                        \

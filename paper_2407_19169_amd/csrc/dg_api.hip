@@ -267,6 +267,15 @@ int maxwave_impl(dg_solver* s, unsigned long long* acc, hipStream_t st)
 
 // Record G fused steps (rotation A->B, (B,A)->C, (C,A)->B; then the mirror)
 // on the capture stream.
+// 1D jump filter or no filter, without the positivity limiter: the three
+// stages of a step run in one launch on tiles with a 6-cell (3-cell) halo,
+// reading u^n once and writing u^{n+1} once.  (The hybrid needs a global max
+// per stage; the limiter's step rejection works per stage.)
+bool fused_step(const dg_solver* s)
+{
+    return s->dim == 1 && s->opt.filter != DG_FILTER_HYBRID && !s->opt.positivity;
+}
+
 template <typename TB>
 int record_steps(dg_solver* s, int G, hipStream_t st)
 {
@@ -314,6 +323,18 @@ int record_steps(dg_solver* s, int G, hipStream_t st)
                     }
                 }
             }
+            continue;
+        }
+        if (fused_step(s)) {
+            // the whole step in one launch: u^n (A) -> u^{n+1} (B)
+            Args1D<TB> a = base_args<TB>(s);
+            a.un = a.us = view_of<TB>(s, A);
+            a.out = view_of<TB>(s, B);
+            a.stage = 2;
+            a.dt_from_ctrl = 1;
+            a.bflux = &c->bstage[0][0];
+            a.alpha_acc = &c->alpha_bits;
+            DG_HIP(launch_stage1d<TB>(s->eq, s->k, a, fmode, st, 3));
             continue;
         }
         for (int stage = 0; stage < 3; ++stage) {
@@ -532,6 +553,20 @@ int time_impl(dg_solver* s, int stage, double dt, int reps, double* avg_us)
                              : launch_filter2d<TB>(s->eq, s->k, f, fmode == 1 ? 1 : 2, st);
         };
         return time_launches(s, scratch, reps, launch, avg_us);
+    }
+    if (stage == 6) {
+        // the fused step kernel of dg_run (u_n -> u_a)
+        if (!fused_step(s)) return DG_ERR_ARG;
+        Args1D<TB> a = base_args<TB>(s);
+        a.un = a.us = view_of<TB>(s, s->u[0]);
+        a.out = view_of<TB>(s, s->u[1]);
+        a.stage = 2;
+        a.dt_host = dt;
+        a.ctrl = scratch;
+        a.bflux = &scratch->bstage[0][0];
+        a.alpha_acc = &scratch->alpha_bits;
+        auto launch3 = [&]() { return launch_stage1d<TB>(s->eq, s->k, a, fmode, st, 3); };
+        return time_launches(s, scratch, reps, launch3, avg_us);
     }
     Args1D<TB> a = base_args<TB>(s);
     a.un = view_of<TB>(s, s->u[0]);
@@ -783,7 +818,9 @@ int dg_report_read(dg_solver* s, dg_report* rep)
 int dg_time_kernel(dg_solver* s, int stage, double dt, int reps, double* avg_us)
 {
     const int top = (s && s->dim == 2) ? 5 : 2;
-    if (!s || stage < 0 || stage > top || reps < 1 || !avg_us || !(dt >= 0.0)) return DG_ERR_ARG;
+    const bool step1d = s && s->dim == 1 && stage == 6;
+    if (!s || stage < 0 || (stage > top && !step1d) || reps < 1 || !avg_us || !(dt >= 0.0))
+        return DG_ERR_ARG;
     if (!s->bound) return DG_ERR_STATE;
     DG_HIP(hipStreamSynchronize(s->user_st));
     return is_fp64(s) ? time_impl<double>(s, stage, dt, reps, avg_us)

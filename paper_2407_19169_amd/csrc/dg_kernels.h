@@ -94,7 +94,10 @@ hipError_t launch_maxwave2d(int eq, StateView<TB> u, int64_t nx, int64_t ny, dou
                             hipStream_t st);
 
 template <typename TB>
-hipError_t launch_stage1d(int eq, int k, const Args1D<TB>& a, int mode, hipStream_t st);
+// nst = 3 (MODE 0 or 1 only): the three SSP-RK3 stages of a step in one
+// launch, u^n (a.un) -> u^{n+1} (a.out), intermediate stages in registers and
+// LDS, boundary fluxes of stage s at a.bflux + 8 s.
+hipError_t launch_stage1d(int eq, int k, const Args1D<TB>& a, int mode, hipStream_t st, int nst = 1);
 template <typename TB>
 hipError_t launch_filter1d(int eq, int k, const Args1D<TB>& a, int mode, hipStream_t st);
 template <typename TB>
