@@ -408,7 +408,9 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
     const bool own = valid && c >= 0 && c < n && tid >= HALO && tid < BS - HALO;
     double lam = 0.0;
     T eta_own = (T)0;
-#pragma unroll 1
+    // unrolled: the stage's coefficients and lane bounds become constants,
+    // which keeps the fused kernels' register counts down
+#pragma unroll
     for (int st = 0; st < NST; ++st) {
     const int stage = NST == 1 ? a.stage : st;
     // lanes whose stage input is valid, and those whose output will be
