@@ -213,8 +213,8 @@ int dg_last_exponents(dg_solver* s, double* E_dev);
  * stage (reads u_n, u_a, u_b; writes u_a or u_b).  2D: 0..2 the residual
  * kernel of that stage (writes the workspace), 3..5 the filter kernel
  * (jump: workspace -> u_a) or hybrid pass A (reads u_a).  1D `stage` 6: the
- * kernel that runs a whole step (jump filter or none, no positivity
- * limiter; u_n -> u_a); DG_ERR_ARG for other options.  u_n is never
+ * kernel that runs a whole step (jump filter or none; u_n -> u_a);
+ * DG_ERR_ARG with the hybrid limiter.  u_n is never
  * modified.  Synchronises. */
 int dg_time_kernel(dg_solver* s, int stage, double dt, int reps, double* avg_us);
 

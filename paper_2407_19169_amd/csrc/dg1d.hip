@@ -420,6 +420,12 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
     // before it every valid lane in range (periodic halo lanes included)
     const bool own_s = last ? own : (valid && tid >= in_lo + H1 && tid <= in_hi - H1);
     if (st > 0) __syncthreads();  // the previous stage's LDS reads are complete
+    // a fused step already flagged by the positivity limiter is discarded and
+    // retried: its later stages may compute from an inadmissible state and
+    // check nothing (every tile reading such a cell has flagged the step
+    // itself, since it recomputes its halo, before this barrier)
+    const bool chk = a.check && !(NST == 3 && st > 0 && a.reject &&
+                                  __hip_atomic_load(a.reject, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 
     // Interface traces u(x^+_{j-1/2}) (left end) and u(x^-_{j+1/2}) (right end).
     T tl[NV], tr[NV];
@@ -438,7 +444,7 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
 
     // Positivity (Euler) of the stage input at the traces, in FP64.  The
     // FP64 path checks the pressures its interface fluxes compute instead.
-    if (EQ == EULER && valid && a.check && sizeof(T) != 8 && tid >= in_lo && tid <= in_hi) {
+    if (EQ == EULER && valid && chk && sizeof(T) != 8 && tid >= in_lo && tid <= in_hi) {
         double dl[NV], dr[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -473,7 +479,7 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
         }
         T pl, pr;
         llf1d<EQ, T, HLLX>(left, tl, fL, a.phys, &pl, &pr);
-        if (EQ == EULER && a.check && sizeof(T) == 8) trace_check(a, left, tl, pl, pr, cc);
+        if (EQ == EULER && chk && sizeof(T) == 8) trace_check(a, left, tl, pl, pr, cc);
 #pragma unroll
         for (int v = 0; v < NV; ++v) sF[v * BS + tid] = fL[v];
     }
@@ -494,7 +500,7 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
             T right[NV], pl, pr;
             ghost_state<NV, T>(a.bc_hi, a.dir_hi, tr, right);
             llf1d<EQ, T, HLLX>(tr, right, fR, a.phys, &pl, &pr);
-            if (EQ == EULER && a.check && sizeof(T) == 8) trace_check(a, tr, right, pl, pr, cc);
+            if (EQ == EULER && chk && sizeof(T) == 8) trace_check(a, tr, right, pl, pr, cc);
         } else {
 #pragma unroll
             for (int v = 0; v < NV; ++v) fR[v] = sF[v * BS + tid + 1];
@@ -526,7 +532,7 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
                 uq[v] = s;
             }
             const T pq = P::flux_pressure(uq, fq, a.phys);
-            if (EQ == EULER && a.check && valid) {
+            if (EQ == EULER && chk && valid) {
                 if (!(uq[0] > (T)0) || !(pq > (T)0)) {
                     bool fin = isfinite((double)uq[0]) && isfinite((double)pq);
                     latch_error(a.ctrl, fin ? -5 : -4, cc);
@@ -563,6 +569,9 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
                 store_cell<K, NV, TB>(a.out, c, v0, vh);
             }
         } else {
+            // an intermediate stage of a fused step: the limiter as the
+            // single-stage kernel applies it to its output
+            if (own_s) finish_cell<EQ, K, TB, NV>(a, c, v0, vh, true);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 u0[v] = v0[v];
@@ -685,6 +694,7 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
                     lam = finish_cell<EQ, K, TB, NV>(a, c, v0, vh, true);
                     store_cell<K, NV, TB>(a.out, c, v0, vh);
                 } else {
+                    finish_cell<EQ, K, TB, NV>(a, c, v0, vh, true);
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         u0[v] = v0[v];

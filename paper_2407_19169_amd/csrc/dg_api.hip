@@ -267,13 +267,14 @@ int maxwave_impl(dg_solver* s, unsigned long long* acc, hipStream_t st)
 
 // Record G fused steps (rotation A->B, (B,A)->C, (C,A)->B; then the mirror)
 // on the capture stream.
-// 1D jump filter or no filter, without the positivity limiter: the three
-// stages of a step run in one launch on tiles with a 6-cell (3-cell) halo,
-// reading u^n once and writing u^{n+1} once.  (The hybrid needs a global max
-// per stage; the limiter's step rejection works per stage.)
+// 1D jump filter or no filter: the three stages of a step run in one launch
+// on tiles with a 6-cell (3-cell) halo, reading u^n once and writing u^{n+1}
+// once.  (The hybrid needs a global max per stage.)  With the positivity
+// limiter a stage that leaves an inadmissible average flags the step, whose
+// output is then replaced by u^n and retried, as with per-stage launches.
 bool fused_step(const dg_solver* s)
 {
-    return s->dim == 1 && s->opt.filter != DG_FILTER_HYBRID && !s->opt.positivity;
+    return s->dim == 1 && s->opt.filter != DG_FILTER_HYBRID;
 }
 
 template <typename TB>
@@ -335,6 +336,7 @@ int record_steps(dg_solver* s, int G, hipStream_t st)
             a.bflux = &c->bstage[0][0];
             a.alpha_acc = &c->alpha_bits;
             DG_HIP(launch_stage1d<TB>(s->eq, s->k, a, fmode, st, 3));
+            if (s->opt.positivity) DG_HIP(launch_restore(c, A, B, s->state_bytes, st));
             continue;
         }
         for (int stage = 0; stage < 3; ++stage) {
@@ -563,6 +565,7 @@ int time_impl(dg_solver* s, int stage, double dt, int reps, double* avg_us)
         a.stage = 2;
         a.dt_host = dt;
         a.ctrl = scratch;
+        a.reject = &scratch->reject;
         a.bflux = &scratch->bstage[0][0];
         a.alpha_acc = &scratch->alpha_bits;
         auto launch3 = [&]() { return launch_stage1d<TB>(s->eq, s->k, a, fmode, st, 3); };
@@ -575,6 +578,7 @@ int time_impl(dg_solver* s, int stage, double dt, int reps, double* avg_us)
     a.stage = stage;
     a.dt_host = dt;
     a.ctrl = scratch;
+    a.reject = &scratch->reject;
     a.bflux = &scratch->bstage[stage][0];
     a.alpha_acc = stage == 2 ? &scratch->alpha_bits : nullptr;
     a.eta_acc = &scratch->eta_bits[stage];

@@ -4,10 +4,10 @@
 // Each workgroup pulls whole problems from an atomic queue (the host orders
 // the queue longest-first, by cost n (k+1)^2 steps) and advances each one
 // through all of its time steps on its own: a CFL reduction over the
-// workgroup, then the three fused SSP-RK3 stage + jump-filter passes, each a
-// loop over the problem's 252-cell tiles with a workgroup barrier between
-// stages.  No grid-wide synchronisation is needed: a problem never leaves its
-// workgroup.
+// workgroup, then one pass over the problem's tiles that runs all three
+// SSP-RK3 stages (with the filter after each) of a 244-cell tile and its
+// 6-cell halo.  No grid-wide synchronisation is needed: a problem never
+// leaves its workgroup.
 // (included at the end of dg1d.hip: it reuses the 1D tile function)
 #include "dg_batch.h"
 
@@ -60,14 +60,15 @@ __device__ __forceinline__ void solve_problem(const BatchArgs& b, const BatchPro
                               unsigned char* lds, double* red, double* tree, double* sflux,
                               int* sreject)
 {
-    constexpr int TILE = MODE == 0 ? 254 : 252;
+    // the step's three stages in one pass: each consumes a halo of 1 (no
+    // filter) or 2 (filter) cells per side
+    constexpr int TILE3 = 256 - 2 * 3 * (MODE == 0 ? 1 : 2);
     StateView<TB> A = prob_view<TB>(b.u[0], pr, K);
     StateView<TB> B = prob_view<TB>(b.u[1], pr, K);
-    const StateView<TB> Cv = prob_view<TB>(b.u[2], pr, K);
     const StateView<TB> A0 = A, B0 = B;
     Ctrl* ctrl = &b.ctrl[pidx];
     const int64_t n = pr.n;
-    const int64_t ntiles = (n + TILE - 1) / TILE;
+    const int64_t ntiles3 = (n + TILE3 - 1) / TILE3;
 
     Args1D<TB> a;
     a.n = n;
@@ -127,32 +128,36 @@ __device__ __forceinline__ void solve_problem(const BatchArgs& b, const BatchPro
         }
         retry = false;
         double net[3] = {0.0, 0.0, 0.0};
-        for (int s = 0; s < 3; ++s) {
-            a.un = A;
-            a.us = s == 0 ? A : s == 1 ? B : Cv;
-            a.out = s == 1 ? Cv : B;
-            a.stage = s;
-            a.want_lam = s == 2;
-            if (threadIdx.x < 8) sflux[threadIdx.x] = 0.0;
+        {
+            // the whole step in one pass over the problem's tiles (6-cell
+            // halo): u^n (A) -> u^{n+1} (B), stages in registers and LDS
+            a.un = a.us = A;
+            a.out = B;
+            a.stage = 2;
+            a.want_lam = true;
+            if (threadIdx.x < 24) sflux[threadIdx.x] = 0.0;
             if (threadIdx.x == 0) *sreject = 0;
             __syncthreads();
             double lmax = 0.0;
-            for (int64_t tile = 0; tile < ntiles; ++tile) {
+            for (int64_t tile = 0; tile < ntiles3; ++tile) {
                 double l, e;
-                stage1d_tile<EULER, K, TB, MODE>(a, tile, dt, lds, &l, &e);
+                stage1d_tile<EULER, K, TB, MODE, 256, false, 3>(a, tile, dt, lds, &l, &e);
                 lmax = (l > lmax || l != l) ? l : lmax;
                 __syncthreads();  // the next tile reuses the LDS
             }
             if (*sreject) {
-                // positivity limiter: this stage left an inadmissible cell
+                // positivity limiter: a stage left an inadmissible cell
                 // average; u^n (buffer A) is untouched, so the step is
                 // simply run again with half the time step
                 retry = true;
-                break;
-            }
+            } else {
 #pragma unroll
-            for (int v = 0; v < 3; ++v) net[v] += kStageWeight[s] * (sflux[4 + v] - sflux[v]);
-            if (s == 2) alpha = block_max256(lmax, red);
+                for (int s = 0; s < 3; ++s)
+#pragma unroll
+                    for (int v = 0; v < 3; ++v)
+                        net[v] += kStageWeight[s] * (sflux[8 * s + 4 + v] - sflux[8 * s + v]);
+                alpha = block_max256(lmax, red);
+            }
         }
         if (retry) {
             __syncthreads();  // every lane has read the flag before it is cleared
@@ -240,7 +245,7 @@ void batch1d_kernel(BatchArgs b)
     __shared__ __align__(16) unsigned char lds[BatchLds<TB, MODE>::bytes];
     __shared__ double red[4];
     __shared__ double tree[256];
-    __shared__ double sflux[8];
+    __shared__ double sflux[24];  // boundary fluxes, lo[4] hi[4] per stage
     __shared__ int sreject;
     __shared__ unsigned int s_pi;
     for (;;) {
