@@ -87,6 +87,27 @@ __device__ __forceinline__ T combine_t(int stage, T un, T adv)
                       : (T)(1.0 / 3.0) * un + (T)(2.0 / 3.0) * adv;
 }
 
+// Hybrid pass B applied on load (deferred blend): a cell whose eta exceeds 1
+// gets u^l <- [omega + (1 - omega) exp(-E^l)] u^l, omega = (M - eta)/(M - 1),
+// with the same operations as the pass-B kernel applies to memory.
+template <int K, int NV, typename TB, typename D>
+__device__ __forceinline__ void deferred_blend(const D& bl, int64_t n, int64_t c,
+                                              TB (&uh)[NV][K > 0 ? K : 1])
+{
+    if constexpr (K > 0) {
+        const double eta = (double)bl.eta[c];
+        if (!(eta > 1.0)) return;
+        const double M = __longlong_as_double((long long)*bl.M);
+        const double w = (M - eta) / (M - 1.0);
+#pragma unroll
+        for (int l = 1; l <= K; ++l) {
+            const TB f = (TB)(w + (1.0 - w) * exp(-(double)bl.E[(int64_t)(l - 1) * n + c]));
+#pragma unroll
+            for (int v = 0; v < NV; ++v) uh[v][l - 1] *= f;
+        }
+    }
+}
+
 // ------------------------------------------------ positivity limiter --
 // Zhang and Shu's positivity-preserving limiter for the Euler equations,
 // applied after the filter (the paper's Sec. 3.2 examples with extreme
@@ -395,6 +416,8 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
         if (NST == 1) {
             load_cell<K, NV, TB>(a.us, cc, u0, uh);
             if (a.stage > 0) load_cell<K, NV, TB>(a.un, cc, n0, nh);
+            if (MODE == 2 && a.bl_us.eta) deferred_blend<K, NV, TB>(a.bl_us, n, cc, uh);
+            if (MODE == 2 && a.stage > 0 && a.bl_un.eta) deferred_blend<K, NV, TB>(a.bl_un, n, cc, nh);
         } else {
             load_cell<K, NV, TB>(a.un, cc, n0, nh);
 #pragma unroll
@@ -706,7 +729,15 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
                 // troubled cells are limited after the blend (pass B)
                 lam = finish_cell<EQ, K, TB, NV>(a, c, v0, vh, !(eta > (T)1));
                 store_cell<K, NV, TB>(a.out, c, v0, vh);
-                if (eta > (T)1) {
+                if (a.dv_eta) {
+                    // pass B deferred to the next reader of this output
+                    a.dv_eta[c] = (TB)eta;
+                    if (eta > (T)1) {
+                        atomicAdd(a.tcount, 1u);
+#pragma unroll
+                        for (int l = 1; l <= K; ++l) a.dv_E[(int64_t)(l - 1) * n + c] = (TB)E[l];
+                    }
+                } else if (eta > (T)1) {
                     unsigned int slot = atomicAdd(a.tcount, 1u);
                     if ((long long)slot < a.tcap) {
                         a.tcell[slot] = c;
@@ -772,6 +803,7 @@ __global__ __launch_bounds__(BS) void stage1d_kernel(Args1D<TB> a)
     // a finished run, or a step already rejected by the positivity limiter
     if (a.ctrl && a.dt_from_ctrl && (a.ctrl->done || a.ctrl->reject)) return;
     const double dt = a.dt_from_ctrl ? a.ctrl->dt : a.dt_host;
+    if (a.zero_bits && blockIdx.x == 0 && threadIdx.x == 0) *a.zero_bits = 0;
     __shared__ __align__(16) unsigned char lds[Stage1DLds<EQ, K, TB, MODE, BS>::bytes];
     double lam, eta;
     stage1d_tile<EQ, K, TB, MODE, BS, HLLX, NST>(a, (int64_t)blockIdx.x, dt, lds, &lam, &eta);
@@ -804,6 +836,20 @@ __global__ __launch_bounds__(256) void blend1d_kernel(StateView<TB> out, const u
     if (stop) return;
     blend_entries<K, NV, TB>(out, cnt, tcell, tdata, eb, cap, pp, blockIdx.x * blockDim.x + threadIdx.x,
                              gridDim.x * blockDim.x);
+}
+
+// The blend a state still owes (deferred hybrid pass B), applied in place.
+template <int K, int NV, typename TB>
+__global__ __launch_bounds__(256) void deferred_blend_kernel(StateView<TB> u, int64_t n,
+                                                             typename Args1D<TB>::Deferred bl)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    double u0[NV];
+    TB uh[NV][K > 0 ? K : 1];
+    load_cell<K, NV, TB>(u, c, u0, uh);
+    deferred_blend<K, NV, TB>(bl, n, c, uh);
+    store_cell<K, NV, TB>(u, c, u0, uh);
 }
 
 // Unfused filter / hybrid (per-call API): reads the unfiltered stage output
@@ -1097,6 +1143,22 @@ hipError_t launch_blend1d(int nv, int k, StateView<TB> out, const unsigned int* 
 }
 
 template <typename TB>
+hipError_t launch_deferred_blend1d(int nv, int k, StateView<TB> u, int64_t n,
+                                   typename Args1D<TB>::Deferred bl, hipStream_t st)
+{
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+#define DG_CASE(NV_, K_)                                                                          \
+    if (nv == NV_ && k == K_) {                                                                   \
+        hipLaunchKernelGGL((deferred_blend_kernel<K_, NV_, TB>), grid, block, 0, st, u, n, bl);   \
+        return hipGetLastError();                                                                 \
+    }
+    DG_CASE(1, 0) DG_CASE(1, 1) DG_CASE(1, 2) DG_CASE(1, 3)
+    DG_CASE(3, 0) DG_CASE(3, 1) DG_CASE(3, 2) DG_CASE(3, 3)
+#undef DG_CASE
+    return hipErrorInvalidValue;
+}
+
+template <typename TB>
 hipError_t launch_blend_all1d(int nv, int k, StateView<TB> w, StateView<TB> out, int64_t n,
                               const double* E, const double* eta,
                               const unsigned long long* eta_bits, unsigned int* tcount,
@@ -1136,6 +1198,8 @@ hipError_t launch_maxwave1d(int eq, StateView<TB> u, int64_t n, PhysParams phys,
                                            const long long*, const double*,                        \
                                            const unsigned long long*, const Ctrl*, int, int64_t,   \
                                            PPArgs, hipStream_t);                                   \
+    template hipError_t launch_deferred_blend1d<TB>(int, int, StateView<TB>, int64_t,              \
+                                                    typename Args1D<TB>::Deferred, hipStream_t);   \
     template hipError_t launch_blend_all1d<TB>(int, int, StateView<TB>, StateView<TB>, int64_t,     \
                                                const double*, const double*,                       \
                                                const unsigned long long*, unsigned int*, PPArgs,   \

@@ -26,6 +26,7 @@ struct dg_solver {
     double h[2], inv_h[2];
     size_t state_bytes, ws_bytes;
     size_t off_w, off_E, off_eta, off_tcell, off_tdata, off_aux;
+    size_t off_dv, dv_slot;  // deferred hybrid blend: 4 slots of eta[n] + E[k][n]
     void* u[3];
     unsigned char* ws;
     bool bound;
@@ -267,6 +268,26 @@ int maxwave_impl(dg_solver* s, unsigned long long* acc, hipStream_t st)
 
 // Record G fused steps (rotation A->B, (B,A)->C, (C,A)->B; then the mirror)
 // on the capture stream.
+// 1D hybrid without the positivity limiter: pass B is not a kernel of its
+// own; pass A records eta and the exponents per cell, and every stage that
+// loads a state owing its blend applies it on load (deferred_blend).  Slots
+// 0 and 1 hold stages 0 and 1 of a step, slots 2 and 3 stage 2 of even and
+// odd steps (u^n of the next step still owes that blend).
+bool deferred_blend_on(const dg_solver* s) { return s->dv_slot != 0; }
+
+template <typename TB>
+typename Args1D<TB>::Deferred dv_view(const dg_solver* s, int slot)
+{
+    typename Args1D<TB>::Deferred d;
+    TB* base = reinterpret_cast<TB*>(s->ws + s->off_dv + (size_t)slot * s->dv_slot);
+    d.eta = base;
+    d.E = base + s->ncell;
+    double* aux = reinterpret_cast<double*>(s->ws + s->off_aux);
+    Ctrl* c = reinterpret_cast<Ctrl*>(s->ws);
+    d.M = slot < 2 ? &c->eta_bits[slot] : reinterpret_cast<const unsigned long long*>(aux + 9 + slot);
+    return d;
+}
+
 // 1D jump filter or no filter: the three stages of a step run in one launch
 // on tiles with a 6-cell (3-cell) halo, reading u^n once and writing u^{n+1}
 // once.  (The hybrid needs a global max per stage.)  With the positivity
@@ -339,6 +360,8 @@ int record_steps(dg_solver* s, int G, hipStream_t st)
             if (s->opt.positivity) DG_HIP(launch_restore(c, A, B, s->state_bytes, st));
             continue;
         }
+        const bool dfr = deferred_blend_on(s);
+        const int prev2 = 2 + ((i + 1) & 1), cur2 = 2 + (i & 1);
         for (int stage = 0; stage < 3; ++stage) {
             Args1D<TB> a = base_args<TB>(s);
             a.un = view_of<TB>(s, A);
@@ -352,7 +375,20 @@ int record_steps(dg_solver* s, int G, hipStream_t st)
             a.tcount = &c->tcount[stage];
             a.tcell = tcell;
             a.tdata = tdata;
+            if (dfr) {
+                // u^n owes the blend of the previous step's last stage; u^(s)
+                // (s >= 1) the blend of stage s - 1 of this step
+                const auto dv_out = dv_view<TB>(s, stage < 2 ? stage : cur2);
+                a.dv_eta = const_cast<TB*>(dv_out.eta);
+                a.dv_E = const_cast<TB*>(dv_out.E);
+                a.bl_un = dv_view<TB>(s, prev2);
+                a.bl_us = stage == 0 ? a.bl_un : dv_view<TB>(s, stage - 1);
+                if (stage == 2) a.eta_acc = const_cast<unsigned long long*>(dv_out.M);
+                // this step's last-stage maximum is cleared before stage 2
+                if (stage == 1) a.zero_bits = const_cast<unsigned long long*>(dv_view<TB>(s, cur2).M);
+            }
             DG_HIP(launch_stage1d<TB>(s->eq, s->k, a, fmode, st));
+            if (dfr) continue;
             if (fmode == 2)
                 DG_HIP(launch_blend1d<TB>(s->nv, s->k, a.out, &c->tcount[stage], tcell, tdata,
                                           &c->eta_bits[stage], c, 1, s->ncell,
@@ -458,6 +494,9 @@ int run_impl(dg_solver* s, double t_end, int64_t max_steps, dg_report* rep)
     }
     int rc = maxwave_impl<TB>(s, &ctrl_of(s)->alpha_bits, st);
     if (rc) return rc;
+    // deferred hybrid blend: the run's first step owes no blend on u^n
+    if (deferred_blend_on(s))
+        DG_HIP(hipMemsetAsync(s->ws + s->off_dv + 3 * s->dv_slot, 0, s->ncell * sizeof(TB), st));
     // Replays: batches double in size between control reads, never beyond
     // the replays the remaining step budget needs.  With the positivity
     // limiter a rejected step is retried, so the budget is re-read.
@@ -482,8 +521,13 @@ int run_impl(dg_solver* s, double t_end, int64_t max_steps, dg_report* rep)
     DG_HIP(hipMemcpyAsync(&c, ctrl_of(s), sizeof c, hipMemcpyDeviceToHost, st));
     DG_HIP(hipStreamSynchronize(st));
     // every executed step (finalised or rejected) swaps the buffer roles
-    if ((c.steps - steps0 + c.restarts - restarts0) & 1)
+    const long long executed = c.steps - steps0 + c.restarts - restarts0;
+    if (executed & 1)
         DG_HIP(hipMemcpyAsync(s->u[0], s->u[1], s->state_bytes, hipMemcpyDeviceToDevice, st));
+    // deferred hybrid blend: the last step's output still owes its blend
+    if (deferred_blend_on(s) && executed > 0)
+        DG_HIP(launch_deferred_blend1d<TB>(s->nv, s->k, view_of<TB>(s, s->u[0]), s->ncell,
+                                           dv_view<TB>(s, 2 + (int)((executed - 1) & 1)), st));
     return report_impl<TB>(s, rep);
 }
 
@@ -679,6 +723,13 @@ int dg_create(const dg_mesh* mesh, int degree, int equation, const dg_options* o
     off += align256((size_t)s->ncell * (s->lmax + 1) * sizeof(double));
     s->off_aux = off;
     off += kAuxBytes;
+    s->off_dv = off;
+    s->dv_slot = 0;
+    if (mesh->dim == 1 && opt->filter == DG_FILTER_HYBRID && !opt->positivity) {
+        const size_t tb = opt->precision == DG_PREC_FP64 ? sizeof(double) : sizeof(float);
+        s->dv_slot = align256((size_t)s->ncell * (degree + 1) * tb);
+        off += 4 * s->dv_slot;
+    }
     s->ws_bytes = off;
     s->user_st = static_cast<hipStream_t>(opt->stream);
     if (hipStreamCreateWithFlags(&s->run_st, hipStreamNonBlocking) != hipSuccess) {

@@ -35,6 +35,18 @@ struct Args1D {
     int want_lam;                   // return the CFL quantity without alpha_acc (batch)
     int pp;                         // Euler: positivity-preserving limiter after the filter
     int* reject;                    // pp: set when an output cell average is inadmissible
+    // Hybrid with pass B deferred to the reader: pass A writes eta (every own
+    // cell) and the exponents (troubled cells) per cell to dv_eta / dv_E
+    // ([l-1][cell]); a stage that loads a state still owing its blend
+    // applies it on load (bl_us for u^(s), bl_un for u^n).
+    TB* dv_eta;                     // nullable
+    TB* dv_E;
+    struct Deferred {
+        const TB* eta;              // nullable: no blend owed
+        const TB* E;
+        const unsigned long long* M;  // domain max of eta of that stage
+    } bl_us, bl_un;
+    unsigned long long* zero_bits;  // nullable: cleared by the first thread of the launch
 };
 
 // Positivity limiter inputs of the blend kernels (hybrid pass B and the
@@ -105,6 +117,10 @@ hipError_t launch_blend1d(int nv, int k, StateView<TB> out, const unsigned int* 
                           const long long* tcell, const double* tdata,
                           const unsigned long long* eta_bits, const Ctrl* ctrl, int from_ctrl,
                           int64_t max_entries, PPArgs pp, hipStream_t st);
+// The blend a state still owes (deferred hybrid pass B), applied in place.
+template <typename TB>
+hipError_t launch_deferred_blend1d(int nv, int k, StateView<TB> u, int64_t n,
+                                   typename Args1D<TB>::Deferred bl, hipStream_t st);
 template <typename TB>
 hipError_t launch_blend_all1d(int nv, int k, StateView<TB> w, StateView<TB> out, int64_t n,
                               const double* E, const double* eta,
