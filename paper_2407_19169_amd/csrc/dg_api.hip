@@ -629,6 +629,15 @@ int time_impl(dg_solver* s, int stage, double dt, int reps, double* avg_us)
     a.tcount = &scratch->tcount[stage];
     a.tcell = reinterpret_cast<long long*>(s->ws + s->off_tcell);
     a.tdata = reinterpret_cast<double*>(s->ws + s->off_tdata);
+    if (fmode == 2 && deferred_blend_on(s)) {
+        // as dg_run launches it: eta / exponents per cell out, blends owed by
+        // the inputs applied on load (their slots hold the last run's values)
+        const auto dv_out = dv_view<TB>(s, stage);
+        a.dv_eta = const_cast<TB*>(dv_out.eta);
+        a.dv_E = const_cast<TB*>(dv_out.E);
+        a.bl_un = dv_view<TB>(s, 3);
+        a.bl_us = stage == 0 ? a.bl_un : dv_view<TB>(s, stage - 1);
+    }
     auto launch = [&]() { return launch_stage1d<TB>(s->eq, s->k, a, fmode, st); };
     return time_launches(s, scratch, reps, launch, avg_us);
 }
@@ -778,6 +787,12 @@ int dg_bind(dg_solver* s, void* u_n, void* u_a, void* u_b, void* workspace)
     c.first_bad = -1;
     DG_HIP(hipStreamSynchronize(s->user_st));
     DG_HIP(hipMemcpy(workspace, &c, sizeof c, hipMemcpyHostToDevice));
+    // deferred hybrid blend: no slot owes a blend until a stage writes it
+    if (deferred_blend_on(s)) {
+        const size_t tb = is_fp64(s) ? sizeof(double) : sizeof(float);
+        for (int slot = 0; slot < 4; ++slot)
+            DG_HIP(hipMemset(s->ws + s->off_dv + (size_t)slot * s->dv_slot, 0, s->ncell * tb));
+    }
     s->bound = true;
     return DG_OK;
 }
