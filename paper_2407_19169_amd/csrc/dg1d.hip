@@ -90,18 +90,45 @@ __device__ __forceinline__ T combine_t(int stage, T un, T adv)
 // Hybrid pass B applied on load (deferred blend): a cell whose eta exceeds 1
 // gets u^l <- [omega + (1 - omega) exp(-E^l)] u^l, omega = (M - eta)/(M - 1),
 // with the same operations as the pass-B kernel applies to memory.
-template <int K, int NV, typename TB, typename D>
-__device__ __forceinline__ void deferred_blend(const D& bl, int64_t n, int64_t c,
-                                              TB (&uh)[NV][K > 0 ? K : 1])
+// What one cell's blend reads: eta, the exponents and the stage maximum M
+// (read whether or not the cell is troubled, with the cell's state).
+template <int K, typename TB>
+struct BlendIn {
+    double eta, M;
+    TB e[K > 0 ? K : 1];
+};
+
+template <int K, typename TB, typename D>
+__device__ __forceinline__ BlendIn<K, TB> blend_fetch(const D& bl, int64_t n, int64_t c)
+{
+    BlendIn<K, TB> b;
+    b.eta = (double)bl.eta[c];
+#pragma unroll
+    for (int l = 1; l <= K; ++l) b.e[l - 1] = bl.E[(int64_t)(l - 1) * n + c];
+    b.M = __longlong_as_double((long long)*bl.M);
+    return b;
+}
+
+// An empty asm statement that uses the fetched values: the compiler cannot
+// sink their loads into the troubled-cell branch, so they travel with the
+// state loads instead of costing troubled cells a second trip to memory.
+template <int K, typename TB>
+__device__ __forceinline__ void blend_pin(const BlendIn<K, TB>& b)
+{
+    asm volatile("" ::"v"(b.eta), "s"(b.M));
+#pragma unroll
+    for (int l = 0; l < K; ++l) asm volatile("" ::"v"(b.e[l]));
+}
+
+template <int K, int NV, typename TB>
+__device__ __forceinline__ void blend_apply(const BlendIn<K, TB>& b, TB (&uh)[NV][K > 0 ? K : 1])
 {
     if constexpr (K > 0) {
-        const double eta = (double)bl.eta[c];
-        if (!(eta > 1.0)) return;
-        const double M = __longlong_as_double((long long)*bl.M);
-        const double w = (M - eta) / (M - 1.0);
+        if (!(b.eta > 1.0)) return;
+        const double w = (b.M - b.eta) / (b.M - 1.0);
 #pragma unroll
         for (int l = 1; l <= K; ++l) {
-            const TB f = (TB)(w + (1.0 - w) * exp(-(double)bl.E[(int64_t)(l - 1) * n + c]));
+            const TB f = (TB)(w + (1.0 - w) * exp(-(double)b.e[l - 1]));
 #pragma unroll
             for (int v = 0; v < NV; ++v) uh[v][l - 1] *= f;
         }
@@ -416,8 +443,16 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
         if (NST == 1) {
             load_cell<K, NV, TB>(a.us, cc, u0, uh);
             if (a.stage > 0) load_cell<K, NV, TB>(a.un, cc, n0, nh);
-            if (MODE == 2 && a.bl_us.eta) deferred_blend<K, NV, TB>(a.bl_us, n, cc, uh);
-            if (MODE == 2 && a.stage > 0 && a.bl_un.eta) deferred_blend<K, NV, TB>(a.bl_un, n, cc, nh);
+            if (MODE == 2 && K > 0 && a.bl_us.eta && a.bl_un.eta) {
+                // deferred blends owed by the inputs (u^n's is fetched at
+                // stage 0 too, where both name the same slot)
+                const auto bs = blend_fetch<K, TB>(a.bl_us, n, cc);
+                const auto bn = blend_fetch<K, TB>(a.bl_un, n, cc);
+                blend_pin(bs);
+                blend_pin(bn);
+                blend_apply<K, NV, TB>(bs, uh);
+                if (a.stage > 0) blend_apply<K, NV, TB>(bn, nh);
+            }
         } else {
             load_cell<K, NV, TB>(a.un, cc, n0, nh);
 #pragma unroll
@@ -800,9 +835,13 @@ __device__ __forceinline__ void blend_entries(StateView<TB> out, unsigned int cn
 template <int EQ, int K, typename TB, int MODE, int BS, bool HLLX, int NST>
 __global__ __launch_bounds__(BS) void stage1d_kernel(Args1D<TB> a)
 {
-    // a finished run, or a step already rejected by the positivity limiter
-    if (a.ctrl && a.dt_from_ctrl && (a.ctrl->done || a.ctrl->reject)) return;
-    const double dt = a.dt_from_ctrl ? a.ctrl->dt : a.dt_host;
+    // a finished run, or a step already rejected by the positivity limiter;
+    // both flags are read in one trip to memory (the host code sets a.ctrl
+    // for every launch)
+    const Ctrl* c = a.ctrl;
+    const int flags = c->done | c->reject;
+    if (a.dt_from_ctrl && flags) return;
+    const double dt = a.dt_from_ctrl ? c->dt : a.dt_host;
     if (a.zero_bits && blockIdx.x == 0 && threadIdx.x == 0) *a.zero_bits = 0;
     __shared__ __align__(16) unsigned char lds[Stage1DLds<EQ, K, TB, MODE, BS>::bytes];
     double lam, eta;
@@ -848,7 +887,7 @@ __global__ __launch_bounds__(256) void deferred_blend_kernel(StateView<TB> u, in
     double u0[NV];
     TB uh[NV][K > 0 ? K : 1];
     load_cell<K, NV, TB>(u, c, u0, uh);
-    deferred_blend<K, NV, TB>(bl, n, c, uh);
+    blend_apply<K, NV, TB>(blend_fetch<K, TB>(bl, n, c), uh);
     store_cell<K, NV, TB>(u, c, u0, uh);
 }
 

@@ -270,7 +270,7 @@ int maxwave_impl(dg_solver* s, unsigned long long* acc, hipStream_t st)
 // on the capture stream.
 // 1D hybrid without the positivity limiter: pass B is not a kernel of its
 // own; pass A records eta and the exponents per cell, and every stage that
-// loads a state owing its blend applies it on load (deferred_blend).  Slots
+// loads a state owing its blend applies it on load (blend_apply).  Slots
 // 0 and 1 hold stages 0 and 1 of a step, slots 2 and 3 stage 2 of even and
 // odd steps (u^n of the next step still owes that blend).
 bool deferred_blend_on(const dg_solver* s) { return s->dv_slot != 0; }
