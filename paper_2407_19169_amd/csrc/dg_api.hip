@@ -40,11 +40,14 @@ namespace {
 
 constexpr size_t kCtrlBytes = 4096;
 // aux scratch: [0..3] ledger, [4..5] minima, [8..10] per-call counters,
-// [16..) a second control block; from byte 4096 the ledger's partial sums.
+// [16..) a second control block, [256] and [272] the eta maxima of the
+// deferred-blend slots 2 and 3 (128-byte lines of their own); from byte 4096
+// the ledger's partial sums.
+constexpr size_t kAuxDeferredM = 256;  // in doubles
 constexpr size_t kAuxLedgerOff = 512;  // in doubles
 constexpr size_t kAuxBytes = 4096 + 4 * kLedgerParts * sizeof(double);
-static_assert(16 * sizeof(double) + sizeof(Ctrl) <= kAuxLedgerOff * sizeof(double),
-              "the second control block overlaps the ledger partials");
+static_assert(16 * sizeof(double) + sizeof(Ctrl) <= kAuxDeferredM * sizeof(double),
+              "the second control block overlaps the deferred-blend maxima");
 constexpr int kGraphSteps = 16;  // even: the three state buffers rotate with period 2
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -284,7 +287,8 @@ typename Args1D<TB>::Deferred dv_view(const dg_solver* s, int slot)
     d.E = base + s->ncell;
     double* aux = reinterpret_cast<double*>(s->ws + s->off_aux);
     Ctrl* c = reinterpret_cast<Ctrl*>(s->ws);
-    d.M = slot < 2 ? &c->eta_bits[slot] : reinterpret_cast<const unsigned long long*>(aux + 9 + slot);
+    d.M = slot < 2 ? &c->eta_line[slot].v
+                   : reinterpret_cast<const unsigned long long*>(aux + kAuxDeferredM + 16 * (slot - 2));
     return d;
 }
 
@@ -335,13 +339,13 @@ int record_steps(dg_solver* s, int G, hipStream_t st)
                     DG_HIP(launch_stage2d<TB>(s->eq, s->k, a, st));
                     if (fmode == 2) {
                         f.us = f.out = a.out;
-                        f.eta_acc = &c->eta_bits[stage];
+                        f.eta_acc = &c->eta_line[stage].v;
                         f.tcount = &c->tcount[stage];
                         f.tcell = tcell;
                         f.tdata = tdata;
                         DG_HIP(launch_filter2d<TB>(s->eq, s->k, f, 2, st));
                         DG_HIP(launch_blend2d<TB>(s->nv, s->k, f.out, s->ncell, &c->tcount[stage], tcell,
-                                                  tdata, &c->eta_bits[stage], c, 1, s->ncell, s->pk, st));
+                                                  tdata, &c->eta_line[stage].v, c, 1, s->ncell, s->pk, st));
                     }
                 }
             }
@@ -371,7 +375,7 @@ int record_steps(dg_solver* s, int G, hipStream_t st)
             a.dt_from_ctrl = 1;
             a.bflux = &c->bstage[stage][0];
             a.alpha_acc = stage == 2 ? &c->alpha_bits : nullptr;
-            a.eta_acc = &c->eta_bits[stage];
+            a.eta_acc = &c->eta_line[stage].v;
             a.tcount = &c->tcount[stage];
             a.tcell = tcell;
             a.tdata = tdata;
@@ -391,7 +395,7 @@ int record_steps(dg_solver* s, int G, hipStream_t st)
             if (dfr) continue;
             if (fmode == 2)
                 DG_HIP(launch_blend1d<TB>(s->nv, s->k, a.out, &c->tcount[stage], tcell, tdata,
-                                          &c->eta_bits[stage], c, 1, s->ncell,
+                                          &c->eta_line[stage].v, c, 1, s->ncell,
                                           pp_args<TB>(s), st));
         }
         // positivity limiter: a rejected step is undone (u^n copied over its
@@ -590,7 +594,7 @@ int time_impl(dg_solver* s, int stage, double dt, int reps, double* avg_us)
         f.dt_host = dt;
         f.us = fmode == 1 ? view_of<TB>(s, s->ws + s->off_w) : view_of<TB>(s, s->u[1]);
         f.out = view_of<TB>(s, s->u[1]);
-        f.eta_acc = &scratch->eta_bits[0];
+        f.eta_acc = &scratch->eta_line[0].v;
         f.tcount = &scratch->tcount[0];
         f.tcell = reinterpret_cast<long long*>(s->ws + s->off_tcell);
         f.tdata = reinterpret_cast<double*>(s->ws + s->off_tdata);
@@ -625,7 +629,7 @@ int time_impl(dg_solver* s, int stage, double dt, int reps, double* avg_us)
     a.reject = &scratch->reject;
     a.bflux = &scratch->bstage[stage][0];
     a.alpha_acc = stage == 2 ? &scratch->alpha_bits : nullptr;
-    a.eta_acc = &scratch->eta_bits[stage];
+    a.eta_acc = &scratch->eta_line[stage].v;
     a.tcount = &scratch->tcount[stage];
     a.tcell = reinterpret_cast<long long*>(s->ws + s->off_tcell);
     a.tdata = reinterpret_cast<double*>(s->ws + s->off_tdata);

@@ -286,10 +286,6 @@ struct Ctrl {
     double t_end;
     double dt_min, dt_max;
     double cfl_num;                  // 1D: cfl*h (dt = cfl_num/alpha); 2D: cfl
-    unsigned long long alpha_bits;   // CFL max (atomicMax of a non-negative double)
-    unsigned long long exp_bits;     // largest damping exponent seen
-    unsigned long long eta_bits[3];  // hybrid: max eta per stage
-    unsigned int tcount[3];          // hybrid: troubled-list entries per stage
     int active;                      // a scheduled step waits to be finalised
     long long steps;
     long long max_steps;             // absolute step limit of the current run
@@ -304,6 +300,17 @@ struct Ctrl {
     long long restarts;              // steps retried with half dt (positivity limiter)
     int retries;                     // consecutive retries of the current step
     int pad;
+    // Accumulators the stage kernels update with atomics, on lines apart
+    // from the fields above (read as each kernel starts).  Each stage's eta
+    // maximum has a 128-byte line of its own: a stage reads the previous
+    // stage's maximum while its own workgroups accumulate into theirs, and
+    // loads of a line that atomics are updating measured slower.
+    alignas(128) unsigned long long alpha_bits;  // CFL max (atomicMax of a non-negative double)
+    unsigned long long exp_bits;                 // largest damping exponent seen
+    unsigned int tcount[3];                      // hybrid: troubled-list entries per stage
+    struct alignas(128) Line {
+        unsigned long long v;
+    } eta_line[3];                               // hybrid: max eta per stage (.v)
 };
 
 // Retries of one step with halved dt (positivity limiter) before a run stops.

@@ -140,7 +140,7 @@ __device__ inline void step_ctrl_body(Ctrl* c, int finalize_only)
         c->alpha_bits = 0;
         for (int s = 0; s < 3; ++s) {
             c->tcount[s] = 0;
-            c->eta_bits[s] = 0;
+            c->eta_line[s].v = 0;
         }
         return;
     }
@@ -165,7 +165,7 @@ __device__ inline void step_ctrl_body(Ctrl* c, int finalize_only)
             c->alpha_bits = 0;
             for (int s = 0; s < 3; ++s) {
                 c->tcount[s] = 0;
-                c->eta_bits[s] = 0;
+                c->eta_line[s].v = 0;
                 for (int v = 0; v < 8; ++v) c->bstage[s][v] = 0.0;
             }
             return;
@@ -217,7 +217,7 @@ __device__ inline void step_ctrl_body(Ctrl* c, int finalize_only)
     c->alpha_bits = 0;
     for (int s = 0; s < 3; ++s) {
         c->tcount[s] = 0;
-        c->eta_bits[s] = 0;
+        c->eta_line[s].v = 0;
         for (int v = 0; v < 8; ++v) c->bstage[s][v] = 0.0;
     }
 }
