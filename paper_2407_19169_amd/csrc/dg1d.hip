@@ -566,12 +566,14 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
         // Boundary fluxes for the conservation ledger (one writer each).
         if (a.bflux && !a.periodic && tid >= HALO && tid < BS - HALO) {
             double* bf = a.bflux + (NST == 1 ? 0 : 8 * st);
+            // atomic stores: the step control may run in another workgroup
+            // of this launch and read them at the point of coherence
             if (c == 0)
 #pragma unroll
-                for (int v = 0; v < NV; ++v) bf[v] = (double)fL[v];
+                for (int v = 0; v < NV; ++v) store_coherent(&bf[v], (double)fL[v]);
             if (c == n - 1)
 #pragma unroll
-                for (int v = 0; v < NV; ++v) bf[4 + v] = (double)fR[v];
+                for (int v = 0; v < NV; ++v) store_coherent(&bf[4 + v], (double)fR[v]);
         }
         // Volume term: int f(u_h) P_l'(xi) dxi by the (K+1)-point Gauss rule.
         T vol[NV][KH];
@@ -832,7 +834,9 @@ __device__ __forceinline__ void blend_entries(StateView<TB> out, unsigned int cn
     }
 }
 
-template <int EQ, int K, typename TB, int MODE, int BS, bool HLLX, int NST>
+// FOLD: the last workgroup to finish runs the next step's control (built for
+// the small-grid hybrid stage only: it raises the kernel's register count).
+template <int EQ, int K, typename TB, int MODE, int BS, bool HLLX, int NST, bool FOLD = false>
 __global__ __launch_bounds__(BS) void stage1d_kernel(Args1D<TB> a)
 {
     // a finished run, or a step already rejected by the positivity limiter;
@@ -855,6 +859,17 @@ __global__ __launch_bounds__(BS) void stage1d_kernel(Args1D<TB> a)
         // CFL reduction of the output's cell averages (next step)
         const double l = wave_max(lam);
         if ((threadIdx.x & 63) == 0) atomic_max_nonneg(a.alpha_acc, l);
+    }
+    if constexpr (FOLD) {
+        // the next step's control, run by the workgroup that finishes last:
+        // each workgroup waits for its own memory operations (its atomics
+        // into the control block are then performed) before counting itself in
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0 &&
+            __hip_atomic_fetch_add(&a.ctrl->arrive.v, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                (unsigned long long)gridDim.x - 1)
+            step_ctrl_in_kernel(a.ctrl);
     }
 }
 
@@ -1101,8 +1116,12 @@ static hipError_t launch_stage_fx(const Args1D<TB>& a, int mode, int nst, hipStr
         hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 0, BS, HLLX, 1>), grid, block, 0, st, a);
     else if (mode == 1)
         hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 1, BS, HLLX, 1>), grid, block, 0, st, a);
-    else
+    else if (!a.fold_ctrl)
         hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 2, BS, HLLX, 1>), grid, block, 0, st, a);
+    else if constexpr (BS == 64)
+        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 2, BS, HLLX, 1, true>), grid, block, 0, st, a);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -1121,7 +1140,7 @@ static hipError_t launch_stage_bs(const Args1D<TB>& a, int mode, int nst, hipStr
 template <int EQ, int K, typename TB>
 static hipError_t launch_stage(const Args1D<TB>& a, int mode, int nst, hipStream_t st)
 {
-    if (a.n < 252 * 1024) return launch_stage_bs<EQ, K, TB, 64>(a, mode, nst, st);
+    if (a.n < kSmallTileCells) return launch_stage_bs<EQ, K, TB, 64>(a, mode, nst, st);
     return launch_stage_bs<EQ, K, TB, 256>(a, mode, nst, st);
 }
 

@@ -302,6 +302,16 @@ bool fused_step(const dg_solver* s)
     return s->dim == 1 && s->opt.filter != DG_FILTER_HYBRID;
 }
 
+// 1D hybrid runs with the deferred blend on small grids (one-wavefront
+// tiles, where launches and their latency bound the step): the step control
+// runs at the end of each step's last stage, in the workgroup that finishes
+// last, instead of as a kernel of its own before the next step (the run's
+// first step is scheduled before the replays).
+bool folded_ctrl(const dg_solver* s)
+{
+    return s->dim == 1 && deferred_blend_on(s) && s->ncell < kSmallTileCells;
+}
+
 template <typename TB>
 int record_steps(dg_solver* s, int G, hipStream_t st)
 {
@@ -313,7 +323,7 @@ int record_steps(dg_solver* s, int G, hipStream_t st)
         void* A = (i % 2 == 0) ? s->u[0] : s->u[1];
         void* B = (i % 2 == 0) ? s->u[1] : s->u[0];
         void* Cb = s->u[2];
-        DG_HIP(launch_step_ctrl(c, 0, st));
+        if (!folded_ctrl(s)) DG_HIP(launch_step_ctrl(c, 0, st));
         if (s->dim == 2) {
             for (int stage = 0; stage < 3; ++stage) {
                 void* target = stage == 1 ? Cb : B;
@@ -388,6 +398,7 @@ int record_steps(dg_solver* s, int G, hipStream_t st)
                 a.bl_un = dv_view<TB>(s, prev2);
                 a.bl_us = stage == 0 ? a.bl_un : dv_view<TB>(s, stage - 1);
                 if (stage == 2) a.eta_acc = const_cast<unsigned long long*>(dv_out.M);
+                a.fold_ctrl = stage == 2 && folded_ctrl(s);
                 // this step's last-stage maximum is cleared before stage 2
                 if (stage == 1) a.zero_bits = const_cast<unsigned long long*>(dv_view<TB>(s, cur2).M);
             }
@@ -490,6 +501,7 @@ int run_impl(dg_solver* s, double t_end, int64_t max_steps, dg_report* rep)
     c.dt_min = INFINITY;
     c.dt_max = 0.0;
     c.alpha_bits = 0;
+    c.arrive.v = 0;
     c.cfl_num = s->dim == 1 ? s->opt.cfl * s->h[0] : s->opt.cfl;
     DG_HIP(hipMemcpy(ctrl_of(s), &c, sizeof c, hipMemcpyHostToDevice));
     if (!s->graph) {
@@ -501,6 +513,10 @@ int run_impl(dg_solver* s, double t_end, int64_t max_steps, dg_report* rep)
     // deferred hybrid blend: the run's first step owes no blend on u^n
     if (deferred_blend_on(s))
         DG_HIP(hipMemsetAsync(s->ws + s->off_dv + 3 * s->dv_slot, 0, s->ncell * sizeof(TB), st));
+    // folded step control: the first step is scheduled here, every later one
+    // at the end of the step before it
+    const bool folded = folded_ctrl(s);
+    if (folded) DG_HIP(launch_step_ctrl(ctrl_of(s), 0, st));
     // Replays: batches double in size between control reads, never beyond
     // the replays the remaining step budget needs.  With the positivity
     // limiter a rejected step is retried, so the budget is re-read.
@@ -517,8 +533,9 @@ int run_impl(dg_solver* s, double t_end, int64_t max_steps, dg_report* rep)
         DG_HIP(hipStreamSynchronize(st));
         if (cr.done) break;
         // the last step of a replay has run but is finalised by the next
-        // step control, unless it was rejected
-        completed = cr.steps - steps0 + ((cr.active && !cr.reject) ? 1 : 0);
+        // step control, unless it was rejected (with the folded control it
+        // is finalised, and an active step is the next one, not yet run)
+        completed = cr.steps - steps0 + ((!folded && cr.active && !cr.reject) ? 1 : 0);
         batch = batch < 64 ? batch * 2 : 64;
     }
     DG_HIP(launch_step_ctrl(ctrl_of(s), 1, st));
@@ -641,6 +658,9 @@ int time_impl(dg_solver* s, int stage, double dt, int reps, double* avg_us)
         a.dv_E = const_cast<TB*>(dv_out.E);
         a.bl_un = dv_view<TB>(s, 3);
         a.bl_us = stage == 0 ? a.bl_un : dv_view<TB>(s, stage - 1);
+        // with the step control folded into the last stage, as dg_run has it
+        // (it then works on the second control block)
+        a.fold_ctrl = stage == 2 && folded_ctrl(s);
     }
     auto launch = [&]() { return launch_stage1d<TB>(s->eq, s->k, a, fmode, st); };
     return time_launches(s, scratch, reps, launch, avg_us);

@@ -311,6 +311,7 @@ struct Ctrl {
     struct alignas(128) Line {
         unsigned long long v;
     } eta_line[3];                               // hybrid: max eta per stage (.v)
+    Line arrive;                                 // workgroups of a launch that have finished
 };
 
 // Retries of one step with halved dt (positivity limiter) before a run stops.
@@ -347,9 +348,20 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// A double stored with an agent-scope atomic store (visible at the point of
+// coherence without a cache write-back).
+__device__ __forceinline__ void store_coherent(double* p, double v)
+{
+    __hip_atomic_store(reinterpret_cast<long long*>(p), __double_as_longlong(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void latch_error(Ctrl* c, int code, long long cell)
 {
-    if (atomicCAS(&c->status, 0, code) == 0) c->first_bad = cell;
+    // (an atomic store: the step control may run in a workgroup of the same
+    // launch, which reads the cell at the point of coherence)
+    if (atomicCAS(&c->status, 0, code) == 0)
+        __hip_atomic_store(&c->first_bad, cell, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace dg

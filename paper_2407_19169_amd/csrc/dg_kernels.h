@@ -23,6 +23,8 @@ struct Args1D {
     double dt_host;
     int check;                // Euler positivity check of the stage input
     Ctrl* ctrl;               // always valid: error latch
+    int fold_ctrl;            // the last workgroup to finish runs the step control
+                              // (MODE 2 single stage, n < kSmallTileCells)
     double* bflux;            // nullable: 8 doubles (x-lo[4], x-hi[4])
     unsigned long long* alpha_acc;  // nullable: CFL max of the output
     unsigned long long* eta_acc;    // hybrid
@@ -134,11 +136,14 @@ hipError_t launch_maxwave1d(int eq, StateView<TB> u, int64_t n, PhysParams phys,
 // unless finalize_only, schedule the next one: dt = cfl_num / alpha from the
 // CFL maximum accumulated by the previous step's last stage, clamped so the
 // run ends exactly at t_end.  Called by one thread (step_ctrl_kernel).
-__device__ inline void step_ctrl_body(Ctrl* c, int finalize_only)
+template <typename C>
+__device__ inline void step_ctrl_body(C* c, int finalize_only)
 {
-    if (finalize_only == 2) {  // clear the per-step accumulators only
+    if (finalize_only == 2) {  // clear the per-step accumulators only (and the
+                               // arrival count: step_ctrl_kernel)
         c->alpha_bits = 0;
-        for (int s = 0; s < 3; ++s) {
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
             c->tcount[s] = 0;
             c->eta_line[s].v = 0;
         }
@@ -163,10 +168,12 @@ __device__ inline void step_ctrl_body(Ctrl* c, int finalize_only)
             c->dt *= 0.5;
             c->last = 0;
             c->alpha_bits = 0;
-            for (int s = 0; s < 3; ++s) {
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
                 c->tcount[s] = 0;
                 c->eta_line[s].v = 0;
-                for (int v = 0; v < 8; ++v) c->bstage[s][v] = 0.0;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) c->bstage[s][v] = 0.0;
             }
             return;
         }
@@ -215,11 +222,120 @@ __device__ inline void step_ctrl_body(Ctrl* c, int finalize_only)
     c->last = last;
     c->active = 1;
     c->alpha_bits = 0;
+#pragma unroll
     for (int s = 0; s < 3; ++s) {
         c->tcount[s] = 0;
         c->eta_line[s].v = 0;
+#pragma unroll
         for (int v = 0; v < 8; ++v) c->bstage[s][v] = 0.0;
     }
+}
+
+// 1D stage kernels use one-wavefront tiles below this many cells.
+constexpr int64_t kSmallTileCells = 252 * 1024;
+
+// The fields of Ctrl that the step control works on, without the control
+// block's padding: a copy this size stays in registers.
+struct CtrlRegs {
+    double t, dt, t_end, dt_min, dt_max, cfl_num;
+    unsigned long long alpha_bits;
+    unsigned int tcount[3];
+    struct {
+        unsigned long long v;
+    } eta_line[3];
+    int active;
+    long long steps, max_steps, troubled;
+    int last, done, status, reject;
+    long long first_bad;
+    double bflux[4];
+    double bstage[3][8];
+    long long restarts;
+    int retries;
+};
+
+// COHERENT: the fields other workgroups of the running launch may have
+// changed (atomics, atomic stores) are read at the point of coherence.
+template <bool COHERENT>
+__device__ inline CtrlRegs load_ctrl_regs(const Ctrl* c)
+{
+    auto ld = [](const auto* p) {
+        using T = typename std::remove_cv<typename std::remove_pointer<decltype(p)>::type>::type;
+        if constexpr (COHERENT)
+            return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            return *p;
+    };
+    CtrlRegs r;
+    r.t = c->t;
+    r.dt = c->dt;
+    r.t_end = c->t_end;
+    r.dt_min = c->dt_min;
+    r.dt_max = c->dt_max;
+    r.cfl_num = c->cfl_num;
+    r.alpha_bits = ld(&c->alpha_bits);
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        r.tcount[s] = ld(&c->tcount[s]);
+        r.eta_line[s].v = c->eta_line[s].v;
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+            r.bstage[s][v] = __longlong_as_double(ld(reinterpret_cast<const long long*>(&c->bstage[s][v])));
+    }
+    r.active = c->active;
+    r.steps = c->steps;
+    r.max_steps = c->max_steps;
+    r.troubled = c->troubled;
+    r.last = c->last;
+    r.done = c->done;
+    r.status = ld(&c->status);
+    r.reject = ld(&c->reject);
+    r.first_bad = ld(&c->first_bad);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) r.bflux[v] = c->bflux[v];
+    r.restarts = c->restarts;
+    r.retries = c->retries;
+    return r;
+}
+
+__device__ inline void store_ctrl_regs(Ctrl* c, const CtrlRegs& r)
+{
+    c->t = r.t;
+    c->dt = r.dt;
+    c->dt_min = r.dt_min;
+    c->dt_max = r.dt_max;
+    c->alpha_bits = r.alpha_bits;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        c->tcount[s] = r.tcount[s];
+        c->eta_line[s].v = r.eta_line[s].v;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) c->bstage[s][v] = r.bstage[s][v];
+    }
+    c->active = r.active;
+    c->steps = r.steps;
+    c->troubled = r.troubled;
+    c->last = r.last;
+    c->done = r.done;
+    c->status = r.status;
+    c->reject = r.reject;
+    c->first_bad = r.first_bad;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) c->bflux[v] = r.bflux[v];
+    c->restarts = r.restarts;
+    c->retries = r.retries;
+}
+
+// The step control run inside a stage kernel, by the workgroup that
+// finishes last (1D dg_run without the positivity limiter): every other
+// workgroup's atomics into the control block completed before it counted
+// itself in, and the fields those atomics change are re-read here at the
+// point of coherence; the rest was written before the launch.
+__device__ inline void step_ctrl_in_kernel(Ctrl* c)
+{
+    CtrlRegs r = load_ctrl_regs<true>(c);
+    step_ctrl_body(&r, 0);
+    store_ctrl_regs(c, r);
+    __hip_atomic_store(&c->arrive.v, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // step control (dg_util.hip)

@@ -10,9 +10,10 @@ namespace dg {
 __global__ void step_ctrl_kernel(Ctrl* c, int finalize_only)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    Ctrl l = *c;
-    step_ctrl_body(&l, finalize_only);
-    *c = l;
+    CtrlRegs r = load_ctrl_regs<false>(c);
+    step_ctrl_body(&r, finalize_only);
+    store_ctrl_regs(c, r);
+    if (finalize_only == 2) c->arrive.v = 0;
 }
 
 hipError_t launch_step_ctrl(Ctrl* c, int finalize_only, hipStream_t st)

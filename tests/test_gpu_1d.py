@@ -193,6 +193,45 @@ def test_shock_run_parity(dg, ref, case):
         assert abs(rep.troubled_cells - orep.troubled_cells) <= 2
 
 
+def test_hybrid_runs_stop_where_the_oracle_does(dg, ref):
+    """Hybrid runs on small grids schedule each step inside the last stage
+    launch of the step before (the workgroup that finishes last runs the step
+    control).  Three consecutive runs on the Lax problem, P2, 200 cells,
+    reflecting ends: to t = 0.05 (ending inside a replay of the step graph),
+    then 7 more steps, then none.  Each is compared with the oracle run from
+    the same state: step count, end time, dt extremes, troubled cells,
+    boundary flux, ledger and state."""
+    w = I.lax(200, 2)
+    s = _solver(dg, 2, 2, 200, -1.0, 1.0, (2, 2), 2)
+    s.set_state(w.u0)
+    P = _oracle(ref, 2, 2, 200, -1.0, 1.0, (2, 2), 2)
+    u_ref = w.u0
+    steps0, t0, troubled0, bf0 = 0, 0.0, 0, np.zeros(3)
+    for t_end, nmax in ((0.05, 1 << 40), (1e30, 7), (1e30, 0)):
+        rep = dg.dg_run(s.h, t_end, nmax)
+        u_ref, orep, rc = ref.run1d(P, u_ref, t_end, nmax)
+        assert rc == 0 and rep.status == 0
+        assert rep.steps - steps0 == orep.steps
+        if t_end < 1.0:
+            assert rep.t == t_end and orep.t == t_end
+        else:
+            assert orep.steps == nmax
+            assert rep.t - t0 == pytest.approx(orep.t, rel=1e-12, abs=1e-15)
+        if nmax:
+            assert rep.dt_min == pytest.approx(orep.dt_min, rel=1e-10)
+            assert rep.dt_max == pytest.approx(orep.dt_max, rel=1e-10)
+        assert abs((rep.troubled_cells - troubled0) - orep.troubled_cells) <= 2
+        got = s.get_state().cpu().numpy()
+        for v in range(3):
+            assert rel_linf(got[v], u_ref[v]) <= 1e-10, v
+            assert rep.ledger[v] == pytest.approx(orep.ledger[v], rel=1e-12, abs=1e-12)
+            assert rep.boundary_flux[v] - bf0[v] == pytest.approx(orep.boundary_flux[v], rel=1e-9,
+                                                                 abs=1e-13)
+        steps0, t0, troubled0 = rep.steps, rep.t, rep.troubled_cells
+        bf0 = np.array([rep.boundary_flux[v] for v in range(3)])
+    s.close()
+
+
 @pytest.mark.parametrize("filt", [1, 2])
 def test_one_step_from_late_state_full_size(dg, ref, filt):
     """Bench configuration (Shu-Osher, 20000 cells, P2, FP64): after 2000
