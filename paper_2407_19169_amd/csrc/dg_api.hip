@@ -33,7 +33,6 @@ struct dg_solver {
     hipStream_t user_st;
     hipStream_t run_st;
     hipGraphExec_t graph;
-    int graph_steps;
 };
 
 namespace {
@@ -438,7 +437,6 @@ int build_graph(dg_solver* s)
         s->graph = nullptr;
         return DG_ERR_DEVICE;
     }
-    s->graph_steps = kGraphSteps;
     return DG_OK;
 }
 
@@ -504,7 +502,12 @@ int run_impl(dg_solver* s, double t_end, int64_t max_steps, dg_report* rep)
     c.arrive.v = 0;
     c.cfl_num = s->dim == 1 ? s->opt.cfl * s->h[0] : s->opt.cfl;
     DG_HIP(hipMemcpy(ctrl_of(s), &c, sizeof c, hipMemcpyHostToDevice));
-    if (!s->graph) {
+    // Small-grid hybrid runs with the folded step control launch their steps
+    // directly on the stream: replayed from a graph, the same kernels ran
+    // slower on the device (35.5 against 32.4 us per step, where the host's
+    // launch rate was then the limit).  Every other run replays a graph.
+    const bool direct = folded_ctrl(s);
+    if (!direct && !s->graph) {
         int rc = build_graph<TB>(s);
         if (rc) return rc;
     }
@@ -525,9 +528,16 @@ int run_impl(dg_solver* s, double t_end, int64_t max_steps, dg_report* rep)
     for (;;) {
         const long long rem = max_steps - completed;
         if (rem <= 0) break;
-        long long nb = (rem + s->graph_steps - 1) / s->graph_steps;
+        long long nb = (rem + kGraphSteps - 1) / kGraphSteps;
         if (nb > batch) nb = batch;
-        for (long long r = 0; r < nb; ++r) DG_HIP(hipGraphLaunch(s->graph, st));
+        for (long long r = 0; r < nb; ++r) {
+            if (!direct) {
+                DG_HIP(hipGraphLaunch(s->graph, st));
+                continue;
+            }
+            const int rs = record_steps<TB>(s, kGraphSteps, st);
+            if (rs) return rs;
+        }
         Ctrl cr;
         DG_HIP(hipMemcpyAsync(&cr, ctrl_of(s), sizeof cr, hipMemcpyDeviceToHost, st));
         DG_HIP(hipStreamSynchronize(st));
