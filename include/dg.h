@@ -210,7 +210,11 @@ int dg_last_exponents(dg_solver* s, double* E_dev);
  * duration in microseconds from HIP events recorded before the first and
  * after the last launch (after one untimed warm-up launch).  1D: `stage`
  * 0..2 selects the fused stage(+filter / hybrid pass A) kernel of that RK
- * stage (reads u_n, u_a, u_b; writes u_a or u_b).  2D: 0..2 the residual
+ * stage (reads u_n, u_a, u_b; writes u_a or u_b), in the form dg_run
+ * launches it: for hybrid runs without the positivity limiter with the
+ * deferred blend, and on grids under 258048 cells stage 2 also runs the
+ * step control in its last workgroup (on a control block of its own).
+ * 2D: 0..2 the residual
  * kernel of that stage (writes the workspace), 3..5 the filter kernel
  * (jump: workspace -> u_a) or hybrid pass A (reads u_a).  1D `stage` 6: the
  * kernel that runs a whole step (jump filter or none; u_n -> u_a);
