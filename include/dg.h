@@ -211,9 +211,9 @@ int dg_last_exponents(dg_solver* s, double* E_dev);
  * after the last launch (after one untimed warm-up launch).  1D: `stage`
  * 0..2 selects the fused stage(+filter / hybrid pass A) kernel of that RK
  * stage (reads u_n, u_a, u_b; writes u_a or u_b), in the form dg_run
- * launches it: for hybrid runs without the positivity limiter with the
- * deferred blend, and on grids under 258048 cells stage 2 also runs the
- * step control in its last workgroup (on a control block of its own).
+ * launches it.  Hybrid runs without the positivity limiter use the deferred
+ * blend; on grids under 258048 cells their stage 2 also runs the step
+ * control in its last workgroup (here on a control block of its own).
  * 2D: 0..2 the residual
  * kernel of that stage (writes the workspace), 3..5 the filter kernel
  * (jump: workspace -> u_a) or hybrid pass A (reads u_a).  1D `stage` 6: the
