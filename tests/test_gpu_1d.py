@@ -329,11 +329,15 @@ def test_mixed_precision_burgers_error_bound(dg, ref):
     s.close()
 
 
-def test_nonfinite_state_is_reported(dg, ref):
+@pytest.mark.parametrize("filt", [1, 2])
+def test_nonfinite_state_is_reported(dg, ref, filt):
+    """A negative density is latched with its cell; with the hybrid limiter
+    (deferred blend) the latch is read by the step control that runs in the
+    last workgroup of stage 2."""
     w = I.shu_osher(500, 2)
     u = w.u0.copy()
     u[0, 0, 123] = -1.0  # negative density
-    s = _solver(dg, 2, 2, 500, -5.0, 5.0, (1, 1), 1)
+    s = _solver(dg, 2, 2, 500, -5.0, 5.0, (1, 1), filt)
     s.set_state(u)
     rep = dg.dg_run(s.h, 1.0, 5, check=False)
     assert rep.status in (dg.DG_ERR_POSITIVITY, dg.DG_ERR_NONFINITE)
