@@ -834,6 +834,16 @@ __device__ __forceinline__ void blend_entries(StateView<TB> out, unsigned int cn
     }
 }
 
+// Tile of this workgroup.  Workgroups are dealt to the 8 XCDs round-robin;
+// each XCD takes one contiguous range of tiles, so neighbouring tiles, which
+// read each other's edge cells, mostly run on the same XCD and its L2.
+__device__ __forceinline__ int64_t xcd_block()
+{
+    const int64_t p = blockIdx.x, q = gridDim.x >> 3, r = gridDim.x & 7;
+    const int64_t x = p & 7, k = p >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
 // FOLD: the last workgroup to finish runs the next step's control (built for
 // the small-grid hybrid stage only: it raises the kernel's register count).
 template <int EQ, int K, typename TB, int MODE, int BS, bool HLLX, int NST, bool FOLD = false>
@@ -849,7 +859,7 @@ __global__ __launch_bounds__(BS) void stage1d_kernel(Args1D<TB> a)
     if (a.zero_bits && blockIdx.x == 0 && threadIdx.x == 0) *a.zero_bits = 0;
     __shared__ __align__(16) unsigned char lds[Stage1DLds<EQ, K, TB, MODE, BS>::bytes];
     double lam, eta;
-    stage1d_tile<EQ, K, TB, MODE, BS, HLLX, NST>(a, (int64_t)blockIdx.x, dt, lds, &lam, &eta);
+    stage1d_tile<EQ, K, TB, MODE, BS, HLLX, NST>(a, xcd_block(), dt, lds, &lam, &eta);
     if (MODE == 2) {
         // max eta over the domain (wave reduction, one atomic per wave)
         const double e = wave_max(eta);
