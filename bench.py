@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # plain 1 GiB device copy (FETCH x2.0, WRITE x1.0); the summary with the
 # commands is profiles/stage1d_headline_traffic.md.  Set to None when that
 # kernel changes until the counters are taken again.
-HEADLINE_TRAFFIC_BYTES = (1701.0 * 2.0 + 1567.3 * 1.0) * 1024
+HEADLINE_TRAFFIC_BYTES = (1700.9 * 2.0 + 1565.4 * 1.0) * 1024
 METRIC = "DOF-updates/s per RK stage and % HBM roofline, FP32 vs FP64, batched vs single"
 
 

@@ -845,7 +845,8 @@ __device__ __forceinline__ int64_t xcd_block()
 }
 
 // FOLD: the last workgroup to finish runs the next step's control (built for
-// the small-grid hybrid stage only: it raises the kernel's register count).
+// the small-grid hybrid stage only, BS = 128: it raises the kernel's register
+// count).
 template <int EQ, int K, typename TB, int MODE, int BS, bool HLLX, int NST, bool FOLD = false>
 __global__ __launch_bounds__(BS) void stage1d_kernel(Args1D<TB> a)
 {
@@ -1110,11 +1111,20 @@ __global__ __launch_bounds__(256) void maxwave1d_kernel(StateView<TB> u, int64_t
 
 // ------------------------------------------------------------ launchers --
 // nst = 1: one RK stage (a.stage); nst = 3: the whole step (MODE 0 or 1).
+// BS = 128 is built for the hybrid stage only.
 template <int EQ, int K, typename TB, int BS, bool HLLX>
 static hipError_t launch_stage_fx(const Args1D<TB>& a, int mode, int nst, hipStream_t st)
 {
     const int tile = BS - 2 * nst * (mode == 0 ? 1 : 2);
     dim3 grid((unsigned)((a.n + tile - 1) / tile)), block(BS);
+    if constexpr (BS == 128) {
+        if (mode != 2 || nst != 1) return hipErrorInvalidValue;
+        if (a.fold_ctrl)
+            hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 2, BS, HLLX, 1, true>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 2, BS, HLLX, 1>), grid, block, 0, st, a);
+        return hipGetLastError();
+    }
     if (nst == 3) {
         if (mode == 0)
             hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 0, BS, HLLX, 3>), grid, block, 0, st, a);
@@ -1128,8 +1138,6 @@ static hipError_t launch_stage_fx(const Args1D<TB>& a, int mode, int nst, hipStr
         hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 1, BS, HLLX, 1>), grid, block, 0, st, a);
     else if (!a.fold_ctrl)
         hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 2, BS, HLLX, 1>), grid, block, 0, st, a);
-    else if constexpr (BS == 64)
-        hipLaunchKernelGGL((stage1d_kernel<EQ, K, TB, 2, BS, HLLX, 1, true>), grid, block, 0, st, a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1144,13 +1152,18 @@ static hipError_t launch_stage_bs(const Args1D<TB>& a, int mode, int nst, hipStr
     return launch_stage_fx<EQ, K, TB, BS, false>(a, mode, nst, st);
 }
 
-// Small grids (under about a thousand 256-cell tiles) use one-wavefront
-// tiles: a single tile's dependent chain then bounds the stage, and smaller
-// tiles spread it over more compute units.
+// Small grids (under about a thousand 256-cell tiles) use small tiles: a
+// single tile's dependent chain then bounds the stage, and smaller tiles
+// spread it over more compute units.  The hybrid stage takes two-wavefront
+// tiles (measured faster than one- or four-wavefront ones there), the rest
+// one-wavefront tiles.
 template <int EQ, int K, typename TB>
 static hipError_t launch_stage(const Args1D<TB>& a, int mode, int nst, hipStream_t st)
 {
-    if (a.n < kSmallTileCells) return launch_stage_bs<EQ, K, TB, 64>(a, mode, nst, st);
+    if (a.n < kSmallTileCells) {
+        if (mode == 2 && nst == 1) return launch_stage_bs<EQ, K, TB, 128>(a, mode, nst, st);
+        return launch_stage_bs<EQ, K, TB, 64>(a, mode, nst, st);
+    }
     return launch_stage_bs<EQ, K, TB, 256>(a, mode, nst, st);
 }
 

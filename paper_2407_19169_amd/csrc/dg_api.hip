@@ -301,11 +301,11 @@ bool fused_step(const dg_solver* s)
     return s->dim == 1 && s->opt.filter != DG_FILTER_HYBRID;
 }
 
-// 1D hybrid runs with the deferred blend on small grids (one-wavefront
-// tiles, where launches and their latency bound the step): the step control
-// runs at the end of each step's last stage, in the workgroup that finishes
-// last, instead of as a kernel of its own before the next step (the run's
-// first step is scheduled before the replays).
+// 1D hybrid runs with the deferred blend on small grids (small tiles, where
+// launches and their latency bound the step): the step control runs at the
+// end of each step's last stage, in the workgroup that finishes last,
+// instead of as a kernel of its own before the next step (the run's first
+// step is scheduled before the first batch of steps).
 bool folded_ctrl(const dg_solver* s)
 {
     return s->dim == 1 && deferred_blend_on(s) && s->ncell < kSmallTileCells;

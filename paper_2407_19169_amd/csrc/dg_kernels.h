@@ -231,7 +231,8 @@ __device__ inline void step_ctrl_body(C* c, int finalize_only)
     }
 }
 
-// 1D stage kernels use one-wavefront tiles below this many cells.
+// 1D stage kernels use small tiles below this many cells (one wavefront; two
+// for the hybrid stage).
 constexpr int64_t kSmallTileCells = 252 * 1024;
 
 // The fields of Ctrl that the step control works on, without the control
