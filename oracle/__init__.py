@@ -53,8 +53,8 @@ class Problem2D(C.Structure):
                 ("adv_speed", C.c_double * 2), ("cfl", C.c_double),
                 ("dirichlet", (C.c_double * 4) * 4), ("shock_x0", C.c_double),
                 ("shock_speed", C.c_double), ("post", C.c_double * 4), ("pre", C.c_double * 4),
-                ("cf_mesh", C.c_int), ("basis", C.c_int), ("cf_scale", C.c_double),
-                ("flux", C.c_int)]
+                ("cf_reading", C.c_int), ("basis", C.c_int), ("flux", C.c_int),
+                ("pp", C.c_int)]
 
 
 class Report(C.Structure):
@@ -117,10 +117,13 @@ def problem1d(eq, k, n, lo, hi, bc=(PERIODIC, PERIODIC), filter=FILTER_JUMP, cfl
 
 def problem2d(eq, k, nx, ny, xlo, xhi, ylo, yhi, bc=(PERIODIC,) * 4, filter=FILTER_JUMP,
               cfl=0.1, gamma=1.4, adv_speed=(1.0, 1.0), nq=0, filter_dt=0,
-              dirichlet=None, shock_x0=0.0, shock_speed=0.0, post=None, pre=None, cf_mesh=0,
-              basis=0, cf_scale=1.0, flux=0) -> Problem2D:
+              dirichlet=None, shock_x0=0.0, shock_speed=0.0, post=None, pre=None, cf_reading=0,
+              basis=0, flux=0, pp=0) -> Problem2D:
+    """cf_reading: mesh factors of the 2D Euler coefficient (c_fx, c_fy): 0 the
+    (h_x, h_y) printed in Sec. 2.4 (default), 1 the (h_y, h_x) printed in
+    Sec. 3.2, 2 none."""
     P = Problem2D()
-    P.cf_mesh, P.basis, P.cf_scale = cf_mesh, basis, cf_scale
+    P.cf_reading, P.basis, P.pp = cf_reading, basis, pp
     P.flux = flux
     P.shock_x0, P.shock_speed = shock_x0, shock_speed
     for v in range(4):
@@ -304,6 +307,32 @@ def check2d(P: Problem2D, u: np.ndarray):
     bad = C.c_int64()
     rc = lib().dgref_check2d(C.byref(P), _ptr(u), C.byref(mr), C.byref(mp), C.byref(bad))
     return rc, mr.value, mp.value, bad.value
+
+
+def pp_limit2d(P: Problem2D, u: np.ndarray):
+    """Positivity-preserving limiter (Zhang and Shu) on every cell of a 2D
+    Euler state."""
+    u = np.array(u, dtype=np.float64, order="C", copy=True)
+    _chk(lib().dgref_pp_limit2d(C.byref(P), _ptr(u)), "pp_limit2d")
+    return u
+
+
+def pp_points2d(P: Problem2D):
+    """Reference coordinates (xi, eta) of the 2D limiter's test points."""
+    xi = np.zeros(6 * 8 + 64)
+    eta = np.zeros(6 * 8 + 64)
+    n = lib().dgref_pp_points2d(C.byref(P), _ptr(xi), _ptr(eta))
+    if n < 0:
+        raise RuntimeError(f"pp_points2d failed with status {n}")
+    return xi[:n].copy(), eta[:n].copy()
+
+
+def step2d_rc(P: Problem2D, dt: float, u: np.ndarray, t: float = 0.0):
+    """One step; returns (new state, or u unchanged when rejected, return code)."""
+    u = np.array(u, dtype=np.float64, order="C", copy=True)
+    tr = C.c_int64(0)
+    rc = lib().dgref_step2d(C.byref(P), C.c_double(t), C.c_double(dt), _ptr(u), C.byref(tr))
+    return u, rc
 
 
 def step2d(P: Problem2D, dt: float, u: np.ndarray, t: float = 0.0):

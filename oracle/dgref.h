@@ -64,11 +64,14 @@ typedef struct {
      * conserved states behind (left of) and ahead of it */
     double shock_x0, shock_speed;
     double post[4], pre[4];
-    int cf_mesh;   /* 1: (c_fx, c_fy) carry the factors (h_x, h_y) as printed in
-                      Sec. 2.4; 0: they do not (see the readings in the 2D part) */
+    int cf_reading; /* mesh factors (m_x, m_y) of the Euler coefficient
+                       (c_fx, c_fy) = (m_x beta^x, m_y beta^y) / (4 lambda_pq H-bar):
+                       0: (h_x, h_y), as printed in Sec. 2.4 (default);
+                       1: (h_y, h_x), as printed in Sec. 3.2;
+                       2: (1, 1), without mesh factors */
     int basis;     /* 0: Q^k tensor product; 1: P^k total degree (p + q <= k) */
-    double cf_scale; /* multiplies (c_fx, c_fy); 0 means 1 */
     int flux;      /* DGREF_FLUX_*: interface flux (HLL / HLLC: Euler) */
+    int pp;        /* 1: positivity-preserving limiter after the filter (Euler) */
 } dgref_problem2d;
 
 typedef struct {
@@ -133,6 +136,10 @@ int dgref_post2d(const dgref_problem2d* P, int stage, double t, double dt, const
                  double* out, int64_t* troubled);
 int dgref_check2d(const dgref_problem2d* P, const double* u, double* min_rho, double* min_p,
                   int64_t* first_bad);
+int dgref_pp_limit2d(const dgref_problem2d* P, double* u);
+/* Reference-coordinate test points of the 2D positivity limiter: xi[i],
+ * eta[i] for i < return value (at most 6 nq + nq^2). */
+int dgref_pp_points2d(const dgref_problem2d* P, double* xi, double* eta);
 int dgref_step2d(const dgref_problem2d* P, double t, double dt, double* u, int64_t* troubled);
 int dgref_run2d(const dgref_problem2d* P, double t_end, int64_t max_steps, double* u,
                 dgref_report* rep);

@@ -16,6 +16,8 @@
 #include "dgref_internal.h"
 
 #define NMAX ((MAXK + 1) * (MAXK + 1))
+/* test points of the positivity limiter: 2 x (3 Lobatto x nq) + nq x nq */
+#define PPMAX (6 * MAXQ + MAXQ * MAXQ)
 
 typedef struct {
     const dgref_problem2d* P;
@@ -36,6 +38,8 @@ static int check2d(const dgref_problem2d* P)
     }
     if ((P->bc[0] == DGREF_PERIODIC) != (P->bc[1] == DGREF_PERIODIC)) return DGREF_ERR_ARG;
     if ((P->bc[2] == DGREF_PERIODIC) != (P->bc[3] == DGREF_PERIODIC)) return DGREF_ERR_ARG;
+    if (P->cf_reading < 0 || P->cf_reading > 2) return DGREF_ERR_ARG;
+    if (P->pp && P->eq != DGREF_EULER) return DGREF_ERR_ARG;
     return DGREF_OK;
 }
 
@@ -472,15 +476,14 @@ static void cell_jumps(const ctx2d* C, double t, const double* u, int64_t ix, in
 
 /* Damping exponents of one cell for every mode (p, q) (Sec. 2.3, mode-
  * dependent coefficient (para:damp22d)-(para:damp22d1); systems Sec. 2.4:
- * max over components; Euler (Sec. 2.4): (c_fx, c_fy) =
- * (m_x beta_x, m_y beta_y) / (4 lambda_pq H-bar)).  Reading of the mesh
- * factors (m_x, m_y): the text prints (h_x, h_y), which makes the 2D
- * exponent h times the 1D one for the same jumps; cf_mesh = 0 (default)
- * takes (1, 1), with which the 2D filter of a state varying along one axis
- * on square cells is exactly the 1D filter; cf_mesh = 1 takes the printed
- * factors.  Reading for Q^k: the
- * sums over |alpha| = m run over alpha1, alpha2 <= k.  Em[m] receives the
- * exponent of mode index m; eta the hybrid indicator (Reading:
+ * max over components; Euler: (c_fx, c_fy) = (m_x beta_x, m_y beta_y) /
+ * (4 lambda_pq H-bar)).  The mesh factors (m_x, m_y) are (h_x, h_y) as
+ * printed in Sec. 2.4 (cf_reading 0), (h_y, h_x) as printed for the Euler
+ * examples of Sec. 3.2 (cf_reading 1; the two agree on square cells), or
+ * (1, 1) (cf_reading 2, with which the 2D filter of a state varying along
+ * one axis on square cells is exactly the 1D filter).  Reading for Q^k:
+ * the sums over |alpha| = m run over alpha1, alpha2 <= k.  Em[m] receives
+ * the exponent of mode index m; eta the hybrid indicator (Reading:
  * Jx/(2hx) + Jy/(2hy), max over components, which reduces to Algorithm 1's
  * indicator for data varying along one axis only). */
 static void cell_exponents(const ctx2d* C, double t, double dt, const double* u, int64_t ix,
@@ -502,8 +505,8 @@ static void cell_exponents(const ctx2d* C, double t, double dt, const double* u,
                 continue;
             }
             double lam = p * (p + 1.0) + q * (q + 1.0);
-            double sc = P->cf_scale > 0.0 ? P->cf_scale : 1.0;
-            double mx = (P->cf_mesh ? C->hx : 1.0) * sc, my = (P->cf_mesh ? C->hy : 1.0) * sc;
+            double mx = P->cf_reading == 0 ? C->hx : P->cf_reading == 1 ? C->hy : 1.0;
+            double my = P->cf_reading == 0 ? C->hy : P->cf_reading == 1 ? C->hx : 1.0;
             double cfx = mx * bx / (4.0 * lam * H);
             double cfy = my * by / (4.0 * lam * H);
             double sig = 0.0;
@@ -572,7 +575,7 @@ int dgref_post2d(const dgref_problem2d* P, int stage, double t, double dt, const
     const size_t ndof = (size_t)C.nv * C.NM * ncell;
     if (P->filter == DGREF_FILTER_NONE) {
         if (out != v) memcpy(out, v, sizeof(double) * ndof);
-        return DGREF_OK;
+        return P->pp ? dgref_pp_limit2d(P, out) : DGREF_OK;
     }
     double tau = (P->filter_dt == 1) ? dt * stage_weight[stage] : dt;
     double* Em = (double*)malloc(sizeof(double) * ncell * C.NM);
@@ -613,12 +616,210 @@ int dgref_post2d(const dgref_problem2d* P, int stage, double t, double dt, const
     if (troubled) *troubled += cnt;
     free(Em);
     free(eta);
+    return P->pp ? dgref_pp_limit2d(P, out) : DGREF_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Positivity-preserving limiter on rectangles (Zhang and Shu; the paper     */
+/* applies it after the jump filter in its Sec. 3.2 examples with extreme    */
+/* positivity demands)                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Test points: the tensor sets (Gauss-Lobatto in xi) x (Gauss in eta) and
+ * (Gauss in xi) x (Gauss-Lobatto in eta), with N = ceil((k+3)/2) Lobatto
+ * points (the ends +-1 and, for N = 3, the centre 0): the Q^k cell average
+ * is a convex combination of the values there, and they contain the edge
+ * Gauss points where the fluxes are evaluated.  The Gauss x Gauss points of
+ * the volume quadrature are added, so the volume fluxes also see admissible
+ * states.  px[i][p] = P_p(xi_i), py[i][q] = P_q(eta_i), taken from the
+ * tables the DG operator uses, so a value here is bitwise the value the
+ * fluxes see. */
+static int pp_tables2d(const ctx2d* C, double px[][MAXK + 1], double py[][MAXK + 1], double* xi,
+                       double* eta)
+{
+    const int K1 = C->K1, nq = C->B.nq;
+    const int N = (C->k + 4) / 2 < 2 ? 2 : (C->k + 4) / 2;
+    double gl[3][MAXK + 1], glx[3];
+    for (int l = 0; l < K1; ++l) {
+        gl[0][l] = C->B.tr[0][l][0];
+        gl[1][l] = C->B.tr[1][l][0];
+        gl[2][l] = dgref_legendre_deriv(l, 0, 0.0);
+    }
+    glx[0] = -1.0;
+    glx[1] = 1.0;
+    glx[2] = 0.0;
+    int cnt = 0;
+    for (int dir = 0; dir < 2; ++dir)
+        for (int i = 0; i < N; ++i)
+            for (int b = 0; b < nq; ++b, ++cnt) {
+                const double* lob = gl[i];
+                const double* gau = C->B.phi[b];
+                for (int l = 0; l < K1; ++l) {
+                    px[cnt][l] = dir == 0 ? lob[l] : gau[l];
+                    py[cnt][l] = dir == 0 ? gau[l] : lob[l];
+                }
+                if (xi) xi[cnt] = dir == 0 ? glx[i] : C->B.xq[b];
+                if (eta) eta[cnt] = dir == 0 ? C->B.xq[b] : glx[i];
+            }
+    for (int a = 0; a < nq; ++a)
+        for (int b = 0; b < nq; ++b, ++cnt) {
+            for (int l = 0; l < K1; ++l) {
+                px[cnt][l] = C->B.phi[a][l];
+                py[cnt][l] = C->B.phi[b][l];
+            }
+            if (xi) xi[cnt] = C->B.xq[a];
+            if (eta) eta[cnt] = C->B.xq[b];
+        }
+    return cnt;
+}
+
+int dgref_pp_points2d(const dgref_problem2d* P, double* xi, double* eta)
+{
+    ctx2d C;
+    int rc = make_ctx(P, &C);
+    if (rc) return rc;
+    double px[PPMAX][MAXK + 1], py[PPMAX][MAXK + 1];
+    return pp_tables2d(&C, px, py, xi, eta);
+}
+
+static double pressure_pp2d(double gamma, const double* w)
+{
+    return (gamma - 1.0) * (w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0]);
+}
+
+/* The pressure as the flux and the wave speed evaluate it (flux2d). */
+static double pressure_flux_pp2d(double gamma, const double* w)
+{
+    const double vx = w[1] / w[0], vy = w[2] / w[0];
+    return (gamma - 1.0) * (w[3] - 0.5 * (w[1] * vx + w[2] * vy));
+}
+
+/* Point value w and the sums wa of the magnitudes of its terms. */
+static void point_value_abs(const ctx2d* C, const double* u, int64_t ix, int64_t jy,
+                            const double* px, const double* py, double* w, double* wa)
+{
+    for (int v = 0; v < 4; ++v) {
+        double s = 0.0, sa = 0.0;
+        for (int p = 0; p < C->K1; ++p)
+            for (int q = 0; q < C->K1; ++q) {
+                const double term = U(C, u, v, p * C->K1 + q, ix, jy) * px[p] * py[q];
+                s += term;
+                sa += fabs(term);
+            }
+        w[v] = s;
+        wa[v] = sa;
+    }
+}
+
+/* Limit cell (ix, jy) in place, as the 1D limiter does: scale the density's
+ * higher modes so the density at every test point is >= eps_r, then all
+ * higher modes so the pressure at each point is >= eps_p (bisection for the
+ * largest t in [0,1] with p(u_bar + t (u(x) - u_bar)) >= eps_p; p is concave
+ * along the segment); eps = min(1e-13, rho_bar, p(u_bar)), raised per point
+ * to its rounding margin (8 units of roundoff times the magnitudes that
+ * cancel), which vanishes in exact arithmetic.  The scaled cell is then
+ * checked in the fluxes' own arithmetic, its higher modes halved until the
+ * density and pressure are positive at every point (dropped after 50
+ * halvings).  Cell averages are not changed. */
+static void pp_limit_cell2d(const ctx2d* C, double* u, int64_t ix, int64_t jy, int np,
+                            double px[][MAXK + 1], double py[][MAXK + 1])
+{
+    const double gamma = C->P->gamma, ur = 0x1p-52;
+    double ub[4];
+    for (int v = 0; v < 4; ++v) ub[v] = U(C, u, v, 0, ix, jy);
+    const double pb = pressure_pp2d(gamma, ub);
+    if (!(ub[0] > 0.0) || !(pb > 0.0)) return; /* inadmissible average: not limitable */
+    double eps = 1e-13;
+    if (ub[0] < eps) eps = ub[0];
+    if (pb < eps) eps = pb;
+    /* density */
+    double rmin = INFINITY, eps_r = eps;
+    for (int i = 0; i < np; ++i) {
+        double w[4], wa[4];
+        point_value_abs(C, u, ix, jy, px[i], py[i], w, wa);
+        if (w[0] < rmin) rmin = w[0];
+        if (8.0 * ur * wa[0] > eps_r) eps_r = 8.0 * ur * wa[0];
+    }
+    if (eps_r > ub[0]) eps_r = ub[0];
+    if (rmin < eps_r) {
+        double th = (ub[0] - eps_r) / (ub[0] - rmin);
+        if (th < 0.0) th = 0.0;
+        for (int m = 1; m < C->NM; ++m) *Up(C, u, 0, m, ix, jy) *= th;
+    }
+    /* pressure */
+    double theta = 1.0;
+    for (int i = 0; i < np; ++i) {
+        double w[4], wa[4];
+        point_value_abs(C, u, ix, jy, px[i], py[i], w, wa);
+        double eps_p = eps;
+        if (w[0] > 0.0) {
+            const double kin = 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0];
+            const double m = 8.0 * ur *
+                             (wa[3] + (fabs(w[1]) * wa[1] + fabs(w[2]) * wa[2]) / w[0] +
+                              kin * wa[0] / w[0]);
+            if (m > eps_p) eps_p = m;
+        }
+        if (eps_p > pb) eps_p = pb;
+        if (pressure_pp2d(gamma, w) >= eps_p) continue;
+        double lo = 0.0, hi = 1.0;
+        for (int it = 0; it < 60; ++it) {
+            double mid = 0.5 * (lo + hi), wm[4];
+            for (int v = 0; v < 4; ++v) wm[v] = ub[v] + mid * (w[v] - ub[v]);
+            if (pressure_pp2d(gamma, wm) >= eps_p)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        if (lo < theta) theta = lo;
+    }
+    if (theta < 1.0)
+        for (int v = 0; v < 4; ++v)
+            for (int m = 1; m < C->NM; ++m) *Up(C, u, v, m, ix, jy) *= theta;
+    /* positivity in the fluxes' own arithmetic */
+    for (int halving = 0; halving <= 50; ++halving) {
+        int ok = 1;
+        for (int i = 0; i < np && ok; ++i) {
+            double w[4];
+            point_value(C, u, ix, jy, px[i], py[i], w);
+            ok = w[0] > 0.0 && pressure_flux_pp2d(gamma, w) > 0.0;
+        }
+        if (ok) return;
+        const double f = halving < 50 ? 0.5 : 0.0;
+        for (int v = 0; v < 4; ++v)
+            for (int m = 1; m < C->NM; ++m) *Up(C, u, v, m, ix, jy) *= f;
+    }
+}
+
+int dgref_pp_limit2d(const dgref_problem2d* P, double* u)
+{
+    ctx2d C;
+    int rc = make_ctx(P, &C);
+    if (rc) return rc;
+    if (P->eq != DGREF_EULER) return DGREF_OK;
+    double px[PPMAX][MAXK + 1], py[PPMAX][MAXK + 1];
+    const int np = pp_tables2d(&C, px, py, NULL, NULL);
+#pragma omp parallel for schedule(static) if (C.nx * C.ny >= 4096)
+    for (int64_t jy = 0; jy < C.ny; ++jy)
+        for (int64_t ix = 0; ix < C.nx; ++ix) pp_limit_cell2d(&C, u, ix, jy, np, px, py);
     return DGREF_OK;
+}
+
+static int averages_admissible2d(const ctx2d* C, const double* u)
+{
+    for (int64_t jy = 0; jy < C->ny; ++jy)
+        for (int64_t ix = 0; ix < C->nx; ++ix) {
+            double w[4];
+            for (int v = 0; v < 4; ++v) w[v] = U(C, u, v, 0, ix, jy);
+            if (!(w[0] > 0.0) || !(pressure_pp2d(C->P->gamma, w) > 0.0)) return 0;
+        }
+    return 1;
 }
 
 /* One SSP-RK3 step from time t with the post-stage operator after every
  * stage; the filter after stage s uses the time its output stands for,
- * t + (1, 1/2, 1)[s] dt, for time-dependent boundary states. */
+ * t + (1, 1/2, 1)[s] dt, for time-dependent boundary states.  With the
+ * positivity limiter a rejected step returns DGREF_ERR_POSITIVITY and leaves
+ * u and troubled untouched. */
 int dgref_step2d(const dgref_problem2d* P, double t, double dt, double* u, int64_t* troubled)
 {
     static const double cf[3] = {1.0, 0.5, 1.0};
@@ -635,11 +836,17 @@ int dgref_step2d(const dgref_problem2d* P, double t, double dt, double* u, int64
     }
     memcpy(un, u, sizeof(double) * ndof);
     memcpy(us, u, sizeof(double) * ndof);
+    const int64_t tr0 = troubled ? *troubled : 0;
     for (int s = 0; s < 3 && !rc; ++s) {
         rc = dgref_stage2d(P, s, t, dt, un, us, w);
         if (!rc) rc = dgref_post2d(P, s, t + cf[s] * dt, dt, w, us, troubled);
+        /* positivity limiter: a stage whose cell averages leave the
+         * admissible set rejects the step (u untouched; retried by the
+         * caller with a smaller dt) */
+        if (!rc && P->pp && !averages_admissible2d(&C, us)) rc = DGREF_ERR_POSITIVITY;
     }
     if (!rc) memcpy(u, us, sizeof(double) * ndof);
+    else if (troubled) *troubled = tr0;
 done:
     free(un);
     free(us);
@@ -684,11 +891,21 @@ int dgref_check2d(const dgref_problem2d* P, const double* u, double* min_rho, do
                     double p = pressure2d(P, uq);
                     if (uq[0] < mr) mr = uq[0];
                     if (p < mp) mp = p;
-                    if ((!(uq[0] > 0.0) || !(p > 0.0)) && status == DGREF_OK) {
+                    if ((!(uq[0] > 0.0) || !(p > 0.0)) && status == DGREF_OK && !P->pp) {
                         status = DGREF_ERR_POSITIVITY;
                         bad = cell;
                     }
                 }
+            /* with the positivity limiter, point values sit at its margin
+             * up to rounding: only an inadmissible cell average is an error */
+            if (P->pp && status == DGREF_OK) {
+                double w[4];
+                for (int v = 0; v < 4; ++v) w[v] = U(&C, u, v, 0, ix, jy);
+                if (!(w[0] > 0.0) || !(pressure2d(P, w) > 0.0)) {
+                    status = DGREF_ERR_POSITIVITY;
+                    bad = cell;
+                }
+            }
         }
     if (min_rho) *min_rho = mr;
     if (min_p) *min_p = mp;
@@ -722,6 +939,16 @@ int dgref_run2d(const dgref_problem2d* P, double t_end, int64_t max_steps, doubl
             last = 1;
         }
         rc = dgref_step2d(P, t, dt, u, &r.troubled_cells);
+        /* positivity limiter: a rejected step is retried with half the time
+         * step (Zhang and Shu's remedy when a stage violates the CFL bound
+         * of the positivity argument) */
+        for (int tries = 0; rc == DGREF_ERR_POSITIVITY && P->pp && tries < DGREF_MAX_RETRIES;
+             ++tries) {
+            dt *= 0.5;
+            last = 0;
+            r.restarts++;
+            rc = dgref_step2d(P, t, dt, u, &r.troubled_cells);
+        }
         if (rc) break;
         t = last ? t_end : t + dt;
         r.steps++;

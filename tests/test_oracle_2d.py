@@ -3,9 +3,10 @@
 The strongest pins reduce the 2D scheme to the separately pinned 1D oracle:
 for data that vary along one axis only, the 2D residual equals the 1D
 residual, the 2D hybrid indicator equals the 1D one, and the 2D damping
-exponent equals the 1D exponent times h_x/h_y (the factor (2/h_x)(2/h_y)
-replaces (2/h)^2; on square cells the two filters coincide) -- or times
-h_x^2/h_y with the mesh factor h_x in c_fx as printed in Sec. 2.4.
+exponent equals the 1D exponent times m_x h_x/h_y, with m_x the mesh factor
+of c_fx: h_x as printed in Sec. 2.4 (the default), h_y as printed in Sec. 3.2,
+or 1 (the factor (2/h_x)(2/h_y) replaces (2/h)^2; with m_x = 1 on square
+cells the two filters coincide).
 Further pins: free-stream
 preservation with every boundary type, conservation, mode 0 untouched,
 exponents depending on p+q only, zero jumps for global polynomials, the
@@ -63,8 +64,10 @@ def test_reduces_to_1d_along_x(ref, k, bc):
         return
     dt = 1e-3
     E1, eta1 = ref.exponents1d(P1, dt, u1)
-    for cf_mesh, factor in ((0, hx / hy), (1, hx * hx / hy)):
-        P2 = ref.problem2d(2, k, n, ny, 0.0, 1.0, 0.0, 0.3, bc=(bc, bc, 0, 0), cf_mesh=cf_mesh)
+    # mesh factors (m_x, m_y) of (c_fx, c_fy): the exponent of x-only data is
+    # the 1D one times m_x h_x / h_y
+    for reading, factor in ((0, hx * hx / hy), (1, hx), (2, hx / hy)):
+        P2 = ref.problem2d(2, k, n, ny, 0.0, 1.0, 0.0, 0.3, bc=(bc, bc, 0, 0), cf_reading=reading)
         E2, eta2 = ref.exponents2d(P2, dt, u2)
         np.testing.assert_allclose(eta2, np.broadcast_to(eta1, eta2.shape), rtol=1e-13, atol=1e-300)
         want = E1 * factor
@@ -92,9 +95,11 @@ def test_reduces_to_1d_along_y(ref, k, bc):
         assert np.max(np.abs(got - L1[v1][:, :, None])) <= 1e-13 * scale
     dt = 1e-3
     E1, eta1 = ref.exponents1d(P1, dt, u1)
-    E2, eta2 = ref.exponents2d(P2, dt, u2)
-    np.testing.assert_allclose(eta2, np.broadcast_to(eta1[:, None], eta2.shape), rtol=1e-13)
-    np.testing.assert_allclose(E2[:, 0, : k + 1], E1 * hy / hx, rtol=1e-12, atol=1e-300)
+    for reading, factor in ((0, hy * hy / hx), (1, hy), (2, hy / hx)):
+        P2 = ref.problem2d(2, k, nx, n, 0.0, 0.5, -1.0, 1.0, bc=(0, 0, bc, bc), cf_reading=reading)
+        E2, eta2 = ref.exponents2d(P2, dt, u2)
+        np.testing.assert_allclose(eta2, np.broadcast_to(eta1[:, None], eta2.shape), rtol=1e-13)
+        np.testing.assert_allclose(E2[:, 0, : k + 1], E1 * factor, rtol=1e-12, atol=1e-300)
 
 
 def test_advection_reduces_to_1d(ref):
