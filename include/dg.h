@@ -103,20 +103,27 @@ typedef struct {
     double adv_speed[2];     /* advection velocity (DG_EQ_ADVECTION)              */
     int quad_points;         /* Gauss points per direction; 0 or degree+1         */
     void* stream;            /* hipStream_t; NULL = null stream                   */
-    int cf_mesh_factor;      /* 2D damping coefficient (c_fx, c_fy):
-                                0 (default): beta_x / (4 lambda H), beta_y / (4 lambda H),
-                                  so a one-dimensional state is filtered exactly as
-                                  by the 1D filter;
-                                1: times (h_x, h_y) as printed in Sec. 2.4 */
-    int positivity;          /* 1D Euler: 1 = Zhang-Shu positivity-preserving limiter
+    int cf_reading;          /* mesh factors (m_x, m_y) of the 2D Euler damping
+                                coefficient (c_fx, c_fy) = (m_x beta_x, m_y beta_y) /
+                                (4 lambda_pq H-bar) (Sec. 2.4, (para:damp22d1)):
+                                0 (default): (h_x, h_y), as printed in Sec. 2.4;
+                                1: (h_y, h_x), as printed for the Euler examples
+                                   of Sec. 3.2 (equal to 0 on square cells);
+                                2: (1, 1), no mesh factors (a state varying along
+                                   one axis of square cells is then filtered
+                                   exactly as by the 1D filter).
+                                Other values: DG_ERR_ARG. */
+    int positivity;          /* Euler: 1 = Zhang-Shu positivity-preserving limiter
                                 after the post-stage operator (Sec. 3.2 uses it for
                                 extreme cases): density and pressure kept positive at
-                                each cell's Gauss-Lobatto and Gauss points.  A step
+                                each cell's test points -- 1D: the Gauss-Lobatto and
+                                Gauss points; 2D: (Gauss-Lobatto x Gauss), (Gauss x
+                                Gauss-Lobatto) and the Gauss x Gauss points.  A step
                                 whose stage leaves an inadmissible cell average is
                                 undone and retried with half the time step (at most
                                 40 times; then the run stops with DG_ERR_POSITIVITY).
                                 Positivity reports then concern cell averages only.
-                                0 = off.  Other equations / 2D: DG_ERR_UNSUPPORTED. */
+                                0 = off.  Other equations: DG_ERR_UNSUPPORTED. */
     int basis;               /* 2D space (Sec. 2.3): 0 = Q^k tensor product (modes
                                 p, q <= k); 1 = P^k total degree (p + q <= k), the
                                 paper's own space.  Both keep the Q^k layout; with P^k

@@ -14,8 +14,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdg.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2407_19169_amd.build` "
-                      "(or __graft_entry__.build()) first")
+    raise ImportError(f"{LIB_PATH} is not built; run `python __graft_entry__.py` "
+                      "(__graft_entry__.build()) first")
 
 _lib = C.CDLL(LIB_PATH)
 
@@ -40,7 +40,7 @@ class dg_mesh(C.Structure):
 class dg_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("filter", C.c_int), ("cfl", C.c_double),
                 ("gamma", C.c_double), ("adv_speed", C.c_double * 2),
-                ("quad_points", C.c_int), ("stream", C.c_void_p), ("cf_mesh_factor", C.c_int),
+                ("quad_points", C.c_int), ("stream", C.c_void_p), ("cf_reading", C.c_int),
                 ("positivity", C.c_int), ("basis", C.c_int), ("flux", C.c_int)]
 
 
@@ -138,11 +138,11 @@ def make_mesh(dim, n, lo, hi, bc, dirichlet=None, shock_x0=0.0, shock_speed=0.0,
 
 
 def make_options(precision=DG_PREC_FP64, filter=DG_FILTER_JUMP, cfl=0.1, gamma=1.4,
-                 adv_speed=(1.0, 0.0), quad_points=0, stream=None, cf_mesh_factor=0,
+                 adv_speed=(1.0, 0.0), quad_points=0, stream=None, cf_reading=0,
                  positivity=0, basis=0, flux=DG_FLUX_LLF) -> dg_options:
     o = dg_options()
     o.flux = flux
-    o.cf_mesh_factor = cf_mesh_factor
+    o.cf_reading = cf_reading
     o.positivity = positivity
     o.basis = basis
     o.precision, o.filter, o.cfl, o.gamma = precision, filter, cfl, gamma

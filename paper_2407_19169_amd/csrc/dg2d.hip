@@ -276,6 +276,247 @@ __device__ __forceinline__ void xcd_tile(int64_t gx, int64_t ntiles, int64_t& bx
     by = l / gx;
 }
 
+// ---------------------------------------------------------------------------
+// Positivity-preserving limiter on rectangles (Zhang and Shu), applied after
+// the jump filter / hybrid limiter (the paper's Sec. 3.2 examples with
+// extreme positivity demands).  Test points: (Gauss-Lobatto x Gauss) and
+// (Gauss x Gauss-Lobatto) with N = ceil((k+3)/2) Lobatto points (the Q^k
+// cell average is a convex combination of the values at the first set, and
+// the sets contain the edge Gauss points of the fluxes), then the Gauss x
+// Gauss points of the volume quadrature.
+template <int K>
+struct PP2DPoints {
+    static constexpr int Q = K + 1;
+    static constexpr int N = (K + 4) / 2 < 2 ? 2 : (K + 4) / 2;
+    static constexpr int NP = 2 * N * Q + Q * Q;
+};
+
+// P_l at Lobatto node i: 0 -> -1, 1 -> +1, 2 -> 0.
+__device__ __forceinline__ constexpr double lob_leg(int i, int l)
+{
+    return i == 0 ? ((l & 1) ? -1.0 : 1.0) : i == 1 ? 1.0 : (l == 0 ? 1.0 : l == 2 ? -0.5 : 0.0);
+}
+
+// P_p(xi) (dir 0) or P_q(eta) (dir 1) at test point i.
+template <int K>
+__device__ __forceinline__ constexpr double pp2_leg(int i, int dir, int l)
+{
+    constexpr int Q = PP2DPoints<K>::Q, N = PP2DPoints<K>::N;
+    if (i < 2 * N * Q) {
+        const int set = i / (N * Q), r = i % (N * Q), lob = r / Q, g = r % Q;
+        return (set == dir) ? lob_leg(lob, l) : leg_at(Q, g, l);
+    }
+    const int r = i - 2 * N * Q;
+    return leg_at(Q, dir == 0 ? r / Q : r % Q, l);
+}
+
+// The modes of one cell: FP64 averages u0[v] and the TB modes uh[v][m]
+// (m = p (K+1) + q >= 1; the entries of m = 0 and of modes outside P^k are
+// zero and never used).
+template <int K, typename TB>
+struct Cell2D {
+    static constexpr int NM = (K + 1) * (K + 1);
+    double u0[4];
+    TB uh[4][NM];
+};
+
+template <int K, bool PK, typename TB>
+__device__ __forceinline__ void pp2_point(const Cell2D<K, TB>& c, int i, double (&w)[4], double (&wa)[4])
+{
+    constexpr int K1 = K + 1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        double sum = c.u0[v], sa = fabs(c.u0[v]);
+#pragma unroll
+        for (int m = 1; m < K1 * K1; ++m) {
+            if (!mode_kept<K, PK>(m)) continue;
+            const double t = ((double)c.uh[v][m] * pp2_leg<K>(i, 0, m / K1)) * pp2_leg<K>(i, 1, m % K1);
+            sum += t;
+            sa += fabs(t);
+        }
+        w[v] = sum;
+        wa[v] = sa;
+    }
+}
+
+__device__ __forceinline__ double pp2_pressure(double gamma, const double (&w)[4])
+{
+    return (gamma - 1.0) * (w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0]);
+}
+
+// True when the limiter provably leaves the cell unchanged: |P_p P_q| <= 1
+// on the cell, so rho_bar - sum |rho_pq| bounds the density and (gamma - 1)
+// (E_lo - (Mx_hi^2 + My_hi^2) / (2 rho_lo)) the pressure from below at every
+// point; both must exceed twice the largest threshold and rounding margin the
+// limiter could apply (as in the 1D screen).  ubar[v], sabs[v] = sum over the
+// modes >= 1 of |u_m| (FP64).
+template <typename TB>
+__device__ __forceinline__ bool pp2_clear(const double (&ubar)[4], const double (&sabs)[4], double gamma)
+{
+    constexpr double ur = sizeof(TB) == 4 ? 0x1p-23 : 0x1p-52;
+    const double rlo = ubar[0] - sabs[0], sr = fabs(ubar[0]) + sabs[0];
+    if (!(rlo > 2.0 * (1e-13 + 8.0 * ur * sr))) return false;
+    const double mx = fabs(ubar[1]) + sabs[1], my = fabs(ubar[2]) + sabs[2];
+    const double elo = ubar[3] - sabs[3], se = fabs(ubar[3]) + sabs[3];
+    const double kin = 0.5 * (mx * mx + my * my) / rlo;
+    const double plo = (gamma - 1.0) * (elo - kin);
+    const double mmax = 8.0 * ur * (se + 2.0 * kin + kin * sr / rlo);
+    return plo > 2.0 * (1e-13 + mmax);
+}
+
+// Limit one cell in place (the 1D limiter's steps on the 2D test points):
+// the density's modes >= 1 scaled so the density at every point is >= eps_r,
+// then all modes >= 1 so the pressure is >= eps_p (60 bisection steps on the
+// segment from the average to each point value, along which the pressure is
+// concave).  eps = min(1e-13, rho_bar, p_bar), raised per point to the
+// rounding margin of its value (8 units of roundoff of the modes' precision
+// times the magnitudes that cancel), which vanishes in exact arithmetic.
+// Finally the cell is checked in the fluxes' own arithmetic (precision TB,
+// pressure as the flux computes it) and its modes >= 1 halved until density
+// and pressure are positive at every point (dropped after 50 halvings).  The
+// averages never change; an inadmissible average is left to the caller.
+template <int K, bool PK, typename TB>
+__device__ __forceinline__ void pp2_limit(Cell2D<K, TB>& c, double gamma)
+{
+    constexpr int K1 = K + 1, NM = K1 * K1, NP = PP2DPoints<K>::NP;
+    constexpr double ur = sizeof(TB) == 4 ? 0x1p-23 : 0x1p-52;
+    const double pb = pp2_pressure(gamma, c.u0);
+    if (!(c.u0[0] > 0.0) || !(pb > 0.0)) return;
+    double eps = 1e-13;
+    if (c.u0[0] < eps) eps = c.u0[0];
+    if (pb < eps) eps = pb;
+    double eps_r = eps, rmin = INFINITY;
+    for (int i = 0; i < NP; ++i) {
+        double w[4], wa[4];
+        pp2_point<K, PK, TB>(c, i, w, wa);
+        if (w[0] < rmin) rmin = w[0];
+        if (8.0 * ur * wa[0] > eps_r) eps_r = 8.0 * ur * wa[0];
+    }
+    if (eps_r > c.u0[0]) eps_r = c.u0[0];
+    if (rmin < eps_r) {
+        double th = (c.u0[0] - eps_r) / (c.u0[0] - rmin);
+        if (th < 0.0) th = 0.0;
+#pragma unroll
+        for (int m = 1; m < NM; ++m) c.uh[0][m] = (TB)((double)c.uh[0][m] * th);
+    }
+    double theta = 1.0;
+    for (int i = 0; i < NP; ++i) {
+        double w[4], wa[4];
+        pp2_point<K, PK, TB>(c, i, w, wa);
+        double eps_i = eps;
+        if (w[0] > 0.0) {
+            const double kin = 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0];
+            const double m = 8.0 * ur * (wa[3] + (fabs(w[1]) * wa[1] + fabs(w[2]) * wa[2]) / w[0] +
+                                         kin * wa[0] / w[0]);
+            if (m > eps_i) eps_i = m;
+        }
+        if (eps_i > pb) eps_i = pb;
+        if (pp2_pressure(gamma, w) >= eps_i) continue;
+        double lo = 0.0, hi = 1.0;
+        for (int it = 0; it < 60; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            double wm[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) wm[v] = c.u0[v] + mid * (w[v] - c.u0[v]);
+            if (pp2_pressure(gamma, wm) >= eps_i)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        if (lo < theta) theta = lo;
+    }
+    if (theta < 1.0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int m = 1; m < NM; ++m) c.uh[v][m] = (TB)((double)c.uh[v][m] * theta);
+    }
+    for (int halving = 0; halving <= 50; ++halving) {
+        bool ok = true;
+        for (int i = 0; i < NP && ok; ++i) {
+            TB w[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                TB sum = (TB)c.u0[v];
+#pragma unroll
+                for (int m = 1; m < NM; ++m)
+                    if (mode_kept<K, PK>(m))
+                        sum += c.uh[v][m] * (TB)(pp2_leg<K>(i, 0, m / K1) * pp2_leg<K>(i, 1, m % K1));
+                w[v] = sum;
+            }
+            const TB ir = (TB)1 / w[0];
+            const TB pr = ((TB)gamma - (TB)1) * (w[3] - (TB)0.5 * (w[1] * (w[1] * ir) + w[2] * (w[2] * ir)));
+            ok = w[0] > (TB)0 && pr > (TB)0;
+        }
+        if (ok) break;
+        const TB f = halving < 50 ? (TB)0.5 : (TB)0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int m = 1; m < NM; ++m) c.uh[v][m] *= f;
+    }
+}
+
+template <int K, bool PK, typename TB>
+__device__ __forceinline__ void load_cell2d(const StateView<TB>& s, int64_t c, Cell2D<K, TB>& cell)
+{
+    constexpr int NM = (K + 1) * (K + 1);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        cell.u0[v] = s.m0[v * s.s0 + c];
+        cell.uh[v][0] = (TB)0;
+#pragma unroll
+        for (int m = 1; m < NM; ++m)
+            cell.uh[v][m] = mode_kept<K, PK>(m) ? s.hi[v * s.sv + (mode_plane<K, PK>(m) - 1) * s.sl + c] : (TB)0;
+    }
+}
+
+template <int K, bool PK, typename TB>
+__device__ __forceinline__ void store_cell2d_hi(const StateView<TB>& s, int64_t c, const Cell2D<K, TB>& cell)
+{
+    constexpr int NM = (K + 1) * (K + 1);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int m = 1; m < NM; ++m)
+            if (mode_kept<K, PK>(m)) s.hi[v * s.sv + (mode_plane<K, PK>(m) - 1) * s.sl + c] = cell.uh[v][m];
+}
+
+// Screen, then (if needed) limit one cell held by one thread; true when the
+// cell changed.  Flags *reject on an inadmissible average.
+template <int K, bool PK, typename TB>
+__device__ __forceinline__ bool pp2_cell(Cell2D<K, TB>& cell, double gamma, int* reject)
+{
+    constexpr int NM = (K + 1) * (K + 1);
+    double sabs[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        double t = 0.0;
+#pragma unroll
+        for (int m = 1; m < NM; ++m) t += fabs((double)cell.uh[v][m]);
+        sabs[v] = t;
+    }
+    if (pp2_clear<TB>(cell.u0, sabs, gamma)) return false;
+    pp2_limit<K, PK, TB>(cell, gamma);
+    if (!(cell.u0[0] > 0.0 && pp2_pressure(gamma, cell.u0) > 0.0) && reject) atomicOr(reject, 1);
+    return true;
+}
+
+// Screen of a cell held by NV = 4 adjacent lanes (lane v holds variable v:
+// FP64 average m0 and the sum of |modes >= 1|); true in every lane of the
+// cell when the limiter would leave it unchanged.
+template <typename TB>
+__device__ __forceinline__ bool pp2_clear_lanes(double m0, double sabs, int base, double gamma)
+{
+    double ub[4], sa[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        ub[w] = __shfl(m0, base + w, 64);
+        sa[w] = __shfl(sabs, base + w, 64);
+    }
+    return pp2_clear<TB>(ub, sa, gamma);
+}
+
 }  // namespace
 
 // -------------------------------------------------------------------------
@@ -318,6 +559,9 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
     T* sF = lds;
     T* sX = lds + HALF;
 
+    // the positivity limiter's list of this stage starts empty (the kernels
+    // that append to it and read it run after this one)
+    if (a.pcount && blockIdx.x == 0 && threadIdx.x == 0) *a.pcount = 0;
     if (a.dt_from_ctrl && a.ctrl->done) return;
     const double dt = a.dt_from_ctrl ? a.ctrl->dt : a.dt_host;
     const double t0 = a.dt_from_ctrl ? a.ctrl->t : a.t_host;
@@ -846,15 +1090,38 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
 #pragma unroll
         for (int l = 1; l < L1; ++l) f[l] = texp<T>(-E[l]);
         a.out.m0[v * a.out.s0 + cell] = m0v;
+        double sabs = 0.0;
 #pragma unroll
         for (int p = 0; p < K1; ++p)
 #pragma unroll
             for (int q = 0; q < K1; ++q) {
                 if ((p == 0 && q == 0) || (PK && p + q > K)) continue;
                 const int m = p * K1 + q;
-                a.out.hi[v * a.out.sv + (mode_plane<K, PK>(m) - 1) * a.out.sl + cell] = um[m] * f[p + q];
+                const T val = um[m] * f[p + q];
+                sabs += fabs((double)val);
+                a.out.hi[v * a.out.sv + (mode_plane<K, PK>(m) - 1) * a.out.sl + cell] = val;
             }
+        // positivity limiter: list the cells its screen does not clear
+        if constexpr (EQ == EULER) {
+            if (a.pp && !pp2_clear_lanes<TB>(m0v, sabs, tid - v, a.phys.gamma) && v == 0) {
+                const unsigned long long slot = atomicAdd(a.pcount, 1ull);
+                if ((long long)slot < a.pcap) a.pcell[slot] = cell;
+            }
+        }
     } else {
+        // positivity limiter: cells that stay unfiltered (eta <= 1) are final
+        // now; troubled cells are screened after their blend
+        if constexpr (EQ == EULER) {
+            if (a.pp) {
+                double sabs = 0.0;
+#pragma unroll
+                for (int m = 1; m < NM; ++m) sabs += fabs((double)um[m]);
+                if (!(eta > (T)1) && !pp2_clear_lanes<TB>(m0v, sabs, tid - v, a.phys.gamma) && v == 0) {
+                    const unsigned long long slot = atomicAdd(a.pcount, 1ull);
+                    if ((long long)slot < a.pcap) a.pcell[slot] = cell;
+                }
+            }
+        }
         if (v == 0) {
             if (a.eta_out) a.eta_out[cell] = (double)eta;
             if (eta > (T)1) {
@@ -871,12 +1138,14 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
     }
 }
 
-// Hybrid pass B over the troubled list: u^{pq} <- [w + (1 - w) exp(-E^{p+q})] u^{pq}.
+// Hybrid pass B over the troubled list: u^{pq} <- [w + (1 - w) exp(-E^{p+q})] u^{pq},
+// then (Euler, pp.on) the positivity limiter on the blended cell.
 template <int K, int NV, typename TB, bool PK>
 __global__ __launch_bounds__(256) void blend2d_kernel(StateView<TB> out, const unsigned int* count,
                                                       const long long* tcell, const double* tdata,
                                                       const unsigned long long* eta_bits,
-                                                      const Ctrl* ctrl, int from_ctrl, long long cap)
+                                                      const Ctrl* ctrl, int from_ctrl, long long cap,
+                                                      PPArgs pp)
 {
     constexpr int K1 = K + 1, L1 = 2 * K + 1;
     if (from_ctrl && ctrl->done) return;
@@ -890,6 +1159,19 @@ __global__ __launch_bounds__(256) void blend2d_kernel(StateView<TB> out, const u
         TB f[L1];
 #pragma unroll
         for (int l = 1; l < L1; ++l) f[l] = (TB)(w + (1.0 - w) * exp(-rec[l]));
+        if constexpr (NV == 4) {
+            if (pp.on) {
+                Cell2D<K, TB> cell;
+                load_cell2d<K, PK, TB>(out, c, cell);
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+#pragma unroll
+                    for (int m = 1; m < K1 * K1; ++m) cell.uh[v][m] *= f[m / K1 + m % K1];
+                pp2_cell<K, PK, TB>(cell, pp.phys.gamma, pp.reject);
+                store_cell2d_hi<K, PK, TB>(out, c, cell);
+                continue;
+            }
+        }
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -899,6 +1181,28 @@ __global__ __launch_bounds__(256) void blend2d_kernel(StateView<TB> out, const u
                     if ((p == 0 && q == 0) || (PK && p + q > K)) continue;
                     out.hi[v * out.sv + (mode_plane<K, PK>(p * K1 + q) - 1) * out.sl + c] *= f[p + q];
                 }
+    }
+}
+
+// Positivity limiter over the cells the post-stage kernels listed (or over
+// every cell when count is null), in place.
+template <int K, typename TB, bool PK>
+__global__ __launch_bounds__(256) void pp2d_kernel(StateView<TB> u, long long ncell,
+                                                   const unsigned long long* count, const long long* cells,
+                                                   long long cap, const Ctrl* ctrl, int from_ctrl, PPArgs pp)
+{
+    if (from_ctrl && ctrl->done) return;
+    long long cnt = ncell;
+    if (count) {
+        const unsigned long long c = *count;
+        cnt = (long long)c < cap ? (long long)c : cap;
+    }
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long c = count ? cells[i] : i;
+        Cell2D<K, TB> cell;
+        load_cell2d<K, PK, TB>(u, c, cell);
+        if (pp2_cell<K, PK, TB>(cell, pp.phys.gamma, pp.reject)) store_cell2d_hi<K, PK, TB>(u, c, cell);
     }
 }
 
@@ -1030,7 +1334,7 @@ template <typename TB>
 hipError_t launch_blend2d(int nv, int k, StateView<TB> out, int64_t ncell, const unsigned int* count,
                           const long long* tcell, const double* tdata,
                           const unsigned long long* eta_bits, const Ctrl* ctrl, int from_ctrl,
-                          int64_t max_entries, int pk, hipStream_t st)
+                          int64_t max_entries, int pk, PPArgs pp, hipStream_t st)
 {
     unsigned g = (unsigned)((max_entries + 255) / 256);
     if (g > 2048) g = 2048;
@@ -1040,17 +1344,43 @@ hipError_t launch_blend2d(int nv, int k, StateView<TB> out, int64_t ncell, const
         if (pk)                                                                                   \
             hipLaunchKernelGGL((blend2d_kernel<K_, NV_, TB, (K_ > 0)>), dim3(g), dim3(256), 0, st, \
                                out, count, tcell, tdata, eta_bits, ctrl, from_ctrl,              \
-                               (long long)max_entries);                                           \
+                               (long long)max_entries, pp);                                       \
         else                                                                                      \
             hipLaunchKernelGGL((blend2d_kernel<K_, NV_, TB, false>), dim3(g), dim3(256), 0, st,   \
                                out, count, tcell, tdata, eta_bits, ctrl, from_ctrl,              \
-                               (long long)max_entries);                                           \
+                               (long long)max_entries, pp);                                       \
         return hipGetLastError();                                                                 \
     }
     DG_CASE(1, 0) DG_CASE(1, 1) DG_CASE(1, 2) DG_CASE(1, 3)
     DG_CASE(4, 0) DG_CASE(4, 1) DG_CASE(4, 2) DG_CASE(4, 3)
 #undef DG_CASE
     (void)ncell;
+    return hipErrorInvalidValue;
+}
+
+template <typename TB>
+hipError_t launch_pp2d(int k, StateView<TB> u, int64_t ncell, const unsigned long long* count,
+                       const long long* cells, int64_t cap, const Ctrl* ctrl, int from_ctrl, int pk,
+                       PPArgs pp, hipStream_t st)
+{
+    // listed cells: a grid sized for a few percent of the mesh, grid-stride
+    // beyond; every cell: one thread per cell up to the same cap of blocks
+    const int64_t span = count ? (cap + 31) / 32 : ncell;
+    int64_t g = (span + 255) / 256;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+#define DG_CASE(K_)                                                                                \
+    if (k == K_) {                                                                                 \
+        if (pk)                                                                                    \
+            hipLaunchKernelGGL((pp2d_kernel<K_, TB, (K_ > 0)>), dim3((unsigned)g), dim3(256), 0, st, u, \
+                               (long long)ncell, count, cells, (long long)cap, ctrl, from_ctrl, pp); \
+        else                                                                                       \
+            hipLaunchKernelGGL((pp2d_kernel<K_, TB, false>), dim3((unsigned)g), dim3(256), 0, st, u,  \
+                               (long long)ncell, count, cells, (long long)cap, ctrl, from_ctrl, pp); \
+        return hipGetLastError();                                                                  \
+    }
+    DG_CASE(0) DG_CASE(1) DG_CASE(2) DG_CASE(3)
+#undef DG_CASE
     return hipErrorInvalidValue;
 }
 
@@ -1076,7 +1406,10 @@ hipError_t launch_maxwave2d(int eq, StateView<TB> u, int64_t nx, int64_t ny, dou
     template hipError_t launch_blend2d<TB>(int, int, StateView<TB>, int64_t, const unsigned int*, \
                                            const long long*, const double*,                      \
                                            const unsigned long long*, const Ctrl*, int, int64_t, \
-                                           int, hipStream_t);                                    \
+                                           int, PPArgs, hipStream_t);                            \
+    template hipError_t launch_pp2d<TB>(int, StateView<TB>, int64_t, const unsigned long long*,  \
+                                        const long long*, int64_t, const Ctrl*, int, int, PPArgs,\
+                                        hipStream_t);                                            \
     template hipError_t launch_convert_pk2d<TB>(int, int, int, int64_t, const double*,           \
                                                 StateView<TB>, hipStream_t);                      \
     template hipError_t launch_maxwave2d<TB>(int, StateView<TB>, int64_t, int64_t, double, double, \

@@ -25,7 +25,7 @@ struct dg_solver {
     int64_t ncell, n_pad;
     double h[2], inv_h[2];
     size_t state_bytes, ws_bytes;
-    size_t off_w, off_E, off_eta, off_tcell, off_tdata, off_aux;
+    size_t off_w, off_E, off_eta, off_tcell, off_tdata, off_aux, off_pcell;
     size_t off_dv, dv_slot;  // deferred hybrid blend: 4 slots of eta[n] + E[k][n]
     void* u[3];
     unsigned char* ws;
@@ -143,12 +143,24 @@ Args2D<TB> base_args2d(const dg_solver* s)
     a.phys.flux = s->opt.flux;
     a.phys.a[0] = s->opt.adv_speed[0];
     a.phys.a[1] = s->opt.adv_speed[1];
-    a.check = s->eq == DG_EQ_EULER;
+    // with the positivity limiter, point values sit at its margin: the
+    // stage kernel's point check is off and only averages are checked
+    a.check = s->eq == DG_EQ_EULER && !s->opt.positivity;
     a.ctrl = ctrl_of(s);
     a.tcap = s->ncell;
     a.pk = s->pk;
-    a.cfmx = s->opt.cf_mesh_factor ? a.hx : 1.0;
-    a.cfmy = s->opt.cf_mesh_factor ? a.hy : 1.0;
+    if (s->opt.positivity) {
+        a.pp = 1;
+        a.pcount = &ctrl_of(s)->pcount.v;
+        a.pcell = reinterpret_cast<long long*>(s->ws + s->off_pcell);
+        a.pcap = s->ncell;
+        a.reject = &ctrl_of(s)->reject;
+    }
+    // mesh factors of (c_fx, c_fy): (hx, hy) printed in Sec. 2.4, (hy, hx)
+    // printed in Sec. 3.2, or none
+    const int rd = s->opt.cf_reading;
+    a.cfmx = rd == 0 ? a.hx : rd == 1 ? a.hy : 1.0;
+    a.cfmy = rd == 0 ? a.hy : rd == 1 ? a.hx : 1.0;
     // jump weights of the multi-index (a1, a2), m = a1 + a2: hx (m = 0),
     // m(m+1) hx^(m+1) (2/hx)^a1 (2/hy)^a2 (x edges); likewise with hy
     for (int a1 = 0; a1 < 4; ++a1)
@@ -195,8 +207,12 @@ int filter_impl(dg_solver* s, int stage, double dt)
                               s->user_st));
         if (s->opt.positivity) {
             const StateView<TB> t = view_of<TB>(s, target);
-            DG_HIP(launch_blend_all1d<TB>(s->nv, s->k, t, t, s->ncell, nullptr, nullptr, nullptr,
-                                          nullptr, pp_args<TB>(s), s->user_st));
+            if (s->dim == 2)
+                DG_HIP(launch_pp2d<TB>(s->k, t, s->ncell, nullptr, nullptr, s->ncell, ctrl_of(s), 0,
+                                       s->pk, pp_args<TB>(s), s->user_st));
+            else
+                DG_HIP(launch_blend_all1d<TB>(s->nv, s->k, t, t, s->ncell, nullptr, nullptr, nullptr,
+                                              nullptr, pp_args<TB>(s), s->user_st));
         }
         return DG_OK;
     }
@@ -206,10 +222,14 @@ int filter_impl(dg_solver* s, int stage, double dt)
         a.dt_host = dt;
         a.t_host = 0.0;
         a.E_out = reinterpret_cast<double*>(s->ws + s->off_E);
+        if (a.pp) DG_HIP(hipMemsetAsync(a.pcount, 0, sizeof *a.pcount, s->user_st));
         if (s->opt.filter == DG_FILTER_JUMP) {
             a.us = view_of<TB>(s, s->ws + s->off_w);
             a.out = view_of<TB>(s, target);
             DG_HIP(launch_filter2d<TB>(s->eq, s->k, a, 1, s->user_st));
+            if (a.pp)
+                DG_HIP(launch_pp2d<TB>(s->k, a.out, s->ncell, a.pcount, a.pcell, a.pcap, ctrl_of(s), 0,
+                                       s->pk, pp_args<TB>(s), s->user_st));
             return DG_OK;
         }
         // hybrid: the unfiltered output goes to the target, pass A records
@@ -229,7 +249,10 @@ int filter_impl(dg_solver* s, int stage, double dt)
         a.eta_out = reinterpret_cast<double*>(s->ws + s->off_eta);
         DG_HIP(launch_filter2d<TB>(s->eq, s->k, a, 2, s->user_st));
         DG_HIP(launch_blend2d<TB>(s->nv, s->k, a.out, s->ncell, tcount, a.tcell, a.tdata, eta_bits,
-                                  ctrl_of(s), 0, s->ncell, s->pk, s->user_st));
+                                  ctrl_of(s), 0, s->ncell, s->pk, pp_args<TB>(s), s->user_st));
+        if (a.pp)
+            DG_HIP(launch_pp2d<TB>(s->k, a.out, s->ncell, a.pcount, a.pcell, a.pcap, ctrl_of(s), 0,
+                                   s->pk, pp_args<TB>(s), s->user_st));
         return DG_OK;
     }
     Args1D<TB> a = base_args<TB>(s);
@@ -354,10 +377,20 @@ int record_steps(dg_solver* s, int G, hipStream_t st)
                         f.tdata = tdata;
                         DG_HIP(launch_filter2d<TB>(s->eq, s->k, f, 2, st));
                         DG_HIP(launch_blend2d<TB>(s->nv, s->k, f.out, s->ncell, &c->tcount[stage], tcell,
-                                                  tdata, &c->eta_line[stage].v, c, 1, s->ncell, s->pk, st));
+                                                  tdata, &c->eta_line[stage].v, c, 1, s->ncell, s->pk,
+                                                  pp_args<TB>(s), st));
                     }
                 }
+                // positivity limiter on the cells the post-stage kernels
+                // listed (without a filter: on every cell)
+                if (s->opt.positivity)
+                    DG_HIP(launch_pp2d<TB>(s->k, view_of<TB>(s, target), s->ncell,
+                                           fmode ? f.pcount : nullptr, f.pcell, f.pcap, c, 1, s->pk,
+                                           pp_args<TB>(s), st));
             }
+            // a rejected step is undone (u^n copied over its output) and
+            // retried with half dt by the next step control
+            if (s->opt.positivity) DG_HIP(launch_restore(c, A, B, s->state_bytes, st));
             continue;
         }
         if (fused_step(s)) {
@@ -521,14 +554,19 @@ int run_impl(dg_solver* s, double t_end, int64_t max_steps, dg_report* rep)
     const bool folded = folded_ctrl(s);
     if (folded) DG_HIP(launch_step_ctrl(ctrl_of(s), 0, st));
     // Replays: batches double in size between control reads, never beyond
-    // the replays the remaining step budget needs.  With the positivity
-    // limiter a rejected step is retried, so the budget is re-read.
+    // the replays the remaining step budget needs; a remainder of fewer than
+    // kGraphSteps steps is launched directly, rounded up to an even count
+    // (every launch sequence then keeps the buffer roles' period of 2; a
+    // slot past the budget finds the run done and exits at once).  With the
+    // positivity limiter a rejected step is retried, so the budget is
+    // re-read.
     const long long restarts0 = c.restarts;
     long long batch = 1, completed = 0;
     for (;;) {
         const long long rem = max_steps - completed;
         if (rem <= 0) break;
-        long long nb = (rem + kGraphSteps - 1) / kGraphSteps;
+        long long nb = rem / kGraphSteps;
+        const int tail = (int)(rem % kGraphSteps);
         if (nb > batch) nb = batch;
         for (long long r = 0; r < nb; ++r) {
             if (!direct) {
@@ -536,6 +574,10 @@ int run_impl(dg_solver* s, double t_end, int64_t max_steps, dg_report* rep)
                 continue;
             }
             const int rs = record_steps<TB>(s, kGraphSteps, st);
+            if (rs) return rs;
+        }
+        if (nb < batch && tail > 0) {
+            const int rs = record_steps<TB>(s, tail + (tail & 1), st);
             if (rs) return rs;
         }
         Ctrl cr;
@@ -706,9 +748,10 @@ int dg_create(const dg_mesh* mesh, int degree, int equation, const dg_options* o
     if (opt->quad_points != 0 && opt->quad_points != degree + 1) return DG_ERR_UNSUPPORTED;
     if (opt->positivity != 0 && opt->positivity != 1) return DG_ERR_ARG;
     if (opt->basis != 0 && opt->basis != 1) return DG_ERR_ARG;
+    if (opt->cf_reading < 0 || opt->cf_reading > 2) return DG_ERR_ARG;
     if (opt->flux < DG_FLUX_LLF || opt->flux > DG_FLUX_HLLC) return DG_ERR_ARG;
     if (opt->flux != DG_FLUX_LLF && equation != DG_EQ_EULER) return DG_ERR_UNSUPPORTED;
-    if (opt->positivity && (equation != DG_EQ_EULER || mesh->dim != 1)) return DG_ERR_UNSUPPORTED;
+    if (opt->positivity && equation != DG_EQ_EULER) return DG_ERR_UNSUPPORTED;
     if (!(opt->cfl > 0.0)) return DG_ERR_ARG;
     if (equation == DG_EQ_EULER && !(opt->gamma > 1.0)) return DG_ERR_ARG;
     for (int d = 0; d < mesh->dim; ++d) {
@@ -766,6 +809,9 @@ int dg_create(const dg_mesh* mesh, int degree, int equation, const dg_options* o
     off += align256((size_t)s->ncell * (s->lmax + 1) * sizeof(double));
     s->off_aux = off;
     off += kAuxBytes;
+    // 2D positivity limiter: the cells a stage lists for it
+    s->off_pcell = off;
+    if (mesh->dim == 2 && opt->positivity) off += align256((size_t)s->ncell * sizeof(long long));
     s->off_dv = off;
     s->dv_slot = 0;
     if (mesh->dim == 1 && opt->filter == DG_FILTER_HYBRID && !opt->positivity) {

@@ -312,6 +312,7 @@ struct Ctrl {
         unsigned long long v;
     } eta_line[3];                               // hybrid: max eta per stage (.v)
     Line arrive;                                 // workgroups of a launch that have finished
+    Line pcount;                                 // 2D positivity limiter: cells listed this stage (.v)
 };
 
 // Retries of one step with halved dt (positivity limiter) before a run stops.

@@ -84,8 +84,16 @@ struct Args2D {
     double* E_out;            // nullable: per-cell exponents, (2k+1) per cell
     double* eta_out;
     double jsx[16], jsy[16];  // jump weights per multi-index a1*4+a2 (see filter2d)
-    double cfmx, cfmy;        // mesh factors of (c_fx, c_fy): (hx, hy) as printed, or (1, 1)
+    double cfmx, cfmy;        // mesh factors of (c_fx, c_fy) (cf_reading)
     int pk;                   // P^k space: compact planes of the modes p + q <= k
+    // Euler positivity limiter: the post-stage kernels list the cells whose
+    // screen fails (pcell, at most pcap, count in *pcount, cleared by the
+    // stage kernel of the next stage), pp2d_kernel limits them
+    int pp;
+    unsigned long long* pcount;
+    long long* pcell;
+    long long pcap;
+    int* reject;              // set when a limited cell's average is inadmissible
 };
 
 template <typename TB>
@@ -96,7 +104,15 @@ template <typename TB>
 hipError_t launch_blend2d(int nv, int k, StateView<TB> out, int64_t ncell, const unsigned int* count,
                           const long long* tcell, const double* tdata,
                           const unsigned long long* eta_bits, const Ctrl* ctrl, int from_ctrl,
-                          int64_t max_entries, int pk, hipStream_t st);
+                          int64_t max_entries, int pk, PPArgs pp, hipStream_t st);
+// 2D Euler positivity limiter (Zhang and Shu on rectangles) in place on the
+// cells listed by the post-stage kernels (count, cells; capacity cap), or on
+// every cell when count is null.  Flags pp.reject when a cell average is
+// inadmissible.
+template <typename TB>
+hipError_t launch_pp2d(int k, StateView<TB> u, int64_t ncell, const unsigned long long* count,
+                       const long long* cells, int64_t cap, const Ctrl* ctrl, int from_ctrl, int pk,
+                       PPArgs pp, hipStream_t st);
 // FP64 exchange layout (every Q^k mode) <-> compact internal P^k planes
 // (modes p + q <= k in p-major order); zeros for the other modes on the way out.
 template <typename TB>

@@ -142,18 +142,18 @@ def test_per_call_2d(dg, ref, flux, k, nx, ny, bcs):
 
 @pytest.mark.parametrize("flux", [1])
 def test_quadrant_hybrid_run_2d(dg, ref, flux):
-    """Four-quadrant Riemann problem, 32x32, Q2, hybrid, HLL, 30 steps.  (With
-    HLLC, less dissipative, this case reaches a negative pressure in the
-    oracle too: the 2D path has no positivity limiter.)"""
+    """Four-quadrant Riemann problem, 32x32, Q2, hybrid with the printed
+    filter coefficient and the positivity limiter (without the limiter the
+    hybrid reaches a negative pressure, in the oracle too), 30 steps."""
     w = I.quadrant2d(32, 2, seed=3002)
     mesh = dg.make_mesh(2, (w.nx, w.ny), (w.xlo, w.ylo), (w.xhi, w.yhi), w.bc)
-    s = dg.Solver(mesh, 2, 2, dg.make_options(filter=2, cfl=w.cfl, flux=flux))
+    s = dg.Solver(mesh, 2, 2, dg.make_options(filter=2, cfl=w.cfl, flux=flux, positivity=1))
     s.set_state(w.u0)
     rep = dg.dg_run(s.h, 1e30, 30)
     got = s.get_state().cpu().numpy()
     s.close()
     P = ref.problem2d(2, 2, w.nx, w.ny, w.xlo, w.xhi, w.ylo, w.yhi, bc=w.bc, filter=2, cfl=w.cfl,
-                      flux=flux)
+                      flux=flux, pp=1)
     want, orep, rc = ref.run2d(P, w.u0, 1e30, 30)
     assert rc == 0 and rep.steps == 30
     for v in range(4):
@@ -179,22 +179,23 @@ def test_vortex_hllc_run_2d(dg, ref, k):
 
 
 def test_double_mach_small_hllc_run(dg, ref):
-    """Double Mach reflection, 64x16, Q2, jump filter, HLLC, 20 steps, with
-    the moving top boundary and the reflecting wall."""
+    """Double Mach reflection, 64x16, Q2, jump filter, HLLC, positivity
+    limiter, 20 steps, with the moving top boundary and the reflecting
+    wall."""
     w = I.double_mach(64, 16, 2)
     post, pre = I.conserved2d(*w.extra["post"]), I.conserved2d(1.4, 0.0, 0.0, 1.0)
     speed = w.extra["shock_speed"] / math.sin(math.pi / 3)
     mesh = dg.make_mesh(2, (64, 16), (0.0, 0.0), (4.0, 1.0), (3, 1, 4, 5),
                         dirichlet=[list(post)] * 4, shock_x0=1 / 6, shock_speed=speed,
                         post=list(post), pre=list(pre))
-    s = dg.Solver(mesh, 2, 2, dg.make_options(filter=1, cfl=0.1, flux=2))
+    s = dg.Solver(mesh, 2, 2, dg.make_options(filter=1, cfl=0.1, flux=2, positivity=1))
     s.set_state(w.u0)
     rep = dg.dg_run(s.h, 1e30, 20)
     got = s.get_state().cpu().numpy()
     s.close()
     P = ref.problem2d(2, 2, 64, 16, 0.0, 4.0, 0.0, 1.0, bc=(3, 1, 4, 5), filter=1, cfl=0.1,
                       dirichlet=[list(post)] * 4, shock_x0=1 / 6, shock_speed=speed, post=post,
-                      pre=pre, flux=2)
+                      pre=pre, flux=2, pp=1)
     want, orep, rc = ref.run2d(P, w.u0, 1e30, 20)
     assert rc == 0 and rep.status == 0
     for v in range(4):

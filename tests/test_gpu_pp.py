@@ -218,4 +218,6 @@ def test_positivity_option_rejected_where_unsupported(dg):
         dg.Solver(mesh, 2, 1, dg.make_options(filter=1, cfl=0.1, positivity=1))
     mesh2 = dg.make_mesh(2, (16, 16), (0.0, 0.0), (1.0, 1.0), (0, 0, 0, 0))
     with pytest.raises(dg.DGError):
-        dg.Solver(mesh2, 2, 2, dg.make_options(filter=1, cfl=0.1, positivity=1))
+        dg.Solver(mesh2, 2, 0, dg.make_options(filter=1, cfl=0.1, positivity=1))
+    # 2D Euler has the limiter
+    dg.Solver(mesh2, 2, 2, dg.make_options(filter=1, cfl=0.1, positivity=1)).close()
