@@ -19,6 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libdgref.so")
+_dp = C.POINTER(C.c_double)
 
 ADVECTION, BURGERS, EULER = 0, 1, 2
 PERIODIC, OUTFLOW, REFLECT, DIRICHLET = 0, 1, 2, 3
@@ -26,15 +27,31 @@ FILTER_NONE, FILTER_JUMP, FILTER_HYBRID = 0, 1, 2
 FLUX_LLF, FLUX_HLL, FLUX_HLLC = 0, 1, 2
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle's C sources with gcc into ``libdgref.so`` (FP64, OpenMP)."""
-    if force or not os.path.exists(_LIB_PATH):
-        cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC", "-shared",
-               "-o", _LIB_PATH + ".tmp", os.path.join(_HERE, "dgref.c"),
-               os.path.join(_HERE, "dgref2d.c"), os.path.join(_HERE, "dgref_hll.c"), "-lm"]
+_SOURCES = ("dgref.c", "dgref2d.c", "dgref_hll.c")
+
+
+def build(force: bool = True, out: str | None = None, opt: tuple = ("-O2",)) -> str:
+    """Compile the oracle's C sources with gcc into ``libdgref.so`` (FP64,
+    OpenMP; ISO C11, so no floating-point contraction).  ``out``/``opt``: a
+    copy at another path with other optimisation flags (the CPU-baseline
+    timing builds one with -O3 -march=native on the host that runs it)."""
+    path = out or _LIB_PATH
+    if force or not os.path.exists(path):
+        cmd = ["gcc", *opt, "-std=c11", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC", "-shared",
+               "-o", path + ".tmp", *(os.path.join(_HERE, f) for f in _SOURCES), "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
-    return _LIB_PATH
+        os.replace(path + ".tmp", path)
+    return path
+
+
+def load_copy(path: str):
+    """Load a separately built copy of the oracle (see build(out=...)) and
+    set up its return types; for timing only."""
+    L = C.CDLL(path)
+    L.dgref_max_wavespeed1d.restype = C.c_double
+    L.dgref_max_wavespeed1d.argtypes = [C.POINTER(Problem1D), _dp]
+    L.dgref_max_wavespeed2d.restype = C.c_double
+    return L
 
 
 class Problem1D(C.Structure):
@@ -67,7 +84,6 @@ class Report(C.Structure):
 
 
 _lib = None
-_dp = C.POINTER(C.c_double)
 
 
 def lib():

@@ -161,6 +161,15 @@ int dgref_num_threads(void)
 #endif
 }
 
+void dgref_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int dgref_nvars(int eq, int dim)
 {
     if (eq == DGREF_EULER) return dim == 1 ? 3 : 4;

@@ -92,6 +92,7 @@ typedef struct {
 
 int dgref_nvars(int eq, int dim);
 int dgref_num_threads(void);   /* OpenMP threads the cell loops use */
+void dgref_set_threads(int n); /* set them (n > 0) */
 
 /* ---- basis tables (exposed so tests can pin them) ---- */
 int dgref_gauss(int q, double* x, double* w);
