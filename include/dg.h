@@ -155,9 +155,16 @@ typedef struct {
 typedef struct dg_solver dg_solver;
 
 /* Create a solver for `mesh`, polynomial degree `degree` (0..3) and
- * `equation`.  Supported: 1D advection/Burgers/Euler; 2D Euler (Q^k).
- * Errors: DG_ERR_ARG (NULL, n < 1, bad domain, BC pairing),
- * DG_ERR_UNSUPPORTED (degree, dim/equation, quad_points). */
+ * `equation`: the DG space V_h^k of piecewise polynomials of degree k on a
+ * uniform mesh of an interval (Sec. 2.1) or a rectangle (Sec. 2.3), with the
+ * modal Legendre basis whose mode 0 is the cell average (Sec. 2.1,
+ * (eq:GLbasisequation)); the conservation law is linear advection, Burgers
+ * (Sec. 3.1) or the Euler equations (Sec. 2.4, Sec. 3).  Supported: 1D
+ * advection/Burgers/Euler; 2D advection/Euler (Q^k, or P^k with
+ * options.basis = 1).  The handle copies *mesh and *opt; it owns no device
+ * memory (dg_bind).  Errors: DG_ERR_ARG (NULL, n < 1, bad domain, BC
+ * pairing, option values), DG_ERR_UNSUPPORTED (degree, dim/equation,
+ * quad_points); *out is NULL then. */
 int dg_create(const dg_mesh* mesh, int degree, int equation, const dg_options* opt,
               dg_solver** out);
 int dg_destroy(dg_solver* s);
@@ -172,9 +179,13 @@ int dg_buffer_sizes(const dg_solver* s, size_t* state_bytes, size_t* workspace_b
  * simulated time and the ledger. */
 int dg_bind(dg_solver* s, void* u_n, void* u_a, void* u_b, void* workspace);
 
-/* Copy an FP64-layout state from device memory into u_n (converting to the
- * mixed layout if needed), and back.  The ledger's reference Q(0) is taken
- * at dg_set_state. */
+/* Copy an FP64-layout state from DEVICE memory into u_n (converting to the
+ * mixed layout if needed), and back.  modes_dev is a device pointer (the
+ * caller's torch tensor, for instance), not a host array: a host array would
+ * cost an extra copy through the caller's stream, so the host -> device copy
+ * is left to the caller.  Stream-ordered; no synchronisation.  For the 2D
+ * P^k space the modes p + q > k are dropped on the way in and written as
+ * zeros on the way out. */
 int dg_set_state(dg_solver* s, const double* modes_dev);
 int dg_get_state(dg_solver* s, double* modes_dev);
 
@@ -185,23 +196,48 @@ int dg_get_state(dg_solver* s, double* modes_dev);
  * max(ax/hx + ay/hy), so dt = cfl / alpha. */
 int dg_max_wavespeed(dg_solver* s, double* alpha);
 
-/* One SSP-RK3 stage of the plain DG scheme (residual + Shu-Osher
- * combination, no filter) into the workspace's stage buffer:
+/* One SSP-RK3 stage of the plain DG scheme into the workspace's stage
+ * buffer: the semi-discrete operator L of (scheme:DG) (Sec. 2.1; 2D
+ * (eq:semiloc_rec) without the viscous term, Sec. 2.3) -- Gauss quadrature
+ * of the volume term, the interface flux (LLF, or HLL / HLLC) at the
+ * interfaces and edge Gauss points -- and the Shu-Osher combination of the
+ * third-order SSP Runge-Kutta method (Sec. 2.2 (rkdg1); Sec. 3):
  *   stage 0: w = u_n + dt L(u_n)
  *   stage 1: w = 3/4 u_n + 1/4 (u_a + dt L(u_a))
  *   stage 2: w = 1/3 u_n + 2/3 (u_b + dt L(u_b))
- * `t` of the step start is taken from the device clock (dg_run) or 0. */
+ * Boundary states are taken at t = 0 (+dt, +dt/2 by stage).  Reads u_n and
+ * u_a / u_b (device, bound); no filter.  Stream-ordered.  Errors:
+ * DG_ERR_ARG (stage, dt < 0), DG_ERR_STATE (unbound), DG_ERR_DEVICE. */
 int dg_stage(dg_solver* s, int stage, double dt);
 
-/* Post-stage operator of the options (jump filter, hybrid limiter or
- * none) applied to the workspace's stage buffer with damping time dt; the
- * result goes to u_a (stage 0), u_b (stage 1) or u_n (stage 2). */
+/* Post-stage operator of the options applied to the workspace's stage
+ * buffer, the result to u_a (stage 0), u_b (stage 1) or u_n (stage 2):
+ *   DG_FILTER_JUMP: u^l <- exp(-sigma^l dt) u^l for every mode l >= 1,
+ *     sigma from the jumps of the derivatives across the cell's interfaces
+ *     (1D: (para:damp2)-(para:damp21), (timespli:1dscalar); 2D:
+ *     (para:damp22d)-(para:damp22d1); systems: the maximum over the
+ *     components, (para:dampsystems1d)-(timespli:sys));
+ *   DG_FILTER_HYBRID: Algorithm 1 (Sec. 3): cells with jump indicator
+ *     eta > 1 get omega u + (1 - omega) (filtered u), omega =
+ *     (max eta - eta) / (max eta - 1); other cells are unchanged;
+ *   DG_FILTER_NONE: a copy;
+ * then, with options.positivity, the positivity limiter.  The damping time
+ * is the full dt after every stage.  Exponents of every cell are kept for
+ * dg_last_exponents.  Stream-ordered.  Errors as dg_stage. */
 int dg_jump_filter(dg_solver* s, int stage, double dt);
 
-/* Advance u_n until t_end or max_steps steps, with dt chosen on the device
- * every step from the CFL reduction (last step clamped to t_end), using
- * the fused stage+filter kernels captured in a HIP graph.  Synchronises the
- * stream and fills *rep (nullable).  Returns rep->status. */
+/* Advance u_n until t_end or max_steps steps: SSP-RK3 steps (Sec. 2.2
+ * (rkdg1)) with the post-stage operator after every stage (Sec. 3), dt
+ * chosen on the device every step from the CFL reduction (Theorem 2.1's
+ * condition dt <= gamma h; dt = cfl h / alpha, 2D cfl / max(ax/hx + ay/hy);
+ * the last step clamped to t_end).  The steps are replayed from a captured
+ * HIP graph (remainders and small 1D hybrid grids launched directly) on a
+ * private stream ordered after the solver's stream.  Synchronises and fills
+ * *rep (nullable): steps and t accumulate over calls, dt_min / dt_max are
+ * this call's.  Returns rep->status: DG_OK, DG_ERR_NONFINITE (the run
+ * stops), DG_ERR_POSITIVITY (reported; with the positivity limiter, a step
+ * still rejected after 40 halvings of dt, which stops the run),
+ * DG_ERR_STATE (unbound), DG_ERR_DEVICE. */
 int dg_run(dg_solver* s, double t_end, int64_t max_steps, dg_report* rep);
 
 /* Read the report of the device control block (synchronises). */
