@@ -16,6 +16,8 @@
 //             edge are sum-factorised contractions of the two cells' modes
 //             with the derivative values P_p^(a)(+-1), per variable; the
 //             maximum over the variables is taken inside the cell's lanes.
+#include <type_traits>
+
 #include "dg_kernels.h"
 
 namespace dg {
@@ -310,35 +312,6 @@ __device__ __forceinline__ constexpr double pp2_leg(int i, int dir, int l)
     return leg_at(Q, dir == 0 ? r / Q : r % Q, l);
 }
 
-// The modes of one cell: FP64 averages u0[v] and the TB modes uh[v][m]
-// (m = p (K+1) + q >= 1; the entries of m = 0 and of modes outside P^k are
-// zero and never used).
-template <int K, typename TB>
-struct Cell2D {
-    static constexpr int NM = (K + 1) * (K + 1);
-    double u0[4];
-    TB uh[4][NM];
-};
-
-template <int K, bool PK, typename TB>
-__device__ __forceinline__ void pp2_point(const Cell2D<K, TB>& c, int i, double (&w)[4], double (&wa)[4])
-{
-    constexpr int K1 = K + 1;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        double sum = c.u0[v], sa = fabs(c.u0[v]);
-#pragma unroll
-        for (int m = 1; m < K1 * K1; ++m) {
-            if (!mode_kept<K, PK>(m)) continue;
-            const double t = ((double)c.uh[v][m] * pp2_leg<K>(i, 0, m / K1)) * pp2_leg<K>(i, 1, m % K1);
-            sum += t;
-            sa += fabs(t);
-        }
-        w[v] = sum;
-        wa[v] = sa;
-    }
-}
-
 __device__ __forceinline__ double pp2_pressure(double gamma, const double (&w)[4])
 {
     return (gamma - 1.0) * (w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0]);
@@ -364,141 +337,175 @@ __device__ __forceinline__ bool pp2_clear(const double (&ubar)[4], const double 
     return plo > 2.0 * (1e-13 + mmax);
 }
 
-// Limit one cell in place (the 1D limiter's steps on the 2D test points):
-// the density's modes >= 1 scaled so the density at every point is >= eps_r,
-// then all modes >= 1 so the pressure is >= eps_p (60 bisection steps on the
-// segment from the average to each point value, along which the pressure is
-// concave).  eps = min(1e-13, rho_bar, p_bar), raised per point to the
-// rounding margin of its value (8 units of roundoff of the modes' precision
-// times the magnitudes that cancel), which vanishes in exact arithmetic.
-// Finally the cell is checked in the fluxes' own arithmetic (precision TB,
-// pressure as the flux computes it) and its modes >= 1 halved until density
-// and pressure are positive at every point (dropped after 50 halvings).  The
-// averages never change; an inadmissible average is left to the caller.
-template <int K, bool PK, typename TB>
-__device__ __forceinline__ void pp2_limit(Cell2D<K, TB>& c, double gamma)
+__device__ __forceinline__ double wave_min(double v)
 {
-    constexpr int K1 = K + 1, NM = K1 * K1, NP = PP2DPoints<K>::NP;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off, 64);
+        v = (o < v || o != o) ? o : v;
+    }
+    return v;
+}
+
+// Point value at test point i of the cell whose coefficients (FP64 average,
+// then the modes >= 1 as stored) are in c[v * NM + m], and the sums of the
+// magnitudes of its terms.
+template <int K, bool PK>
+__device__ __forceinline__ void pp2_point_lds(const double* c, int i, double (&w)[4], double (&wa)[4])
+{
+    constexpr int K1 = K + 1, NM = K1 * K1;
+    double px[K1], py[K1];
+#pragma unroll
+    for (int l = 0; l < K1; ++l) {
+        px[l] = pp2_leg<K>(i, 0, l);
+        py[l] = pp2_leg<K>(i, 1, l);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        double sum = c[v * NM], sa = fabs(c[v * NM]);
+#pragma unroll
+        for (int m = 1; m < NM; ++m) {
+            if (!mode_kept<K, PK>(m)) continue;
+            const double t = (c[v * NM + m] * px[m / K1]) * py[m % K1];
+            sum += t;
+            sa += fabs(t);
+        }
+        w[v] = sum;
+        wa[v] = sa;
+    }
+}
+
+// Positivity limiter of one cell by one wavefront.  Lane l < 4 NM holds
+// coefficient l = v NM + m in `cf` (the FP64 average for m = 0, a mode
+// rounded to TB otherwise) and the wave's LDS block c mirrors them; lane
+// i < NP takes test point i.  The steps are those of the 1D limiter on the
+// 2D test points: the density's modes >= 1 scaled so the density at every
+// point is >= eps_r, then all modes >= 1 so the pressure is >= eps_p (60
+// bisection steps on the segment from the average to each point value,
+// along which the pressure is concave), eps = min(1e-13, rho_bar, p_bar)
+// raised per point to the rounding margin of its value (8 units of
+// roundoff of the modes' precision times the magnitudes that cancel), which
+// vanishes in exact arithmetic; finally the cell is checked in the fluxes'
+// own arithmetic (precision TB, pressure as the flux computes it) and its
+// modes >= 1 halved until density and pressure are positive at every point
+// (dropped after 50 halvings).  Minima over the points are taken across the
+// lanes.  The averages never change.  Returns true when the cell changed;
+// sets *reject (nullable) when its average is inadmissible.
+template <int K, bool PK, typename TB>
+__device__ __forceinline__ bool pp2_wave(double* c, double& cf, int lane, double gamma, int* reject)
+{
+    constexpr int K1 = K + 1, NM = K1 * K1, NC = 4 * NM, NP = PP2DPoints<K>::NP;
     constexpr double ur = sizeof(TB) == 4 ? 0x1p-23 : 0x1p-52;
-    const double pb = pp2_pressure(gamma, c.u0);
-    if (!(c.u0[0] > 0.0) || !(pb > 0.0)) return;
+    static_assert(NP <= 64 && NC <= 64, "one lane per test point and per coefficient");
+    const int m = lane % NM;
+    const bool coef = lane < NC && m > 0;
+    if (lane < NC) c[lane] = cf;
+    wave_lds_sync();
+    double ub[4], sabs[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        ub[v] = c[v * NM];
+        double t = 0.0;
+#pragma unroll
+        for (int q = 1; q < NM; ++q) t += fabs(c[v * NM + q]);
+        sabs[v] = t;
+    }
+    if (pp2_clear<TB>(ub, sabs, gamma)) return false;
+    const double pb = pp2_pressure(gamma, ub);
+    if (!(ub[0] > 0.0) || !(pb > 0.0)) {
+        if (lane == 0 && reject) atomicOr(reject, 1);
+        return false;
+    }
     double eps = 1e-13;
-    if (c.u0[0] < eps) eps = c.u0[0];
+    if (ub[0] < eps) eps = ub[0];
     if (pb < eps) eps = pb;
-    double eps_r = eps, rmin = INFINITY;
-    for (int i = 0; i < NP; ++i) {
+    const bool pt = lane < NP;
+    // density
+    {
         double w[4], wa[4];
-        pp2_point<K, PK, TB>(c, i, w, wa);
-        if (w[0] < rmin) rmin = w[0];
-        if (8.0 * ur * wa[0] > eps_r) eps_r = 8.0 * ur * wa[0];
-    }
-    if (eps_r > c.u0[0]) eps_r = c.u0[0];
-    if (rmin < eps_r) {
-        double th = (c.u0[0] - eps_r) / (c.u0[0] - rmin);
-        if (th < 0.0) th = 0.0;
-#pragma unroll
-        for (int m = 1; m < NM; ++m) c.uh[0][m] = (TB)((double)c.uh[0][m] * th);
-    }
-    double theta = 1.0;
-    for (int i = 0; i < NP; ++i) {
-        double w[4], wa[4];
-        pp2_point<K, PK, TB>(c, i, w, wa);
-        double eps_i = eps;
-        if (w[0] > 0.0) {
-            const double kin = 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0];
-            const double m = 8.0 * ur * (wa[3] + (fabs(w[1]) * wa[1] + fabs(w[2]) * wa[2]) / w[0] +
-                                         kin * wa[0] / w[0]);
-            if (m > eps_i) eps_i = m;
+        pp2_point_lds<K, PK>(c, pt ? lane : 0, w, wa);
+        const double rmin = wave_min(pt ? w[0] : INFINITY);
+        double eps_r = wave_max(pt ? 8.0 * ur * wa[0] : 0.0);
+        if (eps_r < eps) eps_r = eps;
+        if (eps_r > ub[0]) eps_r = ub[0];
+        if (rmin < eps_r) {
+            double th = (ub[0] - eps_r) / (ub[0] - rmin);
+            if (th < 0.0) th = 0.0;
+            wave_lds_sync();
+            if (coef && lane < NM) {
+                cf = (double)(TB)(cf * th);
+                c[lane] = cf;
+            }
+            wave_lds_sync();
         }
-        if (eps_i > pb) eps_i = pb;
-        if (pp2_pressure(gamma, w) >= eps_i) continue;
-        double lo = 0.0, hi = 1.0;
-        for (int it = 0; it < 60; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            double wm[4];
+    }
+    // pressure
+    {
+        double t = 1.0;
+        if (pt) {
+            double w[4], wa[4];
+            pp2_point_lds<K, PK>(c, lane, w, wa);
+            double eps_i = eps;
+            if (w[0] > 0.0) {
+                const double kin = 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0];
+                const double mg = 8.0 * ur * (wa[3] + (fabs(w[1]) * wa[1] + fabs(w[2]) * wa[2]) / w[0] +
+                                              kin * wa[0] / w[0]);
+                if (mg > eps_i) eps_i = mg;
+            }
+            if (eps_i > pb) eps_i = pb;
+            if (!(pp2_pressure(gamma, w) >= eps_i)) {
+                double lo = 0.0, hi = 1.0;
+                for (int it = 0; it < 60; ++it) {
+                    const double mid = 0.5 * (lo + hi);
+                    double wm[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) wm[v] = c.u0[v] + mid * (w[v] - c.u0[v]);
-            if (pp2_pressure(gamma, wm) >= eps_i)
-                lo = mid;
-            else
-                hi = mid;
+                    for (int v = 0; v < 4; ++v) wm[v] = ub[v] + mid * (w[v] - ub[v]);
+                    if (pp2_pressure(gamma, wm) >= eps_i)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                t = lo;
+            }
         }
-        if (lo < theta) theta = lo;
+        const double theta = wave_min(t);
+        if (theta < 1.0) {
+            wave_lds_sync();
+            if (coef) {
+                cf = (double)(TB)(cf * theta);
+                c[lane] = cf;
+            }
+            wave_lds_sync();
+        }
     }
-    if (theta < 1.0) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-            for (int m = 1; m < NM; ++m) c.uh[v][m] = (TB)((double)c.uh[v][m] * theta);
-    }
+    // positivity in the fluxes' own arithmetic
     for (int halving = 0; halving <= 50; ++halving) {
         bool ok = true;
-        for (int i = 0; i < NP && ok; ++i) {
+        if (pt) {
             TB w[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                TB sum = (TB)c.u0[v];
+                TB sum = (TB)c[v * NM];
 #pragma unroll
-                for (int m = 1; m < NM; ++m)
-                    if (mode_kept<K, PK>(m))
-                        sum += c.uh[v][m] * (TB)(pp2_leg<K>(i, 0, m / K1) * pp2_leg<K>(i, 1, m % K1));
+                for (int q = 1; q < NM; ++q)
+                    if (mode_kept<K, PK>(q))
+                        sum += (TB)c[v * NM + q] *
+                               (TB)(pp2_leg<K>(lane, 0, q / K1) * pp2_leg<K>(lane, 1, q % K1));
                 w[v] = sum;
             }
             const TB ir = (TB)1 / w[0];
             const TB pr = ((TB)gamma - (TB)1) * (w[3] - (TB)0.5 * (w[1] * (w[1] * ir) + w[2] * (w[2] * ir)));
             ok = w[0] > (TB)0 && pr > (TB)0;
         }
-        if (ok) break;
-        const TB f = halving < 50 ? (TB)0.5 : (TB)0;
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-            for (int m = 1; m < NM; ++m) c.uh[v][m] *= f;
+        if (__ballot(!ok) == 0) break;
+        const double f = halving < 50 ? 0.5 : 0.0;
+        wave_lds_sync();
+        if (coef) {
+            cf = (double)((TB)cf * (TB)f);
+            c[lane] = cf;
+        }
+        wave_lds_sync();
     }
-}
-
-template <int K, bool PK, typename TB>
-__device__ __forceinline__ void load_cell2d(const StateView<TB>& s, int64_t c, Cell2D<K, TB>& cell)
-{
-    constexpr int NM = (K + 1) * (K + 1);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        cell.u0[v] = s.m0[v * s.s0 + c];
-        cell.uh[v][0] = (TB)0;
-#pragma unroll
-        for (int m = 1; m < NM; ++m)
-            cell.uh[v][m] = mode_kept<K, PK>(m) ? s.hi[v * s.sv + (mode_plane<K, PK>(m) - 1) * s.sl + c] : (TB)0;
-    }
-}
-
-template <int K, bool PK, typename TB>
-__device__ __forceinline__ void store_cell2d_hi(const StateView<TB>& s, int64_t c, const Cell2D<K, TB>& cell)
-{
-    constexpr int NM = (K + 1) * (K + 1);
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int m = 1; m < NM; ++m)
-            if (mode_kept<K, PK>(m)) s.hi[v * s.sv + (mode_plane<K, PK>(m) - 1) * s.sl + c] = cell.uh[v][m];
-}
-
-// Screen, then (if needed) limit one cell held by one thread; true when the
-// cell changed.  Flags *reject on an inadmissible average.
-template <int K, bool PK, typename TB>
-__device__ __forceinline__ bool pp2_cell(Cell2D<K, TB>& cell, double gamma, int* reject)
-{
-    constexpr int NM = (K + 1) * (K + 1);
-    double sabs[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        double t = 0.0;
-#pragma unroll
-        for (int m = 1; m < NM; ++m) t += fabs((double)cell.uh[v][m]);
-        sabs[v] = t;
-    }
-    if (pp2_clear<TB>(cell.u0, sabs, gamma)) return false;
-    pp2_limit<K, PK, TB>(cell, gamma);
-    if (!(cell.u0[0] > 0.0 && pp2_pressure(gamma, cell.u0) > 0.0) && reject) atomicOr(reject, 1);
     return true;
 }
 
@@ -956,7 +963,13 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
 #pragma unroll
     for (int m = 0; m < L1; ++m) Jx[m] = Jy[m] = (T)0;
     T jx0 = (T)0, jy0_ = (T)0;
-    if (own) {
+    // Jumps of the derivatives d^a u at the corners of the four faces.  FULL:
+    // every multi-index a (a1, a2 <= k) into Jx, Jy; otherwise the value
+    // jumps (a = 0) only, into jx0, jy0_ (the hybrid indicator).  The a = 0
+    // terms are the same operations either way.
+    auto face_jumps = [&](auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        constexpr int AL = FULL ? K1 : 1;
         // DIR 0: vertical faces (x = const), DIR 1: horizontal faces.  The
         // face side is a run-time loop index (keeps one face live at a time).
 #pragma unroll
@@ -975,9 +988,9 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
                 };
                 // D[al][o] = sum_n (nb - own) u^{..} P_n^(al)(end), n the
                 // across-face index, o the along-face index
-                T D[K1][K1];
+                T D[AL][K1];
 #pragma unroll
-                for (int al = 0; al < K1; ++al)
+                for (int al = 0; al < AL; ++al)
 #pragma unroll
                     for (int o = 0; o < K1; ++o) {
                         T go = (T)0, gn = (T)0;
@@ -1009,9 +1022,9 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
 #pragma unroll
                 for (int cc = 0; cc < 2; ++cc)
 #pragma unroll
-                    for (int al = 0; al < K1; ++al)
+                    for (int al = 0; al < AL; ++al)
 #pragma unroll
-                        for (int bl = 0; bl < K1; ++bl) {
+                        for (int bl = 0; bl < AL; ++bl) {
                             // al: across-face derivative order, bl: along-face
                             T sum = (T)0;
 #pragma unroll
@@ -1027,17 +1040,40 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
                                     j = (T)0;
                             }
                             const int a1 = dir == 0 ? al : bl, a2 = dir == 0 ? bl : al;
-                            if (dir == 0) {
-                                Jx[a1 + a2] += (T)(0.5 * a.jsx[a1 * 4 + a2]) * j;
-                                if (al == 0 && bl == 0) jx0 += (T)0.5 * j;
+                            if constexpr (FULL) {
+                                if (dir == 0)
+                                    Jx[a1 + a2] += (T)(0.5 * a.jsx[a1 * 4 + a2]) * j;
+                                else
+                                    Jy[a1 + a2] += (T)(0.5 * a.jsy[a1 * 4 + a2]) * j;
                             } else {
-                                Jy[a1 + a2] += (T)(0.5 * a.jsy[a1 * 4 + a2]) * j;
-                                if (al == 0 && bl == 0) jy0_ += (T)0.5 * j;
+                                if (dir == 0)
+                                    jx0 += (T)0.5 * j;
+                                else
+                                    jy0_ += (T)0.5 * j;
                             }
                         }
             }
         }
+    };
+    if (own) face_jumps(std::false_type{});
+    T eta;
+    {
+        const T ev = jx0 * (T)(0.5 * a.inv_hx) + jy0_ * (T)(0.5 * a.inv_hy);
+        const int base = tid - v;
+        eta = ev;
+#pragma unroll
+        for (int w = 0; w < NV; ++w) {
+            const T o = NV > 1 ? __shfl(ev, base + w, 64) : ev;
+            eta = (w == 0 || o > eta) ? o : eta;
+        }
     }
+    // The exponents need every derivative jump.  The hybrid (MODE 2) needs
+    // them only for troubled cells (eta > 1, Algorithm 1), so a wavefront
+    // with none skips them (unless the per-call API asks for every cell's
+    // exponents).
+    bool full = MODE == 1 || a.E_out != nullptr;
+    if (!full) full = __ballot(own && eta > (T)1) != 0;
+    if (full && own) face_jumps(std::true_type{});
     // running partial sums over the derivative order, then the maximum over
     // the variables (in variable order, as a sequential loop would take it)
     T best[L1];
@@ -1056,17 +1092,6 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
                 bl = (w == 0 || o > bl) ? o : bl;
             }
             best[l] = bl;
-        }
-    }
-    T eta;
-    {
-        const T ev = jx0 * (T)(0.5 * a.inv_hx) + jy0_ * (T)(0.5 * a.inv_hy);
-        const int base = tid - v;
-        eta = ev;
-#pragma unroll
-        for (int w = 0; w < NV; ++w) {
-            const T o = NV > 1 ? __shfl(ev, base + w, 64) : ev;
-            eta = (w == 0 || o > eta) ? o : eta;
         }
     }
     if (MODE == 2) {
@@ -1139,7 +1164,9 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
 }
 
 // Hybrid pass B over the troubled list: u^{pq} <- [w + (1 - w) exp(-E^{p+q})] u^{pq},
-// then (Euler, pp.on) the positivity limiter on the blended cell.
+// then (Euler, pp.on) the positivity limiter on the blended cell.  One
+// wavefront per troubled cell: lane l < NV (K+1)^2 holds coefficient
+// (variable l / (K+1)^2, mode l % (K+1)^2).
 template <int K, int NV, typename TB, bool PK>
 __global__ __launch_bounds__(256) void blend2d_kernel(StateView<TB> out, const unsigned int* count,
                                                       const long long* tcell, const double* tdata,
@@ -1147,62 +1174,62 @@ __global__ __launch_bounds__(256) void blend2d_kernel(StateView<TB> out, const u
                                                       const Ctrl* ctrl, int from_ctrl, long long cap,
                                                       PPArgs pp)
 {
-    constexpr int K1 = K + 1, L1 = 2 * K + 1;
+    constexpr int K1 = K + 1, NM = K1 * K1, L1 = 2 * K + 1, NC = NV * NM;
+    __shared__ double sc[4][NV == 4 ? NC : 1];
     if (from_ctrl && ctrl->done) return;
     unsigned int cnt = *count;
     if ((long long)cnt > cap) cnt = (unsigned int)cap;
     const double M = __longlong_as_double((long long)*eta_bits);
-    for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int v = lane / NM, m = lane % NM, p = m / K1, q = m % K1;
+    const bool mine = lane < NC && m > 0 && mode_kept<K, PK>(m);
+    const int64_t off = mine ? v * out.sv + (mode_plane<K, PK>(m) - 1) * out.sl : 0;
+    for (unsigned int i = blockIdx.x * 4 + wv; i < cnt; i += gridDim.x * 4) {
         const long long c = tcell[i];
         const double* rec = tdata + (size_t)i * L1;
         const double w = (M - rec[0]) / (M - 1.0);
-        TB f[L1];
-#pragma unroll
-        for (int l = 1; l < L1; ++l) f[l] = (TB)(w + (1.0 - w) * exp(-rec[l]));
-        if constexpr (NV == 4) {
-            if (pp.on) {
-                Cell2D<K, TB> cell;
-                load_cell2d<K, PK, TB>(out, c, cell);
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-#pragma unroll
-                    for (int m = 1; m < K1 * K1; ++m) cell.uh[v][m] *= f[m / K1 + m % K1];
-                pp2_cell<K, PK, TB>(cell, pp.phys.gamma, pp.reject);
-                store_cell2d_hi<K, PK, TB>(out, c, cell);
-                continue;
-            }
+        double cf = 0.0;
+        if (mine) {
+            const TB f = (TB)(w + (1.0 - w) * exp(-rec[p + q]));
+            cf = (double)(out.hi[off + c] * f);
+        } else if (lane < NC && m == 0) {
+            cf = out.m0[v * out.s0 + c];
         }
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int p = 0; p < K1; ++p)
-#pragma unroll
-                for (int q = 0; q < K1; ++q) {
-                    if ((p == 0 && q == 0) || (PK && p + q > K)) continue;
-                    out.hi[v * out.sv + (mode_plane<K, PK>(p * K1 + q) - 1) * out.sl + c] *= f[p + q];
-                }
+        if constexpr (NV == 4) {
+            if (pp.on) pp2_wave<K, PK, TB>(sc[wv], cf, lane, pp.phys.gamma, pp.reject);
+        }
+        if (mine) out.hi[off + c] = (TB)cf;
     }
 }
 
 // Positivity limiter over the cells the post-stage kernels listed (or over
-// every cell when count is null), in place.
+// every cell when count is null), in place; one wavefront per cell.
 template <int K, typename TB, bool PK>
 __global__ __launch_bounds__(256) void pp2d_kernel(StateView<TB> u, long long ncell,
                                                    const unsigned long long* count, const long long* cells,
                                                    long long cap, const Ctrl* ctrl, int from_ctrl, PPArgs pp)
 {
+    constexpr int K1 = K + 1, NM = K1 * K1, NC = 4 * NM;
+    __shared__ double sc[4][NC];
     if (from_ctrl && ctrl->done) return;
     long long cnt = ncell;
     if (count) {
         const unsigned long long c = *count;
         cnt = (long long)c < cap ? (long long)c : cap;
     }
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
-         i += (long long)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int v = lane / NM, m = lane % NM;
+    const bool mine = lane < NC && m > 0 && mode_kept<K, PK>(m);
+    const int64_t off = mine ? v * u.sv + (mode_plane<K, PK>(m) - 1) * u.sl : 0;
+    for (long long i = (long long)blockIdx.x * 4 + wv; i < cnt; i += (long long)gridDim.x * 4) {
         const long long c = count ? cells[i] : i;
-        Cell2D<K, TB> cell;
-        load_cell2d<K, PK, TB>(u, c, cell);
-        if (pp2_cell<K, PK, TB>(cell, pp.phys.gamma, pp.reject)) store_cell2d_hi<K, PK, TB>(u, c, cell);
+        double cf = 0.0;
+        if (mine)
+            cf = (double)u.hi[off + c];
+        else if (lane < NC && m == 0)
+            cf = u.m0[v * u.s0 + c];
+        if (pp2_wave<K, PK, TB>(sc[wv], cf, lane, pp.phys.gamma, pp.reject) && mine)
+            u.hi[off + c] = (TB)cf;
     }
 }
 
@@ -1336,8 +1363,10 @@ hipError_t launch_blend2d(int nv, int k, StateView<TB> out, int64_t ncell, const
                           const unsigned long long* eta_bits, const Ctrl* ctrl, int from_ctrl,
                           int64_t max_entries, int pk, PPArgs pp, hipStream_t st)
 {
-    unsigned g = (unsigned)((max_entries + 255) / 256);
-    if (g > 2048) g = 2048;
+    // one wavefront per troubled cell, 4 per workgroup, grid-stride beyond
+    // 4096 workgroups (the list's length is only known on the device)
+    unsigned g = (unsigned)((max_entries + 3) / 4);
+    if (g > 4096) g = 4096;
     if (g < 1) g = 1;
 #define DG_CASE(NV_, K_)                                                                          \
     if (nv == NV_ && k == K_) {                                                                   \
@@ -1363,10 +1392,10 @@ hipError_t launch_pp2d(int k, StateView<TB> u, int64_t ncell, const unsigned lon
                        const long long* cells, int64_t cap, const Ctrl* ctrl, int from_ctrl, int pk,
                        PPArgs pp, hipStream_t st)
 {
-    // listed cells: a grid sized for a few percent of the mesh, grid-stride
-    // beyond; every cell: one thread per cell up to the same cap of blocks
-    const int64_t span = count ? (cap + 31) / 32 : ncell;
-    int64_t g = (span + 255) / 256;
+    // one wavefront per cell, 4 per workgroup, grid-stride beyond 4096
+    // workgroups
+    const int64_t span = count ? cap : ncell;
+    int64_t g = (span + 3) / 4;
     if (g > 4096) g = 4096;
     if (g < 1) g = 1;
 #define DG_CASE(K_)                                                                                \
