@@ -196,6 +196,24 @@ int dg_get_state(dg_solver* s, double* modes_dev);
  * max(ax/hx + ay/hy), so dt = cfl / alpha. */
 int dg_max_wavespeed(dg_solver* s, double* alpha);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the CFL
+ * reduction of dg_max_wavespeed on the state buffer u_dev (device, the
+ * solver's internal layout and size, dg_buffer_sizes' state_bytes; it need
+ * not be bound, and the solver needs no workspace).  Allocates nothing: its
+ * scratch (one partial maximum per 256 cells, and the result) is a fixed
+ * device array of the library, 1.1 MB on each GPU it runs on, held until the
+ * process ends.  Limit: at most 16,777,216 cells (65536 x 256); larger
+ * meshes: DG_ERR_ARG.  The maximum is reduced in a fixed order (no
+ * atomics), so it equals dg_max_wavespeed's bit for bit.  *first_bad
+ * (nullable) receives the lowest index of a cell whose average is
+ * inadmissible (Euler) or non-finite, else -1.  Every call on a GPU uses
+ * that GPU's one array: calls that overlap on one GPU race.  Runs on the
+ * solver's stream and synchronises it.  Errors: DG_ERR_ARG (NULL, size),
+ * DG_ERR_DEVICE, DG_ERR_NONFINITE (alpha not finite). */
+int dg_max_wavespeed_noalloc(const dg_solver* s, const void* u_dev, double* alpha,
+                             int64_t* first_bad);
+
 /* One SSP-RK3 stage of the plain DG scheme into the workspace's stage
  * buffer: the semi-discrete operator L of (scheme:DG) (Sec. 2.1; 2D
  * (eq:semiloc_rec) without the viscous term, Sec. 2.3) -- Gauss quadrature

@@ -67,6 +67,7 @@ _sig = {
     "dg_set_state": [_vp, _vp],
     "dg_get_state": [_vp, _vp],
     "dg_max_wavespeed": [_vp, C.POINTER(C.c_double)],
+    "dg_max_wavespeed_noalloc": [_vp, _vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
     "dg_stage": [_vp, C.c_int, C.c_double],
     "dg_jump_filter": [_vp, C.c_int, C.c_double],
     "dg_run": [_vp, C.c_double, C.c_int64, C.POINTER(dg_report)],
@@ -213,6 +214,18 @@ def dg_report_read(h, check: bool = False) -> dg_report:
 
 def dg_last_exponents(h, out) -> None:
     _check(_lib.dg_last_exponents(h, _ptr(out)), "dg_last_exponents")
+
+
+def dg_max_wavespeed_noalloc(h, u_dev_ptr: int):
+    """(alpha, first_bad, status) of the state buffer at device address
+    u_dev_ptr, with the library's fixed scratch (allocates nothing); status
+    is DG_OK or DG_ERR_NONFINITE (other errors raise)."""
+    a = C.c_double()
+    bad = C.c_int64()
+    rc = _lib.dg_max_wavespeed_noalloc(h, u_dev_ptr, C.byref(a), C.byref(bad))
+    if rc not in (DG_OK, DG_ERR_NONFINITE):
+        _check(rc, "dg_max_wavespeed_noalloc")
+    return a.value, bad.value, rc
 
 
 def dg_time_kernel(h, stage: int, dt: float, reps: int) -> float:

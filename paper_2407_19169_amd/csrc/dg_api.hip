@@ -10,6 +10,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "../../include/dg.h"
@@ -718,6 +719,171 @@ int time_impl(dg_solver* s, int stage, double dt, int reps, double* avg_us)
     return time_launches(s, scratch, reps, launch, avg_us);
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free CFL reduction (dg_max_wavespeed_noalloc).  Its scratch --
+// one partial maximum and one first-bad-cell entry per workgroup, and the
+// result -- lives in a file-scope device array, one copy per GPU, held until
+// the process ends.  Host code never uses the array's name as an address: the
+// address is taken once per device with hipGetSymbolAddress and kept.
+constexpr int kNoallocBlocks = 65536;          // workgroups of 256 cells
+struct NoallocScratch {
+    double part[kNoallocBlocks];               // per-workgroup maximum of lambda
+    long long bad[kNoallocBlocks];             // per workgroup: first bad cell or -1
+    int code[kNoallocBlocks];                  // per workgroup: 0, -5 or -4
+    double alpha;                              // result
+    long long first_bad;
+    int status;
+};
+
+__device__ __align__(256) NoallocScratch scratch;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+NoallocScratch* g_noalloc_ptr[kMaxDevices];
+
+// Address of this device's scratch (taken once per device, with the device
+// current); nullptr on failure.
+NoallocScratch* noalloc_scratch()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_noalloc_ptr[dev] = static_cast<NoallocScratch*>(p);
+    }
+    return g_noalloc_ptr[dev];
+}
+
+// The wave speed of one cell average, as the CFL kernels compute it: 1D
+// |f'(u)| (Euler |u| + c); 2D lambda_x / h_x + lambda_y / h_y.
+template <int EQ, int DIM>
+__device__ __forceinline__ double cell_lambda(const double* ub, const PhysParams& ph, double ihx,
+                                              double ihy)
+{
+    if constexpr (DIM == 1) {
+        return Phys1D<EQ>::speed(ub, ph);
+    } else if constexpr (EQ == ADV) {
+        return fabs(ph.a[0]) * ihx + fabs(ph.a[1]) * ihy;
+    } else {
+        const double pr = (ph.gamma - 1.0) * (ub[3] - 0.5 * (ub[1] * ub[1] + ub[2] * ub[2]) / ub[0]);
+        const double sx = fabs(ub[1] / ub[0]) + sqrt(ph.gamma * pr / ub[0]);
+        const double sy = fabs(ub[2] / ub[0]) + sqrt(ph.gamma * pr / ub[0]);
+        return sx * ihx + sy * ihy;
+    }
+}
+
+// Pass 1: workgroup b reduces cells [256 b, 256 b + 256) into part[b], with
+// the first inadmissible (-5) or non-finite (-4) cell of the workgroup.
+template <int EQ, int DIM>
+__global__ __launch_bounds__(256) void noalloc_part_kernel(const double* m0, int64_t s0, int64_t n,
+                                                           PhysParams ph, double ihx, double ihy,
+                                                           NoallocScratch* sc)
+{
+    constexpr int NV = EQ == EULER ? (DIM == 1 ? 3 : 4) : 1;
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double lam = 0.0;
+    int code = 0;
+    if (c < n) {
+        double ub[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ub[v] = m0[v * s0 + c];
+        lam = cell_lambda<EQ, DIM>(ub, ph, ihx, ihy);
+        if constexpr (EQ == EULER) {
+            const double p = DIM == 1 ? (ph.gamma - 1.0) * (ub[2] - 0.5 * ub[1] * ub[1] / ub[0])
+                                      : (ph.gamma - 1.0) * (ub[NV - 1] - 0.5 * (ub[1] * ub[1] + ub[2] * ub[2]) / ub[0]);
+            if (!(ub[0] > 0.0) || !(p > 0.0)) code = (isfinite(ub[0]) && isfinite(p)) ? -5 : -4;
+        }
+        if (!isfinite(lam)) code = -4;
+    }
+    __shared__ double smax[4];
+    __shared__ long long sbad[4];
+    __shared__ int scode[4];
+    const double z = wave_max(lam);
+    // first bad cell of the wavefront (lowest lane with a code)
+    const unsigned long long mask = __ballot(code != 0);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    long long bad = -1;
+    int bcode = 0;
+    if (mask) {
+        const int first = __ffsll((long long)mask) - 1;
+        bad = (int64_t)blockIdx.x * 256 + w * 64 + first;
+        bcode = __shfl(code, first, 64);
+    }
+    if (lane == 0) {
+        smax[w] = z;
+        sbad[w] = bad;
+        scode[w] = bcode;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = smax[0];
+        long long b = -1;
+        int cd = 0;
+        for (int i = 0; i < 4; ++i) {
+            m = (smax[i] > m || smax[i] != smax[i]) ? smax[i] : m;
+            if (b < 0 && sbad[i] >= 0) {
+                b = sbad[i];
+                cd = scode[i];
+            }
+        }
+        sc->part[blockIdx.x] = m;
+        sc->bad[blockIdx.x] = b;
+        sc->code[blockIdx.x] = cd;
+    }
+}
+
+// Pass 2: one workgroup reduces the nb partial maxima in a fixed order.
+__global__ __launch_bounds__(256) void noalloc_final_kernel(int nb, NoallocScratch* sc)
+{
+    __shared__ double smax[256];
+    __shared__ long long sbad[256];
+    __shared__ int scode[256];
+    double m = 0.0;
+    long long b = -1;
+    int cd = 0;
+    for (int i = threadIdx.x; i < nb; i += 256) {
+        const double v = sc->part[i];
+        m = (v > m || v != v) ? v : m;
+        if (b < 0 && sc->bad[i] >= 0) {
+            b = sc->bad[i];
+            cd = sc->code[i];
+        }
+    }
+    smax[threadIdx.x] = m;
+    sbad[threadIdx.x] = b;
+    scode[threadIdx.x] = cd;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // the first bad cell is the smallest index over the threads
+        double mm = smax[0];
+        long long bb = -1;
+        int cc = 0;
+        for (int i = 0; i < 256; ++i) {
+            mm = (smax[i] > mm || smax[i] != smax[i]) ? smax[i] : mm;
+            if (sbad[i] >= 0 && (bb < 0 || sbad[i] < bb)) {
+                bb = sbad[i];
+                cc = scode[i];
+            }
+        }
+        sc->alpha = mm;
+        sc->first_bad = bb;
+        sc->status = cc;
+    }
+}
+
+template <int EQ, int DIM>
+hipError_t launch_noalloc(const double* m0, int64_t s0, int64_t n, PhysParams ph, double ihx,
+                          double ihy, NoallocScratch* sc, hipStream_t st)
+{
+    const int nb = (int)((n + 255) / 256);
+    hipLaunchKernelGGL((noalloc_part_kernel<EQ, DIM>), dim3(nb), dim3(256), 0, st, m0, s0, n, ph, ihx,
+                       ihy, sc);
+    hipLaunchKernelGGL(noalloc_final_kernel, dim3(1), dim3(256), 0, st, nb, sc);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 extern "C" {
@@ -975,6 +1141,47 @@ int dg_time_kernel(dg_solver* s, int stage, double dt, int reps, double* avg_us)
     DG_HIP(hipStreamSynchronize(s->user_st));
     return is_fp64(s) ? time_impl<double>(s, stage, dt, reps, avg_us)
                       : time_impl<float>(s, stage, dt, reps, avg_us);
+}
+
+int dg_max_wavespeed_noalloc(const dg_solver* s, const void* u_dev, double* alpha, int64_t* first_bad)
+{
+    if (!s || !u_dev || !alpha) return DG_ERR_ARG;
+    if (s->ncell > (int64_t)kNoallocBlocks * 256) return DG_ERR_ARG;
+    NoallocScratch* sc = noalloc_scratch();
+    if (!sc) return DG_ERR_DEVICE;
+    // mode 0 of variable v of the state buffer: FP64 layout v * nmodes * ncell;
+    // mixed layout v * n_pad (the planes of mode 0 come first)
+    const double* m0 = static_cast<const double*>(u_dev);
+    const int64_t s0 = s->opt.precision == DG_PREC_FP64 ? (int64_t)s->nmodes * s->ncell : s->n_pad;
+    PhysParams ph;
+    memset(&ph, 0, sizeof ph);
+    ph.gamma = s->opt.gamma;
+    ph.flux = s->opt.flux;
+    ph.a[0] = s->opt.adv_speed[0];
+    ph.a[1] = s->opt.adv_speed[1];
+    const double ihx = s->inv_h[0], ihy = s->dim == 2 ? s->inv_h[1] : 0.0;
+    hipStream_t st = s->user_st;
+    hipError_t e = hipErrorInvalidValue;
+    if (s->dim == 1)
+        e = s->eq == DG_EQ_EULER    ? launch_noalloc<EULER, 1>(m0, s0, s->ncell, ph, ihx, ihy, sc, st)
+          : s->eq == DG_EQ_BURGERS ? launch_noalloc<BURGERS, 1>(m0, s0, s->ncell, ph, ihx, ihy, sc, st)
+                                   : launch_noalloc<ADV, 1>(m0, s0, s->ncell, ph, ihx, ihy, sc, st);
+    else
+        e = s->eq == DG_EQ_EULER ? launch_noalloc<EULER, 2>(m0, s0, s->ncell, ph, ihx, ihy, sc, st)
+                                 : launch_noalloc<ADV, 2>(m0, s0, s->ncell, ph, ihx, ihy, sc, st);
+    if (e != hipSuccess) return DG_ERR_DEVICE;
+    struct {
+        double alpha;
+        long long first_bad;
+        int status;
+    } r;
+    DG_HIP(hipMemcpyAsync(&r.alpha, &sc->alpha, sizeof(double), hipMemcpyDeviceToHost, st));
+    DG_HIP(hipMemcpyAsync(&r.first_bad, &sc->first_bad, sizeof(long long), hipMemcpyDeviceToHost, st));
+    DG_HIP(hipMemcpyAsync(&r.status, &sc->status, sizeof(int), hipMemcpyDeviceToHost, st));
+    DG_HIP(hipStreamSynchronize(st));
+    *alpha = r.alpha;
+    if (first_bad) *first_bad = r.status ? r.first_bad : -1;
+    return isfinite(*alpha) ? DG_OK : DG_ERR_NONFINITE;
 }
 
 int dg_last_exponents(dg_solver* s, double* E_dev)
