@@ -315,17 +315,33 @@ int dg_batch_bind(dg_batch* b, void* u_n, void* u_a, void* u_b, void* workspace)
 int dg_batch_set_state(dg_batch* b, const double* packed_dev);
 int dg_batch_get_state(dg_batch* b, double* packed_dev);
 /* Advance every problem by `steps` steps (or until its t_end[i], host
- * array, nullable), each with its own CFL time step.  per_problem (host,
- * nullable, nprob entries) receives each problem's report. */
+ * array, nullable), each with its own CFL time step, in one persistent
+ * launch: the reset of the queue and error latches, the launch and the copy
+ * of the reports to pinned host memory are captured once in a HIP graph
+ * (rebuilt when the step count or the schedule changes) and replayed on a
+ * private stream ordered after the caller's.  per_problem (host, nullable,
+ * nprob entries) receives each problem's report.  Synchronises. */
 int dg_batch_run(dg_batch* b, const double* t_end, int64_t steps, dg_report* per_problem);
 
 /* Autotuner of the batched launch: times `trial_steps` steps of the whole
- * batch for each candidate schedule (persistent workgroups per compute
- * unit: 1, 2, 4, 8; queue order: longest-first or as given), each from the
- * same saved state (u_n is restored afterwards), keeps the fastest for
- * later dg_batch_run calls, and writes a JSON summary of all candidates
- * into json (nullable; truncated to cap bytes).  Synchronises. */
+ * batch for each candidate schedule (threads per workgroup: 256 or 128,
+ * i.e. tiles of 244 or 116 cells; persistent workgroups per compute unit:
+ * 1, 2, 4, 8 of 256 threads or twice as many of 128; queue order:
+ * longest-first or as given), each from the same saved state (u_n is
+ * restored afterwards), keeps the fastest for later dg_batch_run calls, and
+ * writes a JSON summary into json (nullable; truncated to cap bytes): the
+ * batch's key ("k_mix": fractions of degrees 0..3, "n_bucket":
+ * round(log2(mean cells))) under which a caller may cache the choice, every
+ * candidate's time, and "best".  Results do not depend on the schedule
+ * (each problem's step is computed cell by cell the same way).
+ * Synchronises. */
 int dg_batch_tune(dg_batch* b, int64_t trial_steps, char* json, size_t cap);
+
+/* Apply a schedule chosen earlier (by dg_batch_tune, e.g. from a cache keyed
+ * as its JSON): block_size 128 or 256, wg_per_cu 1..16 workgroups of that
+ * size per compute unit, lpt 1 = longest-first queue, 0 = as given.
+ * Errors: DG_ERR_ARG, DG_ERR_STATE (unbound). */
+int dg_batch_set_schedule(dg_batch* b, int block_size, int wg_per_cu, int lpt);
 
 #ifdef __cplusplus
 }

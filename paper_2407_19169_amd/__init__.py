@@ -83,6 +83,7 @@ _sig = {
     "dg_batch_get_state": [_vp, _vp],
     "dg_batch_run": [_vp, _vp, C.c_int64, C.POINTER(dg_report)],
     "dg_batch_tune": [_vp, C.c_int64, C.c_char_p, C.c_size_t],
+    "dg_batch_set_schedule": [_vp, C.c_int, C.c_int, C.c_int],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -370,6 +371,17 @@ def dg_batch_tune(h, trial_steps: int) -> str:
     return buf.value.decode()
 
 
+def _batch_key(problems) -> str:
+    """The autotuner's cache key of a batch: the fractions of degrees 0..3
+    and round(log2(mean cells)), as dg_batch_tune reports them."""
+    import math
+
+    n = len(problems)
+    kf = [sum(1 for p in problems if int(p[1]) == k) / n for k in range(4)]
+    mean_n = sum(int(p[0]) for p in problems) / n
+    return "k%s_n%d" % ("-".join(f"{x:.2f}" for x in kf), round(math.log2(max(mean_n, 1.0))))
+
+
 class Batch:
     """Owns a batch handle plus torch-allocated buffers."""
 
@@ -405,8 +417,36 @@ class Batch:
     def run(self, steps: int, t_end=None, check: bool = True):
         return dg_batch_run(self.h, len(self.problems), steps, t_end, check)
 
-    def tune(self, trial_steps: int = 5) -> str:
-        return dg_batch_tune(self.h, trial_steps)
+    def tune(self, trial_steps: int = 5, cache: str | None = None) -> str:
+        """Autotune the schedule (JSON summary).  With `cache` (a JSON file
+        path), a schedule stored there under this batch's key (degree mix,
+        size bucket) is applied without timing, and a new one is stored."""
+        import json
+        import os
+
+        key = _batch_key(self.problems)
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                table = json.load(fh)
+        if key in table:
+            best = table[key]
+            _check(_lib.dg_batch_set_schedule(self.h, best["block_size"], best["wg_per_cu"],
+                                              1 if best["order"] == "lpt" else 0),
+                   "dg_batch_set_schedule")
+            return json.dumps({"key": key, "cached": True, "best": best})
+        out = dg_batch_tune(self.h, trial_steps)
+        if cache:
+            table[key] = json.loads(out)["best"]
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(table, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return out
+
+    def set_schedule(self, block_size: int, wg_per_cu: int, lpt: bool = True) -> None:
+        _check(_lib.dg_batch_set_schedule(self.h, block_size, wg_per_cu, int(lpt)),
+               "dg_batch_set_schedule")
 
     def close(self) -> None:
         if self.h:

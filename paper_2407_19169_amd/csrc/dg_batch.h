@@ -37,7 +37,9 @@ struct BatchArgs {
     int pp;                 // positivity-preserving limiter after the filter
 };
 
-hipError_t launch_batch1d(int mixed, int mode, const BatchArgs& b, int grid, hipStream_t st);
+// bs: threads per workgroup, 128 or 256 (tiles of bs - 12 cells)
+hipError_t launch_batch1d(int mixed, int mode, const BatchArgs& b, int grid, int bs, hipStream_t st);
+hipError_t launch_batch_reset(const BatchArgs& b, hipStream_t st);
 template <typename TB>
 hipError_t launch_batch_convert(int to_internal, const BatchArgs& b, const double* ext, int nprob,
                                 hipStream_t st);

@@ -24,8 +24,14 @@ struct dg_batch {
     void* u[3];
     unsigned char* ws;
     bool bound;
-    hipStream_t st;
+    hipStream_t st;      // the caller's stream
+    hipStream_t run_st;  // private stream the run's graph is captured on and replayed
+    hipGraphExec_t graph;
+    long long graph_steps;
+    int graph_grid, graph_bs;
+    BatchReport* host_rep;  // pinned host copy of the per-problem reports
     int grid;          // persistent workgroups
+    int bs;            // threads per workgroup (128 or 256)
     int use_lpt;       // queue order
     int cus;           // compute units of the device
 };
@@ -67,18 +73,59 @@ int upload_order(dg_batch* b, int lpt)
     return DG_OK;
 }
 
-// Clear the queue head and the per-problem error latches (stream ordered).
-int reset_run(dg_batch* b)
+// Clear the queue head and the per-problem error latches (a kernel, so the
+// run can be captured in a graph).
+int reset_run(dg_batch* b, hipStream_t st)
 {
-    DG_HIP(hipMemsetAsync(b->ws + b->off_queue, 0, 256, b->st));
-    DG_HIP(hipMemsetAsync(b->ws + b->off_ctrl, 0, (size_t)b->nprob * sizeof(Ctrl), b->st));
+    DG_HIP(launch_batch_reset(batch_args(b, 0), st));
     return DG_OK;
 }
 
-int launch(dg_batch* b, long long steps)
+int launch(dg_batch* b, long long steps, hipStream_t st)
 {
     const int mode = b->opt.filter == DG_FILTER_NONE ? 0 : 1;
-    DG_HIP(launch_batch1d(b->opt.precision == DG_PREC_MIXED, mode, batch_args(b, steps), b->grid, b->st));
+    DG_HIP(launch_batch1d(b->opt.precision == DG_PREC_MIXED, mode, batch_args(b, steps), b->grid, b->bs, st));
+    return DG_OK;
+}
+
+void drop_graph(dg_batch* b)
+{
+    if (b->graph) hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+}
+
+// The run as one graph on the private stream: reset, the persistent launch,
+// and the copy of the reports into pinned host memory.  Kept while the step
+// count and the schedule stay the same.
+int run_graph(dg_batch* b, long long steps)
+{
+    if (b->graph && (b->graph_steps != steps || b->graph_grid != b->grid || b->graph_bs != b->bs))
+        drop_graph(b);
+    if (!b->graph) {
+        hipGraph_t g = nullptr;
+        DG_HIP(hipStreamBeginCapture(b->run_st, hipStreamCaptureModeThreadLocal));
+        int rc = reset_run(b, b->run_st);
+        if (!rc) rc = launch(b, steps, b->run_st);
+        if (!rc && hipMemcpyAsync(b->host_rep, b->ws + b->off_report, sizeof(BatchReport) * b->nprob,
+                                  hipMemcpyDeviceToHost, b->run_st) != hipSuccess)
+            rc = DG_ERR_DEVICE;
+        const hipError_t e = hipStreamEndCapture(b->run_st, &g);
+        if (rc || e != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return rc ? rc : DG_ERR_DEVICE;
+        }
+        const hipError_t ei = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            b->graph = nullptr;
+            return DG_ERR_DEVICE;
+        }
+        b->graph_steps = steps;
+        b->graph_grid = b->grid;
+        b->graph_bs = b->bs;
+    }
+    DG_HIP(hipGraphLaunch(b->graph, b->run_st));
+    DG_HIP(hipStreamSynchronize(b->run_st));
     return DG_OK;
 }
 
@@ -167,8 +214,19 @@ int dg_batch_create(int nprob, dg_problem1d* probs, int equation, const dg_optio
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
         b->cus = prop.multiProcessorCount;
     b->grid = 2 * b->cus;
+    b->bs = 256;
     b->use_lpt = 1;
     b->st = static_cast<hipStream_t>(opt->stream);
+    if (hipStreamCreateWithFlags(&b->run_st, hipStreamNonBlocking) != hipSuccess) {
+        delete b;
+        return DG_ERR_DEVICE;
+    }
+    if (hipHostMalloc(reinterpret_cast<void**>(&b->host_rep), sizeof(BatchReport) * nprob,
+                      hipHostMallocDefault) != hipSuccess) {
+        hipStreamDestroy(b->run_st);
+        delete b;
+        return DG_ERR_DEVICE;
+    }
     *out = b;
     return DG_OK;
 }
@@ -176,6 +234,9 @@ int dg_batch_create(int nprob, dg_problem1d* probs, int equation, const dg_optio
 int dg_batch_destroy(dg_batch* b)
 {
     if (!b) return DG_ERR_ARG;
+    drop_graph(b);
+    if (b->run_st) hipStreamDestroy(b->run_st);
+    if (b->host_rep) hipHostFree(b->host_rep);
     delete b;
     return DG_OK;
 }
@@ -198,6 +259,7 @@ int dg_batch_bind(dg_batch* b, void* u_n, void* u_a, void* u_b, void* workspace)
     b->u[1] = u_a;
     b->u[2] = u_b;
     b->ws = static_cast<unsigned char*>(workspace);
+    drop_graph(b);
     DG_HIP(hipStreamSynchronize(b->st));
     DG_HIP(hipMemcpy(b->ws + b->off_probs, b->probs.data(), sizeof(BatchProb) * b->nprob,
                      hipMemcpyHostToDevice));
@@ -242,13 +304,9 @@ int dg_batch_run(dg_batch* b, const double* t_end, int64_t steps, dg_report* per
         DG_HIP(hipMemcpy(b->ws + b->off_probs, b->probs.data(), sizeof(BatchProb) * b->nprob,
                          hipMemcpyHostToDevice));
     }
-    int rc = reset_run(b);
-    if (!rc) rc = launch(b, steps);
+    const int rc = run_graph(b, steps);
     if (rc) return rc;
-    std::vector<BatchReport> rep(b->nprob);
-    DG_HIP(hipMemcpyAsync(rep.data(), b->ws + b->off_report, sizeof(BatchReport) * b->nprob,
-                          hipMemcpyDeviceToHost, b->st));
-    DG_HIP(hipStreamSynchronize(b->st));
+    const BatchReport* rep = b->host_rep;
     int status = DG_OK;
     for (int i = 0; i < b->nprob; ++i) {
         if (rep[i].status && status == DG_OK) status = rep[i].status;
@@ -272,9 +330,12 @@ int dg_batch_run(dg_batch* b, const double* t_end, int64_t steps, dg_report* per
 }
 
 // Autotuner: times `trial_steps` steps of the whole batch for every
-// candidate (persistent workgroups per compute unit x queue order), each
-// from the same saved state, keeps the fastest, restores the state and
-// writes a JSON summary to json (nullable, capacity cap).
+// candidate schedule (threads per workgroup 256 or 128, i.e. tiles of 244 or
+// 116 cells; persistent workgroups per compute unit; queue order), each from
+// the same saved state, keeps the fastest, restores the state and writes a
+// JSON summary to json (nullable, capacity cap) with the key of the batch's
+// shape: the fractions of P0..P3 problems and the size bucket
+// round(log2(mean cells)).
 int dg_batch_tune(dg_batch* b, int64_t trial_steps, char* json, size_t cap)
 {
     if (!b || trial_steps < 1) return DG_ERR_ARG;
@@ -282,8 +343,9 @@ int dg_batch_tune(dg_batch* b, int64_t trial_steps, char* json, size_t cap)
     DG_HIP(hipStreamSynchronize(b->st));
     DG_HIP(hipMemcpy(b->ws + b->off_backup, b->u[0], b->state_bytes, hipMemcpyDeviceToDevice));
     const int factors[4] = {1, 2, 4, 8};
+    const int sizes[2] = {256, 128};
     struct Cand {
-        int factor, lpt;
+        int bs, factor, lpt;
         float ms;
     };
     std::vector<Cand> cands;
@@ -293,20 +355,25 @@ int dg_batch_tune(dg_batch* b, int64_t trial_steps, char* json, size_t cap)
     int rc = DG_OK;
     for (int lpt = 1; lpt >= 0 && rc == DG_OK; --lpt) {
         rc = upload_order(b, lpt);
-        for (int f = 0; f < 4 && rc == DG_OK; ++f) {
-            b->grid = factors[f] * b->cus;
-            if (hipMemcpyAsync(b->u[0], b->ws + b->off_backup, b->state_bytes, hipMemcpyDeviceToDevice,
-                               b->st) != hipSuccess)
-                rc = DG_ERR_DEVICE;
-            if (!rc) rc = reset_run(b);
-            if (!rc && hipEventRecord(e0, b->st) != hipSuccess) rc = DG_ERR_DEVICE;
-            if (!rc) rc = launch(b, trial_steps);
-            if (!rc && hipEventRecord(e1, b->st) != hipSuccess) rc = DG_ERR_DEVICE;
-            if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = DG_ERR_DEVICE;
-            float ms = 0.f;
-            if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = DG_ERR_DEVICE;
-            cands.push_back({factors[f], lpt, ms});
-        }
+        for (int sz = 0; sz < 2 && rc == DG_OK; ++sz)
+            for (int f = 0; f < 4 && rc == DG_OK; ++f) {
+                b->bs = sizes[sz];
+                // a 128-thread workgroup is half a 256-thread one: twice as
+                // many fill the same compute unit
+                const int per_cu = factors[f] * (256 / b->bs);
+                b->grid = per_cu * b->cus;
+                if (hipMemcpyAsync(b->u[0], b->ws + b->off_backup, b->state_bytes,
+                                   hipMemcpyDeviceToDevice, b->st) != hipSuccess)
+                    rc = DG_ERR_DEVICE;
+                if (!rc) rc = reset_run(b, b->st);
+                if (!rc && hipEventRecord(e0, b->st) != hipSuccess) rc = DG_ERR_DEVICE;
+                if (!rc) rc = launch(b, trial_steps, b->st);
+                if (!rc && hipEventRecord(e1, b->st) != hipSuccess) rc = DG_ERR_DEVICE;
+                if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = DG_ERR_DEVICE;
+                float ms = 0.f;
+                if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = DG_ERR_DEVICE;
+                cands.push_back({sizes[sz], per_cu, lpt, ms});
+            }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -316,9 +383,15 @@ int dg_batch_tune(dg_batch* b, int64_t trial_steps, char* json, size_t cap)
     const Cand* best = &cands[0];
     for (const Cand& c : cands)
         if (c.ms < best->ms) best = &c;
+    b->bs = best->bs;
     b->grid = best->factor * b->cus;
     rc = upload_order(b, best->lpt);
     if (json && cap) {
+        double kf[4] = {0, 0, 0, 0}, mean_n = 0.0;
+        for (const BatchProb& q : b->probs) {
+            kf[q.k] += 1.0 / b->nprob;
+            mean_n += (double)q.n / b->nprob;
+        }
         size_t used = 0;
         auto put = [&](const char* fmt, auto... args) {
             if (used < cap) {
@@ -326,14 +399,29 @@ int dg_batch_tune(dg_batch* b, int64_t trial_steps, char* json, size_t cap)
                 if (w > 0) used += (size_t)w;
             }
         };
-        put("{\"trial_steps\": %lld, \"candidates\": [", (long long)trial_steps);
+        put("{\"key\": {\"k_mix\": [%.2f, %.2f, %.2f, %.2f], \"n_bucket\": %d}, \"trial_steps\": %lld, "
+            "\"candidates\": [",
+            kf[0], kf[1], kf[2], kf[3], (int)lround(log2(mean_n > 1.0 ? mean_n : 1.0)),
+            (long long)trial_steps);
         for (size_t i = 0; i < cands.size(); ++i)
-            put("%s{\"wg_per_cu\": %d, \"order\": \"%s\", \"ms\": %.4f}", i ? ", " : "", cands[i].factor,
-                cands[i].lpt ? "lpt" : "natural", cands[i].ms);
-        put("], \"best\": {\"wg_per_cu\": %d, \"order\": \"%s\", \"ms\": %.4f}}", best->factor,
-            best->lpt ? "lpt" : "natural", best->ms);
+            put("%s{\"block_size\": %d, \"wg_per_cu\": %d, \"order\": \"%s\", \"ms\": %.4f}", i ? ", " : "",
+                cands[i].bs, cands[i].factor, cands[i].lpt ? "lpt" : "natural", cands[i].ms);
+        put("], \"best\": {\"block_size\": %d, \"wg_per_cu\": %d, \"order\": \"%s\", \"ms\": %.4f}}",
+            best->bs, best->factor, best->lpt ? "lpt" : "natural", best->ms);
     }
     return rc;
+}
+
+int dg_batch_set_schedule(dg_batch* b, int block_size, int wg_per_cu, int lpt)
+{
+    if (!b || (block_size != 128 && block_size != 256) || wg_per_cu < 1 || wg_per_cu > 16 ||
+        (lpt != 0 && lpt != 1))
+        return DG_ERR_ARG;
+    if (!b->bound) return DG_ERR_STATE;
+    DG_HIP(hipStreamSynchronize(b->st));
+    b->bs = block_size;
+    b->grid = wg_per_cu * b->cus;
+    return upload_order(b, lpt);
 }
 
 }  // extern "C"

@@ -5,8 +5,8 @@
 // the queue longest-first, by cost n (k+1)^2 steps) and advances each one
 // through all of its time steps on its own: a CFL reduction over the
 // workgroup, then one pass over the problem's tiles that runs all three
-// SSP-RK3 stages (with the filter after each) of a 244-cell tile and its
-// 6-cell halo.  No grid-wide synchronisation is needed: a problem never
+// SSP-RK3 stages (with the filter after each) of a tile of BS - 12 cells
+// (BS = 128 or 256 threads, a choice of the autotuner) and its 6-cell halo.  No grid-wide synchronisation is needed: a problem never
 // leaves its workgroup.
 // (included at the end of dg1d.hip: it reuses the 1D tile function)
 #include "dg_batch.h"
@@ -15,7 +15,8 @@ namespace dg {
 
 namespace {
 
-__device__ __forceinline__ double block_max256(double v, double* red)
+template <int BS>
+__device__ __forceinline__ double block_max(double v, double* red)
 {
     v = wave_max(v);
     const int w = threadIdx.x >> 6;
@@ -23,17 +24,18 @@ __device__ __forceinline__ double block_max256(double v, double* red)
     __syncthreads();
     double r = red[0];
 #pragma unroll
-    for (int i = 1; i < 4; ++i) r = (red[i] > r || red[i] != red[i]) ? red[i] : r;
+    for (int i = 1; i < BS / 64; ++i) r = (red[i] > r || red[i] != red[i]) ? red[i] : r;
     __syncthreads();
     return r;
 }
 
 // Deterministic block sum: fixed strided partial sums, fixed-order tree.
-__device__ __forceinline__ double block_sum256(double v, double* tree)
+template <int BS>
+__device__ __forceinline__ double block_sum(double v, double* tree)
 {
     tree[threadIdx.x] = v;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = BS / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) tree[threadIdx.x] += tree[threadIdx.x + w];
         __syncthreads();
     }
@@ -55,14 +57,14 @@ __device__ __forceinline__ StateView<TB> prob_view(void* base, const BatchProb& 
     return v;
 }
 
-template <int K, typename TB, int MODE, int PP>
+template <int K, typename TB, int MODE, int PP, int BS>
 __device__ __forceinline__ void solve_problem(const BatchArgs& b, const BatchProb& pr, unsigned int pidx,
                               unsigned char* lds, double* red, double* tree, double* sflux,
                               int* sreject)
 {
     // the step's three stages in one pass: each consumes a halo of 1 (no
     // filter) or 2 (filter) cells per side
-    constexpr int TILE3 = 256 - 2 * 3 * (MODE == 0 ? 1 : 2);
+    constexpr int TILE3 = BS - 2 * 3 * (MODE == 0 ? 1 : 2);
     StateView<TB> A = prob_view<TB>(b.u[0], pr, K);
     StateView<TB> B = prob_view<TB>(b.u[1], pr, K);
     const StateView<TB> A0 = A, B0 = B;
@@ -95,14 +97,14 @@ __device__ __forceinline__ void solve_problem(const BatchArgs& b, const BatchPro
 
     // CFL quantity of the initial state
     double lam = 0.0;
-    for (int64_t c = threadIdx.x; c < n; c += 256) {
+    for (int64_t c = threadIdx.x; c < n; c += BS) {
         double ub[3];
 #pragma unroll
         for (int v = 0; v < 3; ++v) ub[v] = A.m0[v * A.s0 + c];
         const double l = Phys1D<EULER>::speed(ub, b.phys);
         lam = (l > lam || l != l) ? l : lam;
     }
-    double alpha = block_max256(lam, red);
+    double alpha = block_max<BS>(lam, red);
 
     double t = 0.0, dtmin = INFINITY, dtmax = 0.0;
     double bfl[3] = {0.0, 0.0, 0.0};
@@ -141,7 +143,7 @@ __device__ __forceinline__ void solve_problem(const BatchArgs& b, const BatchPro
             double lmax = 0.0;
             for (int64_t tile = 0; tile < ntiles3; ++tile) {
                 double l, e;
-                stage1d_tile<EULER, K, TB, MODE, 256, false, 3>(a, tile, dt, lds, &l, &e);
+                stage1d_tile<EULER, K, TB, MODE, BS, false, 3>(a, tile, dt, lds, &l, &e);
                 lmax = (l > lmax || l != l) ? l : lmax;
                 __syncthreads();  // the next tile reuses the LDS
             }
@@ -156,7 +158,7 @@ __device__ __forceinline__ void solve_problem(const BatchArgs& b, const BatchPro
 #pragma unroll
                     for (int v = 0; v < 3; ++v)
                         net[v] += kStageWeight[s] * (sflux[8 * s + 4 + v] - sflux[8 * s + v]);
-                alpha = block_max256(lmax, red);
+                alpha = block_max<BS>(lmax, red);
             }
         }
         if (retry) {
@@ -183,7 +185,7 @@ __device__ __forceinline__ void solve_problem(const BatchArgs& b, const BatchPro
     }
     if (steps & 1) {
         // the solution sits in the second buffer: copy it to the first
-        for (int64_t c = threadIdx.x; c < n; c += 256)
+        for (int64_t c = threadIdx.x; c < n; c += BS)
 #pragma unroll
             for (int v = 0; v < 3; ++v) {
                 A0.m0[v * A0.s0 + c] = B0.m0[v * B0.s0 + c];
@@ -198,8 +200,8 @@ __device__ __forceinline__ void solve_problem(const BatchArgs& b, const BatchPro
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
         double acc = 0.0;
-        for (int64_t c = threadIdx.x; c < n; c += 256) acc += A0.m0[v * A0.s0 + c];
-        led[v] = pr.h * block_sum256(acc, tree);
+        for (int64_t c = threadIdx.x; c < n; c += BS) acc += A0.m0[v * A0.s0 + c];
+        led[v] = pr.h * block_sum<BS>(acc, tree);
     }
     if (threadIdx.x == 0) {
         BatchReport& r = b.report[pidx];
@@ -217,12 +219,12 @@ __device__ __forceinline__ void solve_problem(const BatchArgs& b, const BatchPro
     }
 }
 
-template <typename TB, int MODE>
+template <typename TB, int MODE, int BS>
 struct BatchLds {
-    static constexpr int a = Stage1DLds<EULER, 0, TB, MODE>::bytes;
-    static constexpr int b = Stage1DLds<EULER, 1, TB, MODE>::bytes;
-    static constexpr int c = Stage1DLds<EULER, 2, TB, MODE>::bytes;
-    static constexpr int d = Stage1DLds<EULER, 3, TB, MODE>::bytes;
+    static constexpr int a = Stage1DLds<EULER, 0, TB, MODE, BS>::bytes;
+    static constexpr int b = Stage1DLds<EULER, 1, TB, MODE, BS>::bytes;
+    static constexpr int c = Stage1DLds<EULER, 2, TB, MODE, BS>::bytes;
+    static constexpr int d = Stage1DLds<EULER, 3, TB, MODE, BS>::bytes;
     static constexpr int ab = a > b ? a : b;
     static constexpr int cd = c > d ? c : d;
     static constexpr int bytes = ab > cd ? ab : cd;
@@ -238,13 +240,13 @@ struct BatchWaves {
     static constexpr int value = sizeof(TB) == 4 ? 3 : 1;
 };
 
-template <typename TB, int MODE, int PP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BatchWaves<TB, PP>::value)))
+template <typename TB, int MODE, int PP, int BS>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BatchWaves<TB, PP>::value)))
 void batch1d_kernel(BatchArgs b)
 {
-    __shared__ __align__(16) unsigned char lds[BatchLds<TB, MODE>::bytes];
-    __shared__ double red[4];
-    __shared__ double tree[256];
+    __shared__ __align__(16) unsigned char lds[BatchLds<TB, MODE, BS>::bytes];
+    __shared__ double red[BS / 64];
+    __shared__ double tree[BS];
     __shared__ double sflux[24];  // boundary fluxes, lo[4] hi[4] per stage
     __shared__ int sreject;
     __shared__ unsigned int s_pi;
@@ -257,12 +259,25 @@ void batch1d_kernel(BatchArgs b)
         const unsigned int p = b.order[pi];
         const BatchProb pr = b.probs[p];
         switch (pr.k) {
-        case 0: solve_problem<0, TB, MODE, PP>(b, pr, p, lds, red, tree, sflux, &sreject); break;
-        case 1: solve_problem<1, TB, MODE, PP>(b, pr, p, lds, red, tree, sflux, &sreject); break;
-        case 2: solve_problem<2, TB, MODE, PP>(b, pr, p, lds, red, tree, sflux, &sreject); break;
-        default: solve_problem<3, TB, MODE, PP>(b, pr, p, lds, red, tree, sflux, &sreject); break;
+        case 0: solve_problem<0, TB, MODE, PP, BS>(b, pr, p, lds, red, tree, sflux, &sreject); break;
+        case 1: solve_problem<1, TB, MODE, PP, BS>(b, pr, p, lds, red, tree, sflux, &sreject); break;
+        case 2: solve_problem<2, TB, MODE, PP, BS>(b, pr, p, lds, red, tree, sflux, &sreject); break;
+        default: solve_problem<3, TB, MODE, PP, BS>(b, pr, p, lds, red, tree, sflux, &sreject); break;
         }
         __syncthreads();
+    }
+}
+
+// Start of a batched run: the queue head and every problem's error latch
+// cleared (a kernel, so the run can be captured in a graph).
+__global__ __launch_bounds__(256) void batch_reset_kernel(unsigned int* queue, Ctrl* ctrl, int nprob)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i == 0) *queue = 0u;
+    if (i < nprob) {
+        ctrl[i].status = 0;
+        ctrl[i].first_bad = -1;
+        ctrl[i].reject = 0;
     }
 }
 
@@ -307,25 +322,33 @@ hipError_t launch_batch_convert(int to_internal, const BatchArgs& b, const doubl
 template hipError_t launch_batch_convert<double>(int, const BatchArgs&, const double*, int, hipStream_t);
 template hipError_t launch_batch_convert<float>(int, const BatchArgs&, const double*, int, hipStream_t);
 
-template <typename TB>
+template <typename TB, int BS>
 static void launch_batch_tb(int mode, const BatchArgs& b, int grid, hipStream_t st)
 {
     if (mode == 0 && !b.pp)
-        hipLaunchKernelGGL((batch1d_kernel<TB, 0, 0>), dim3(grid), dim3(256), 0, st, b);
+        hipLaunchKernelGGL((batch1d_kernel<TB, 0, 0, BS>), dim3(grid), dim3(BS), 0, st, b);
     else if (mode == 0)
-        hipLaunchKernelGGL((batch1d_kernel<TB, 0, 1>), dim3(grid), dim3(256), 0, st, b);
+        hipLaunchKernelGGL((batch1d_kernel<TB, 0, 1, BS>), dim3(grid), dim3(BS), 0, st, b);
     else if (!b.pp)
-        hipLaunchKernelGGL((batch1d_kernel<TB, 1, 0>), dim3(grid), dim3(256), 0, st, b);
+        hipLaunchKernelGGL((batch1d_kernel<TB, 1, 0, BS>), dim3(grid), dim3(BS), 0, st, b);
     else
-        hipLaunchKernelGGL((batch1d_kernel<TB, 1, 1>), dim3(grid), dim3(256), 0, st, b);
+        hipLaunchKernelGGL((batch1d_kernel<TB, 1, 1, BS>), dim3(grid), dim3(BS), 0, st, b);
 }
 
-hipError_t launch_batch1d(int mixed, int mode, const BatchArgs& b, int grid, hipStream_t st)
+hipError_t launch_batch1d(int mixed, int mode, const BatchArgs& b, int grid, int bs, hipStream_t st)
 {
+    if (bs != 128 && bs != 256) return hipErrorInvalidValue;
     if (mixed)
-        launch_batch_tb<float>(mode, b, grid, st);
+        bs == 128 ? launch_batch_tb<float, 128>(mode, b, grid, st) : launch_batch_tb<float, 256>(mode, b, grid, st);
     else
-        launch_batch_tb<double>(mode, b, grid, st);
+        bs == 128 ? launch_batch_tb<double, 128>(mode, b, grid, st) : launch_batch_tb<double, 256>(mode, b, grid, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(const BatchArgs& b, hipStream_t st)
+{
+    const unsigned g = (unsigned)((b.nprob + 255) / 256);
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(g < 1 ? 1 : g), dim3(256), 0, st, b.queue, b.ctrl, b.nprob);
     return hipGetLastError();
 }
 
