@@ -263,7 +263,8 @@ int dg_report_read(dg_solver* s, dg_report* rep);
 
 /* Per-cell damping exponents of the last dg_jump_filter call, FP64,
  * E[cell*(Lmax+1) + l] with Lmax = k (1D) or 2k (2D); written to a device
- * buffer of ncells*(Lmax+1) doubles. */
+ * buffer of ncells*(Lmax+1) doubles.  2D hybrid: the troubled cells' only
+ * (zero elsewhere; Algorithm 1 damps no other cell). */
 int dg_last_exponents(dg_solver* s, double* E_dev);
 
 /* Measurement hook: launch a kernel of dg_run `reps` times back to back on
@@ -277,7 +278,8 @@ int dg_last_exponents(dg_solver* s, double* E_dev);
  * control in its last workgroup (here on a control block of its own).
  * 2D: 0..2 the residual
  * kernel of that stage (writes the workspace), 3..5 the filter kernel
- * (jump: workspace -> u_a) or hybrid pass A (reads u_a).  1D `stage` 6: the
+ * (jump: workspace -> u_a) or hybrid pass A, the indicator (which reads the
+ * corner values the residual kernel of a hybrid solver writes, as in dg_run).  1D `stage` 6: the
  * kernel that runs a whole step (jump filter or none; u_n -> u_a);
  * DG_ERR_ARG with the hybrid limiter.  u_n is never
  * modified.  Synchronises. */

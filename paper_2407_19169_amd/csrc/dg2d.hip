@@ -94,13 +94,16 @@ __device__ __forceinline__ void llf2d(const T* ul, const T* ur, int dir, T* fh, 
     for (int v = 0; v < NV; ++v) fh[v] = (T)0.5 * (fl[v] + fr[v]) - (T)0.5 * alpha * (ur[v] - ul[v]);
 }
 
-// Global index along an axis: wrapped if periodic, -1 if outside.
+// Global index along an axis: wrapped if periodic, -1 if outside.  Callers
+// pass indices within a tile and a cell of the domain, so the wrap is a few
+// subtractions at most (no 64-bit division).
 __device__ __forceinline__ int64_t slot_index(int64_t g, int64_t n, bool periodic)
 {
     if (g >= 0 && g < n) return g;
     if (!periodic) return -1;
-    int64_t r = g % n;
-    return r < 0 ? r + n : r;
+    while (g < 0) g += n;
+    while (g >= n) g -= n;
+    return g;
 }
 
 __device__ __forceinline__ double shock_line_x(const double x0, const double speed, double y, double t)
@@ -255,6 +258,25 @@ __device__ __forceinline__ void load_var2d(const StateView<TB>& s, int64_t c, in
         um[m] = mode_kept<K, PK>(m) ? (T)s.hi[v * s.sv + (mode_plane<K, PK>(m) - 1) * s.sl + c] : (T)0;
 }
 
+// Value of one variable's polynomial at the cell corner (sx, sy), sx, sy =
+// 1 at the +x, +y side: sum_pq u_pq (+-1)^p (+-1)^q, summed in the order p, q
+// (P_p(+-1) = (+-1)^p).
+template <int K, bool PK, typename T>
+__device__ __forceinline__ T corner2d(const T (&u)[(K + 1) * (K + 1)], int sx, int sy)
+{
+    constexpr int K1 = K + 1;
+    T sum = (T)0;
+#pragma unroll
+    for (int p = 0; p < K1; ++p)
+#pragma unroll
+        for (int q = 0; q < K1; ++q) {
+            if (!mode_kept<K, PK>(p * K1 + q)) continue;
+            const bool neg = (!sx && (p & 1)) != (!sy && (q & 1));
+            sum += neg ? -u[p * K1 + q] : u[p * K1 + q];
+        }
+    return sum;
+}
+
 // Orders LDS writes before later LDS reads of other lanes of the same
 // wavefront (the lanes of one cell always share a wavefront).
 __device__ __forceinline__ void wave_lds_sync()
@@ -271,11 +293,12 @@ __device__ __forceinline__ void wave_lds_sync()
 // fetched into the same L2 by the tiles around it.
 __device__ __forceinline__ void xcd_tile(int64_t gx, int64_t ntiles, int64_t& bx, int64_t& by)
 {
-    const int64_t p = blockIdx.x, q = ntiles >> 3, r = ntiles & 7;
-    const int64_t x = p & 7, k = p >> 3;
-    const int64_t l = x * q + (x < r ? x : r) + k;
-    bx = l % gx;
-    by = l / gx;
+    // tile counts stay far below 2^32 (a launch has at most 2^32 - 1 workgroups)
+    const uint32_t p = blockIdx.x, q = (uint32_t)ntiles >> 3, r = (uint32_t)ntiles & 7;
+    const uint32_t x = p & 7, k = p >> 3;
+    const uint32_t l = x * q + (x < r ? x : r) + k;
+    bx = l % (uint32_t)gx;
+    by = l / (uint32_t)gx;
 }
 
 // ---------------------------------------------------------------------------
@@ -553,13 +576,23 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
     constexpr int NV = P::NV, K1 = K + 1, NM = K1 * K1, Q = K1;
     constexpr int FX = StageTile<NV>::FX, FY = StageTile<NV>::FY;
     constexpr int NVE = StageTile<NV>::NVE, NHE = StageTile<NV>::NHE;
-    constexpr int TS = Q * NV;  // one edge: Q points x NV variables
+    // One edge holds Q points x NV variables in ES words, entry (b, v) at
+    // sw(b, v); the exchange block of a cell holds NV x NV entries in XS
+    // words, entry (i, j) at sw(i, j).  With 4 variables the entries are
+    // rotated, sw(i, j) = 4 i + (i + j) mod 4, and ES, XS = 4 mod 16 words:
+    // then each group of 16 lanes (4 cells x 4 variables, one 128-byte LDS
+    // cycle of 64-bit accesses) hits 16 different banks whether the lanes
+    // vary the cell and the variable (traces, edge fluxes per cell, point
+    // values) or the edge and the point (the flux work items).
+    constexpr int ES = NV == 4 ? (Q == 1 ? 4 : 20) : Q + 1;
+    constexpr int XS = NV == 4 ? 20 : 1;
+    auto sw = [](int i, int j) { return NV == 4 ? 4 * i + ((i + j) & 3) : i * NV + j; };
     // traces: lower side (the -x / -y cell) and upper side of every edge
     // (vertical edges first); the lower half later takes the edge fluxes and
     // the upper half the per-cell exchange blocks of the volume term (NV x NV
     // values per cell: point values, then F1, then F2)
-    constexpr int HALF = (NVE + NHE) * TS;
-    constexpr int XB = NV > 1 ? (256 / NV) * NV * NV : 0;
+    constexpr int HALF = (NVE + NHE) * ES;
+    constexpr int XB = NV > 1 ? (256 / NV) * XS : 0;
     __shared__ __align__(16) T lds[HALF + (HALF > XB ? HALF : XB)];
     T* sLo = lds;
     T* sHi = lds + HALF;
@@ -596,28 +629,21 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
 #pragma unroll
     for (int m = 0; m < NM; ++m) um[m] = (T)0;
     if (loadable) load_var2d<K, PK, TB, T>(a.us, cy * a.nx + cx, v, m0v, um);
-    // u^n of the own cell for the combination, fetched now so that its
-    // latency overlaps the flux phases
     const int64_t cell = jy * a.nx + ix;
-    double n0 = 0.0;
-    T nm[NM];
-#pragma unroll
-    for (int m = 0; m < NM; ++m) nm[m] = (T)0;
-    if (own && stage > 0) load_var2d<K, PK, TB, T>(a.un, cell, v, n0, nm);
     if (loadable) {
         T tr[Q];
         face_trace_var<0, K, T>(um, tr);  // left face: upper side of vertical edge tx
 #pragma unroll
-        for (int b = 0; b < Q; ++b) sHi[vslot(ty, tx) * TS + b * NV + v] = tr[b];
+        for (int b = 0; b < Q; ++b) sHi[vslot(ty, tx) * ES + sw(b, v)] = tr[b];
         face_trace_var<1, K, T>(um, tr);  // right face: lower side of edge tx+1
 #pragma unroll
-        for (int b = 0; b < Q; ++b) sLo[vslot(ty, tx + 1) * TS + b * NV + v] = tr[b];
+        for (int b = 0; b < Q; ++b) sLo[vslot(ty, tx + 1) * ES + sw(b, v)] = tr[b];
         face_trace_var<2, K, T>(um, tr);  // bottom face: upper side of horizontal edge ty
 #pragma unroll
-        for (int b = 0; b < Q; ++b) sHi[hslot(tx, ty) * TS + b * NV + v] = tr[b];
+        for (int b = 0; b < Q; ++b) sHi[hslot(tx, ty) * ES + sw(b, v)] = tr[b];
         face_trace_var<3, K, T>(um, tr);  // top face: lower side of edge ty+1
 #pragma unroll
-        for (int b = 0; b < Q; ++b) sLo[hslot(tx, ty + 1) * TS + b * NV + v] = tr[b];
+        for (int b = 0; b < Q; ++b) sLo[hslot(tx, ty + 1) * ES + sw(b, v)] = tr[b];
     }
     constexpr int NRING = 2 * FY + 2 * FX;
     if (tid < NRING * NV) {
@@ -638,19 +664,19 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
             T* dst;
             if (g == 0) {
                 face_trace_var<1, K, T>(wm, tr);
-                dst = &sLo[vslot(i, 0) * TS];
+                dst = &sLo[vslot(i, 0) * ES];
             } else if (g == 1) {
                 face_trace_var<0, K, T>(wm, tr);
-                dst = &sHi[vslot(i, FX) * TS];
+                dst = &sHi[vslot(i, FX) * ES];
             } else if (g == 2) {
                 face_trace_var<3, K, T>(wm, tr);
-                dst = &sLo[hslot(i, 0) * TS];
+                dst = &sLo[hslot(i, 0) * ES];
             } else {
                 face_trace_var<2, K, T>(wm, tr);
-                dst = &sHi[hslot(i, FY) * TS];
+                dst = &sHi[hslot(i, FY) * ES];
             }
 #pragma unroll
-            for (int b = 0; b < Q; ++b) dst[b * NV + rv] = tr[b];
+            for (int b = 0; b < Q; ++b) dst[sw(b, rv)] = tr[b];
         }
     }
     __syncthreads();
@@ -689,8 +715,8 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
             T ul[NV], ur[NV];
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
-                ul[q] = sLo[es * TS + b * NV + q];
-                ur[q] = sHi[es * TS + b * NV + q];
+                ul[q] = sLo[es * ES + sw(b, q)];
+                ur[q] = sHi[es * ES + sw(b, q)];
             }
             const double edge = vert ? a.xlo + (double)ghi * a.hx : a.ylo + (double)ghi * a.hy;
             const double along = vert ? a.ylo + (double)other * a.hy + 0.5 * a.hy * (1.0 + gl_node(Q, b))
@@ -709,7 +735,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
         const int w = tid + 256 * k;
         if (w >= NITEM) break;
 #pragma unroll
-        for (int q = 0; q < NV; ++q) sF[(w / Q) * TS + (w % Q) * NV + q] = fl[k][q];
+        for (int q = 0; q < NV; ++q) sF[(w / Q) * ES + sw(w % Q, q)] = fl[k][q];
     }
     __syncthreads();
 
@@ -755,14 +781,14 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
         } else {
             // lane v of the cell takes point (qa, v): the cell's lanes swap
             // point values and fluxes through their LDS block
-            T* X = &sX[cidx * NV * NV];
+            T* X = &sX[cidx * XS];
 #pragma unroll
-            for (int b = 0; b < NV; ++b) X[b * NV + v] = uv[b];
+            for (int b = 0; b < NV; ++b) X[sw(b, v)] = uv[b];
             wave_lds_sync();
             T uq[NV], f1[NV], f2[NV];
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
-                uq[q] = X[v * NV + q];
+                uq[q] = X[sw(v, q)];
                 f1[q] = f2[q] = (T)0;
             }
             wave_lds_sync();  // the block is rewritten with F1
@@ -778,16 +804,16 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
                 P::flux(uq, 1, f2, a.phys);
             }
 #pragma unroll
-            for (int q = 0; q < NV; ++q) X[v * NV + q] = f1[q];
+            for (int q = 0; q < NV; ++q) X[sw(v, q)] = f1[q];
             wave_lds_sync();
 #pragma unroll
-            for (int b = 0; b < NB; ++b) g1[b] = X[b * NV + v];
+            for (int b = 0; b < NB; ++b) g1[b] = X[sw(b, v)];
             wave_lds_sync();  // then with F2
 #pragma unroll
-            for (int q = 0; q < NV; ++q) X[v * NV + q] = f2[q];
+            for (int q = 0; q < NV; ++q) X[sw(v, q)] = f2[q];
             wave_lds_sync();
 #pragma unroll
-            for (int b = 0; b < NB; ++b) g2[b] = X[b * NV + v];
+            for (int b = 0; b < NB; ++b) g2[b] = X[sw(b, v)];
             wave_lds_sync();  // the block is rewritten by the next row
         }
         T t1[K1], t2[K1];  // sum_b w_b F1 P_q(eta_b), sum_b w_b F2 P_q'(eta_b)
@@ -808,44 +834,101 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
 #pragma unroll
             for (int q = 0; q < K1; ++q)
                 acc[p * K1 + q] += wa * (hy2 * (T)dleg_at(Q, qa, p) * t1[q] + hx2 * (T)leg_at(Q, qa, p) * t2[q]);
+        // keep the rows apart: interleaving them only raises the register
+        // count (and so lowers the occupancy)
+        __builtin_amdgcn_sched_barrier(0);
     }
 
     double v0 = 0.0;
     if (own) {
-        const T* FL = &sF[vslot(ty, tx) * TS];
-        const T* FR = &sF[vslot(ty, tx + 1) * TS];
-        const T* FB = &sF[hslot(tx, ty) * TS];
-        const T* FT = &sF[hslot(tx, ty + 1) * TS];
+        const T* FL = &sF[vslot(ty, tx) * ES];
+        const T* FR = &sF[vslot(ty, tx + 1) * ES];
+        const T* FB = &sF[hslot(tx, ty) * ES];
+        const T* FT = &sF[hslot(tx, ty + 1) * ES];
         const double ivol = a.inv_hx * a.inv_hy;
         // mode (0,0): -(hy/2) sum_b w_b (FR - FL) - (hx/2) sum_a w_a (FT - FB), in FP64
         double ex = 0.0, ey = 0.0;
 #pragma unroll
         for (int b = 0; b < Q; ++b) {
-            ex += gl_weight(Q, b) * ((double)FR[b * NV + v] - (double)FL[b * NV + v]);
-            ey += gl_weight(Q, b) * ((double)FT[b * NV + v] - (double)FB[b * NV + v]);
+            ex += gl_weight(Q, b) * ((double)FR[sw(b, v)] - (double)FL[sw(b, v)]);
+            ey += gl_weight(Q, b) * ((double)FT[sw(b, v)] - (double)FB[sw(b, v)]);
         }
         const double L0 = -(0.5 * a.hy * ex + 0.5 * a.hx * ey) * ivol;
-        v0 = combine2(stage, n0, m0v + dt * L0);
+        // modes >= 1: the edge moments of each face, sum_b w_b F_b P_o(b),
+        // enter mode (p, q) with the sign (-1)^p (left) or (-1)^q (bottom) of
+        // P_p(-1), P_q(-1); L overwrites acc
+        {
+            T xr[K1], xl[K1], yt[K1], yb[K1];
+#pragma unroll
+            for (int o = 0; o < K1; ++o) xr[o] = xl[o] = yt[o] = yb[o] = (T)0;
+#pragma unroll
+            for (int b = 0; b < Q; ++b) {
+                const T wr = (T)gl_weight(Q, b) * FR[sw(b, v)], wl = (T)gl_weight(Q, b) * FL[sw(b, v)];
+                const T wt = (T)gl_weight(Q, b) * FT[sw(b, v)], wb = (T)gl_weight(Q, b) * FB[sw(b, v)];
+#pragma unroll
+                for (int o = 0; o < K1; ++o) {
+                    const T lb = (T)leg_at(Q, b, o);
+                    xr[o] += wr * lb;
+                    xl[o] += wl * lb;
+                    yt[o] += wt * lb;
+                    yb[o] += wb * lb;
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < K1; ++p)
+#pragma unroll
+                for (int q = 0; q < K1; ++q) {
+                    if ((p == 0 && q == 0) || (PK && p + q > K)) continue;
+                    const T ex_ = (p & 1) ? xr[q] + xl[q] : xr[q] - xl[q];
+                    const T ey_ = (q & 1) ? yt[p] + yb[p] : yt[p] - yb[p];
+                    const T r = acc[p * K1 + q] - hy2 * ex_ - hx2 * ey_;
+                    acc[p * K1 + q] = (T)((2 * p + 1) * (2 * q + 1)) * (T)ivol * r;
+                }
+        }
+        // Euler step u + dt L in place, pinned (empty asm) before the loads of
+        // u^n so that they do not hold registers during the flux sums
+        double w0 = m0v + dt * L0;
+        asm volatile("" : "+v"(w0));
+#pragma unroll
+        for (int m = 1; m < NM; ++m) {
+            if (!mode_kept<K, PK>(m)) continue;
+            um[m] = um[m] + (T)dt * acc[m];
+            asm volatile("" : "+v"(um[m]));
+        }
+        asm volatile("" ::: "memory");
+        // u^n of the own cell for the combination
+        double n0 = 0.0;
+        T nm[NM];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) nm[m] = (T)0;
+        if (stage > 0) load_var2d<K, PK, TB, T>(a.un, cell, v, n0, nm);
+        v0 = combine2(stage, n0, w0);
         a.out.m0[v * a.out.s0 + cell] = v0;
 #pragma unroll
-        for (int p = 0; p < K1; ++p)
+        for (int m = 1; m < NM; ++m) {
+            if (!mode_kept<K, PK>(m)) continue;
+            um[m] = combine2_t<T>(stage, nm[m], um[m]);
+            a.out.hi[v * a.out.sv + (mode_plane<K, PK>(m) - 1) * a.out.sl + cell] = um[m];
+        }
+        if (a.corner) {
+            // the output's values at the cell corners, for the hybrid
+            // indicator: the same sums over the stored modes that the
+            // indicator forms from the state (corner2d)
+            um[0] = (T)v0;
 #pragma unroll
-            for (int q = 0; q < K1; ++q) {
-                if ((p == 0 && q == 0) || (PK && p + q > K)) continue;
-                T ex_ = (T)0, ey_ = (T)0;
+            for (int c = 0; c < 4; ++c)
+                a.corner[(c * NV + v) * a.cstride + cell] = corner2d<K, PK, T>(um, c & 1, c >> 1);
+            if constexpr (EQ == EULER) {
+                if (a.ppfail) {
+                    double sabs = 0.0;
 #pragma unroll
-                for (int b = 0; b < Q; ++b) {
-                    const T fl_ = (p & 1) ? -FL[b * NV + v] : FL[b * NV + v];
-                    ex_ += (T)gl_weight(Q, b) * (FR[b * NV + v] - fl_) * (T)leg_at(Q, b, q);
-                    const T fb = (q & 1) ? -FB[b * NV + v] : FB[b * NV + v];
-                    ey_ += (T)gl_weight(Q, b) * (FT[b * NV + v] - fb) * (T)leg_at(Q, b, p);
+                    for (int m = 1; m < NM; ++m)
+                        if (mode_kept<K, PK>(m)) sabs += fabs((double)um[m]);
+                    const bool clear = pp2_clear_lanes<TB>(v0, sabs, base, a.phys.gamma);
+                    if (v == 0) a.ppfail[cell] = clear ? 0 : 1;
                 }
-                const T r = acc[p * K1 + q] - hy2 * ex_ - hx2 * ey_;
-                const T L = (T)((2 * p + 1) * (2 * q + 1)) * (T)ivol * r;
-                const int m = p * K1 + q;
-                a.out.hi[v * a.out.sv + (mode_plane<K, PK>(m) - 1) * a.out.sl + cell] =
-                    combine2_t<T>(stage, nm[m], um[m] + (T)dt * L);
             }
+        }
     }
     // CFL quantity of the output's cell average (all variables of the cell)
     if (a.alpha_acc) {
@@ -860,8 +943,8 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
 }
 
 // -------------------------------------------------------------------------
-// Jump filter (MODE 1: filtered copy of a.us into a.out) or hybrid pass A
-// (MODE 2: records of the troubled cells of a.us, and max eta).
+// Jump filter: filtered copy of a.us into a.out, then (pp) the positivity
+// limiter's screen (the hybrid limiter has kernels of its own below).
 //   E^l = dt / (hx hy H) * max_v [cfmx beta_x Sx^l_v + cfmy beta_y Sy^l_v],
 //   Sx^l = sum_{|a| <= l} jsx[a] * Jx^a (edge-averaged |[d^a u]| in reference
 //   derivatives; jsx[0] = hx, jsx[a] = m(m+1) hx^(m+1) (2/hx)^a1 (2/hy)^a2).
@@ -877,7 +960,7 @@ struct FilterTile {
     static constexpr int SX = FX + 2, SY = FY + 2;
 };
 
-template <int EQ, int K, typename TB, int MODE, bool PK>
+template <int EQ, int K, typename TB, bool PK>
 __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
 {
     using P = Phys2D<EQ>;
@@ -962,14 +1045,10 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
     T Jx[L1], Jy[L1];  // weighted sums per derivative order m = a1 + a2 (variable v)
 #pragma unroll
     for (int m = 0; m < L1; ++m) Jx[m] = Jy[m] = (T)0;
-    T jx0 = (T)0, jy0_ = (T)0;
-    // Jumps of the derivatives d^a u at the corners of the four faces.  FULL:
-    // every multi-index a (a1, a2 <= k) into Jx, Jy; otherwise the value
-    // jumps (a = 0) only, into jx0, jy0_ (the hybrid indicator).  The a = 0
-    // terms are the same operations either way.
-    auto face_jumps = [&](auto full_tag) {
-        constexpr bool FULL = decltype(full_tag)::value;
-        constexpr int AL = FULL ? K1 : 1;
+    // Jumps of every mixed derivative d^a u (a1, a2 <= k) at the corners of
+    // the four faces.
+    if (own) {
+        constexpr int AL = K1;
         // DIR 0: vertical faces (x = const), DIR 1: horizontal faces.  The
         // face side is a run-time loop index (keeps one face live at a time).
 #pragma unroll
@@ -1040,40 +1119,14 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
                                     j = (T)0;
                             }
                             const int a1 = dir == 0 ? al : bl, a2 = dir == 0 ? bl : al;
-                            if constexpr (FULL) {
-                                if (dir == 0)
-                                    Jx[a1 + a2] += (T)(0.5 * a.jsx[a1 * 4 + a2]) * j;
-                                else
-                                    Jy[a1 + a2] += (T)(0.5 * a.jsy[a1 * 4 + a2]) * j;
-                            } else {
-                                if (dir == 0)
-                                    jx0 += (T)0.5 * j;
-                                else
-                                    jy0_ += (T)0.5 * j;
-                            }
+                            if (dir == 0)
+                                Jx[a1 + a2] += (T)(0.5 * a.jsx[a1 * 4 + a2]) * j;
+                            else
+                                Jy[a1 + a2] += (T)(0.5 * a.jsy[a1 * 4 + a2]) * j;
                         }
             }
         }
-    };
-    if (own) face_jumps(std::false_type{});
-    T eta;
-    {
-        const T ev = jx0 * (T)(0.5 * a.inv_hx) + jy0_ * (T)(0.5 * a.inv_hy);
-        const int base = tid - v;
-        eta = ev;
-#pragma unroll
-        for (int w = 0; w < NV; ++w) {
-            const T o = NV > 1 ? __shfl(ev, base + w, 64) : ev;
-            eta = (w == 0 || o > eta) ? o : eta;
-        }
     }
-    // The exponents need every derivative jump.  The hybrid (MODE 2) needs
-    // them only for troubled cells (eta > 1, Algorithm 1), so a wavefront
-    // with none skips them (unless the per-call API asks for every cell's
-    // exponents).
-    bool full = MODE == 1 || a.E_out != nullptr;
-    if (!full) full = __ballot(own && eta > (T)1) != 0;
-    if (full && own) face_jumps(std::true_type{});
     // running partial sums over the derivative order, then the maximum over
     // the variables (in variable order, as a sequential loop would take it)
     T best[L1];
@@ -1094,11 +1147,6 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
             best[l] = bl;
         }
     }
-    if (MODE == 2) {
-        // max eta over the grid: every lane reaches the wave reduction
-        const double z = wave_max(own ? (double)eta : 0.0);
-        if ((tid & 63) == 0) atomic_max_nonneg(a.eta_acc, z);
-    }
     if (!own) return;
     const int64_t cell = jy * a.nx + ix;
     const T coef = (T)dt * (T)(a.inv_hx * a.inv_hy) / H;
@@ -1110,60 +1158,31 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
 #pragma unroll
         for (int l = 0; l < L1; ++l) a.E_out[cell * L1 + l] = (double)E[l];
     }
-    if constexpr (MODE == 1) {
-        T f[L1];
+    T f[L1];
 #pragma unroll
-        for (int l = 1; l < L1; ++l) f[l] = texp<T>(-E[l]);
-        a.out.m0[v * a.out.s0 + cell] = m0v;
-        double sabs = 0.0;
+    for (int l = 1; l < L1; ++l) f[l] = texp<T>(-E[l]);
+    a.out.m0[v * a.out.s0 + cell] = m0v;
+    double sabs = 0.0;
 #pragma unroll
-        for (int p = 0; p < K1; ++p)
+    for (int p = 0; p < K1; ++p)
 #pragma unroll
-            for (int q = 0; q < K1; ++q) {
-                if ((p == 0 && q == 0) || (PK && p + q > K)) continue;
-                const int m = p * K1 + q;
-                const T val = um[m] * f[p + q];
-                sabs += fabs((double)val);
-                a.out.hi[v * a.out.sv + (mode_plane<K, PK>(m) - 1) * a.out.sl + cell] = val;
-            }
-        // positivity limiter: list the cells its screen does not clear
-        if constexpr (EQ == EULER) {
-            if (a.pp && !pp2_clear_lanes<TB>(m0v, sabs, tid - v, a.phys.gamma) && v == 0) {
-                const unsigned long long slot = atomicAdd(a.pcount, 1ull);
-                if ((long long)slot < a.pcap) a.pcell[slot] = cell;
-            }
+        for (int q = 0; q < K1; ++q) {
+            if ((p == 0 && q == 0) || (PK && p + q > K)) continue;
+            const int m = p * K1 + q;
+            const T val = um[m] * f[p + q];
+            sabs += fabs((double)val);
+            a.out.hi[v * a.out.sv + (mode_plane<K, PK>(m) - 1) * a.out.sl + cell] = val;
         }
-    } else {
-        // positivity limiter: cells that stay unfiltered (eta <= 1) are final
-        // now; troubled cells are screened after their blend
-        if constexpr (EQ == EULER) {
-            if (a.pp) {
-                double sabs = 0.0;
-#pragma unroll
-                for (int m = 1; m < NM; ++m) sabs += fabs((double)um[m]);
-                if (!(eta > (T)1) && !pp2_clear_lanes<TB>(m0v, sabs, tid - v, a.phys.gamma) && v == 0) {
-                    const unsigned long long slot = atomicAdd(a.pcount, 1ull);
-                    if ((long long)slot < a.pcap) a.pcell[slot] = cell;
-                }
-            }
-        }
-        if (v == 0) {
-            if (a.eta_out) a.eta_out[cell] = (double)eta;
-            if (eta > (T)1) {
-                const unsigned int slot = atomicAdd(a.tcount, 1u);
-                if ((long long)slot < a.tcap) {
-                    a.tcell[slot] = cell;
-                    double* rec = a.tdata + (size_t)slot * L1;
-                    rec[0] = (double)eta;
-#pragma unroll
-                    for (int l = 1; l < L1; ++l) rec[l] = (double)E[l];
-                }
-            }
+    // positivity limiter: list the cells its screen does not clear
+    if constexpr (EQ == EULER) {
+        if (a.pp && !pp2_clear_lanes<TB>(m0v, sabs, tid - v, a.phys.gamma) && v == 0) {
+            const unsigned long long slot = atomicAdd(a.pcount, 1ull);
+            if ((long long)slot < a.pcap) a.pcell[slot] = cell;
         }
     }
 }
 
-// Hybrid pass B over the troubled list: u^{pq} <- [w + (1 - w) exp(-E^{p+q})] u^{pq},
+// Hybrid limiter, pass B2, over the troubled list: u^{pq} <- [w + (1 - w) exp(-E^{p+q})] u^{pq},
 // then (Euler, pp.on) the positivity limiter on the blended cell.  One
 // wavefront per troubled cell: lane l < NV (K+1)^2 holds coefficient
 // (variable l / (K+1)^2, mode l % (K+1)^2).
@@ -1230,6 +1249,365 @@ __global__ __launch_bounds__(256) void pp2d_kernel(StateView<TB> u, long long nc
             cf = u.m0[v * u.s0 + c];
         if (pp2_wave<K, PK, TB>(sc[wv], cf, lane, pp.phys.gamma, pp.reject) && mine)
             u.hi[off + c] = (TB)cf;
+    }
+}
+
+// -------------------------------------------------------------------------
+// Hybrid limiter, pass A (Algorithm 1): the jump indicator
+//   eta = max_v (Jx0_v / (2 hx) + Jy0_v / (2 hy)),
+// Jx0, Jy0 the trapezoid edge averages of the value jumps over the vertical
+// and horizontal faces, for every cell of a.us (read only); the domain
+// maximum of eta (a.eta_acc), the troubled cells (eta > 1: a.tcell, with eta
+// in the first entry of each a.tdata record), and, with the positivity
+// limiter, the cells that stay unfiltered and whose screen fails (a.pcell).
+// The exponents of the troubled cells are computed by troubled2d_kernel.
+// Mapping as filter2d: one lane per (cell, variable), FX x FY cells per
+// workgroup; each lane evaluates its variable at the four corners of its
+// cell (the values P_p(+-1) P_q(+-1) = +-1, summed in the order p, q), the
+// tile's ring cells their two facing corners, and the corner values meet in
+// LDS.
+// -------------------------------------------------------------------------
+template <int EQ, int K, typename TB, bool PK>
+__global__ __launch_bounds__(256) void indicator2d_kernel(Args2D<TB> a)
+{
+    using P = Phys2D<EQ>;
+    using T = TB;
+    constexpr int NV = P::NV, K1 = K + 1, NM = K1 * K1, L1 = 2 * K + 1;
+    constexpr int FX = FilterTile<NV>::FX, FY = FilterTile<NV>::FY;
+    constexpr int NRING = 2 * FY + 2 * FX;
+    // corner values: own cells [corner sx + 2 sy][cell][var]; ring cells
+    // [the two facing corners][ring index][var] (consecutive lanes,
+    // consecutive words)
+    constexpr int CS = FX * FY * NV, RS = NRING * NV;
+    __shared__ T sC[4 * CS];
+    __shared__ T sR[2 * RS];
+
+    if (a.dt_from_ctrl && a.ctrl->done) return;
+    const double dt = a.dt_from_ctrl ? a.ctrl->dt : a.dt_host;
+    const double t0 = a.dt_from_ctrl ? a.ctrl->t : a.t_host;
+    const double tf = t0 + (a.stage == 1 ? 0.5 : 1.0) * dt;  // time the stage output stands for
+
+    const int tid = threadIdx.x, v = tid % NV, cidx = tid / NV;
+    const int tx = cidx % FX, ty = cidx / FX;
+    int64_t tbx, tby;
+    xcd_tile((a.nx + FX - 1) / FX, gridDim.x, tbx, tby);
+    const int64_t ix0 = tbx * FX, jy0 = tby * FY;
+    const int64_t ix = ix0 + tx, jy = jy0 + ty;
+    const bool px = a.bc[0] == BC_PERIODIC, py = a.bc[2] == BC_PERIODIC;
+    const bool own = ix < a.nx && jy < a.ny;
+    // a slot past the mesh in a ragged tile holds the periodic image (the
+    // face neighbour of the last own cell), or nothing
+    const int64_t cx = slot_index(ix, a.nx, px), cy = slot_index(jy, a.ny, py);
+    const bool loadable = cx >= 0 && cy >= 0;
+
+    double m0v = 0.0;
+    T um[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) um[m] = (T)0;
+    if (loadable) {
+        const int64_t c0 = cy * a.nx + cx;
+        if (a.corner) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) sC[c * CS + cidx * NV + v] = a.corner[(c * NV + v) * a.cstride + c0];
+        } else {
+            load_var2d<K, PK, TB, T>(a.us, c0, v, m0v, um);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) sC[c * CS + cidx * NV + v] = corner2d<K, PK, T>(um, c & 1, c >> 1);
+        }
+    }
+    if (tid < NRING * NV) {
+        const int r = tid / NV, rv = tid % NV;
+        int g, i;  // 0 left column, 1 right column, 2 bottom row, 3 top row
+        if (r < FY) { g = 0; i = r; }
+        else if (r < 2 * FY) { g = 1; i = r - FY; }
+        else if (r < 2 * FY + FX) { g = 2; i = r - 2 * FY; }
+        else { g = 3; i = r - 2 * FY - FX; }
+        const int64_t gx = g == 0 ? ix0 - 1 : g == 1 ? ix0 + FX : ix0 + i;
+        const int64_t gy = g == 2 ? jy0 - 1 : g == 3 ? jy0 + FY : jy0 + i;
+        const int64_t hx_ = slot_index(gx, a.nx, px), hy_ = slot_index(gy, a.ny, py);
+        if (hx_ >= 0 && hy_ >= 0) {
+            const int64_t c1 = hy_ * a.nx + hx_;
+            // facing corners, ordered along the face: the left column's
+            // right corners (bottom, top), the right column's left corners,
+            // the bottom row's top corners (left, right), the top row's
+            // bottom corners
+            if (a.corner) {
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int sx = g == 0 ? 1 : g == 1 ? 0 : c, sy = g == 2 ? 1 : g == 3 ? 0 : c;
+                    sR[c * RS + r * NV + rv] = a.corner[((sx + 2 * sy) * NV + rv) * a.cstride + c1];
+                }
+            } else {
+                double w0;
+                T wm[NM];
+                load_var2d<K, PK, TB, T>(a.us, c1, rv, w0, wm);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int sx = g == 0 ? 1 : g == 1 ? 0 : c, sy = g == 2 ? 1 : g == 3 ? 0 : c;
+                    sR[c * RS + r * NV + rv] = corner2d<K, PK, T>(wm, sx, sy);
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    T eta = (T)0;
+    if (own) {
+        const bool lin = slot_index(ix - 1, a.nx, px) >= 0, rin = slot_index(ix + 1, a.nx, px) >= 0;
+        const bool bin = slot_index(jy - 1, a.ny, py) >= 0, tin = slot_index(jy + 1, a.ny, py) >= 0;
+        const double xl = a.xlo + (double)ix * a.hx, yb = a.ylo + (double)jy * a.hy;
+        // the neighbour's value at corner c of the face (dir, side): from the
+        // tile or its ring
+        auto nb_corner = [&](int dir, int side, int c) -> T {
+            if (dir == 0) {
+                const int nx_ = tx + (side ? 1 : -1);
+                if (nx_ >= 0 && nx_ < FX) return sC[((side ? 0 : 1) + 2 * c) * CS + (ty * FX + nx_) * NV + v];
+                const int r = side ? FY + ty : ty;
+                return sR[c * RS + r * NV + v];
+            }
+            const int ny_ = ty + (side ? 1 : -1);
+            if (ny_ >= 0 && ny_ < FY) return sC[(c + (side ? 0 : 2)) * CS + (ny_ * FX + tx) * NV + v];
+            const int r = side ? 2 * FY + FX + tx : 2 * FY + tx;
+            return sR[c * RS + r * NV + v];
+        };
+        T jx = (T)0, jyv = (T)0;
+#pragma unroll
+        for (int side = 0; side < 2; ++side)
+#pragma unroll
+            for (int dir = 0; dir < 2; ++dir) {
+                const bool inside = dir == 0 ? (side ? rin : lin) : (side ? tin : bin);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    // own corner of this face
+                    const int sx = dir == 0 ? side : c, sy = dir == 0 ? c : side;
+                    const T in = sC[(sx + 2 * sy) * CS + cidx * NV + v];
+                    T j;
+                    if (inside) {
+                        j = fabs(nb_corner(dir, side, c) - in);
+                    } else {
+                        const double xc = xl + (sx ? a.hx : 0.0), yc = yb + (sy ? a.hy : 0.0);
+                        bool rf;
+                        const int kind = boundary_kind(a, 2 * dir + side, xc, yc, tf, &rf);
+                        if (kind)
+                            j = fabs((T)boundary_state(a, 2 * dir + side, kind, v) - in);
+                        else if (rf)
+                            j = (v == 1 + dir) ? (T)2 * fabs(in) : (T)0;
+                        else
+                            j = (T)0;
+                    }
+                    if (dir == 0)
+                        jx += (T)0.5 * j;
+                    else
+                        jyv += (T)0.5 * j;
+                }
+            }
+        eta = jx * (T)(0.5 * a.inv_hx) + jyv * (T)(0.5 * a.inv_hy);
+    }
+    {
+        const int base = tid - v;
+        T e = eta;
+#pragma unroll
+        for (int w = 0; w < NV; ++w) {
+            const T o = NV > 1 ? __shfl(eta, base + w, 64) : eta;
+            e = (w == 0 || o > e) ? o : e;
+        }
+        eta = e;
+    }
+    // max eta over the grid: every lane reaches the wave reduction
+    const double z = wave_max(own ? (double)eta : 0.0);
+    if ((tid & 63) == 0) atomic_max_nonneg(a.eta_acc, z);
+    if (!own) return;
+    const int64_t cell = jy * a.nx + ix;
+    if (a.E_out && v == 0) {
+#pragma unroll
+        for (int l = 0; l < L1; ++l) a.E_out[cell * L1 + l] = 0.0;
+    }
+    if constexpr (EQ == EULER) {
+        // positivity limiter: cells that stay unfiltered (eta <= 1) are final
+        // now; troubled cells are screened after their blend
+        if (a.pp) {
+            bool fail;
+            if (a.corner) {
+                fail = a.ppfail[cell] != 0;  // the stage kernel's screen
+            } else {
+                double sabs = 0.0;
+#pragma unroll
+                for (int m = 1; m < NM; ++m) sabs += fabs((double)um[m]);
+                fail = !pp2_clear_lanes<TB>(m0v, sabs, tid - v, a.phys.gamma);
+            }
+            if (!(eta > (T)1) && fail && v == 0) {
+                const unsigned long long slot = atomicAdd(a.pcount, 1ull);
+                if ((long long)slot < a.pcap) a.pcell[slot] = cell;
+            }
+        }
+    }
+    if (v == 0) {
+        if (a.eta_out) a.eta_out[cell] = (double)eta;
+        if (eta > (T)1) {
+            const unsigned int slot = atomicAdd(a.tcount, 1u);
+            if ((long long)slot < a.tcap) {
+                a.tcell[slot] = cell;
+                a.tdata[(size_t)slot * L1] = (double)eta;
+            }
+        }
+    }
+}
+
+// -------------------------------------------------------------------------
+// Hybrid limiter, pass B1: for each troubled cell of the list (one wavefront
+// per cell) the damping exponents of the jump filter, from the jumps of every
+// mixed derivative d^a u (a1, a2 <= k) at the corners of the four faces
+// (para:damp22d)-(para:damp22d1) with the systems rule (maximum over the
+// variables), into the cell's a.tdata record (E^1..E^{2k} after eta).  The
+// state is only read: every troubled cell's exponents come from the
+// unfiltered stage output (Jacobi), and blend2d_kernel applies them after.
+// Lanes: l = v (k+1)^2 + al (k+1) + bl takes the derivative orders (al across
+// a face, bl along it) of variable v on every face; l = v (k+1)^2 + m loads
+// coefficient m of variable v.
+// -------------------------------------------------------------------------
+template <int EQ, int K, typename TB, bool PK>
+__global__ __launch_bounds__(256) void troubled2d_kernel(Args2D<TB> a)
+{
+    using P = Phys2D<EQ>;
+    using T = TB;
+    constexpr int NV = P::NV, K1 = K + 1, NM = K1 * K1, L1 = 2 * K + 1, NC = NV * NM;
+    static_assert(NC <= 64, "one lane per coefficient");
+    // per wavefront: the modes of the cell and of its four face neighbours
+    // (own, left, right, bottom, top), the per-lane weighted jump sums and the
+    // per-variable sums
+    struct WaveLds {
+        T u[5][NC];
+        T wx[NC], wy[NC];
+        T sv[NV][L1];
+    };
+    __shared__ WaveLds sh[4];
+    if (a.dt_from_ctrl && a.ctrl->done) return;
+    const double dt = a.dt_from_ctrl ? a.ctrl->dt : a.dt_host;
+    const double t0 = a.dt_from_ctrl ? a.ctrl->t : a.t_host;
+    const double tf = t0 + (a.stage == 1 ? 0.5 : 1.0) * dt;
+    unsigned int cnt = *a.tcount;
+    if ((long long)cnt > a.tcap) cnt = (unsigned int)a.tcap;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    WaveLds& L = sh[wv];
+    const int v = lane / NM, m = lane % NM;
+    const int al = m / K1, bl = m % K1;  // derivative orders of this lane
+    const bool act = lane < NC;
+    const bool px = a.bc[0] == BC_PERIODIC, py = a.bc[2] == BC_PERIODIC;
+    for (unsigned int i = blockIdx.x * 4 + wv; i < cnt; i += gridDim.x * 4) {
+        const long long c = a.tcell[i];
+        const int64_t ix = c % a.nx, jy = c / a.nx;
+        const int64_t nbx[4] = {slot_index(ix - 1, a.nx, px), slot_index(ix + 1, a.nx, px), ix, ix};
+        const int64_t nby[4] = {jy, jy, slot_index(jy - 1, a.ny, py), slot_index(jy + 1, a.ny, py)};
+        // loads: coefficient m of variable v of the cell and its neighbours
+        if (act) {
+            const bool kept = mode_kept<K, PK>(m);
+            const int64_t off = m == 0 ? v * a.us.s0 : v * a.us.sv + (mode_plane<K, PK>(m > 0 ? m : 1) - 1) * a.us.sl;
+            for (int nb = 0; nb < 5; ++nb) {
+                const int64_t gx = nb == 0 ? ix : nbx[nb - 1], gy = nb == 0 ? jy : nby[nb - 1];
+                T val = (T)0;
+                if (gx >= 0 && gy >= 0 && kept) {
+                    const int64_t cc = gy * a.nx + gx;
+                    val = m == 0 ? (T)a.us.m0[off + cc] : (T)a.us.hi[off + cc];
+                }
+                L.u[nb][lane] = val;
+            }
+        }
+        wave_lds_sync();
+        // jumps of d^(al, bl) (x faces) and d^(bl, al) (y faces) of variable v
+        T wxs = (T)0, wys = (T)0;
+        if (act) {
+            const double xl = a.xlo + (double)ix * a.hx, yb = a.ylo + (double)jy * a.hy;
+            const T* U = &L.u[0][v * NM];
+#pragma unroll
+            for (int dir = 0; dir < 2; ++dir)
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    const int nb = 1 + 2 * dir + side;
+                    const bool inside = (dir == 0 ? nbx[2 * dir + side] : nby[2 * dir + side]) >= 0;
+                    const T* UN = &L.u[nb][v * NM];
+                    auto across = [&](int n, int sd) -> T {
+                        const double r = dtrace_r(n, al);
+                        return (T)((sd || !((n + al) & 1)) ? r : -r);
+                    };
+                    T D[K1];
+#pragma unroll
+                    for (int o = 0; o < K1; ++o) {
+                        T go = (T)0, gn = (T)0;
+#pragma unroll
+                        for (int n = 0; n < K1; ++n) {
+                            if (n < al) continue;
+                            const int mm = dir == 0 ? n * K1 + o : o * K1 + n;
+                            go += U[mm] * across(n, side);
+                            if (inside) gn += UN[mm] * across(n, 1 - side);
+                        }
+                        D[o] = inside ? gn - go : go;
+                    }
+#pragma unroll
+                    for (int cc = 0; cc < 2; ++cc) {
+                        T sum = (T)0;
+#pragma unroll
+                        for (int o = 0; o < K1; ++o)
+                            if (o >= bl) sum += D[o] * (T)dtr(o, bl, cc);
+                        T j = fabs(sum);
+                        if (!inside) {
+                            const double xc = dir == 0 ? xl + (side ? a.hx : 0.0) : xl + (cc ? a.hx : 0.0);
+                            const double yc = dir == 0 ? yb + (cc ? a.hy : 0.0) : yb + (side ? a.hy : 0.0);
+                            bool rf;
+                            const int kind = boundary_kind(a, 2 * dir + side, xc, yc, tf, &rf);
+                            if (kind)
+                                j = (al == 0 && bl == 0) ? fabs((T)boundary_state(a, 2 * dir + side, kind, v) - sum)
+                                                         : fabs(sum);
+                            else if (rf)
+                                j = (((al & 1) != 0) != (v == 1 + dir)) ? (T)2 * fabs(sum) : (T)0;
+                            else
+                                j = (T)0;
+                        }
+                        if (dir == 0)
+                            wxs += (T)(0.5 * a.jsx[al * 4 + bl]) * j;
+                        else
+                            wys += (T)(0.5 * a.jsy[bl * 4 + al]) * j;
+                    }
+                }
+            L.wx[lane] = wxs;
+            L.wy[lane] = wys;
+        }
+        wave_lds_sync();
+        // per variable: running sums over the derivative order l = al + bl,
+        // weighted by the coefficient's mesh factors and wave speeds
+        if (lane < NV) {
+            T ub[NV];
+#pragma unroll
+            for (int w = 0; w < NV; ++w) ub[w] = L.u[0][w * NM];
+            const T bx = P::speed(ub, 0, a.phys), by = P::speed(ub, 1, a.phys);
+            T sx = (T)0, sy = (T)0;
+#pragma unroll
+            for (int l = 0; l < L1; ++l) {
+#pragma unroll
+                for (int x = 0; x < K1; ++x) {
+                    const int y = l - x;
+                    if (y < 0 || y >= K1) continue;
+                    sx += L.wx[lane * NM + x * K1 + y];
+                    sy += L.wy[lane * NM + x * K1 + y];
+                }
+                L.sv[lane][l] = (T)a.cfmx * bx * sx + (T)a.cfmy * by * sy;
+            }
+        }
+        wave_lds_sync();
+        T ubt[NV];
+#pragma unroll
+        for (int w = 0; w < NV; ++w) ubt[w] = L.u[0][w * NM];
+        const T H = P::enthalpy(ubt, a.phys);
+        const T coef = (T)dt * (T)(a.inv_hx * a.inv_hy) / H;
+        // E^l = coef max_v sv[v][l], l = 1..2k, after eta in the record
+        if (lane < L1) {
+            T bl_ = L.sv[0][lane];
+#pragma unroll
+            for (int vv = 1; vv < NV; ++vv) bl_ = L.sv[vv][lane] > bl_ ? L.sv[vv][lane] : bl_;
+            const double E = lane == 0 ? 0.0 : (double)(coef * bl_);
+            if (lane > 0) a.tdata[(size_t)i * L1 + lane] = E;
+            if (a.E_out) a.E_out[c * L1 + lane] = E;
+        }
+        wave_lds_sync();  // the next cell rewrites the block
     }
 }
 
@@ -1334,22 +1712,18 @@ hipError_t launch_stage2d(int eq, int k, const Args2D<TB>& a, hipStream_t st)
 }
 
 template <typename TB>
-hipError_t launch_filter2d(int eq, int k, const Args2D<TB>& a, int mode, hipStream_t st)
+hipError_t launch_filter2d(int eq, int k, const Args2D<TB>& a, hipStream_t st)
 {
     const int fx = eq == ADV ? FilterTile<1>::FX : FilterTile<4>::FX;
     const int fy = eq == ADV ? FilterTile<1>::FY : FilterTile<4>::FY;
     dim3 grid((unsigned)(((a.nx + fx - 1) / fx) * ((a.ny + fy - 1) / fy))), block(256);
-#define DG_CASE(E_, K_)                                                                        \
-    if (eq == E_ && k == K_) {                                                                 \
-        if (mode == 1 && a.pk)                                                                 \
-            hipLaunchKernelGGL((filter2d_kernel<E_, K_, TB, 1, (K_ > 0)>), grid, block, 0, st, a); \
-        else if (mode == 1)                                                                    \
-            hipLaunchKernelGGL((filter2d_kernel<E_, K_, TB, 1, false>), grid, block, 0, st, a); \
-        else if (a.pk)                                                                         \
-            hipLaunchKernelGGL((filter2d_kernel<E_, K_, TB, 2, (K_ > 0)>), grid, block, 0, st, a); \
-        else                                                                                   \
-            hipLaunchKernelGGL((filter2d_kernel<E_, K_, TB, 2, false>), grid, block, 0, st, a); \
-        return hipGetLastError();                                                              \
+#define DG_CASE(E_, K_)                                                                         \
+    if (eq == E_ && k == K_) {                                                                  \
+        if (a.pk)                                                                               \
+            hipLaunchKernelGGL((filter2d_kernel<E_, K_, TB, (K_ > 0)>), grid, block, 0, st, a); \
+        else                                                                                    \
+            hipLaunchKernelGGL((filter2d_kernel<E_, K_, TB, false>), grid, block, 0, st, a);    \
+        return hipGetLastError();                                                               \
     }
     DG_CASE(ADV, 0) DG_CASE(ADV, 1) DG_CASE(ADV, 2) DG_CASE(ADV, 3)
     DG_CASE(EULER, 0) DG_CASE(EULER, 1) DG_CASE(EULER, 2) DG_CASE(EULER, 3)
@@ -1358,32 +1732,70 @@ hipError_t launch_filter2d(int eq, int k, const Args2D<TB>& a, int mode, hipStre
 }
 
 template <typename TB>
-hipError_t launch_blend2d(int nv, int k, StateView<TB> out, int64_t ncell, const unsigned int* count,
-                          const long long* tcell, const double* tdata,
-                          const unsigned long long* eta_bits, const Ctrl* ctrl, int from_ctrl,
-                          int64_t max_entries, int pk, PPArgs pp, hipStream_t st)
+hipError_t launch_indicator2d(int eq, int k, const Args2D<TB>& a, hipStream_t st)
+{
+    const int fx = eq == ADV ? FilterTile<1>::FX : FilterTile<4>::FX;
+    const int fy = eq == ADV ? FilterTile<1>::FY : FilterTile<4>::FY;
+    dim3 grid((unsigned)(((a.nx + fx - 1) / fx) * ((a.ny + fy - 1) / fy))), block(256);
+#define DG_CASE(E_, K_)                                                                            \
+    if (eq == E_ && k == K_) {                                                                     \
+        if (a.pk)                                                                                  \
+            hipLaunchKernelGGL((indicator2d_kernel<E_, K_, TB, (K_ > 0)>), grid, block, 0, st, a);  \
+        else                                                                                       \
+            hipLaunchKernelGGL((indicator2d_kernel<E_, K_, TB, false>), grid, block, 0, st, a);     \
+        return hipGetLastError();                                                                  \
+    }
+    DG_CASE(ADV, 0) DG_CASE(ADV, 1) DG_CASE(ADV, 2) DG_CASE(ADV, 3)
+    DG_CASE(EULER, 0) DG_CASE(EULER, 1) DG_CASE(EULER, 2) DG_CASE(EULER, 3)
+#undef DG_CASE
+    return hipErrorInvalidValue;
+}
+
+template <typename TB>
+hipError_t launch_troubled2d(int eq, int k, const Args2D<TB>& a, hipStream_t st)
 {
     // one wavefront per troubled cell, 4 per workgroup, grid-stride beyond
     // 4096 workgroups (the list's length is only known on the device)
-    unsigned g = (unsigned)((max_entries + 3) / 4);
+    int64_t g = (a.tcap + 3) / 4;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+#define DG_CASE(E_, K_)                                                                            \
+    if (eq == E_ && k == K_) {                                                                     \
+        if (a.pk)                                                                                  \
+            hipLaunchKernelGGL((troubled2d_kernel<E_, K_, TB, (K_ > 0)>), dim3((unsigned)g), dim3(256), 0, st, a); \
+        else                                                                                       \
+            hipLaunchKernelGGL((troubled2d_kernel<E_, K_, TB, false>), dim3((unsigned)g), dim3(256), 0, st, a);    \
+        return hipGetLastError();                                                                  \
+    }
+    DG_CASE(ADV, 0) DG_CASE(ADV, 1) DG_CASE(ADV, 2) DG_CASE(ADV, 3)
+    DG_CASE(EULER, 0) DG_CASE(EULER, 1) DG_CASE(EULER, 2) DG_CASE(EULER, 3)
+#undef DG_CASE
+    return hipErrorInvalidValue;
+}
+
+template <typename TB>
+hipError_t launch_blend2d(int nv, int k, const Args2D<TB>& a, PPArgs pp, hipStream_t st)
+{
+    // one wavefront per troubled cell, 4 per workgroup, grid-stride beyond
+    // 4096 workgroups (the list's length is only known on the device)
+    int64_t g = (a.tcap + 3) / 4;
     if (g > 4096) g = 4096;
     if (g < 1) g = 1;
 #define DG_CASE(NV_, K_)                                                                          \
     if (nv == NV_ && k == K_) {                                                                   \
-        if (pk)                                                                                   \
-            hipLaunchKernelGGL((blend2d_kernel<K_, NV_, TB, (K_ > 0)>), dim3(g), dim3(256), 0, st, \
-                               out, count, tcell, tdata, eta_bits, ctrl, from_ctrl,              \
-                               (long long)max_entries, pp);                                       \
+        if (a.pk)                                                                                 \
+            hipLaunchKernelGGL((blend2d_kernel<K_, NV_, TB, (K_ > 0)>), dim3((unsigned)g), dim3(256), 0, \
+                               st, a.out, a.tcount, a.tcell, a.tdata, a.eta_acc, a.ctrl,          \
+                               a.dt_from_ctrl, (long long)a.tcap, pp);                            \
         else                                                                                      \
-            hipLaunchKernelGGL((blend2d_kernel<K_, NV_, TB, false>), dim3(g), dim3(256), 0, st,   \
-                               out, count, tcell, tdata, eta_bits, ctrl, from_ctrl,              \
-                               (long long)max_entries, pp);                                       \
+            hipLaunchKernelGGL((blend2d_kernel<K_, NV_, TB, false>), dim3((unsigned)g), dim3(256), 0, \
+                               st, a.out, a.tcount, a.tcell, a.tdata, a.eta_acc, a.ctrl,          \
+                               a.dt_from_ctrl, (long long)a.tcap, pp);                            \
         return hipGetLastError();                                                                 \
     }
     DG_CASE(1, 0) DG_CASE(1, 1) DG_CASE(1, 2) DG_CASE(1, 3)
     DG_CASE(4, 0) DG_CASE(4, 1) DG_CASE(4, 2) DG_CASE(4, 3)
 #undef DG_CASE
-    (void)ncell;
     return hipErrorInvalidValue;
 }
 
@@ -1431,11 +1843,10 @@ hipError_t launch_maxwave2d(int eq, StateView<TB> u, int64_t nx, int64_t ny, dou
 
 #define DG_INST(TB)                                                                               \
     template hipError_t launch_stage2d<TB>(int, int, const Args2D<TB>&, hipStream_t);             \
-    template hipError_t launch_filter2d<TB>(int, int, const Args2D<TB>&, int, hipStream_t);       \
-    template hipError_t launch_blend2d<TB>(int, int, StateView<TB>, int64_t, const unsigned int*, \
-                                           const long long*, const double*,                      \
-                                           const unsigned long long*, const Ctrl*, int, int64_t, \
-                                           int, PPArgs, hipStream_t);                            \
+    template hipError_t launch_filter2d<TB>(int, int, const Args2D<TB>&, hipStream_t);           \
+    template hipError_t launch_indicator2d<TB>(int, int, const Args2D<TB>&, hipStream_t);       \
+    template hipError_t launch_troubled2d<TB>(int, int, const Args2D<TB>&, hipStream_t);         \
+    template hipError_t launch_blend2d<TB>(int, int, const Args2D<TB>&, PPArgs, hipStream_t);    \
     template hipError_t launch_pp2d<TB>(int, StateView<TB>, int64_t, const unsigned long long*,  \
                                         const long long*, int64_t, const Ctrl*, int, int, PPArgs,\
                                         hipStream_t);                                            \

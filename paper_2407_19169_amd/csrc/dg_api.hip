@@ -27,6 +27,7 @@ struct dg_solver {
     double h[2], inv_h[2];
     size_t state_bytes, ws_bytes;
     size_t off_w, off_E, off_eta, off_tcell, off_tdata, off_aux, off_pcell;
+    size_t off_corner, off_ppfail;  // 2D hybrid runs: corner values, screen verdicts
     size_t off_dv, dv_slot;  // deferred hybrid blend: 4 slots of eta[n] + E[k][n]
     void* u[3];
     unsigned char* ws;
@@ -227,7 +228,7 @@ int filter_impl(dg_solver* s, int stage, double dt)
         if (s->opt.filter == DG_FILTER_JUMP) {
             a.us = view_of<TB>(s, s->ws + s->off_w);
             a.out = view_of<TB>(s, target);
-            DG_HIP(launch_filter2d<TB>(s->eq, s->k, a, 1, s->user_st));
+            DG_HIP(launch_filter2d<TB>(s->eq, s->k, a, s->user_st));
             if (a.pp)
                 DG_HIP(launch_pp2d<TB>(s->k, a.out, s->ncell, a.pcount, a.pcell, a.pcap, ctrl_of(s), 0,
                                        s->pk, pp_args<TB>(s), s->user_st));
@@ -248,9 +249,9 @@ int filter_impl(dg_solver* s, int stage, double dt)
         a.tcell = reinterpret_cast<long long*>(s->ws + s->off_tcell);
         a.tdata = reinterpret_cast<double*>(s->ws + s->off_tdata);
         a.eta_out = reinterpret_cast<double*>(s->ws + s->off_eta);
-        DG_HIP(launch_filter2d<TB>(s->eq, s->k, a, 2, s->user_st));
-        DG_HIP(launch_blend2d<TB>(s->nv, s->k, a.out, s->ncell, tcount, a.tcell, a.tdata, eta_bits,
-                                  ctrl_of(s), 0, s->ncell, s->pk, pp_args<TB>(s), s->user_st));
+        DG_HIP(launch_indicator2d<TB>(s->eq, s->k, a, s->user_st));
+        DG_HIP(launch_troubled2d<TB>(s->eq, s->k, a, s->user_st));
+        DG_HIP(launch_blend2d<TB>(s->nv, s->k, a, pp_args<TB>(s), s->user_st));
         if (a.pp)
             DG_HIP(launch_pp2d<TB>(s->k, a.out, s->ncell, a.pcount, a.pcell, a.pcap, ctrl_of(s), 0,
                                    s->pk, pp_args<TB>(s), s->user_st));
@@ -335,6 +336,16 @@ bool folded_ctrl(const dg_solver* s)
     return s->dim == 1 && deferred_blend_on(s) && s->ncell < kSmallTileCells;
 }
 
+// 2D hybrid: the stage kernel writes its output's corner values (and the
+// limiter screen's verdicts) for the indicator that follows it
+template <typename TB>
+void corner_args(const dg_solver* s, Args2D<TB>& a)
+{
+    a.corner = reinterpret_cast<TB*>(s->ws + s->off_corner);
+    a.cstride = s->ncell;
+    a.ppfail = s->opt.positivity ? reinterpret_cast<unsigned char*>(s->ws + s->off_ppfail) : nullptr;
+}
+
 template <typename TB>
 int record_steps(dg_solver* s, int G, hipStream_t st)
 {
@@ -366,20 +377,25 @@ int record_steps(dg_solver* s, int G, hipStream_t st)
                     DG_HIP(launch_stage2d<TB>(s->eq, s->k, a, st));
                     f.us = a.out;
                     f.out = view_of<TB>(s, target);
-                    DG_HIP(launch_filter2d<TB>(s->eq, s->k, f, 1, st));
+                    DG_HIP(launch_filter2d<TB>(s->eq, s->k, f, st));
                 } else {
                     a.out = view_of<TB>(s, target);
+                    if (fmode == 2) {
+                        corner_args<TB>(s, a);
+                        corner_args<TB>(s, f);
+                    }
                     DG_HIP(launch_stage2d<TB>(s->eq, s->k, a, st));
                     if (fmode == 2) {
+                        // hybrid: pass A (indicator, troubled list), pass B
+                        // (exponents, blend and limiter of the troubled cells)
                         f.us = f.out = a.out;
                         f.eta_acc = &c->eta_line[stage].v;
                         f.tcount = &c->tcount[stage];
                         f.tcell = tcell;
                         f.tdata = tdata;
-                        DG_HIP(launch_filter2d<TB>(s->eq, s->k, f, 2, st));
-                        DG_HIP(launch_blend2d<TB>(s->nv, s->k, f.out, s->ncell, &c->tcount[stage], tcell,
-                                                  tdata, &c->eta_line[stage].v, c, 1, s->ncell, s->pk,
-                                                  pp_args<TB>(s), st));
+                        DG_HIP(launch_indicator2d<TB>(s->eq, s->k, f, st));
+                        DG_HIP(launch_troubled2d<TB>(s->eq, s->k, f, st));
+                        DG_HIP(launch_blend2d<TB>(s->nv, s->k, f, pp_args<TB>(s), st));
                     }
                 }
                 // positivity limiter on the cells the post-stage kernels
@@ -668,9 +684,15 @@ int time_impl(dg_solver* s, int stage, double dt, int reps, double* avg_us)
         f.tcount = &scratch->tcount[0];
         f.tcell = reinterpret_cast<long long*>(s->ws + s->off_tcell);
         f.tdata = reinterpret_cast<double*>(s->ws + s->off_tdata);
+        if (fmode == 2) {
+            // as in dg_run: the stage kernel hands the corner values over
+            corner_args<TB>(s, a);
+            corner_args<TB>(s, f);
+        }
         auto launch = [&]() {
-            return which < 3 ? launch_stage2d<TB>(s->eq, s->k, a, st)
-                             : launch_filter2d<TB>(s->eq, s->k, f, fmode == 1 ? 1 : 2, st);
+            return which < 3   ? launch_stage2d<TB>(s->eq, s->k, a, st)
+                 : fmode == 1 ? launch_filter2d<TB>(s->eq, s->k, f, st)
+                              : launch_indicator2d<TB>(s->eq, s->k, f, st);
         };
         return time_launches(s, scratch, reps, launch, avg_us);
     }
@@ -978,6 +1000,15 @@ int dg_create(const dg_mesh* mesh, int degree, int equation, const dg_options* o
     // 2D positivity limiter: the cells a stage lists for it
     s->off_pcell = off;
     if (mesh->dim == 2 && opt->positivity) off += align256((size_t)s->ncell * sizeof(long long));
+    // 2D hybrid runs: the stage output's corner values and the limiter
+    // screen's verdicts, handed from the stage kernel to the indicator
+    s->off_corner = s->off_ppfail = off;
+    if (mesh->dim == 2 && opt->filter == DG_FILTER_HYBRID) {
+        const size_t tb = opt->precision == DG_PREC_FP64 ? sizeof(double) : sizeof(float);
+        off += align256((size_t)4 * s->nv * s->ncell * tb);
+        s->off_ppfail = off;
+        if (opt->positivity) off += align256((size_t)s->ncell);
+    }
     s->off_dv = off;
     s->dv_slot = 0;
     if (mesh->dim == 1 && opt->filter == DG_FILTER_HYBRID && !opt->positivity) {

@@ -94,17 +94,33 @@ struct Args2D {
     long long* pcell;
     long long pcap;
     int* reject;              // set when a limited cell's average is inadmissible
+    // Hybrid runs: the stage kernel writes, and the indicator then reads, the
+    // values of its output at the four cell corners, corner[(c NV + v)
+    // cstride + cell] with c = sx + 2 sy (sx, sy = 1 at the +x, +y corner),
+    // and with the positivity limiter its screen's verdict, ppfail[cell] = 1
+    // when the screen does not clear the cell.  Null: the indicator reads
+    // the state itself.
+    TB* corner;
+    unsigned char* ppfail;
+    int64_t cstride;
 };
 
 template <typename TB>
 hipError_t launch_stage2d(int eq, int k, const Args2D<TB>& a, hipStream_t st);
+// The 2D jump filter, a.us -> a.out (and per-cell exponents to a.E_out if set).
 template <typename TB>
-hipError_t launch_filter2d(int eq, int k, const Args2D<TB>& a, int mode, hipStream_t st);
+hipError_t launch_filter2d(int eq, int k, const Args2D<TB>& a, hipStream_t st);
+// Hybrid limiter in 2D (Algorithm 1) on a.us = a.out: pass A (the indicator
+// of every cell, the domain maximum a.eta_acc, the troubled list a.tcount /
+// tcell / tdata, the limiter's list), pass B1 (the exponents of the troubled
+// cells into their tdata records, the state only read) and pass B2 (the
+// blend of the troubled cells, then the limiter on them).
 template <typename TB>
-hipError_t launch_blend2d(int nv, int k, StateView<TB> out, int64_t ncell, const unsigned int* count,
-                          const long long* tcell, const double* tdata,
-                          const unsigned long long* eta_bits, const Ctrl* ctrl, int from_ctrl,
-                          int64_t max_entries, int pk, PPArgs pp, hipStream_t st);
+hipError_t launch_indicator2d(int eq, int k, const Args2D<TB>& a, hipStream_t st);
+template <typename TB>
+hipError_t launch_troubled2d(int eq, int k, const Args2D<TB>& a, hipStream_t st);
+template <typename TB>
+hipError_t launch_blend2d(int nv, int k, const Args2D<TB>& a, PPArgs pp, hipStream_t st);
 // 2D Euler positivity limiter (Zhang and Shu on rectangles) in place on the
 // cells listed by the post-stage kernels (count, cells; capacity cap), or on
 // every cell when count is null.  Flags pp.reject when a cell average is

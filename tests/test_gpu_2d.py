@@ -127,6 +127,34 @@ def test_stage_and_filter_per_call_2d(dg, ref, eq, k, nx, ny, bcs):
         s.close()
 
 
+def test_hybrid_per_call_many_troubled_cells(dg, ref):
+    """Hybrid post-stage operator (Algorithm 1) on a 480 x 360 random Euler
+    state (Q2, periodic) in which every cell is troubled: more
+    troubled cells than the exponent and blend launches have wavefronts, so
+    each wavefront takes several cells in turn.  Every troubled cell's
+    exponents must come from the unfiltered stage output, neighbours
+    included, whatever order the cells are processed in: FP64 result vs the
+    oracle at 1e-13."""
+    import torch
+
+    k, nx, ny = 2, 480, 360
+    un = random_euler2d(11, k, ny, nx, amp=0.05)
+    dt = 0.05 / nx
+    s, P = _pair(dg, ref, 2, k, nx, ny, (0, 0, 0, 0), 2)
+    s.set_state(un)
+    dg.dg_stage(s.h, 0, dt)
+    dg.dg_jump_filter(s.h, 0, dt)
+    torch.cuda.synchronize()
+    got = dg.buffer_view(s, 1).cpu().numpy()
+    s.close()
+    w = ref.stage2d(P, 0, dt, un, un, t=0.0)
+    want, troubled = ref.post2d(P, 0, dt, w, t=dt)
+    assert troubled > 4 * 16384 and np.all(np.isfinite(want)), troubled
+    for v in range(4):
+        err = rel_linf(got[v], want[v])
+        assert err <= 1e-13, (v, err)
+
+
 @pytest.mark.parametrize("reading", [1, 2])
 @pytest.mark.parametrize("k,nx,ny,bcs", [(1, 33, 20, (1, 1, 2, 2)), (2, 31, 17, (3, 1, 4, 5)),
                                          (3, 18, 35, (2, 2, 1, 1))])
@@ -232,10 +260,12 @@ def test_vortex_run_parity(dg, ref, k):
         assert abs(rep.ledger[v] - q0) < 1e-12 * max(1.0, abs(q0))
 
 
-def test_quadrant_hybrid_run_parity(dg, ref):
-    """Seeded four-quadrant Riemann problem, 32x32, Q2, hybrid with the
-    positivity limiter, 30 steps."""
-    w = I.quadrant2d(32, 2, seed=3002)
+@pytest.mark.parametrize("n", [32, 34])
+def test_quadrant_hybrid_run_parity(dg, ref, n):
+    """Seeded four-quadrant Riemann problem, 32x32 and 34x34 (ragged tiles
+    on a periodic mesh, whose slots past the edge hold the wrapped cells),
+    Q2, hybrid with the positivity limiter, 30 steps."""
+    w = I.quadrant2d(n, 2, seed=3002)
     got, want, rep, orep, rc = _run_pair(dg, ref, w, 2, 2, 30, pp=1)
     assert rc == 0 and rep.steps == 30
     for v in range(4):
@@ -332,6 +362,35 @@ def test_full_size_vortex_sampled_step(dg, ref, prec):
         err = np.max(np.abs(got[:, :, jy, ix] - want)) / np.max(np.abs(want[:, 0]))
         assert err <= tol, (jy, ix, err)
     s.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_full_size_quadrant_sampled_step(dg, ref, prec):
+    """1024x1024, Q2, periodic, jump filter (four-quadrant Riemann workload,
+    seed 3002): one dg_run step on the GPU vs oracle steps of patches around
+    cells on the two discontinuity lines (x = 5, y = 0, including their
+    crossing and the periodic seams) and random ones."""
+    n, k = 1024, 2
+    w = I.quadrant2d(n, k, seed=3002)
+    mesh = dg.make_mesh(2, (n, n), (0.0, -5.0), (10.0, 5.0), (0, 0, 0, 0))
+    s = dg.Solver(mesh, k, 2, dg.make_options(precision=prec, filter=1, cfl=0.1))
+    s.set_state(w.u0)
+    rep = dg.dg_run(s.h, 1e30, 1)
+    assert rep.status == 0
+    got = s.get_state().cpu().numpy()
+    s.close()
+    P = ref.problem2d(2, k, n, n, 0.0, 10.0, -5.0, 5.0, bc=(0, 0, 0, 0), filter=1, cfl=0.1)
+    dt = 0.1 / ref.max_wavespeed2d(P, w.u0)
+    assert rep.dt_max == pytest.approx(dt, rel=1e-14)
+    rng = np.random.default_rng(8)
+    samples = [(512, 512), (511, 511), (512, 511), (511, 512), (0, 0), (1023, 1023), (0, 512),
+               (512, 0), (300, 511), (300, 512), (511, 700), (512, 700)]
+    samples += [(int(jy), int(ix)) for jy, ix in rng.integers(0, n, (8, 2))]
+    tol = 1e-12 if prec == 0 else 2e-5
+    for jy, ix in samples:
+        want = _patch_step(ref, P, w.u0, jy, ix, dt)
+        err = np.max(np.abs(got[:, :, jy, ix] - want)) / np.max(np.abs(want[:, 0]))
+        assert err <= tol, (jy, ix, err)
 
 
 @pytest.mark.parametrize("filt", [1, 2])
