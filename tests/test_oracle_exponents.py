@@ -17,6 +17,9 @@ the oracle's own formula.
   the trapezoidal edge averages at the cell corners carry the result, and the
   three readings of the mesh factors of (c_fx, c_fy) give three different
   exponents.
+* 2D hybrid indicator (Algorithm 1 in two dimensions): value jumps of
+  different size across the two face directions of non-square cells, so
+  the sum of the two directions' terms and their mesh widths carry eta.
 """
 import numpy as np
 import pytest
@@ -118,3 +121,27 @@ def test_2d_reading_default_is_printed_sec_2_4(ref):
     Sec. 2.4 (reading 0)."""
     P0 = ref.problem2d(0, 1, 2, 2, 0.0, 4.0, 0.0, 2.0, filter=1, adv_speed=(1.0, -0.5))
     assert P0.cf_reading == 0
+
+
+def test_2d_hybrid_indicator_worked_example(ref):
+    """2D hybrid indicator (Algorithm 1 with the 2D reading: the value jumps
+    averaged over each face by the trapezoid rule at its two corners, summed
+    over the two faces of each direction, eta = Jx0/(2 h_x) + Jy0/(2 h_y)).
+
+    Advection on [0, 4] x [0, 2] with 2 x 2 periodic P^0 cells (h_x = 2,
+    h_y = 1) holding u = 1 + a (-1)^ix + b (-1)^jy, a = 0.3, b = 0.05.  Every
+    vertical face separates ix = 0 from ix = 1 (a jump of 2a = 0.6 at both
+    corners), every horizontal face jy = 0 from jy = 1 (2b = 0.1).  Per
+    cell Jx0 = 0.6 + 0.6 = 1.2 and Jy0 = 0.1 + 0.1 = 0.2, so
+    eta = 1.2/4 + 0.2/2 = 0.3 + 0.1 = 0.4 in every cell.  (A maximum of the
+    two terms would give 0.3, swapped mesh widths 0.65.)
+    """
+    a, b = 0.3, 0.05
+    u = np.zeros((1, 1, 2, 2))
+    for jy in range(2):
+        for ix in range(2):
+            u[0, 0, jy, ix] = 1.0 + a * (-1) ** ix + b * (-1) ** jy
+    P = ref.problem2d(0, 0, 2, 2, 0.0, 4.0, 0.0, 2.0, bc=(0, 0, 0, 0), filter=2,
+                      adv_speed=(1.0, -0.5))
+    _, eta = ref.exponents2d(P, 0.01, u)
+    np.testing.assert_allclose(eta, np.full((2, 2), 0.4), rtol=1e-14)
