@@ -1183,15 +1183,17 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
 }
 
 // Hybrid limiter, pass B2, over the troubled list: u^{pq} <- [w + (1 - w) exp(-E^{p+q})] u^{pq},
-// then (Euler, pp.on) the positivity limiter on the blended cell.  One
-// wavefront per troubled cell: lane l < NV (K+1)^2 holds coefficient
-// (variable l / (K+1)^2, mode l % (K+1)^2).
+// then (Euler, pp.on) the positivity limiter's screen on the blended cell:
+// the cells it does not clear are appended to the limiter's list (pcell),
+// which pp2d_kernel limits next.  One wavefront per troubled cell: lane
+// l < NV (K+1)^2 holds coefficient (variable l / (K+1)^2, mode l % (K+1)^2).
 template <int K, int NV, typename TB, bool PK>
 __global__ __launch_bounds__(256) void blend2d_kernel(StateView<TB> out, const unsigned int* count,
                                                       const long long* tcell, const double* tdata,
                                                       const unsigned long long* eta_bits,
                                                       const Ctrl* ctrl, int from_ctrl, long long cap,
-                                                      PPArgs pp)
+                                                      PPArgs pp, unsigned long long* pcount,
+                                                      long long* pcell, long long pcap)
 {
     constexpr int K1 = K + 1, NM = K1 * K1, L1 = 2 * K + 1, NC = NV * NM;
     __shared__ double sc[4][NV == 4 ? NC : 1];
@@ -1211,13 +1213,32 @@ __global__ __launch_bounds__(256) void blend2d_kernel(StateView<TB> out, const u
         if (mine) {
             const TB f = (TB)(w + (1.0 - w) * exp(-rec[p + q]));
             cf = (double)(out.hi[off + c] * f);
+            out.hi[off + c] = (TB)cf;
         } else if (lane < NC && m == 0) {
             cf = out.m0[v * out.s0 + c];
         }
         if constexpr (NV == 4) {
-            if (pp.on) pp2_wave<K, PK, TB>(sc[wv], cf, lane, pp.phys.gamma, pp.reject);
+            if (pp.on) {
+                // the screen pp2_wave starts with, on the blended cell
+                double* cw = sc[wv];
+                if (lane < NC) cw[lane] = cf;
+                wave_lds_sync();
+                double ub[4], sabs[4];
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) {
+                    ub[vv] = cw[vv * NM];
+                    double t = 0.0;
+#pragma unroll
+                    for (int mm = 1; mm < NM; ++mm) t += fabs(cw[vv * NM + mm]);
+                    sabs[vv] = t;
+                }
+                if (!pp2_clear<TB>(ub, sabs, pp.phys.gamma) && lane == 0) {
+                    const unsigned long long slot = atomicAdd(pcount, 1ull);
+                    if ((long long)slot < pcap) pcell[slot] = c;
+                }
+                wave_lds_sync();  // the next cell rewrites the block
+            }
         }
-        if (mine) out.hi[off + c] = (TB)cf;
     }
 }
 
@@ -1267,7 +1288,7 @@ __global__ __launch_bounds__(256) void pp2d_kernel(StateView<TB> u, long long nc
 // tile's ring cells their two facing corners, and the corner values meet in
 // LDS.
 // -------------------------------------------------------------------------
-template <int EQ, int K, typename TB, bool PK>
+template <int EQ, int K, typename TB, bool PK, bool CORNER>
 __global__ __launch_bounds__(256) void indicator2d_kernel(Args2D<TB> a)
 {
     using P = Phys2D<EQ>;
@@ -1306,7 +1327,7 @@ __global__ __launch_bounds__(256) void indicator2d_kernel(Args2D<TB> a)
     for (int m = 0; m < NM; ++m) um[m] = (T)0;
     if (loadable) {
         const int64_t c0 = cy * a.nx + cx;
-        if (a.corner) {
+        if constexpr (CORNER) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) sC[c * CS + cidx * NV + v] = a.corner[(c * NV + v) * a.cstride + c0];
         } else {
@@ -1331,7 +1352,7 @@ __global__ __launch_bounds__(256) void indicator2d_kernel(Args2D<TB> a)
             // right corners (bottom, top), the right column's left corners,
             // the bottom row's top corners (left, right), the top row's
             // bottom corners
-            if (a.corner) {
+            if constexpr (CORNER) {
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     const int sx = g == 0 ? 1 : g == 1 ? 0 : c, sy = g == 2 ? 1 : g == 3 ? 0 : c;
@@ -1427,7 +1448,7 @@ __global__ __launch_bounds__(256) void indicator2d_kernel(Args2D<TB> a)
         // now; troubled cells are screened after their blend
         if (a.pp) {
             bool fail;
-            if (a.corner) {
+            if constexpr (CORNER) {
                 fail = a.ppfail[cell] != 0;  // the stage kernel's screen
             } else {
                 double sabs = 0.0;
@@ -1737,12 +1758,17 @@ hipError_t launch_indicator2d(int eq, int k, const Args2D<TB>& a, hipStream_t st
     const int fx = eq == ADV ? FilterTile<1>::FX : FilterTile<4>::FX;
     const int fy = eq == ADV ? FilterTile<1>::FY : FilterTile<4>::FY;
     dim3 grid((unsigned)(((a.nx + fx - 1) / fx) * ((a.ny + fy - 1) / fy))), block(256);
+    // corner values handed over by the stage kernel (dg_run), or the state
 #define DG_CASE(E_, K_)                                                                            \
     if (eq == E_ && k == K_) {                                                                     \
-        if (a.pk)                                                                                  \
-            hipLaunchKernelGGL((indicator2d_kernel<E_, K_, TB, (K_ > 0)>), grid, block, 0, st, a);  \
+        if (a.pk && a.corner)                                                                      \
+            hipLaunchKernelGGL((indicator2d_kernel<E_, K_, TB, (K_ > 0), true>), grid, block, 0, st, a); \
+        else if (a.pk)                                                                             \
+            hipLaunchKernelGGL((indicator2d_kernel<E_, K_, TB, (K_ > 0), false>), grid, block, 0, st, a); \
+        else if (a.corner)                                                                         \
+            hipLaunchKernelGGL((indicator2d_kernel<E_, K_, TB, false, true>), grid, block, 0, st, a); \
         else                                                                                       \
-            hipLaunchKernelGGL((indicator2d_kernel<E_, K_, TB, false>), grid, block, 0, st, a);     \
+            hipLaunchKernelGGL((indicator2d_kernel<E_, K_, TB, false, false>), grid, block, 0, st, a); \
         return hipGetLastError();                                                                  \
     }
     DG_CASE(ADV, 0) DG_CASE(ADV, 1) DG_CASE(ADV, 2) DG_CASE(ADV, 3)
@@ -1786,11 +1812,11 @@ hipError_t launch_blend2d(int nv, int k, const Args2D<TB>& a, PPArgs pp, hipStre
         if (a.pk)                                                                                 \
             hipLaunchKernelGGL((blend2d_kernel<K_, NV_, TB, (K_ > 0)>), dim3((unsigned)g), dim3(256), 0, \
                                st, a.out, a.tcount, a.tcell, a.tdata, a.eta_acc, a.ctrl,          \
-                               a.dt_from_ctrl, (long long)a.tcap, pp);                            \
+                               a.dt_from_ctrl, (long long)a.tcap, pp, a.pcount, a.pcell, a.pcap); \
         else                                                                                      \
             hipLaunchKernelGGL((blend2d_kernel<K_, NV_, TB, false>), dim3((unsigned)g), dim3(256), 0, \
                                st, a.out, a.tcount, a.tcell, a.tdata, a.eta_acc, a.ctrl,          \
-                               a.dt_from_ctrl, (long long)a.tcap, pp);                            \
+                               a.dt_from_ctrl, (long long)a.tcap, pp, a.pcount, a.pcell, a.pcap); \
         return hipGetLastError();                                                                 \
     }
     DG_CASE(1, 0) DG_CASE(1, 1) DG_CASE(1, 2) DG_CASE(1, 3)
