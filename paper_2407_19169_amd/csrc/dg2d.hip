@@ -968,7 +968,10 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
     constexpr int NV = P::NV, K1 = K + 1, NM = K1 * K1, L1 = 2 * K + 1;
     constexpr int FX = FilterTile<NV>::FX, FY = FilterTile<NV>::FY;
     constexpr int SX = FilterTile<NV>::SX, SY = FilterTile<NV>::SY;
-    constexpr int STRIDE = NM * NV + 1;  // T words per slot, padded against bank conflicts
+    // T words per slot: with 4 variables = 4 mod 32, so the 4 cells x 4
+    // variables of a 16-lane group (FP64) or the 8 x 4 of a 32-lane group
+    // (FP32) hit distinct banks; with one variable odd
+    constexpr int STRIDE = NV == 4 ? NM * NV + (36 - (NM * NV) % 32) % 32 : (NM | 1);
     __shared__ __align__(16) T sM[SX * SY * STRIDE];
 
     if (a.dt_from_ctrl && a.ctrl->done) return;
