@@ -15,10 +15,18 @@ def pytest_configure(config):
 
 @pytest.fixture(scope="session")
 def ref():
-    """The FP64 CPU oracle (built on first use if nothing is built)."""
+    """The FP64 CPU oracle (built on first use if nothing is built).  Its
+    OpenMP loops have no reductions, so the thread count changes only the
+    speed; half the cores available (the host's, capped by OMP_NUM_THREADS)
+    keep its many short parallel loops (1D) from waiting on threads that the
+    host is using for something else."""
     import oracle
 
-    oracle.lib()
+    n = os.cpu_count() or 2
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    oracle.lib().dgref_set_threads(max(1, n // 2))
     return oracle
 
 
