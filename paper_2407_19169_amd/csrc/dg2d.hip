@@ -288,17 +288,29 @@ __device__ __forceinline__ void wave_lds_sync()
 
 // Tile of a 1D launch of `ntiles` workgroups over a grid `gx` tiles wide.
 // Workgroups are dispatched to the 8 XCDs round-robin by index, and each XCD
-// has its own L2; consecutive tiles in row-major order are therefore given
-// to one XCD, so the neighbour rows and columns a tile reads were mostly
-// fetched into the same L2 by the tiles around it.
+// has its own L2; consecutive tile numbers are therefore given to one XCD.
+// Tiles are numbered in strips of 32 tile columns, row by row inside a strip
+// (the last strip as wide as what is left), so the tile above a tile was
+// processed one strip row earlier on the same XCD: the neighbour rows and
+// columns a tile reads are still in that L2.
 __device__ __forceinline__ void xcd_tile(int64_t gx, int64_t ntiles, int64_t& bx, int64_t& by)
 {
     // tile counts stay far below 2^32 (a launch has at most 2^32 - 1 workgroups)
+    constexpr uint32_t W = 32;
     const uint32_t p = blockIdx.x, q = (uint32_t)ntiles >> 3, r = (uint32_t)ntiles & 7;
     const uint32_t x = p & 7, k = p >> 3;
     const uint32_t l = x * q + (x < r ? x : r) + k;
-    bx = l % (uint32_t)gx;
-    by = l / (uint32_t)gx;
+    const uint32_t ux = (uint32_t)gx, uy = (uint32_t)ntiles / ux;
+    const uint32_t full = ux / W, in_full = full * W * uy;
+    if (l < in_full) {
+        const uint32_t st = l / (W * uy), w = l % (W * uy);
+        bx = st * W + w % W;
+        by = w / W;
+    } else {
+        const uint32_t rest = ux - full * W, w = l - in_full;
+        bx = full * W + w % rest;
+        by = w / rest;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -624,12 +636,35 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
     auto hslot = [&](int c, int e) { return NVE + c * (FY + 1) + e; };
 
     // ---- phase 1: own traces (and the ring's facing traces) to LDS ----
+    // The own modes and the ring cell's modes are requested together, so the
+    // two trips to memory overlap.
     double m0v = 0.0;
     T um[NM];
 #pragma unroll
     for (int m = 0; m < NM; ++m) um[m] = (T)0;
     if (loadable) load_var2d<K, PK, TB, T>(a.us, cy * a.nx + cx, v, m0v, um);
     const int64_t cell = jy * a.nx + ix;
+    constexpr int NRING = 2 * FY + 2 * FX;
+    const int r = tid / NV, rv = tid % NV;
+    int g = 0, i = 0;  // g: 0 left column, 1 right column, 2 bottom row, 3 top row
+    if (r < FY) { g = 0; i = r; }
+    else if (r < 2 * FY) { g = 1; i = r - FY; }
+    else if (r < 2 * FY + FX) { g = 2; i = r - 2 * FY; }
+    else { g = 3; i = r - 2 * FY - FX; }
+    bool ring = false;
+    T wm[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) wm[m] = (T)0;
+    if (tid < NRING * NV) {
+        const int64_t gx = g == 0 ? ix0 - 1 : g == 1 ? ix0 + FX : ix0 + i;
+        const int64_t gy = g == 2 ? jy0 - 1 : g == 3 ? jy0 + FY : jy0 + i;
+        const int64_t hx_ = slot_index(gx, a.nx, px), hy_ = slot_index(gy, a.ny, py);
+        ring = hx_ >= 0 && hy_ >= 0;
+        if (ring) {
+            double w0;
+            load_var2d<K, PK, TB, T>(a.us, hy_ * a.nx + hx_, rv, w0, wm);
+        }
+    }
     if (loadable) {
         T tr[Q];
         face_trace_var<0, K, T>(um, tr);  // left face: upper side of vertical edge tx
@@ -645,39 +680,24 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
 #pragma unroll
         for (int b = 0; b < Q; ++b) sLo[hslot(tx, ty + 1) * ES + sw(b, v)] = tr[b];
     }
-    constexpr int NRING = 2 * FY + 2 * FX;
-    if (tid < NRING * NV) {
-        const int r = tid / NV, rv = tid % NV;
-        int g, i;  // g: 0 left column, 1 right column, 2 bottom row, 3 top row
-        if (r < FY) { g = 0; i = r; }
-        else if (r < 2 * FY) { g = 1; i = r - FY; }
-        else if (r < 2 * FY + FX) { g = 2; i = r - 2 * FY; }
-        else { g = 3; i = r - 2 * FY - FX; }
-        const int64_t gx = g == 0 ? ix0 - 1 : g == 1 ? ix0 + FX : ix0 + i;
-        const int64_t gy = g == 2 ? jy0 - 1 : g == 3 ? jy0 + FY : jy0 + i;
-        const int64_t hx_ = slot_index(gx, a.nx, px), hy_ = slot_index(gy, a.ny, py);
-        if (hx_ >= 0 && hy_ >= 0) {
-            double w0;
-            T wm[NM];
-            load_var2d<K, PK, TB, T>(a.us, hy_ * a.nx + hx_, rv, w0, wm);
-            T tr[Q];
-            T* dst;
-            if (g == 0) {
-                face_trace_var<1, K, T>(wm, tr);
-                dst = &sLo[vslot(i, 0) * ES];
-            } else if (g == 1) {
-                face_trace_var<0, K, T>(wm, tr);
-                dst = &sHi[vslot(i, FX) * ES];
-            } else if (g == 2) {
-                face_trace_var<3, K, T>(wm, tr);
-                dst = &sLo[hslot(i, 0) * ES];
-            } else {
-                face_trace_var<2, K, T>(wm, tr);
-                dst = &sHi[hslot(i, FY) * ES];
-            }
-#pragma unroll
-            for (int b = 0; b < Q; ++b) dst[sw(b, rv)] = tr[b];
+    if (ring) {
+        T tr[Q];
+        T* dst;
+        if (g == 0) {
+            face_trace_var<1, K, T>(wm, tr);
+            dst = &sLo[vslot(i, 0) * ES];
+        } else if (g == 1) {
+            face_trace_var<0, K, T>(wm, tr);
+            dst = &sHi[vslot(i, FX) * ES];
+        } else if (g == 2) {
+            face_trace_var<3, K, T>(wm, tr);
+            dst = &sLo[hslot(i, 0) * ES];
+        } else {
+            face_trace_var<2, K, T>(wm, tr);
+            dst = &sHi[hslot(i, FY) * ES];
         }
+#pragma unroll
+        for (int b = 0; b < Q; ++b) dst[sw(b, rv)] = tr[b];
     }
     __syncthreads();
 
@@ -991,46 +1011,50 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
     const bool own = ix < a.nx && jy < a.ny;
     const int oslot = (ty + 1) * SX + tx + 1;
 
-    // own modes of variable v: registers and LDS
+    // own modes of variable v (registers and LDS) and the face-neighbour
+    // ring's (left/right columns, bottom/top rows of the tile): both are
+    // requested before either is stored, so the two trips to memory overlap
     double m0v = 0.0;
     T um[NM];
 #pragma unroll
     for (int m = 0; m < NM; ++m) um[m] = (T)0;
+    if (loadable) load_var2d<K, PK, TB, T>(a.us, cy * a.nx + cx, v, m0v, um);
+    constexpr int NRING = 2 * FY + 2 * FX;
+    const int r = tid / NV, rv = tid % NV;
+    int sx = 0, sy = 0;
+    if (r < FY) {
+        sx = 0;
+        sy = r + 1;
+    } else if (r < 2 * FY) {
+        sx = FX + 1;
+        sy = r - FY + 1;
+    } else if (r < 2 * FY + FX) {
+        sx = r - 2 * FY + 1;
+        sy = 0;
+    } else {
+        sx = r - 2 * FY - FX + 1;
+        sy = FY + 1;
+    }
+    bool ring = false;
+    T wm[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) wm[m] = (T)0;
+    if (tid < NRING * NV) {
+        const int64_t gx = slot_index(ix0 + sx - 1, a.nx, px), gy = slot_index(jy0 + sy - 1, a.ny, py);
+        ring = gx >= 0 && gy >= 0;
+        if (ring) {
+            double w0;
+            load_var2d<K, PK, TB, T>(a.us, gy * a.nx + gx, rv, w0, wm);
+        }
+    }
     if (loadable) {
-        const int64_t c = cy * a.nx + cx;
-        load_var2d<K, PK, TB, T>(a.us, c, v, m0v, um);
 #pragma unroll
         for (int m = 0; m < NM; ++m) sM[oslot * STRIDE + m * NV + v] = um[m];
     }
-    // face-neighbour ring: left/right columns and bottom/top rows of the tile
-    constexpr int NRING = 2 * FY + 2 * FX;
-    if (tid < NRING * NV) {
-        const int r = tid / NV, rv = tid % NV;
-        int sx, sy;
-        if (r < FY) {
-            sx = 0;
-            sy = r + 1;
-        } else if (r < 2 * FY) {
-            sx = FX + 1;
-            sy = r - FY + 1;
-        } else if (r < 2 * FY + FX) {
-            sx = r - 2 * FY + 1;
-            sy = 0;
-        } else {
-            sx = r - 2 * FY - FX + 1;
-            sy = FY + 1;
-        }
-        const int64_t gx = slot_index(ix0 + sx - 1, a.nx, px), gy = slot_index(jy0 + sy - 1, a.ny, py);
-        if (gx >= 0 && gy >= 0) {
-            const int64_t c = gy * a.nx + gx;
-            const int slot = sy * SX + sx;
-            sM[slot * STRIDE + rv] = (T)a.us.m0[rv * a.us.s0 + c];
+    if (ring) {
+        const int slot = sy * SX + sx;
 #pragma unroll
-            for (int m = 1; m < NM; ++m)
-                sM[slot * STRIDE + m * NV + rv] =
-                    mode_kept<K, PK>(m) ? (T)a.us.hi[rv * a.us.sv + (mode_plane<K, PK>(m) - 1) * a.us.sl + c]
-                                        : (T)0;
-        }
+        for (int m = 0; m < NM; ++m) sM[slot * STRIDE + m * NV + rv] = wm[m];
     }
     __syncthreads();
 
