@@ -701,6 +701,20 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
     }
     __syncthreads();
 
+    // u^n of the own cell (stages 2 and 3).  FP64: requested now, so that its
+    // trip to memory overlaps the flux and volume phases, and folded into
+    // the accumulators at the start of phase 3 (no registers of its own in
+    // the volume loop, which sets the register count); FP32 (mixed) modes
+    // keep the plain combination at the end, where the fold's larger
+    // intermediate would cost precision, and so do the HLL/HLLC kernels,
+    // whose flux phase has no registers to spare.
+    constexpr bool FOLD = sizeof(T) == 8 && !HLLX;
+    double n0 = 0.0;
+    T nm[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) nm[m] = (T)0;
+    if (FOLD && own && stage > 0) load_var2d<K, PK, TB, T>(a.un, cell, v, n0, nm);
+
     // ---- phase 2: LLF flux at every (edge, Gauss point) of the tile ----
     constexpr int NITEM = (NVE + NHE) * Q;
     constexpr int PER = (NITEM + 255) / 256;
@@ -764,6 +778,28 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
     T acc[NM];
 #pragma unroll
     for (int m = 0; m < NM; ++m) acc[m] = (T)0;
+    if constexpr (FOLD) {
+        // out = c0 u^n + c1 (u + dt L) = c1 (u + dt L'), L' = L + (c0/c1) u^n /
+        // dt: with L = (2p+1)(2q+1)/(hx hy) r, r seeded with
+        // (c0/c1) u^n hy hx / ((2p+1)(2q+1) dt); c0/c1 = 3 (stage 2), 1/2 (stage 3)
+        // (dt = 0, a per-call stage: dt L vanishes, so u^n is added to u
+        // instead, which the volume term no longer needs)
+        if (stage > 0) {
+            const double ratio = stage == 1 ? 3.0 : 0.5;
+            const double base = ratio * a.hx * a.hy / dt;
+#pragma unroll
+            for (int p = 0; p < K1; ++p)
+#pragma unroll
+                for (int q = 0; q < K1; ++q) {
+                    const int m = p * K1 + q;
+                    if (m == 0 || !mode_kept<K, PK>(m)) continue;
+                    if (dt != 0.0)
+                        acc[m] = nm[m] * (T)(base / (double)((2 * p + 1) * (2 * q + 1)));
+                    else
+                        um[m] = um[m] + (T)ratio * nm[m];
+                }
+        }
+    }
     // Volume term: (hy/2) sum w_a w_b F1 P_p'(xi_a) P_q(eta_b)
     //            + (hx/2) sum w_a w_b F2 P_p(xi_a) P_q'(eta_b)
 #pragma unroll
@@ -916,18 +952,15 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
             asm volatile("" : "+v"(um[m]));
         }
         asm volatile("" ::: "memory");
-        // u^n of the own cell for the combination
-        double n0 = 0.0;
-        T nm[NM];
-#pragma unroll
-        for (int m = 0; m < NM; ++m) nm[m] = (T)0;
-        if (stage > 0) load_var2d<K, PK, TB, T>(a.un, cell, v, n0, nm);
+        // u^n of the own cell for the combination (FP64: loaded early, its
+        // modes >= 1 already in um through the fold)
+        if (!FOLD && stage > 0) load_var2d<K, PK, TB, T>(a.un, cell, v, n0, nm);
         v0 = combine2(stage, n0, w0);
         a.out.m0[v * a.out.s0 + cell] = v0;
 #pragma unroll
         for (int m = 1; m < NM; ++m) {
             if (!mode_kept<K, PK>(m)) continue;
-            um[m] = combine2_t<T>(stage, nm[m], um[m]);
+            um[m] = combine2_t<T>(stage, FOLD ? (T)0 : nm[m], um[m]);
             a.out.hi[v * a.out.sv + (mode_plane<K, PK>(m) - 1) * a.out.sl + cell] = um[m];
         }
         if (a.corner) {

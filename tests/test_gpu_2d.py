@@ -127,6 +127,28 @@ def test_stage_and_filter_per_call_2d(dg, ref, eq, k, nx, ny, bcs):
         s.close()
 
 
+@pytest.mark.parametrize("k", [2, 3])
+def test_stage_zero_dt_2d(dg, ref, k):
+    """A per-call stage with dt = 0 is the bare Shu-Osher combination
+    (3/4 u_n + 1/4 u_a, 1/3 u_n + 2/3 u_b), FP64, against the oracle."""
+    import torch
+
+    nx, ny = 20, 13
+    un, ua, ub = (random_euler2d(s, k, ny, nx) for s in (1, 2, 3))
+    s, P = _pair(dg, ref, 2, k, nx, ny, (0, 0, 0, 0), 0)
+    for stage, us in ((1, ua), (2, ub)):
+        s.set_state(un)
+        dg.buffer_view(s, stage).copy_(torch.as_tensor(us))
+        dg.dg_stage(s.h, stage, 0.0)
+        dg.dg_jump_filter(s.h, stage, 0.0)
+        torch.cuda.synchronize()
+        got = dg.buffer_view(s, {1: 2, 2: 0}[stage]).cpu().numpy()
+        want = ref.stage2d(P, stage, 0.0, un, us, t=0.0)
+        for v in range(4):
+            assert rel_linf(got[v], want[v]) <= 1e-15, (stage, v)
+    s.close()
+
+
 def test_hybrid_per_call_many_troubled_cells(dg, ref):
     """Hybrid post-stage operator (Algorithm 1) on a 480 x 360 random Euler
     state (Q2, periodic) in which every cell is troubled: more
