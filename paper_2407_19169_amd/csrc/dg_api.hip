@@ -469,7 +469,7 @@ template <typename TB>
 int build_graph(dg_solver* s)
 {
     if (s->graph) {
-        hipGraphExecDestroy(s->graph);
+        (void)hipGraphExecDestroy(s->graph);
         s->graph = nullptr;
     }
     hipGraph_t g = nullptr;
@@ -477,12 +477,12 @@ int build_graph(dg_solver* s)
     int rc = record_steps<TB>(s, kGraphSteps, s->run_st);
     hipError_t e = hipStreamEndCapture(s->run_st, &g);
     if (rc != DG_OK) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return rc;
     }
     if (e != hipSuccess) return DG_ERR_DEVICE;
     e = hipGraphInstantiate(&s->graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
         s->graph = nullptr;
         return DG_ERR_DEVICE;
@@ -649,8 +649,8 @@ int time_launches(dg_solver* s, Ctrl* scratch, int reps, F launch, double* avg_u
     if (rc == DG_OK && hipEventSynchronize(e1) != hipSuccess) rc = DG_ERR_DEVICE;
     float ms = 0.f;
     if (rc == DG_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = DG_ERR_DEVICE;
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     if (rc == DG_OK) *avg_us = 1000.0 * ms / reps;
     return rc;
 }
@@ -1029,8 +1029,8 @@ int dg_create(const dg_mesh* mesh, int degree, int equation, const dg_options* o
 int dg_destroy(dg_solver* s)
 {
     if (!s) return DG_ERR_ARG;
-    if (s->graph) hipGraphExecDestroy(s->graph);
-    if (s->run_st) hipStreamDestroy(s->run_st);
+    if (s->graph) (void)hipGraphExecDestroy(s->graph);
+    if (s->run_st) (void)hipStreamDestroy(s->run_st);
     delete s;
     return DG_OK;
 }
@@ -1055,7 +1055,7 @@ int dg_bind(dg_solver* s, void* u_n, void* u_a, void* u_b, void* workspace)
     s->u[2] = u_b;
     s->ws = static_cast<unsigned char*>(workspace);
     if (s->graph) {
-        hipGraphExecDestroy(s->graph);
+        (void)hipGraphExecDestroy(s->graph);
         s->graph = nullptr;
     }
     Ctrl c;

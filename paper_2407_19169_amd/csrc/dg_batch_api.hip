@@ -90,7 +90,7 @@ int launch(dg_batch* b, long long steps, hipStream_t st)
 
 void drop_graph(dg_batch* b)
 {
-    if (b->graph) hipGraphExecDestroy(b->graph);
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
     b->graph = nullptr;
 }
 
@@ -111,11 +111,11 @@ int run_graph(dg_batch* b, long long steps)
             rc = DG_ERR_DEVICE;
         const hipError_t e = hipStreamEndCapture(b->run_st, &g);
         if (rc || e != hipSuccess) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return rc ? rc : DG_ERR_DEVICE;
         }
         const hipError_t ei = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         if (ei != hipSuccess) {
             b->graph = nullptr;
             return DG_ERR_DEVICE;
@@ -223,7 +223,7 @@ int dg_batch_create(int nprob, dg_problem1d* probs, int equation, const dg_optio
     }
     if (hipHostMalloc(reinterpret_cast<void**>(&b->host_rep), sizeof(BatchReport) * nprob,
                       hipHostMallocDefault) != hipSuccess) {
-        hipStreamDestroy(b->run_st);
+        (void)hipStreamDestroy(b->run_st);
         delete b;
         return DG_ERR_DEVICE;
     }
@@ -235,8 +235,8 @@ int dg_batch_destroy(dg_batch* b)
 {
     if (!b) return DG_ERR_ARG;
     drop_graph(b);
-    if (b->run_st) hipStreamDestroy(b->run_st);
-    if (b->host_rep) hipHostFree(b->host_rep);
+    if (b->run_st) (void)hipStreamDestroy(b->run_st);
+    if (b->host_rep) (void)hipHostFree(b->host_rep);
     delete b;
     return DG_OK;
 }
@@ -375,8 +375,8 @@ int dg_batch_tune(dg_batch* b, int64_t trial_steps, char* json, size_t cap)
                 cands.push_back({sizes[sz], per_cu, lpt, ms});
             }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (hipMemcpy(b->u[0], b->ws + b->off_backup, b->state_bytes, hipMemcpyDeviceToDevice) != hipSuccess)
         rc = DG_ERR_DEVICE;
     if (rc) return rc;
