@@ -37,6 +37,12 @@ struct Phys2D<ADV> {
     }
     template <typename T>
     __device__ static T speed(const T* u, int dir, const PhysParams& p) { return fabs((T)p.a[dir]); }
+    // CFL quantity speed_x / hx + speed_y / hy
+    template <typename T>
+    __device__ static T cfl(const T* u, T ihx, T ihy, const PhysParams& p)
+    {
+        return fabs((T)p.a[0]) * ihx + fabs((T)p.a[1]) * ihy;
+    }
     template <typename T>
     __device__ static T enthalpy(const T* u, const PhysParams& p) { return (T)1; }
 };
@@ -67,6 +73,48 @@ struct Phys2D<EULER> {
         const T pr = pressure(u, p);
         return fabs(u[1 + dir] / u[0]) + tsqrt<T>((T)p.gamma * pr / u[0]);
     }
+    // CFL quantity (|u| + c) / hx + (|v| + c) / hy from a single division
+    template <typename T>
+    __device__ static T cfl(const T* u, T ihx, T ihy, const PhysParams& p)
+    {
+        const T ir = (T)1 / u[0];
+        const T vx = u[1] * ir, vy = u[2] * ir;
+        const T pr = ((T)p.gamma - (T)1) * (u[3] - (T)0.5 * (u[1] * vx + u[2] * vy));
+        const T c = tsqrt<T>((T)p.gamma * pr * ir);
+        return (fabs(vx) + c) * ihx + (fabs(vy) + c) * ihy;
+    }
+    // flux() and speed() of one state from a single division (1/rho)
+    template <typename T>
+    __device__ static T flux_speed(const T* u, int dir, T* f, const PhysParams& p)
+    {
+        const T ir = (T)1 / u[0];
+        const T vx = u[1] * ir, vy = u[2] * ir;
+        const T pr = ((T)p.gamma - (T)1) * (u[3] - (T)0.5 * (u[1] * vx + u[2] * vy));
+        const T vn = dir == 0 ? vx : vy;
+        f[0] = u[0] * vn;
+        f[1] = u[1] * vn + (dir == 0 ? pr : (T)0);
+        f[2] = u[2] * vn + (dir == 1 ? pr : (T)0);
+        f[3] = vn * (u[3] + pr);
+        return fabs(vn) + tsqrt<T>((T)p.gamma * pr * ir);
+    }
+    // the fluxes in x and y of one state from a single division; returns
+    // the pressure
+    template <typename T>
+    __device__ static T flux_xy(const T* u, T* f1, T* f2, const PhysParams& p)
+    {
+        const T ir = (T)1 / u[0];
+        const T vx = u[1] * ir, vy = u[2] * ir;
+        const T pr = ((T)p.gamma - (T)1) * (u[3] - (T)0.5 * (u[1] * vx + u[2] * vy));
+        f1[0] = u[0] * vx;
+        f1[1] = u[1] * vx + pr;
+        f1[2] = u[2] * vx;
+        f1[3] = vx * (u[3] + pr);
+        f2[0] = u[0] * vy;
+        f2[1] = u[1] * vy;
+        f2[2] = u[2] * vy + pr;
+        f2[3] = vy * (u[3] + pr);
+        return pr;
+    }
     template <typename T>
     __device__ static T enthalpy(const T* u, const PhysParams& p)
     {
@@ -81,14 +129,22 @@ __device__ __forceinline__ void llf2d(const T* ul, const T* ur, int dir, T* fh, 
 {
     constexpr int NV = Phys2D<EQ>::NV;
     T fl[NV], fr[NV];
-    Phys2D<EQ>::flux(ul, dir, fl, p);
-    Phys2D<EQ>::flux(ur, dir, fr, p);
+    T al, ar;
     if constexpr (EQ == EULER && HLLX) {
+        Phys2D<EQ>::flux(ul, dir, fl, p);
+        Phys2D<EQ>::flux(ur, dir, fr, p);
         hll_euler<NV, T>(p.flux, dir == 1, ul, ur, fl, fr, Phys2D<EULER>::pressure(ul, p),
                          Phys2D<EULER>::pressure(ur, p), (T)p.gamma, fh);
         return;
+    } else if constexpr (EQ == EULER) {
+        al = Phys2D<EQ>::flux_speed(ul, dir, fl, p);
+        ar = Phys2D<EQ>::flux_speed(ur, dir, fr, p);
+    } else {
+        Phys2D<EQ>::flux(ul, dir, fl, p);
+        Phys2D<EQ>::flux(ur, dir, fr, p);
+        al = Phys2D<EQ>::speed(ul, dir, p);
+        ar = Phys2D<EQ>::speed(ur, dir, p);
     }
-    const T al = Phys2D<EQ>::speed(ul, dir, p), ar = Phys2D<EQ>::speed(ur, dir, p);
     const T alpha = al > ar ? al : ar;
 #pragma unroll
     for (int v = 0; v < NV; ++v) fh[v] = (T)0.5 * (fl[v] + fr[v]) - (T)0.5 * alpha * (ur[v] - ul[v]);
@@ -591,12 +647,15 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
     // One edge holds Q points x NV variables in ES words, entry (b, v) at
     // sw(b, v); the exchange block of a cell holds NV x NV entries in XS
     // words, entry (i, j) at sw(i, j).  With 4 variables the entries are
-    // rotated, sw(i, j) = 4 i + (i + j) mod 4, and ES, XS = 4 mod 16 words:
-    // then each group of 16 lanes (4 cells x 4 variables, one 128-byte LDS
-    // cycle of 64-bit accesses) hits 16 different banks whether the lanes
-    // vary the cell and the variable (traces, edge fluxes per cell, point
-    // values) or the edge and the point (the flux work items).
-    constexpr int ES = NV == 4 ? (Q == 1 ? 4 : 20) : Q + 1;
+    // rotated, sw(i, j) = 4 i + (i + j) mod 4, and ES, XS are odd multiples
+    // of 4 words (4 or 12 mod 16): then each group of 16 lanes (4 cells x 4
+    // variables, one 128-byte LDS cycle of 64-bit accesses) hits 16
+    // different banks whether the lanes vary the cell and the variable
+    // (traces, edge fluxes per cell, point values) or the edge and the point
+    // (the flux work items; with Q = 3 two of them share a bank).  ES is the
+    // smallest such stride that holds the 4 Q words, which keeps the tile's
+    // LDS for Q <= 3 low enough for a fourth workgroup per CU.
+    constexpr int ES = NV == 4 ? 4 * (Q | 1) : Q + 1;
     constexpr int XS = NV == 4 ? 20 : 1;
     auto sw = [](int i, int j) { return NV == 4 ? 4 * i + ((i + j) & 3) : i * NV + j; };
     // traces: lower side (the -x / -y cell) and upper side of every edge
@@ -794,7 +853,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
                     const int m = p * K1 + q;
                     if (m == 0 || !mode_kept<K, PK>(m)) continue;
                     if (dt != 0.0)
-                        acc[m] = nm[m] * (T)(base / (double)((2 * p + 1) * (2 * q + 1)));
+                        acc[m] = nm[m] * (T)(base * (1.0 / (double)((2 * p + 1) * (2 * q + 1))));
                     else
                         um[m] = um[m] + (T)ratio * nm[m];
                 }
@@ -850,7 +909,10 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
             wave_lds_sync();  // the block is rewritten with F1
             if (v < Q && own) {
                 if (EQ == EULER && a.check) {
-                    const T pr = Phys2D<EULER>::pressure(uq, a.phys);
+                    // the flux's own reciprocal of the density (one division)
+                    const T ir = (T)1 / uq[0];
+                    const T pr = ((T)a.phys.gamma - (T)1) *
+                                 (uq[3] - (T)0.5 * (uq[1] * (uq[1] * ir) + uq[2] * (uq[2] * ir)));
                     if (!(uq[0] > (T)0) || !(pr > (T)0)) {
                         const bool fin = isfinite((double)uq[0]) && isfinite((double)pr);
                         latch_error(a.ctrl, fin ? -5 : -4, cell);
@@ -988,8 +1050,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
         double w0[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) w0[q] = NV > 1 ? __shfl(v0, base + q, 64) : v0;
-        const double lam = own ? P::speed(w0, 0, a.phys) * a.inv_hx + P::speed(w0, 1, a.phys) * a.inv_hy
-                               : 0.0;
+        const double lam = own ? P::cfl(w0, a.inv_hx, a.inv_hy, a.phys) : 0.0;
         const double z = wave_max(lam);
         if ((tid & 63) == 0) atomic_max_nonneg(a.alpha_acc, z);
     }
@@ -1755,7 +1816,7 @@ __global__ __launch_bounds__(256) void maxwave2d_kernel(StateView<TB> u, int64_t
         double ub[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) ub[v] = u.m0[v * u.s0 + c];
-        lam = Phys2D<EQ>::speed(ub, 0, phys) * ihx + Phys2D<EQ>::speed(ub, 1, phys) * ihy;
+        lam = Phys2D<EQ>::cfl(ub, ihx, ihy, phys);
         if (EQ == EULER) {
             const double p = Phys2D<EULER>::pressure(ub, phys);
             if (!(ub[0] > 0.0) || !(p > 0.0)) latch_error(err, (isfinite(ub[0]) && isfinite(p)) ? -5 : -4, c);

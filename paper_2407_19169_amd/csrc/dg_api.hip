@@ -789,10 +789,11 @@ __device__ __forceinline__ double cell_lambda(const double* ub, const PhysParams
     } else if constexpr (EQ == ADV) {
         return fabs(ph.a[0]) * ihx + fabs(ph.a[1]) * ihy;
     } else {
-        const double pr = (ph.gamma - 1.0) * (ub[3] - 0.5 * (ub[1] * ub[1] + ub[2] * ub[2]) / ub[0]);
-        const double sx = fabs(ub[1] / ub[0]) + sqrt(ph.gamma * pr / ub[0]);
-        const double sy = fabs(ub[2] / ub[0]) + sqrt(ph.gamma * pr / ub[0]);
-        return sx * ihx + sy * ihy;
+        const double ir = 1.0 / ub[0];
+        const double vx = ub[1] * ir, vy = ub[2] * ir;
+        const double pr = (ph.gamma - 1.0) * (ub[3] - 0.5 * (ub[1] * vx + ub[2] * vy));
+        const double c = sqrt(ph.gamma * pr * ir);
+        return (fabs(vx) + c) * ihx + (fabs(vy) + c) * ihy;
     }
 }
 
