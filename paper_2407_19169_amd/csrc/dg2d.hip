@@ -369,6 +369,33 @@ __device__ __forceinline__ void xcd_tile(int64_t gx, int64_t ntiles, int64_t& bx
     }
 }
 
+// Split of a gx x gy tile grid into the interior tiles [x0, x1) x [y0, y1),
+// none of whose cells has a face on a non-periodic domain edge, and the
+// boundary tiles around them (all others).
+struct TileSplit {
+    int64_t gx, gy, x0, x1, y0, y1;
+    int64_t interior() const { return (x1 - x0) * (y1 - y0); }
+    int64_t boundary() const { return gx * gy - interior(); }
+};
+
+// Boundary tile i of a split: first the rows outside [y0, y1) over the full
+// width, then the columns outside [x0, x1) over the rows inside.
+__device__ __forceinline__ void ring_tile(uint32_t i, const TileSplit& t, int64_t& bx, int64_t& by)
+{
+    const uint32_t gx = (uint32_t)t.gx, lo_rows = (uint32_t)t.y0;
+    const uint32_t row_tiles = (uint32_t)(t.gy - (t.y1 - t.y0)) * gx;
+    if (i < row_tiles) {
+        const uint32_t r = i / gx;
+        bx = i % gx;
+        by = r < lo_rows ? r : t.y1 + (r - lo_rows);
+    } else {
+        const uint32_t lo_cols = (uint32_t)t.x0, ncols = (uint32_t)(t.gx - (t.x1 - t.x0));
+        const uint32_t j = i - row_tiles, c = j % ncols;
+        by = t.y0 + j / ncols;
+        bx = c < lo_cols ? c : t.x1 + (c - lo_cols);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Positivity-preserving limiter on rectangles (Zhang and Shu), applied after
 // the jump filter / hybrid limiter (the paper's Sec. 3.2 examples with
@@ -1074,8 +1101,12 @@ struct FilterTile {
     static constexpr int SX = FX + 2, SY = FY + 2;
 };
 
-template <int EQ, int K, typename TB, bool PK>
-__global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
+// BND: the launch over the boundary tiles of the split, with the ghost
+// jumps of faces on the domain edge; without it, the launch over the
+// interior tiles, whose faces all have a neighbour cell (that code holds no
+// registers for the boundary cases: 126 instead of 163 VGPRs for FP64 Q^2).
+template <int EQ, int K, typename TB, bool PK, bool BND>
+__global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a, TileSplit split)
 {
     using P = Phys2D<EQ>;
     using T = TB;
@@ -1096,7 +1127,13 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
     const int tid = threadIdx.x, v = tid % NV, cidx = tid / NV;
     const int tx = cidx % FX, ty = cidx / FX;
     int64_t tbx, tby;
-    xcd_tile((a.nx + FX - 1) / FX, gridDim.x, tbx, tby);
+    if constexpr (BND) {
+        ring_tile(blockIdx.x, split, tbx, tby);
+    } else {
+        xcd_tile(split.x1 - split.x0, gridDim.x, tbx, tby);
+        tbx += split.x0;
+        tby += split.y0;
+    }
     const int64_t ix0 = tbx * FX, jy0 = tby * FY;
     const int64_t ix = ix0 + tx, jy = jy0 + ty;
     const bool px = a.bc[0] == BC_PERIODIC, py = a.bc[2] == BC_PERIODIC;
@@ -1176,7 +1213,7 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a)
         for (int dir = 0; dir < 2; ++dir) {
 #pragma unroll 1
             for (int side = 0; side < 2; ++side) {
-                const bool inside = dir == 0 ? (side ? rin : lin) : (side ? tin : bin);
+                const bool inside = !BND || (dir == 0 ? (side ? rin : lin) : (side ? tin : bin));
                 const int nslot = oslot + (dir == 0 ? (side ? 1 : -1) : (side ? SX : -SX));
                 const T* UN = &sM[nslot * STRIDE + v];
                 // across-face derivative values P_n^(a)(end): +1 end for
@@ -1858,18 +1895,33 @@ hipError_t launch_filter2d(int eq, int k, const Args2D<TB>& a, hipStream_t st)
 {
     const int fx = eq == ADV ? FilterTile<1>::FX : FilterTile<4>::FX;
     const int fy = eq == ADV ? FilterTile<1>::FY : FilterTile<4>::FY;
-    dim3 grid((unsigned)(((a.nx + fx - 1) / fx) * ((a.ny + fy - 1) / fy))), block(256);
-#define DG_CASE(E_, K_)                                                                         \
-    if (eq == E_ && k == K_) {                                                                  \
-        if (a.pk)                                                                               \
-            hipLaunchKernelGGL((filter2d_kernel<E_, K_, TB, (K_ > 0)>), grid, block, 0, st, a); \
-        else                                                                                    \
-            hipLaunchKernelGGL((filter2d_kernel<E_, K_, TB, false>), grid, block, 0, st, a);    \
-        return hipGetLastError();                                                               \
+    TileSplit t;
+    t.gx = (a.nx + fx - 1) / fx;
+    t.gy = (a.ny + fy - 1) / fy;
+    const bool px = a.bc[0] == BC_PERIODIC, py = a.bc[2] == BC_PERIODIC;
+    t.x0 = px ? 0 : (t.gx < 1 ? t.gx : 1);
+    t.x1 = px ? t.gx : (t.gx - 1 > t.x0 ? t.gx - 1 : t.x0);
+    t.y0 = py ? 0 : (t.gy < 1 ? t.gy : 1);
+    t.y1 = py ? t.gy : (t.gy - 1 > t.y0 ? t.gy - 1 : t.y0);
+    const dim3 gi((unsigned)t.interior()), gb((unsigned)t.boundary()), block(256);
+    // interior tiles, then the boundary tiles (disjoint cells, same stream)
+#define DG_LAUNCH(E_, K_, PK_)                                                                     \
+    do {                                                                                           \
+        if (gi.x) hipLaunchKernelGGL((filter2d_kernel<E_, K_, TB, PK_, false>), gi, block, 0, st, a, t); \
+        if (gb.x) hipLaunchKernelGGL((filter2d_kernel<E_, K_, TB, PK_, true>), gb, block, 0, st, a, t);  \
+    } while (0)
+#define DG_CASE(E_, K_)                                                                            \
+    if (eq == E_ && k == K_) {                                                                     \
+        if (a.pk)                                                                                  \
+            DG_LAUNCH(E_, K_, (K_ > 0));                                                           \
+        else                                                                                       \
+            DG_LAUNCH(E_, K_, false);                                                              \
+        return hipGetLastError();                                                                  \
     }
     DG_CASE(ADV, 0) DG_CASE(ADV, 1) DG_CASE(ADV, 2) DG_CASE(ADV, 3)
     DG_CASE(EULER, 0) DG_CASE(EULER, 1) DG_CASE(EULER, 2) DG_CASE(EULER, 3)
 #undef DG_CASE
+#undef DG_LAUNCH
     return hipErrorInvalidValue;
 }
 
