@@ -804,7 +804,9 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
     // ---- phase 2: LLF flux at every (edge, Gauss point) of the tile ----
     constexpr int NITEM = (NVE + NHE) * Q;
     constexpr int PER = (NITEM + 255) / 256;
-    T fl[PER][NV];
+    // Each (edge, point) item is the only reader of its lower-side trace
+    // entries, so it overwrites them with its flux at once: no other lane
+    // reads that slot, and the flux needs no registers until a barrier.
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int w = tid + 256 * k;
@@ -847,17 +849,9 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
             llf2d<EQ, T, HLLX>(ul, ur, vert ? 0 : 1, f, a.phys);
         }
 #pragma unroll
-        for (int q = 0; q < NV; ++q) fl[k][q] = f[q];
+        for (int q = 0; q < NV; ++q) sF[es * ES + sw(b, q)] = f[q];
     }
-    __syncthreads();  // traces consumed; the LDS now takes the fluxes
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int w = tid + 256 * k;
-        if (w >= NITEM) break;
-#pragma unroll
-        for (int q = 0; q < NV; ++q) sF[(w / Q) * ES + sw(w % Q, q)] = fl[k][q];
-    }
-    __syncthreads();
+    __syncthreads();  // fluxes complete; the upper half takes the exchange blocks
 
     // ---- phase 3: volume term, edge terms, combination (variable v) ----
     const T hy2 = (T)(0.5 * a.hy), hx2 = (T)(0.5 * a.hx);
@@ -961,24 +955,37 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
             for (int b = 0; b < NB; ++b) g2[b] = X[sw(b, v)];
             wave_lds_sync();  // the block is rewritten by the next row
         }
-        T t1[K1], t2[K1];  // sum_b w_b F1 P_q(eta_b), sum_b w_b F2 P_q'(eta_b)
+        // t1[q] = wa hy/2 sum_b w_b F1 P_q(eta_b), t2[q] = wa hx/2 sum_b w_b
+        // F2 P_q'(eta_b); P_0' = 0, so t2[0] and the p = 0 terms of F1 vanish
+        // and are not formed
+        T t1[K1], t2[K1];
 #pragma unroll
         for (int q = 0; q < K1; ++q) t1[q] = t2[q] = (T)0;
 #pragma unroll
         for (int b = 0; b < Q; ++b) {
-            const T wb = (T)gl_weight(Q, b);
+            const T w1 = (T)gl_weight(Q, b) * g1[b], w2 = (T)gl_weight(Q, b) * g2[b];
 #pragma unroll
             for (int q = 0; q < K1; ++q) {
-                t1[q] += wb * g1[b] * (T)leg_at(Q, b, q);
-                t2[q] += wb * g2[b] * (T)dleg_at(Q, b, q);
+                t1[q] += w1 * (T)leg_at(Q, b, q);
+                if (q > 0) t2[q] += w2 * (T)dleg_at(Q, b, q);
             }
         }
-        const T wa = (T)gl_weight(Q, qa);
+        const T s1 = (T)gl_weight(Q, qa) * hy2, s2 = (T)gl_weight(Q, qa) * hx2;
+#pragma unroll
+        for (int q = 0; q < K1; ++q) {
+            t1[q] *= s1;
+            t2[q] *= s2;
+        }
 #pragma unroll
         for (int p = 0; p < K1; ++p)
 #pragma unroll
-            for (int q = 0; q < K1; ++q)
-                acc[p * K1 + q] += wa * (hy2 * (T)dleg_at(Q, qa, p) * t1[q] + hx2 * (T)leg_at(Q, qa, p) * t2[q]);
+            for (int q = 0; q < K1; ++q) {
+                if ((p == 0 && q == 0) || !mode_kept<K, PK>(p * K1 + q)) continue;
+                T r = acc[p * K1 + q];
+                if (p > 0) r += (T)dleg_at(Q, qa, p) * t1[q];
+                if (q > 0) r += (T)leg_at(Q, qa, p) * t2[q];
+                acc[p * K1 + q] = r;
+            }
         // keep the rows apart: interleaving them only raises the register
         // count (and so lowers the occupancy)
         __builtin_amdgcn_sched_barrier(0);
