@@ -1453,18 +1453,28 @@ __global__ __launch_bounds__(256) void pp2d_kernel(StateView<TB> u, long long nc
 // tile's ring cells their two facing corners, and the corner values meet in
 // LDS.
 // -------------------------------------------------------------------------
+// Rows of cells per lane of the indicator: two when it reads the corner
+// values (the time steps), so each lane has twice the loads in flight and a
+// workgroup's tile is FX x 2 FY cells; one when it forms them from the state.
+template <bool CORNER>
+struct IndicatorRows {
+    static constexpr int RPL = CORNER ? 2 : 1;
+};
+
 template <int EQ, int K, typename TB, bool PK, bool CORNER>
 __global__ __launch_bounds__(256) void indicator2d_kernel(Args2D<TB> a)
 {
     using P = Phys2D<EQ>;
     using T = TB;
     constexpr int NV = P::NV, K1 = K + 1, NM = K1 * K1, L1 = 2 * K + 1;
-    constexpr int FX = FilterTile<NV>::FX, FY = FilterTile<NV>::FY;
-    constexpr int NRING = 2 * FY + 2 * FX;
+    constexpr int RPL = IndicatorRows<CORNER>::RPL;
+    constexpr int FX = FilterTile<NV>::FX, FY = FilterTile<NV>::FY, TY = RPL * FY;
+    constexpr int NRING = 2 * TY + 2 * FX;
+    static_assert(NRING * NV <= 256, "one lane per (ring cell, variable)");
     // corner values: own cells [corner sx + 2 sy][cell][var]; ring cells
     // [the two facing corners][ring index][var] (consecutive lanes,
     // consecutive words)
-    constexpr int CS = FX * FY * NV, RS = NRING * NV;
+    constexpr int CS = FX * TY * NV, RS = NRING * NV;
     __shared__ T sC[4 * CS];
     __shared__ T sR[2 * RS];
 
@@ -1473,43 +1483,64 @@ __global__ __launch_bounds__(256) void indicator2d_kernel(Args2D<TB> a)
     const double t0 = a.dt_from_ctrl ? a.ctrl->t : a.t_host;
     const double tf = t0 + (a.stage == 1 ? 0.5 : 1.0) * dt;  // time the stage output stands for
 
+    // lane (cell, variable) of the first row band; the lane also takes the
+    // cell FY rows above for RPL = 2
     const int tid = threadIdx.x, v = tid % NV, cidx = tid / NV;
-    const int tx = cidx % FX, ty = cidx / FX;
+    const int tx = cidx % FX, ty0 = cidx / FX;
     int64_t tbx, tby;
     xcd_tile((a.nx + FX - 1) / FX, gridDim.x, tbx, tby);
-    const int64_t ix0 = tbx * FX, jy0 = tby * FY;
-    const int64_t ix = ix0 + tx, jy = jy0 + ty;
+    const int64_t ix0 = tbx * FX, jy0 = tby * TY;
+    const int64_t ix = ix0 + tx;
     const bool px = a.bc[0] == BC_PERIODIC, py = a.bc[2] == BC_PERIODIC;
-    const bool own = ix < a.nx && jy < a.ny;
     // a slot past the mesh in a ragged tile holds the periodic image (the
     // face neighbour of the last own cell), or nothing
-    const int64_t cx = slot_index(ix, a.nx, px), cy = slot_index(jy, a.ny, py);
-    const bool loadable = cx >= 0 && cy >= 0;
-
-    double m0v = 0.0;
-    T um[NM];
+    const int64_t cx = slot_index(ix, a.nx, px);
+    int64_t jy[RPL];
+    bool own[RPL];
+    double m0v[RPL];
+    T um[RPL][NM];
+    {
+        T cv[RPL][4];
+        bool loadable[RPL];
 #pragma unroll
-    for (int m = 0; m < NM; ++m) um[m] = (T)0;
-    if (loadable) {
-        const int64_t c0 = cy * a.nx + cx;
-        if constexpr (CORNER) {
+        for (int h = 0; h < RPL; ++h) {
+            jy[h] = jy0 + ty0 + h * FY;
+            own[h] = ix < a.nx && jy[h] < a.ny;
+            const int64_t cy = slot_index(jy[h], a.ny, py);
+            loadable[h] = cx >= 0 && cy >= 0;
+            m0v[h] = 0.0;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) sC[c * CS + cidx * NV + v] = a.corner[(c * NV + v) * a.cstride + c0];
-        } else {
-            load_var2d<K, PK, TB, T>(a.us, c0, v, m0v, um);
+            for (int m = 0; m < NM; ++m) um[h][m] = (T)0;
+            if (loadable[h]) {
+                const int64_t c0 = cy * a.nx + cx;
+                if constexpr (CORNER) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) sC[c * CS + cidx * NV + v] = corner2d<K, PK, T>(um, c & 1, c >> 1);
+                    for (int c = 0; c < 4; ++c) cv[h][c] = a.corner[(c * NV + v) * a.cstride + c0];
+                } else {
+                    load_var2d<K, PK, TB, T>(a.us, c0, v, m0v[h], um[h]);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) cv[h][c] = corner2d<K, PK, T>(um[h], c & 1, c >> 1);
+                }
+            }
         }
+        // (the loads of all rows are requested before any is stored)
+#pragma unroll
+        for (int h = 0; h < RPL; ++h)
+            if (loadable[h]) {
+                const int cl = (ty0 + h * FY) * FX + tx;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sC[c * CS + cl * NV + v] = cv[h][c];
+            }
     }
     if (tid < NRING * NV) {
         const int r = tid / NV, rv = tid % NV;
         int g, i;  // 0 left column, 1 right column, 2 bottom row, 3 top row
-        if (r < FY) { g = 0; i = r; }
-        else if (r < 2 * FY) { g = 1; i = r - FY; }
-        else if (r < 2 * FY + FX) { g = 2; i = r - 2 * FY; }
-        else { g = 3; i = r - 2 * FY - FX; }
+        if (r < TY) { g = 0; i = r; }
+        else if (r < 2 * TY) { g = 1; i = r - TY; }
+        else if (r < 2 * TY + FX) { g = 2; i = r - 2 * TY; }
+        else { g = 3; i = r - 2 * TY - FX; }
         const int64_t gx = g == 0 ? ix0 - 1 : g == 1 ? ix0 + FX : ix0 + i;
-        const int64_t gy = g == 2 ? jy0 - 1 : g == 3 ? jy0 + FY : jy0 + i;
+        const int64_t gy = g == 2 ? jy0 - 1 : g == 3 ? jy0 + TY : jy0 + i;
         const int64_t hx_ = slot_index(gx, a.nx, px), hy_ = slot_index(gy, a.ny, py);
         if (hx_ >= 0 && hy_ >= 0) {
             const int64_t c1 = hy_ * a.nx + hx_;
@@ -1537,103 +1568,114 @@ __global__ __launch_bounds__(256) void indicator2d_kernel(Args2D<TB> a)
     }
     __syncthreads();
 
-    T eta = (T)0;
-    if (own) {
-        const bool lin = slot_index(ix - 1, a.nx, px) >= 0, rin = slot_index(ix + 1, a.nx, px) >= 0;
-        const bool bin = slot_index(jy - 1, a.ny, py) >= 0, tin = slot_index(jy + 1, a.ny, py) >= 0;
-        const double xl = a.xlo + (double)ix * a.hx, yb = a.ylo + (double)jy * a.hy;
-        // the neighbour's value at corner c of the face (dir, side): from the
-        // tile or its ring
-        auto nb_corner = [&](int dir, int side, int c) -> T {
-            if (dir == 0) {
-                const int nx_ = tx + (side ? 1 : -1);
-                if (nx_ >= 0 && nx_ < FX) return sC[((side ? 0 : 1) + 2 * c) * CS + (ty * FX + nx_) * NV + v];
-                const int r = side ? FY + ty : ty;
-                return sR[c * RS + r * NV + v];
-            }
-            const int ny_ = ty + (side ? 1 : -1);
-            if (ny_ >= 0 && ny_ < FY) return sC[(c + (side ? 0 : 2)) * CS + (ny_ * FX + tx) * NV + v];
-            const int r = side ? 2 * FY + FX + tx : 2 * FY + tx;
-            return sR[c * RS + r * NV + v];
-        };
-        T jx = (T)0, jyv = (T)0;
+    T eta[RPL];
+    double zmax = 0.0;
 #pragma unroll
-        for (int side = 0; side < 2; ++side)
-#pragma unroll
-            for (int dir = 0; dir < 2; ++dir) {
-                const bool inside = dir == 0 ? (side ? rin : lin) : (side ? tin : bin);
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    // own corner of this face
-                    const int sx = dir == 0 ? side : c, sy = dir == 0 ? c : side;
-                    const T in = sC[(sx + 2 * sy) * CS + cidx * NV + v];
-                    T j;
-                    if (inside) {
-                        j = fabs(nb_corner(dir, side, c) - in);
-                    } else {
-                        const double xc = xl + (sx ? a.hx : 0.0), yc = yb + (sy ? a.hy : 0.0);
-                        bool rf;
-                        const int kind = boundary_kind(a, 2 * dir + side, xc, yc, tf, &rf);
-                        if (kind)
-                            j = fabs((T)boundary_state(a, 2 * dir + side, kind, v) - in);
-                        else if (rf)
-                            j = (v == 1 + dir) ? (T)2 * fabs(in) : (T)0;
-                        else
-                            j = (T)0;
-                    }
-                    if (dir == 0)
-                        jx += (T)0.5 * j;
-                    else
-                        jyv += (T)0.5 * j;
+    for (int h = 0; h < RPL; ++h) {
+        const int ty = ty0 + h * FY;
+        eta[h] = (T)0;
+        if (own[h]) {
+            const bool lin = slot_index(ix - 1, a.nx, px) >= 0, rin = slot_index(ix + 1, a.nx, px) >= 0;
+            const bool bin = slot_index(jy[h] - 1, a.ny, py) >= 0, tin = slot_index(jy[h] + 1, a.ny, py) >= 0;
+            const double xl = a.xlo + (double)ix * a.hx, yb = a.ylo + (double)jy[h] * a.hy;
+            // the neighbour's value at corner c of the face (dir, side): from
+            // the tile or its ring
+            auto nb_corner = [&](int dir, int side, int c) -> T {
+                if (dir == 0) {
+                    const int nx_ = tx + (side ? 1 : -1);
+                    if (nx_ >= 0 && nx_ < FX) return sC[((side ? 0 : 1) + 2 * c) * CS + (ty * FX + nx_) * NV + v];
+                    const int r = side ? TY + ty : ty;
+                    return sR[c * RS + r * NV + v];
                 }
-            }
-        eta = jx * (T)(0.5 * a.inv_hx) + jyv * (T)(0.5 * a.inv_hy);
-    }
-    {
-        const int base = tid - v;
-        T e = eta;
+                const int ny_ = ty + (side ? 1 : -1);
+                if (ny_ >= 0 && ny_ < TY) return sC[(c + (side ? 0 : 2)) * CS + (ny_ * FX + tx) * NV + v];
+                const int r = side ? 2 * TY + FX + tx : 2 * TY + tx;
+                return sR[c * RS + r * NV + v];
+            };
+            T jx = (T)0, jyv = (T)0;
 #pragma unroll
-        for (int w = 0; w < NV; ++w) {
-            const T o = NV > 1 ? __shfl(eta, base + w, 64) : eta;
-            e = (w == 0 || o > e) ? o : e;
+            for (int side = 0; side < 2; ++side)
+#pragma unroll
+                for (int dir = 0; dir < 2; ++dir) {
+                    const bool inside = dir == 0 ? (side ? rin : lin) : (side ? tin : bin);
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        // own corner of this face
+                        const int sx = dir == 0 ? side : c, sy = dir == 0 ? c : side;
+                        const T in = sC[(sx + 2 * sy) * CS + (ty * FX + tx) * NV + v];
+                        T j;
+                        if (inside) {
+                            j = fabs(nb_corner(dir, side, c) - in);
+                        } else {
+                            const double xc = xl + (sx ? a.hx : 0.0), yc = yb + (sy ? a.hy : 0.0);
+                            bool rf;
+                            const int kind = boundary_kind(a, 2 * dir + side, xc, yc, tf, &rf);
+                            if (kind)
+                                j = fabs((T)boundary_state(a, 2 * dir + side, kind, v) - in);
+                            else if (rf)
+                                j = (v == 1 + dir) ? (T)2 * fabs(in) : (T)0;
+                            else
+                                j = (T)0;
+                        }
+                        if (dir == 0)
+                            jx += (T)0.5 * j;
+                        else
+                            jyv += (T)0.5 * j;
+                    }
+                }
+            eta[h] = jx * (T)(0.5 * a.inv_hx) + jyv * (T)(0.5 * a.inv_hy);
         }
-        eta = e;
+        {
+            const int base = tid - v;
+            T e = eta[h];
+#pragma unroll
+            for (int w = 0; w < NV; ++w) {
+                const T o = NV > 1 ? __shfl(eta[h], base + w, 64) : eta[h];
+                e = (w == 0 || o > e) ? o : e;
+            }
+            eta[h] = e;
+        }
+        const double z = own[h] ? (double)eta[h] : 0.0;
+        zmax = (z > zmax || z != z) ? z : zmax;
     }
     // max eta over the grid: every lane reaches the wave reduction
-    const double z = wave_max(own ? (double)eta : 0.0);
+    const double z = wave_max(zmax);
     if ((tid & 63) == 0) atomic_max_nonneg(a.eta_acc, z);
-    if (!own) return;
-    const int64_t cell = jy * a.nx + ix;
-    if (a.E_out && v == 0) {
 #pragma unroll
-        for (int l = 0; l < L1; ++l) a.E_out[cell * L1 + l] = 0.0;
-    }
-    if constexpr (EQ == EULER) {
-        // positivity limiter: cells that stay unfiltered (eta <= 1) are final
-        // now; troubled cells are screened after their blend
-        if (a.pp) {
-            bool fail;
-            if constexpr (CORNER) {
-                fail = a.ppfail[cell] != 0;  // the stage kernel's screen
-            } else {
-                double sabs = 0.0;
+    for (int h = 0; h < RPL; ++h) {
+        if (!own[h]) continue;
+        const int64_t cell = jy[h] * a.nx + ix;
+        if (a.E_out && v == 0) {
 #pragma unroll
-                for (int m = 1; m < NM; ++m) sabs += fabs((double)um[m]);
-                fail = !pp2_clear_lanes<TB>(m0v, sabs, tid - v, a.phys.gamma);
-            }
-            if (!(eta > (T)1) && fail && v == 0) {
-                const unsigned long long slot = atomicAdd(a.pcount, 1ull);
-                if ((long long)slot < a.pcap) a.pcell[slot] = cell;
+            for (int l = 0; l < L1; ++l) a.E_out[cell * L1 + l] = 0.0;
+        }
+        if constexpr (EQ == EULER) {
+            // positivity limiter: cells that stay unfiltered (eta <= 1) are
+            // final now; troubled cells are screened after their blend
+            if (a.pp) {
+                bool fail;
+                if constexpr (CORNER) {
+                    fail = a.ppfail[cell] != 0;  // the stage kernel's screen
+                } else {
+                    double sabs = 0.0;
+#pragma unroll
+                    for (int m = 1; m < NM; ++m) sabs += fabs((double)um[h][m]);
+                    fail = !pp2_clear_lanes<TB>(m0v[h], sabs, tid - v, a.phys.gamma);
+                }
+                if (!(eta[h] > (T)1) && fail && v == 0) {
+                    const unsigned long long slot = atomicAdd(a.pcount, 1ull);
+                    if ((long long)slot < a.pcap) a.pcell[slot] = cell;
+                }
             }
         }
-    }
-    if (v == 0) {
-        if (a.eta_out) a.eta_out[cell] = (double)eta;
-        if (eta > (T)1) {
-            const unsigned int slot = atomicAdd(a.tcount, 1u);
-            if ((long long)slot < a.tcap) {
-                a.tcell[slot] = cell;
-                a.tdata[(size_t)slot * L1] = (double)eta;
+        if (v == 0) {
+            if (a.eta_out) a.eta_out[cell] = (double)eta[h];
+            if (eta[h] > (T)1) {
+                const unsigned int slot = atomicAdd(a.tcount, 1u);
+                if ((long long)slot < a.tcap) {
+                    a.tcell[slot] = cell;
+                    a.tdata[(size_t)slot * L1] = (double)eta[h];
+                }
             }
         }
     }
@@ -1936,7 +1978,8 @@ template <typename TB>
 hipError_t launch_indicator2d(int eq, int k, const Args2D<TB>& a, hipStream_t st)
 {
     const int fx = eq == ADV ? FilterTile<1>::FX : FilterTile<4>::FX;
-    const int fy = eq == ADV ? FilterTile<1>::FY : FilterTile<4>::FY;
+    const int fy = (eq == ADV ? FilterTile<1>::FY : FilterTile<4>::FY) *
+                   (a.corner ? IndicatorRows<true>::RPL : IndicatorRows<false>::RPL);
     dim3 grid((unsigned)(((a.nx + fx - 1) / fx) * ((a.ny + fy - 1) / fy))), block(256);
     // corner values handed over by the stage kernel (dg_run), or the state
 #define DG_CASE(E_, K_)                                                                            \

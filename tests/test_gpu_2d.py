@@ -90,6 +90,11 @@ CASES = [
     (2, 3, 40, 24, (3, 1, 4, 5)),
     (0, 2, 19, 21, (0, 0, 0, 0)),
     (0, 3, 17, 16, (1, 1, 3, 3)),
+    # periodic in one direction only: the jump filter's interior launch
+    # then spans a full tile row (x) or column (y) range, and its boundary
+    # launch only the rows (columns) at the non-periodic edges
+    (2, 2, 50, 26, (0, 0, 2, 2)),
+    (2, 1, 45, 12, (1, 1, 0, 0)),
 ]
 
 
