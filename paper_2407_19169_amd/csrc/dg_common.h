@@ -147,19 +147,19 @@ struct Phys1D<EULER> {
         T pr = ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * u[1] / u[0]);
         return (u[2] + pr) / u[0];
     }
-    // flux and speed of one state sharing the velocity and pressure (the
-    // same expressions as flux() and speed(), so the same values); the
-    // pressure is returned in *pr_out
+    // flux and speed of one state (an interface flux's side) from a single
+    // division, 1/rho; the pressure is returned in *pr_out
     template <typename T>
     __device__ static T flux_speed(const T* u, T* f, const PhysParams& p, T* pr_out = nullptr)
     {
-        T vel = u[1] / u[0];
-        T pr = ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * vel);
+        const T ir = (T)1 / u[0];
+        const T vel = u[1] * ir;
+        const T pr = ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * vel);
         f[0] = u[1];
         f[1] = u[1] * vel + pr;
         f[2] = vel * (u[2] + pr);
         if (pr_out) *pr_out = pr;
-        return fabs(vel) + tsqrt<T>((T)p.gamma * pr / u[0]);
+        return fabs(vel) + tsqrt<T>((T)p.gamma * pr * ir);
     }
     // flux of one state, returning the pressure it used
     template <typename T>
