@@ -67,13 +67,15 @@ struct Phys2D<EULER> {
         f[2] = u[2] * vn + (dir == 1 ? pr : (T)0);
         f[3] = vn * (u[3] + pr);
     }
+    // (speed, enthalpy and the CFL quantity each from a single division, 1/rho)
     template <typename T>
     __device__ static T speed(const T* u, int dir, const PhysParams& p)
     {
-        const T pr = pressure(u, p);
-        return fabs(u[1 + dir] / u[0]) + tsqrt<T>((T)p.gamma * pr / u[0]);
+        const T ir = (T)1 / u[0];
+        const T vx = u[1] * ir, vy = u[2] * ir;
+        const T pr = ((T)p.gamma - (T)1) * (u[3] - (T)0.5 * (u[1] * vx + u[2] * vy));
+        return fabs(dir == 0 ? vx : vy) + tsqrt<T>((T)p.gamma * pr * ir);
     }
-    // CFL quantity (|u| + c) / hx + (|v| + c) / hy from a single division
     template <typename T>
     __device__ static T cfl(const T* u, T ihx, T ihy, const PhysParams& p)
     {
@@ -118,7 +120,9 @@ struct Phys2D<EULER> {
     template <typename T>
     __device__ static T enthalpy(const T* u, const PhysParams& p)
     {
-        return (u[3] + pressure(u, p)) / u[0];
+        const T ir = (T)1 / u[0];
+        const T pr = ((T)p.gamma - (T)1) * (u[3] - (T)0.5 * (u[1] * (u[1] * ir) + u[2] * (u[2] * ir)));
+        return (u[3] + pr) * ir;
     }
 };
 

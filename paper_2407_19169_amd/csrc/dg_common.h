@@ -134,18 +134,21 @@ struct Phys1D<EULER> {
         f[1] = u[1] * vel + pr;
         f[2] = vel * (u[2] + pr);
     }
+    // (speed and enthalpy from a single division, 1/rho)
     template <typename T>
     __device__ static T speed(const T* u, const PhysParams& p)
     {
-        T vel = u[1] / u[0];
-        T pr = ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * vel);
-        return fabs(vel) + tsqrt<T>((T)p.gamma * pr / u[0]);
+        const T ir = (T)1 / u[0];
+        const T vel = u[1] * ir;
+        const T pr = ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * vel);
+        return fabs(vel) + tsqrt<T>((T)p.gamma * pr * ir);
     }
     template <typename T>
     __device__ static T enthalpy(const T* u, const PhysParams& p)
     {
-        T pr = ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * u[1] / u[0]);
-        return (u[2] + pr) / u[0];
+        const T ir = (T)1 / u[0];
+        const T pr = ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * (u[1] * ir));
+        return (u[2] + pr) * ir;
     }
     // flux and speed of one state (an interface flux's side) from a single
     // division, 1/rho; the pressure is returned in *pr_out
