@@ -58,7 +58,7 @@ struct Phys2D<EULER> {
     template <typename T>
     __device__ static void flux(const T* u, int dir, T* f, const PhysParams& p)
     {
-        const T ir = (T)1 / u[0];
+        const T ir = trcp<T>(u[0]);
         const T vx = u[1] * ir, vy = u[2] * ir;
         const T pr = ((T)p.gamma - (T)1) * (u[3] - (T)0.5 * (u[1] * vx + u[2] * vy));
         const T vn = dir == 0 ? vx : vy;
@@ -67,11 +67,11 @@ struct Phys2D<EULER> {
         f[2] = u[2] * vn + (dir == 1 ? pr : (T)0);
         f[3] = vn * (u[3] + pr);
     }
-    // (speed, enthalpy and the CFL quantity each from a single division, 1/rho)
+    // (speed, enthalpy and the CFL quantity each from one reciprocal of the density)
     template <typename T>
     __device__ static T speed(const T* u, int dir, const PhysParams& p)
     {
-        const T ir = (T)1 / u[0];
+        const T ir = trcp<T>(u[0]);
         const T vx = u[1] * ir, vy = u[2] * ir;
         const T pr = ((T)p.gamma - (T)1) * (u[3] - (T)0.5 * (u[1] * vx + u[2] * vy));
         return fabs(dir == 0 ? vx : vy) + tsqrt<T>((T)p.gamma * pr * ir);
@@ -79,17 +79,17 @@ struct Phys2D<EULER> {
     template <typename T>
     __device__ static T cfl(const T* u, T ihx, T ihy, const PhysParams& p)
     {
-        const T ir = (T)1 / u[0];
+        const T ir = trcp<T>(u[0]);
         const T vx = u[1] * ir, vy = u[2] * ir;
         const T pr = ((T)p.gamma - (T)1) * (u[3] - (T)0.5 * (u[1] * vx + u[2] * vy));
         const T c = tsqrt<T>((T)p.gamma * pr * ir);
         return (fabs(vx) + c) * ihx + (fabs(vy) + c) * ihy;
     }
-    // flux() and speed() of one state from a single division (1/rho)
+    // flux() and speed() of one state from one reciprocal of the density
     template <typename T>
     __device__ static T flux_speed(const T* u, int dir, T* f, const PhysParams& p)
     {
-        const T ir = (T)1 / u[0];
+        const T ir = trcp<T>(u[0]);
         const T vx = u[1] * ir, vy = u[2] * ir;
         const T pr = ((T)p.gamma - (T)1) * (u[3] - (T)0.5 * (u[1] * vx + u[2] * vy));
         const T vn = dir == 0 ? vx : vy;
@@ -99,28 +99,10 @@ struct Phys2D<EULER> {
         f[3] = vn * (u[3] + pr);
         return fabs(vn) + tsqrt<T>((T)p.gamma * pr * ir);
     }
-    // the fluxes in x and y of one state from a single division; returns
-    // the pressure
-    template <typename T>
-    __device__ static T flux_xy(const T* u, T* f1, T* f2, const PhysParams& p)
-    {
-        const T ir = (T)1 / u[0];
-        const T vx = u[1] * ir, vy = u[2] * ir;
-        const T pr = ((T)p.gamma - (T)1) * (u[3] - (T)0.5 * (u[1] * vx + u[2] * vy));
-        f1[0] = u[0] * vx;
-        f1[1] = u[1] * vx + pr;
-        f1[2] = u[2] * vx;
-        f1[3] = vx * (u[3] + pr);
-        f2[0] = u[0] * vy;
-        f2[1] = u[1] * vy;
-        f2[2] = u[2] * vy + pr;
-        f2[3] = vy * (u[3] + pr);
-        return pr;
-    }
     template <typename T>
     __device__ static T enthalpy(const T* u, const PhysParams& p)
     {
-        const T ir = (T)1 / u[0];
+        const T ir = trcp<T>(u[0]);
         const T pr = ((T)p.gamma - (T)1) * (u[3] - (T)0.5 * (u[1] * (u[1] * ir) + u[2] * (u[2] * ir)));
         return (u[3] + pr) * ir;
     }
@@ -934,8 +916,8 @@ __global__ __launch_bounds__(256) void stage2d_kernel(Args2D<TB> a)
             wave_lds_sync();  // the block is rewritten with F1
             if (v < Q && own) {
                 if (EQ == EULER && a.check) {
-                    // the flux's own reciprocal of the density (one division)
-                    const T ir = (T)1 / uq[0];
+                    // the flux's own reciprocal of the density (shared with it)
+                    const T ir = trcp<T>(uq[0]);
                     const T pr = ((T)a.phys.gamma - (T)1) *
                                  (uq[3] - (T)0.5 * (uq[1] * (uq[1] * ir) + uq[2] * (uq[2] * ir)));
                     if (!(uq[0] > (T)0) || !(pr > (T)0)) {

@@ -789,7 +789,7 @@ __device__ __forceinline__ double cell_lambda(const double* ub, const PhysParams
     } else if constexpr (EQ == ADV) {
         return fabs(ph.a[0]) * ihx + fabs(ph.a[1]) * ihy;
     } else {
-        const double ir = 1.0 / ub[0];
+        const double ir = trcp<double>(ub[0]);
         const double vx = ub[1] * ir, vy = ub[2] * ir;
         const double pr = (ph.gamma - 1.0) * (ub[3] - 0.5 * (ub[1] * vx + ub[2] * vy));
         const double c = sqrt(ph.gamma * pr * ir);

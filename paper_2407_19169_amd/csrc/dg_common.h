@@ -66,6 +66,23 @@ __device__ __forceinline__ T tsqrt(T x) { return sqrt(x); }
 template <>
 __device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
 
+// 1/x for the flux arithmetic (the reciprocal of a density): FP64 by two
+// Newton-Raphson steps r <- r + r (1 - x r) from the hardware estimate,
+// within about an ulp of the rounded quotient for normal x (5 instructions
+// where the IEEE quotient takes 10); FP32 the hardware reciprocal (1 ulp).
+// A zero or non-finite x gives a non-finite result, as the quotient does.
+template <typename T>
+__device__ __forceinline__ T trcp(T x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+template <>
+__device__ __forceinline__ float trcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
 template <int EQ>
 struct Phys1D;
 
@@ -134,11 +151,11 @@ struct Phys1D<EULER> {
         f[1] = u[1] * vel + pr;
         f[2] = vel * (u[2] + pr);
     }
-    // (speed and enthalpy from a single division, 1/rho)
+    // (speed and enthalpy from one reciprocal of the density, trcp)
     template <typename T>
     __device__ static T speed(const T* u, const PhysParams& p)
     {
-        const T ir = (T)1 / u[0];
+        const T ir = trcp<T>(u[0]);
         const T vel = u[1] * ir;
         const T pr = ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * vel);
         return fabs(vel) + tsqrt<T>((T)p.gamma * pr * ir);
@@ -146,16 +163,16 @@ struct Phys1D<EULER> {
     template <typename T>
     __device__ static T enthalpy(const T* u, const PhysParams& p)
     {
-        const T ir = (T)1 / u[0];
+        const T ir = trcp<T>(u[0]);
         const T pr = ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * (u[1] * ir));
         return (u[2] + pr) * ir;
     }
-    // flux and speed of one state (an interface flux's side) from a single
-    // division, 1/rho; the pressure is returned in *pr_out
+    // flux and speed of one state (an interface flux's side) from one
+    // reciprocal of the density; the pressure is returned in *pr_out
     template <typename T>
     __device__ static T flux_speed(const T* u, T* f, const PhysParams& p, T* pr_out = nullptr)
     {
-        const T ir = (T)1 / u[0];
+        const T ir = trcp<T>(u[0]);
         const T vel = u[1] * ir;
         const T pr = ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * vel);
         f[0] = u[1];
@@ -168,8 +185,8 @@ struct Phys1D<EULER> {
     template <typename T>
     __device__ static T flux_pressure(const T* u, T* f, const PhysParams& p)
     {
-        T vel = u[1] / u[0];
-        T pr = ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * vel);
+        const T vel = u[1] * trcp<T>(u[0]);
+        const T pr = ((T)p.gamma - (T)1) * (u[2] - (T)0.5 * u[1] * vel);
         f[0] = u[1];
         f[1] = u[1] * vel + pr;
         f[2] = vel * (u[2] + pr);
