@@ -719,7 +719,7 @@ __device__ __forceinline__ void stage1d_tile(const Args1D<TB>& a, int64_t blk, d
             for (int v = 0; v < NV; ++v) ub[v] = (T)v0[v];
             const T beta = P::speed(ub, a.phys);
             const T H = P::enthalpy(ub, a.phys);
-            const T coef = beta * (T)dt * (T)a.inv_h / H;
+            const T coef = beta * (T)dt * (T)a.inv_h * trcp<T>(H);
             T E[K1];
             E[0] = (T)0;
             T S[NV];
@@ -1008,7 +1008,7 @@ __global__ __launch_bounds__(256) void filter1d_kernel(Args1D<TB> a)
     for (int v = 0; v < NV; ++v) ub[v] = (T)v0[v];
     const T beta = P::speed(ub, a.phys);
     const T H = P::enthalpy(ub, a.phys);
-    const T coef = beta * (T)dt * (T)a.inv_h / H;
+    const T coef = beta * (T)dt * (T)a.inv_h * trcp<T>(H);
     T E[K1];
     E[0] = (T)0;
     T S[NV];

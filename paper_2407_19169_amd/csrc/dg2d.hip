@@ -1300,7 +1300,7 @@ __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a, TileSplit s
     }
     if (!own) return;
     const int64_t cell = jy * a.nx + ix;
-    const T coef = (T)dt * (T)(a.inv_hx * a.inv_hy) / H;
+    const T coef = (T)dt * (T)(a.inv_hx * a.inv_hy) * trcp<T>(H);
     T E[L1];
     E[0] = (T)0;
 #pragma unroll
@@ -1811,7 +1811,7 @@ __global__ __launch_bounds__(256) void troubled2d_kernel(Args2D<TB> a)
 #pragma unroll
         for (int w = 0; w < NV; ++w) ubt[w] = L.u[0][w * NM];
         const T H = P::enthalpy(ubt, a.phys);
-        const T coef = (T)dt * (T)(a.inv_hx * a.inv_hy) / H;
+        const T coef = (T)dt * (T)(a.inv_hx * a.inv_hy) * trcp<T>(H);
         // E^l = coef max_v sv[v][l], l = 1..2k, after eta in the record
         if (lane < L1) {
             T bl_ = L.sv[0][lane];
