@@ -231,9 +231,11 @@ __device__ __forceinline__ bool pp_clear(const double (&u0)[3], const TB (&uh)[3
     if (!(rlo > 2.0 * (1e-13 + 8.0 * ur * sr))) return false;
     const double mhi = fabs(u0[1]) + sa[1];
     const double elo = u0[2] - sa[2], se = fabs(u0[2]) + sa[2];
-    const double kin = 0.5 * mhi * mhi / rlo;
+    // (1/rlo by the reciprocal helper: the margins below are two-fold)
+    const double irlo = trcp<double>(rlo);
+    const double kin = 0.5 * mhi * mhi * irlo;
     const double plo = (gamma - 1.0) * (elo - kin);
-    const double mmax = 8.0 * ur * (se + 2.0 * kin + kin * sr / rlo);
+    const double mmax = 8.0 * ur * (se + 2.0 * kin + kin * sr * irlo);
     return plo > 2.0 * (1e-13 + mmax);
 }
 

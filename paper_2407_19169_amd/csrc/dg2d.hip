@@ -435,9 +435,11 @@ __device__ __forceinline__ bool pp2_clear(const double (&ubar)[4], const double 
     if (!(rlo > 2.0 * (1e-13 + 8.0 * ur * sr))) return false;
     const double mx = fabs(ubar[1]) + sabs[1], my = fabs(ubar[2]) + sabs[2];
     const double elo = ubar[3] - sabs[3], se = fabs(ubar[3]) + sabs[3];
-    const double kin = 0.5 * (mx * mx + my * my) / rlo;
+    // (1/rlo by the reciprocal helper: the margins below are two-fold)
+    const double irlo = trcp<double>(rlo);
+    const double kin = 0.5 * (mx * mx + my * my) * irlo;
     const double plo = (gamma - 1.0) * (elo - kin);
-    const double mmax = 8.0 * ur * (se + 2.0 * kin + kin * sr / rlo);
+    const double mmax = 8.0 * ur * (se + 2.0 * kin + kin * sr * irlo);
     return plo > 2.0 * (1e-13 + mmax);
 }
 

@@ -7,7 +7,9 @@ and checks, on many seeded cells near and far from vacuum, that every cell
 it skips is one the oracle's limiter (Zhang and Shu, FP64) leaves bitwise
 unchanged (a screen without the margins fails this), and, as a sanity
 check, that the modes' own precision (FP32 for the mixed form) keeps every
-test-point density and pressure positive there as well."""
+test-point density and pressure positive there as well.  (The device forms
+1/rho_lo by a Newton-refined reciprocal, within about an ulp of the quotient
+restated here; the two-fold margins cover that.)"""
 import numpy as np
 from numpy.polynomial import legendre as npleg
 
