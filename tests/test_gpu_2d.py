@@ -95,6 +95,9 @@ CASES = [
     # launch only the rows (columns) at the non-periodic edges
     (2, 2, 50, 26, (0, 0, 2, 2)),
     (2, 1, 45, 12, (1, 1, 0, 0)),
+    # one tile column (x not periodic) or one tile row (y not periodic)
+    (2, 2, 5, 40, (1, 1, 0, 0)),
+    (2, 1, 40, 3, (0, 0, 2, 2)),
 ]
 
 
@@ -312,6 +315,25 @@ def test_double_mach_small_run_parity(dg, ref, k, filt):
     want, orep, rc = ref.run2d(P, w.u0, 1e30, 20)
     assert rc == 0 and rep.status == 0, (rc, rep.status)
     assert rep.steps == orep.steps == 20 and rep.restarts == orep.restarts
+    assert rep.troubled_cells == orep.troubled_cells
+    for v in range(4):
+        assert rel_linf(got[v], want[v]) <= 1e-10, (v, rel_linf(got[v], want[v]))
+    s.close()
+
+
+@pytest.mark.parametrize("k,filt,nx,ny", [(2, 2, 40, 12), (1, 1, 21, 5)])
+def test_double_mach_ragged_run_parity(dg, ref, k, filt, nx, ny):
+    """The double Mach run on meshes that fill no tile evenly: 40x12 with the
+    hybrid limiter (the indicator's 16x8 tiles: the second tile row holds 4
+    of its 8 rows), 21x5 with the jump filter (one tile row, so every tile is
+    a boundary tile); FP64 within 1e-10 after 12 steps."""
+    w, s, P = _dmr(dg, ref, nx, ny, k, filt)
+    s.set_state(w.u0)
+    rep = dg.dg_run(s.h, 1e30, 12)
+    got = s.get_state().cpu().numpy()
+    want, orep, rc = ref.run2d(P, w.u0, 1e30, 12)
+    assert rc == 0 and rep.status == 0, (rc, rep.status)
+    assert rep.steps == orep.steps == 12 and rep.restarts == orep.restarts
     assert rep.troubled_cells == orep.troubled_cells
     for v in range(4):
         assert rel_linf(got[v], want[v]) <= 1e-10, (v, rel_linf(got[v], want[v]))
