@@ -1099,7 +1099,7 @@ struct FilterTile {
 // BND: the launch over the boundary tiles of the split, with the ghost
 // jumps of faces on the domain edge; without it, the launch over the
 // interior tiles, whose faces all have a neighbour cell (that code holds no
-// registers for the boundary cases: 126 instead of 163 VGPRs for FP64 Q^2).
+// registers for the boundary cases: 124 instead of 163 VGPRs for FP64 Q^2).
 template <int EQ, int K, typename TB, bool PK, bool BND>
 __global__ __launch_bounds__(256) void filter2d_kernel(Args2D<TB> a, TileSplit split)
 {
@@ -1436,10 +1436,11 @@ __global__ __launch_bounds__(256) void pp2d_kernel(StateView<TB> u, long long nc
 // limiter, the cells that stay unfiltered and whose screen fails (a.pcell).
 // The exponents of the troubled cells are computed by troubled2d_kernel.
 // Mapping as filter2d: one lane per (cell, variable), FX x FY cells per
-// workgroup; each lane evaluates its variable at the four corners of its
-// cell (the values P_p(+-1) P_q(+-1) = +-1, summed in the order p, q), the
-// tile's ring cells their two facing corners, and the corner values meet in
-// LDS.
+// workgroup (FX x 2 FY, two cells per lane, when it reads the corner values
+// the stage kernel handed over); each lane evaluates its variable at the
+// four corners of its cell (the values P_p(+-1) P_q(+-1) = +-1, summed in the
+// order p, q), the tile's ring cells their two facing corners, and the
+// corner values meet in LDS.
 // -------------------------------------------------------------------------
 // Rows of cells per lane of the indicator: two when it reads the corner
 // values (the time steps), so each lane has twice the loads in flight and a
