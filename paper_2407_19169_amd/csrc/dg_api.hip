@@ -792,7 +792,7 @@ __device__ __forceinline__ double cell_lambda(const double* ub, const PhysParams
         const double ir = trcp<double>(ub[0]);
         const double vx = ub[1] * ir, vy = ub[2] * ir;
         const double pr = (ph.gamma - 1.0) * (ub[3] - 0.5 * (ub[1] * vx + ub[2] * vy));
-        const double c = sqrt(ph.gamma * pr * ir);
+        const double c = tsqrt<double>(ph.gamma * pr * ir);
         return (fabs(vx) + c) * ihx + (fabs(vy) + c) * ihy;
     }
 }

@@ -61,10 +61,26 @@ struct PhysParams {
 // names HLL and HLLC as alternatives that work with the filter as well.
 enum { FLUX_LLF = 0, FLUX_HLL = 1, FLUX_HLLC = 2 };
 
-// Square root for the wave speeds: FP64 the IEEE root, FP32 the hardware
-// square root (1 ulp; the correctly rounded FP32 root takes ten instructions).
+// Square root for the wave speeds.  FP64: for x in [2^-1000, 2^1000],
+// Markstein's iteration from the hardware reciprocal square root estimate y:
+// g = x y, h = y/2, one coupled Newton step (r = 1/2 - g h, g <- g + g r,
+// h <- h + h r), then two corrections g <- g + (x - g^2) h; this is the
+// library's own sequence without its rescaling of extreme arguments, which
+// takes the other values (zero, negative, non-finite, extreme) here.  FP32:
+// the hardware square root (1 ulp; the correctly rounded FP32 root takes ten
+// instructions).
 template <typename T>
-__device__ __forceinline__ T tsqrt(T x) { return sqrt(x); }
+__device__ __forceinline__ T tsqrt(T x)
+{
+    if (!(x >= 0x1p-1000 && x <= 0x1p1000)) return sqrt(x);
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    g = fma(fma(-g, g, x), h, g);
+    return fma(fma(-g, g, x), h, g);
+}
 template <>
 __device__ __forceinline__ float tsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 
