@@ -178,6 +178,26 @@ def run_1d(dg, torch, w, prec, filt, steps, warmup, t_end=1e30, bc=None):
     return r, state
 
 
+def shu_osher_only(dg, torch, I, prec: int, steps: int, warmup: int):
+    """The Shu-Osher problem alone (20000 cells, P2, hybrid limiter), for its
+    profiles: the timed dg_run, then each stage kernel's launch time
+    (dg_time_kernel: one warm-up and 50 back-to-back launches per stage)."""
+    w = I.shu_osher(20000, 2)
+    mesh = dg.make_mesh(1, (w.n,), (w.lo,), (w.hi,), (dg.DG_BC_OUTFLOW, dg.DG_BC_OUTFLOW))
+    s = dg.Solver(mesh, w.k, w.eq, dg.make_options(precision=prec, filter=dg.DG_FILTER_HYBRID,
+                                                   cfl=w.cfl, gamma=w.gamma))
+    s.set_state(w.u0)
+    rep, wall = timed_run(dg, torch, s, steps, warmup)
+    ndof = 3 * (w.k + 1) * w.n
+    done = rep.timed_steps
+    per_stage = [dg.dg_time_kernel(s.h, st, rep.dt_max, 50) for st in range(3)]
+    s.close()
+    return {"dofs": ndof, "precision": "fp64" if prec == 0 else "mixed", "status": rep.status,
+            "steps": done, "dof_updates_per_s": ndof * 3 * done / wall,
+            "ms_per_step": 1e3 * wall / max(done, 1),
+            "stage_kernel_us": [round(x, 2) for x in per_stage]}
+
+
 def sweep_1d(dg, torch, I, sizes, steps: int):
     """Jump filter on HBM-sized 1D states (Shu-Osher profile on n cells, P2):
     dg_run runs all three stages of a step in one pass (2 state passes per
@@ -302,9 +322,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=24.0)
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--only", choices=["dmr", "sweep", "batch", "copy"], default=None,
+    ap.add_argument("--only", choices=["dmr", "sweep", "batch", "copy", "shu"], default=None,
                     help="run one workload alone and print its figures (for profiler runs)")
-    ap.add_argument("--prec", type=int, default=0, help="--only dmr: 0 FP64, 1 mixed")
+    ap.add_argument("--prec", type=int, default=0, help="--only dmr / shu: 0 FP64, 1 mixed")
     ap.add_argument("--sweep", default="1000000,4000000,16000000",
                     help="1D cell counts of the HBM sweep (comma separated, empty: skip)")
     args = ap.parse_args()
@@ -334,6 +354,10 @@ def main() -> int:
     if args.only == "sweep":
         r = sweep_1d(dg, torch, I, [int(x) for x in args.sweep.split(",") if x], args.steps)
         print(json.dumps({"only": "sweep", "result": r}), flush=True)
+        return 0
+    if args.only == "shu":
+        r = shu_osher_only(dg, torch, I, args.prec, args.steps, args.warmup)
+        print(json.dumps({"only": "shu", "result": r}), flush=True)
         return 0
     if args.only == "batch":
         print(json.dumps({"only": "batch", "result": bench_batch(dg, torch, I, args.steps)}),
